@@ -1,0 +1,232 @@
+"""CPU oracle for Replica-Exchange Wang-Landau sampling (test infrastructure).
+
+Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The product library never loads it: it exists to prove
+the GPU path right.  The arithmetic lives in rewl_oracle.c (plain C, binary64,
+no FMA); this module only loads that library and marshals arguments, plus the
+brute-force density of states in bruteforce.py.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+OK, CONVERGED, EINVAL, ENOMEM, ESTATE, EBUDGET = 0, 1, -1, -2, -4, -5
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i32, i64, u32, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [i32, i32, i32, dbl, i32, u64, u32, u32, u32, dbl, dbl, i32, i64,
+                                 i32, i32, i32, P]
+        L.orc_destroy.argtypes = [P]
+        L.orc_set_threads.argtypes = [P, i32]
+        L.orc_walkin.argtypes = [P, i64]
+        L.orc_walkin.restype = i32
+        L.orc_run.argtypes = [P, i64, i64]
+        L.orc_run.restype = i32
+        L.orc_exchange.argtypes = [P]
+        L.orc_exchange.restype = i32
+        L.orc_info.argtypes = [P, P]
+        L.orc_starts.argtypes = [P, P]
+        L.orc_get_walker.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+        L.orc_get_window.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+        L.orc_set_lng.argtypes = [P, i32, P]
+        L.orc_join.argtypes = [P, P, P]
+        L.orc_join.restype = i32
+        L.orc_join_pieces.argtypes = [i32, i32, P, i32, i32, P, P, dbl, P, P]
+        L.orc_join_pieces.restype = i32
+        L.orc_thermo.argtypes = [P, i32, i32, P, i32, P, P, P]
+        L.orc_philox.argtypes = [P, P, P]
+        L.orc_exp_poly.argtypes = [dbl]
+        L.orc_exp_poly.restype = dbl
+        L.orc_exp_poly32.argtypes = [ctypes.c_float]
+        L.orc_exp_poly32.restype = ctypes.c_float
+        L.orc_window_layout.argtypes = [i32, i32, dbl, i32, P, P]
+        L.orc_window_layout.restype = i32
+        L.orc_potts_energy.argtypes = [P, i32]
+        L.orc_potts_energy.restype = i32
+        L.orc_constants.argtypes = [P]
+        L.orc_constants32.argtypes = [P]
+        L.orc_twosum_accumulate.argtypes = [P, P, ctypes.c_float, i64]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def philox(ctr, key):
+    """Philox4x32-10 block: ctr = 4 uint32 words, key = 2 uint32 words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def exp_poly(x):
+    return lib().orc_exp_poly(float(x))
+
+
+def exp_poly32(x):
+    return lib().orc_exp_poly32(float(np.float32(x)))
+
+
+def constants():
+    c = np.zeros(3)
+    lib().orc_constants(_ptr(c))
+    return c
+
+
+def constants32():
+    c = np.zeros(3, dtype=np.float32)
+    lib().orc_constants32(_ptr(c))
+    return c
+
+
+def twosum_accumulate(hi, lo, x, n):
+    a = np.array([hi], dtype=np.float32)
+    b = np.array([lo], dtype=np.float32)
+    lib().orc_twosum_accumulate(_ptr(a), _ptr(b), float(np.float32(x)), int(n))
+    return float(a[0]), float(b[0])
+
+
+def window_layout(B, h, overlap, e_lo):
+    W = ctypes.c_int(0)
+    starts = np.zeros(h, dtype=np.int32)
+    st = lib().orc_window_layout(B, h, overlap, e_lo, ctypes.byref(W), _ptr(starts))
+    if st != OK:
+        raise ValueError("invalid window layout")
+    return W.value, starts
+
+
+def potts_energy(spins, L):
+    s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
+    return lib().orc_potts_energy(_ptr(s), L)
+
+
+def thermo(lng, e_first, T):
+    g = np.ascontiguousarray(lng, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    lnZ, U, C = np.zeros_like(T), np.zeros_like(T), np.zeros_like(T)
+    lib().orc_thermo(_ptr(g), len(g), int(e_first), _ptr(T), len(T), _ptr(lnZ), _ptr(U), _ptr(C))
+    return lnZ, U, C
+
+
+def join_pieces(pieces, visited, starts, e_lo, B, log_total):
+    pieces = np.ascontiguousarray(pieces, dtype=np.float64)
+    vis = np.ascontiguousarray(visited, dtype=np.uint8)
+    starts = np.ascontiguousarray(starts, dtype=np.int32)
+    h, W = pieces.shape
+    out = np.zeros(B)
+    cuts = np.zeros(max(h - 1, 1), dtype=np.int32)
+    st = lib().orc_join_pieces(h, W, _ptr(starts), e_lo, B, _ptr(pieces), _ptr(vis),
+                               float(log_total), _ptr(out), _ptr(cuts))
+    return st, out, cuts[: h - 1]
+
+
+class Rewl:
+    """Sequential REWL run over h windows x m walkers of the 2D Potts model."""
+
+    def __init__(self, L, q, windows, overlap, walkers, init_spins, seed=1, instance=0,
+                 flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0, sync_attempts=1000,
+                 exchange=1, precision=0, fixed_lnf=0, threads=1):
+        self.L, self.q, self.h, self.m = L, q, windows, walkers
+        self.precision = precision
+        spins = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(-1)
+        if spins.size != windows * walkers * L * L:
+            raise ValueError("init_spins must hold one L*L lattice per walker")
+        self._keep = spins
+        self.h_ = lib().orc_create(L, q, windows, overlap, walkers, seed, instance, flat[0], flat[1],
+                                   lnf_init, lnf_final, schedule, sync_attempts, exchange, precision,
+                                   fixed_lnf, _ptr(spins))
+        if not self.h_:
+            raise ValueError("oracle rejected the parameters")
+        lib().orc_set_threads(self.h_, threads)
+        info = self.info()
+        self.N, self.W, self.B, self.e_lo, self.nw = info[:5]
+        self.starts = np.zeros(windows, dtype=np.int32)
+        lib().orc_starts(self.h_, _ptr(self.starts))
+
+    def __del__(self):
+        if getattr(self, "h_", None):
+            lib().orc_destroy(self.h_)
+            self.h_ = None
+
+    def info(self):
+        out = np.zeros(9, dtype=np.int64)
+        lib().orc_info(self.h_, _ptr(out))
+        return [int(x) for x in out]
+
+    @property
+    def step(self):
+        return self.info()[5]
+
+    @property
+    def round(self):
+        return self.info()[6]
+
+    def set_threads(self, n):
+        lib().orc_set_threads(self.h_, n)
+
+    def walkin(self, budget=10**9):
+        return lib().orc_walkin(self.h_, budget)
+
+    def run(self, attempts, walkin_budget=10**9):
+        return lib().orc_run(self.h_, int(attempts), int(walkin_budget))
+
+    def exchange(self):
+        return lib().orc_exchange(self.h_)
+
+    def walker(self, w):
+        N, W = self.N, self.W
+        spins = np.zeros(N, dtype=np.int8)
+        E = ctypes.c_int32(0)
+        H = np.zeros(W, dtype=np.uint32)
+        lng = np.zeros(W)
+        hi = np.zeros(W, dtype=np.float32)
+        lo = np.zeros(W, dtype=np.float32)
+        rep = ctypes.c_uint32(0)
+        wa = ctypes.c_int64(0)
+        lib().orc_get_walker(self.h_, w, _ptr(spins), ctypes.byref(E), _ptr(H), _ptr(lng),
+                             _ptr(hi), _ptr(lo), ctypes.byref(rep), ctypes.byref(wa))
+        d = dict(spins=spins, E=E.value, H=H, lng=lng, replica=rep.value, walkin_attempts=wa.value)
+        if self.precision == 1:
+            d["lng_hi"], d["lng_lo"] = hi, lo
+        return d
+
+    def window(self, k):
+        lnf, lnf_last = ctypes.c_double(0), ctypes.c_double(0)
+        regime, fin = ctypes.c_int32(0), ctypes.c_int32(0)
+        it = ctypes.c_int64(0)
+        vis = np.zeros(self.W, dtype=np.uint8)
+        xa, xc = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        lib().orc_get_window(self.h_, k, ctypes.byref(lnf), ctypes.byref(lnf_last), ctypes.byref(regime),
+                             ctypes.byref(fin), ctypes.byref(it), _ptr(vis), ctypes.byref(xa),
+                             ctypes.byref(xc))
+        return dict(lnf=lnf.value, lnf_last=lnf_last.value, regime=regime.value, finished=fin.value,
+                    iterations=it.value, visited=vis, x_att=xa.value, x_acc=xc.value)
+
+    def set_lng(self, w, lng):
+        a = np.ascontiguousarray(lng, dtype=np.float64)
+        assert a.size == self.W
+        lib().orc_set_lng(self.h_, w, _ptr(a))
+
+    def join(self):
+        out = np.zeros(self.B)
+        cuts = np.zeros(max(self.h - 1, 1), dtype=np.int32)
+        st = lib().orc_join(self.h_, _ptr(out), _ptr(cuts))
+        return st, out, cuts[: self.h - 1]

@@ -1,0 +1,829 @@
+/*
+ * rewl_oracle.c -- plain, sequential CPU reference of Replica-Exchange
+ * Wang-Landau (REWL) sampling, written for checking the GPU library.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header or constant with the HIP
+ * library: every routine below is written out from the paper and from the
+ * published definitions it names.
+ *
+ * Paper: T. Vogel, Y. W. Li, T. Wuest, D. P. Landau, "Exploring new
+ * frontiers in statistical physics with a new, parallel Wang-Landau
+ * framework", J. Phys.: Conf. Ser. (2014).  Citations below give the section,
+ * equation or figure of that paper.
+ *
+ * Arithmetic is IEEE binary64 unless a routine says otherwise.  Build with
+ * -ffp-contract=off (no fused multiply-add) and without -ffast-math: the
+ * acceptance decisions must follow the exact operation order written here.
+ *
+ * Parity status: every routine has a pin in tests/ (rocRAND for Philox,
+ * mpmath for exp_poly, brute-force enumeration for the converged density of
+ * states, closed forms for the exchange rule and the thermodynamics).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Status codes returned by the oracle entry points.                         */
+enum { ORC_OK = 0, ORC_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENOMEM = -2,
+       ORC_ESTATE = -4, ORC_EBUDGET = -5 };
+
+/* Philox counter domains: the fourth counter word carries domain << 24 | instance. */
+enum { DOM_MOVE = 0, DOM_WALKIN = 2, DOM_EXCH = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and
+ * Shaw (SC'11): ten rounds of two 32x32->64 multiplications with a Weyl key
+ * schedule.  The paper names no generator; this one is keyed by
+ * (seed, walker, step) so every draw is reproducible independently of the
+ * order in which walkers are simulated.                                      */
+static void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {               /* key schedule between rounds */
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* exp(x) for x < 0 by Cody-Waite range reduction and the Taylor series of
+ * degree 13 evaluated by Horner's rule, every step rounded separately.
+ * Needed for the Wang-Landau acceptance min[1, g(E_old)/g(E_new)] (Sec. 2)
+ * evaluated as exp(ln g(E_old) - ln g(E_new)).
+ *   k = rint(x / ln 2),  r = (x - k*C1) - k*C2,  exp(x) = 2^k * exp(r).
+ * C1 is ln 2 rounded to 40 significant bits (so k*C1 is exact for |k| < 2^13)
+ * and C2 = ln 2 - C1 rounded to double.  Coefficients are 1/n! rounded to
+ * double; n! is exact in binary64 for n <= 18 so 1.0/n! is correctly rounded. */
+static const double ORC_INV_LN2 = 0x1.71547652b82fep+0;   /* RN(1/ln 2)          */
+static const double ORC_LN2_C1  = 0x1.62e42fefa4000p-1;   /* ln 2, 40 bits       */
+static const double ORC_LN2_C2  = -0x1.8432a1b0e2634p-43; /* RN(ln 2 - C1)       */
+
+static double exp_poly(double x)
+{
+    if (x < -64.0) return 0.0;
+    double kd = rint(x * ORC_INV_LN2);
+    double r = (x - kd * ORC_LN2_C1) - kd * ORC_LN2_C2;
+    double coef[14];
+    double fact = 1.0;
+    coef[0] = 1.0;
+    for (int n = 1; n <= 13; ++n) { fact = fact * (double)n; coef[n] = 1.0 / fact; }
+    double p = coef[13];
+    for (int n = 12; n >= 0; --n) {
+        double t = r * p;
+        p = coef[n] + t;
+    }
+    return ldexp(p, (int)kd);
+}
+
+/* Single-precision twin used by the FP32 (hi, lo) ln g variant: the same
+ * reduction with C1 of 16 significant bits and a degree-7 Taylor series.     */
+static const float ORC_INV_LN2_F = 0x1.715476p+0f;
+static const float ORC_LN2_C1_F  = 0x1.62e4p-1f;
+static const float ORC_LN2_C2_F  = 0x1.7f7d1cp-20f;
+
+static float exp_poly32(float x)
+{
+    if (x < -64.0f) return 0.0f;
+    float kf = rintf(x * ORC_INV_LN2_F);
+    float r = (x - kf * ORC_LN2_C1_F) - kf * ORC_LN2_C2_F;
+    float coef[8];
+    float fact = 1.0f;
+    coef[0] = 1.0f;
+    for (int n = 1; n <= 7; ++n) { fact = fact * (float)n; coef[n] = 1.0f / fact; }
+    float p = coef[7];
+    for (int n = 6; n >= 0; --n) {
+        float t = r * p;
+        p = coef[n] + t;
+    }
+    return ldexpf(p, (int)kf);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Energy-range splitting (Sec. 2, Fig. 1): h windows of equal size W with a
+ * constant overlap o over the B = 2N+1 integer energies of the Potts model.
+ * W = ceil(B / (1 + (h-1)(1-o))); window k starts at
+ * E_lo + round(k (B - W) / (h - 1)) so the last window ends at E = 0.        */
+static int window_layout(int B, int h, double o, int e_lo, int *W_out, int *start)
+{
+    if (h < 1 || !(o >= 0.0 && o < 1.0) || B < 1) return ORC_EINVAL;
+    int W;
+    if (h == 1) {
+        W = B;
+    } else {
+        double denom = 1.0 + (double)(h - 1) * (1.0 - o);
+        W = (int)ceil((double)B / denom);
+        if (W > B) W = B;
+    }
+    for (int k = 0; k < h; ++k) {
+        if (h == 1) { start[k] = e_lo; continue; }
+        /* floor(k(B-W)/(h-1) + 1/2) in integers */
+        int64_t num = 2 * (int64_t)k * (int64_t)(B - W) + (int64_t)(h - 1);
+        int64_t den = 2 * (int64_t)(h - 1);
+        start[k] = e_lo + (int)(num / den);
+    }
+    *W_out = W;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2D q-state Potts model, Eq. (2): H = -sum over nearest-neighbour pairs of
+ * delta(s_i, s_j), on an L x L periodic lattice (each bond counted once via
+ * the right and lower neighbour), so E lies in [-2N, 0].                    */
+static int potts_energy(const int8_t *s, int L)
+{
+    int e = 0;
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            int i = y * L + x;
+            int right = y * L + (x + 1) % L;
+            int down = ((y + 1) % L) * L + x;
+            if (s[i] == s[right]) e -= 1;
+            if (s[i] == s[down]) e -= 1;
+        }
+    return e;
+}
+
+/* Energy change of setting site i to value nv (single spin flip, Sec. 3.1). */
+static int potts_delta_e(const int8_t *s, int L, int i, int nv)
+{
+    int x = i % L, y = i / L;
+    int nb[4];
+    nb[0] = y * L + (x + 1) % L;
+    nb[1] = y * L + (x + L - 1) % L;
+    nb[2] = ((y + 1) % L) * L + x;
+    nb[3] = ((y + L - 1) % L) * L + x;
+    int de = 0;
+    for (int t = 0; t < 4; ++t) {
+        int sn = s[nb[t]];
+        de += (s[i] == sn) ? 1 : 0;
+        de -= (nv == sn) ? 1 : 0;
+    }
+    return de;
+}
+
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int L, q, N;
+    int h, m, nw;          /* windows, walkers per window, walkers            */
+    int W, B, e_lo;        /* bins per window, global bins, lowest energy     */
+    int *start;            /* [h] lowest energy of window k                   */
+    uint32_t key[2];
+    uint32_t instance;
+    uint32_t flat_num, flat_den;
+    double lnf_init, lnf_final;
+    int schedule;          /* 0: halve ln f; 1: halve, then the 1/t rule     */
+    int64_t S;             /* attempts per walker between sync points        */
+    int exchange;          /* exchange round at every sync point             */
+    int precision;         /* 0: binary64 ln g; 1: binary32 (hi, lo) pair    */
+    int fixed_lnf;         /* 1: sync points never change ln f or average    */
+    int threads;
+    /* walker state, walker w = k*m + j */
+    int8_t *spin;          /* [nw][N] */
+    int32_t *E;            /* [nw]    */
+    double *lng;           /* [nw][W] (precision 0) */
+    float *lng_hi, *lng_lo;/* [nw][W] (precision 1) */
+    uint32_t *H;           /* [nw][W] */
+    uint8_t *vis;          /* [nw][W] bins this walker reached since creation */
+    uint32_t *replica;     /* [nw] */
+    int64_t *walkin_att;   /* [nw] */
+    /* window state */
+    double *lnf;           /* [h] current ln f (0 once finished)             */
+    double *lnf_last;      /* [h] ln f value at which the window finished     */
+    int32_t *regime;       /* [h] 0 halving, 1 1/t                           */
+    int32_t *finished;     /* [h] */
+    int64_t *iterations;   /* [h] ln f reductions so far                      */
+    uint8_t *visited;      /* [h][W] union of the walkers' visited bins       */
+    uint64_t *x_att, *x_acc;/* [h] exchange attempts/accepts of pair (k,k+1)  */
+    int64_t step;          /* main-phase attempts per walker                  */
+    int64_t round;         /* exchange rounds performed                       */
+    int walked_in;
+    int converged;
+} orc_t;
+
+static void orc_free(orc_t *o)
+{
+    if (!o) return;
+    free(o->start); free(o->spin); free(o->E); free(o->lng); free(o->lng_hi);
+    free(o->lng_lo); free(o->H); free(o->vis); free(o->replica); free(o->walkin_att);
+    free(o->lnf); free(o->lnf_last); free(o->regime); free(o->finished);
+    free(o->iterations); free(o->visited); free(o->x_att); free(o->x_acc);
+    free(o);
+}
+
+void orc_destroy(orc_t *o) { orc_free(o); }
+
+/* Exposed for the tests. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox4x32_10(ctr, key, out); }
+double orc_exp_poly(double x) { return exp_poly(x); }
+float orc_exp_poly32(float x) { return exp_poly32(x); }
+int orc_window_layout(int B, int h, double o, int e_lo, int *W, int *start)
+{
+    return window_layout(B, h, o, e_lo, W, start);
+}
+int orc_potts_energy(const int8_t *s, int L) { return potts_energy(s, L); }
+void orc_constants(double *c) { c[0] = ORC_INV_LN2; c[1] = ORC_LN2_C1; c[2] = ORC_LN2_C2; }
+void orc_constants32(float *c) { c[0] = ORC_INV_LN2_F; c[1] = ORC_LN2_C1_F; c[2] = ORC_LN2_C2_F; }
+
+/* Create a REWL run: h windows with overlap o and m walkers each (Sec. 2).
+ * init_spins holds one starting lattice per walker ([h*m][L*L], values in
+ * [0, q)).  Returns NULL on invalid arguments.                              */
+orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uint32_t instance,
+                  uint32_t flat_num, uint32_t flat_den, double lnf_init, double lnf_final,
+                  int schedule, int64_t sync_attempts, int exchange, int precision, int fixed_lnf,
+                  const int8_t *init_spins)
+{
+    if (L < 3 || L > 724 || q < 2 || q > 127 || h < 1 || m < 1) return NULL;
+    if (!(overlap >= 0.0 && overlap < 1.0)) return NULL;
+    if (flat_den == 0 || flat_den > 1000 || flat_num > flat_den) return NULL;
+    if (sync_attempts < 1 || precision < 0 || precision > 1 || schedule < 0 || schedule > 1) return NULL;
+    if (!init_spins) return NULL;
+    orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
+    if (!o) return NULL;
+    o->L = L; o->q = q; o->N = L * L; o->h = h; o->m = m; o->nw = h * m;
+    o->B = 2 * o->N + 1; o->e_lo = -2 * o->N;
+    o->start = (int *)calloc((size_t)h, sizeof(int));
+    if (!o->start || window_layout(o->B, h, overlap, o->e_lo, &o->W, o->start) != ORC_OK || o->W < 8) {
+        orc_free(o);
+        return NULL;
+    }
+    o->key[0] = (uint32_t)seed; o->key[1] = (uint32_t)(seed >> 32);
+    o->instance = instance & 0xFFFFFFu;
+    o->flat_num = flat_num; o->flat_den = flat_den;
+    o->lnf_init = lnf_init; o->lnf_final = lnf_final;
+    o->schedule = schedule; o->S = sync_attempts; o->exchange = exchange;
+    o->precision = precision; o->fixed_lnf = fixed_lnf; o->threads = 1;
+    size_t nw = (size_t)o->nw, N = (size_t)o->N, W = (size_t)o->W;
+    o->spin = (int8_t *)malloc(nw * N);
+    o->E = (int32_t *)calloc(nw, sizeof(int32_t));
+    if (precision == 0) o->lng = (double *)calloc(nw * W, sizeof(double));
+    else { o->lng_hi = (float *)calloc(nw * W, sizeof(float)); o->lng_lo = (float *)calloc(nw * W, sizeof(float)); }
+    o->H = (uint32_t *)calloc(nw * W, sizeof(uint32_t));
+    o->vis = (uint8_t *)calloc(nw * W, 1);
+    o->replica = (uint32_t *)calloc(nw, sizeof(uint32_t));
+    o->walkin_att = (int64_t *)calloc(nw, sizeof(int64_t));
+    o->lnf = (double *)calloc((size_t)h, sizeof(double));
+    o->lnf_last = (double *)calloc((size_t)h, sizeof(double));
+    o->regime = (int32_t *)calloc((size_t)h, sizeof(int32_t));
+    o->finished = (int32_t *)calloc((size_t)h, sizeof(int32_t));
+    o->iterations = (int64_t *)calloc((size_t)h, sizeof(int64_t));
+    o->visited = (uint8_t *)calloc((size_t)h * W, 1);
+    o->x_att = (uint64_t *)calloc((size_t)h, sizeof(uint64_t));
+    o->x_acc = (uint64_t *)calloc((size_t)h, sizeof(uint64_t));
+    if (!o->spin || !o->E || !(o->lng || (o->lng_hi && o->lng_lo)) || !o->H || !o->vis ||
+        !o->replica || !o->walkin_att || !o->lnf || !o->lnf_last || !o->regime ||
+        !o->finished || !o->iterations || !o->visited || !o->x_att || !o->x_acc) {
+        orc_free(o);
+        return NULL;
+    }
+    for (size_t i = 0; i < nw * N; ++i) {
+        if (init_spins[i] < 0 || init_spins[i] >= q) { orc_free(o); return NULL; }
+        o->spin[i] = init_spins[i];
+    }
+    for (int w = 0; w < o->nw; ++w) {
+        o->E[w] = potts_energy(o->spin + (size_t)w * N, L);
+        o->replica[w] = (uint32_t)w;
+    }
+    for (int k = 0; k < h; ++k) o->lnf[k] = lnf_init;
+    return o;
+}
+
+void orc_set_threads(orc_t *o, int n) { o->threads = n < 1 ? 1 : n; }
+
+/* ------------------------------------------------------------------------ */
+/* ln g of walker w at bin b, as a binary64 value (the (hi, lo) pair is summed
+ * in binary64 for the exchange, averaging and joining steps).               */
+static double lng_get(const orc_t *o, int w, int b)
+{
+    size_t i = (size_t)w * o->W + b;
+    if (o->precision == 0) return o->lng[i];
+    return (double)o->lng_hi[i] + (double)o->lng_lo[i];
+}
+
+/* The accept test of one Wang-Landau move (Sec. 2): accept with probability
+ * min[1, g(E_old)/g(E_new)], decided as  d >= 0  or  u < exp(d)  with
+ * d = ln g(E_old) - ln g(E_new) and u = r/2^32 from one 32-bit random word. */
+static int accept64(double d, uint32_t r)
+{
+    if (d >= 0.0) return 1;
+    double u = (double)r * 0x1p-32;
+    return u < exp_poly(d);
+}
+
+/* The same test on the binary32 (hi, lo) representation: d is formed in
+ * binary32 as (hi_old - hi_new) + (lo_old - lo_new) and compared with a
+ * 24-bit uniform u = (r >> 8) / 2^24, exact in binary32.                    */
+static int accept32(float d, uint32_t r)
+{
+    if (d >= 0.0f) return 1;
+    float u = (float)(r >> 8) * 0x1p-24f;
+    return u < exp_poly32(d);
+}
+
+/* Knuth's TwoSum: ln g(E) += ln f on the (hi, lo) pair; the rounding error
+ * of the high part is carried into the low part.                            */
+static void twosum_add(float *hi, float *lo, float x)
+{
+    float s = *hi + x;
+    float bb = s - *hi;
+    float err = (*hi - (s - bb)) + (x - bb);
+    *hi = s;
+    *lo = *lo + err;
+}
+
+/* Exposed for the tests: n additions of x to the pair (hi, lo).            */
+void orc_twosum_accumulate(float *hi, float *lo, float x, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) twosum_add(hi, lo, x);
+}
+
+/* One Wang-Landau attempt of walker w in window k (Sec. 2, Sec. 3.1):
+ * propose a single spin flip, accept with min[1, g(E_old)/g(E_new)] (moves
+ * leaving the window are rejected), then g(E) -> f g(E) and H(E) += 1 at the
+ * energy after the decision.  ctr selects the Philox draw.                  */
+static void potts_attempt(orc_t *o, int w, int k, double lnf, uint32_t domain, uint64_t cnt)
+{
+    int N = o->N, L = o->L, q = o->q, W = o->W;
+    int8_t *s = o->spin + (size_t)w * N;
+    uint32_t ctr[4] = { (uint32_t)cnt, (uint32_t)(cnt >> 32), (uint32_t)w, (domain << 24) | o->instance };
+    uint32_t r[4];
+    philox4x32_10(ctr, o->key, r);
+    int i = (int)(((uint64_t)r[0] * (uint64_t)N) >> 32);
+    int off = (int)(((uint64_t)r[1] * (uint64_t)(q - 1)) >> 32);
+    int nv = s[i] + 1 + off;
+    if (nv >= q) nv -= q;
+    int e_old = o->E[w];
+    int e_new = e_old + potts_delta_e(s, L, i, nv);
+    int lo = o->start[k], hi = o->start[k] + W - 1;
+    int acc = 0;
+    if (e_new >= lo && e_new <= hi) {
+        int bo = e_old - lo, bn = e_new - lo;
+        if (o->precision == 0) {
+            double d = o->lng[(size_t)w * W + bo] - o->lng[(size_t)w * W + bn];
+            acc = accept64(d, r[2]);
+        } else {
+            size_t io = (size_t)w * W + bo, in = (size_t)w * W + bn;
+            float d = (o->lng_hi[io] - o->lng_hi[in]) + (o->lng_lo[io] - o->lng_lo[in]);
+            acc = accept32(d, r[2]);
+        }
+    }
+    if (acc) {
+        s[i] = (int8_t)nv;
+        o->E[w] = e_new;
+    }
+    int b = o->E[w] - lo;
+    size_t ib = (size_t)w * W + b;
+    if (o->precision == 0) o->lng[ib] += lnf;
+    else twosum_add(&o->lng_hi[ib], &o->lng_lo[ib], (float)lnf);
+    o->H[ib] += 1u;
+    if (!o->finished[k]) o->vis[ib] = 1;
+}
+
+/* Placement before the run: each walker must carry a configuration whose
+ * energy lies inside its own window (Sec. 3.2, discussion of Fig. 7).  The
+ * paper does not say how; here a global Wang-Landau walk with its own ln g
+ * over all B energies and ln f = 1 moves the configuration until its energy
+ * first lies in the window.  Returns ORC_EBUDGET if a walker needs more than
+ * max_attempts attempts.                                                    */
+int orc_walkin(orc_t *o, int64_t max_attempts)
+{
+    if (o->walked_in) return ORC_OK;
+    int status = ORC_OK;
+    int nt = o->threads;
+    (void)nt;
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int w = 0; w < o->nw; ++w) {
+        int k = w / o->m;
+        int lo = o->start[k], hi = o->start[k] + o->W - 1;
+        int N = o->N, L = o->L, q = o->q;
+        int8_t *s = o->spin + (size_t)w * N;
+        double *g = (double *)calloc((size_t)o->B, sizeof(double));
+        int64_t t = 0;
+        while (!(o->E[w] >= lo && o->E[w] <= hi)) {
+            if (t >= max_attempts || !g) {
+#pragma omp atomic write
+                status = ORC_EBUDGET;
+                break;
+            }
+            uint32_t ctr[4] = { (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)w,
+                                ((uint32_t)DOM_WALKIN << 24) | o->instance };
+            uint32_t r[4];
+            philox4x32_10(ctr, o->key, r);
+            int i = (int)(((uint64_t)r[0] * (uint64_t)N) >> 32);
+            int off = (int)(((uint64_t)r[1] * (uint64_t)(q - 1)) >> 32);
+            int nv = s[i] + 1 + off;
+            if (nv >= q) nv -= q;
+            int e_new = o->E[w] + potts_delta_e(s, L, i, nv);
+            double d = g[o->E[w] - o->e_lo] - g[e_new - o->e_lo];
+            if (accept64(d, r[2])) {
+                s[i] = (int8_t)nv;
+                o->E[w] = e_new;
+            }
+            g[o->E[w] - o->e_lo] += 1.0;
+            ++t;
+        }
+        o->walkin_att[w] = t;
+        free(g);
+    }
+    if (status == ORC_OK) o->walked_in = 1;
+    return status;
+}
+
+/* Average the m estimators of window k and hand the mean back to every
+ * walker (Sec. 2: "averaged and redistributed").  The mean is taken of ln g,
+ * summed in walker order and divided by m.                                   */
+static void window_average(orc_t *o, int k)
+{
+    int W = o->W, m = o->m;
+    for (int b = 0; b < W; ++b) {
+        double sum = lng_get(o, k * m, b);
+        for (int j = 1; j < m; ++j) sum = sum + lng_get(o, k * m + j, b);
+        double mean = sum / (double)m;
+        for (int j = 0; j < m; ++j) {
+            size_t i = (size_t)(k * m + j) * W + b;
+            if (o->precision == 0) o->lng[i] = mean;
+            else {
+                float hi = (float)mean;
+                o->lng_hi[i] = hi;
+                o->lng_lo[i] = (float)(mean - (double)hi);
+            }
+        }
+    }
+}
+
+/* Sync point of window k after every S attempts per walker (Sec. 2):
+ * each walker must be flat on its own; when all m are flat their ln g are
+ * averaged, H is reset and ln f is halved (f -> sqrt f); optionally the
+ * 1/t rule of Belardinelli and Pereyra takes over once ln f <= 1/t with
+ * t = attempts per walker / W.  The window is finished once ln f < ln f_final. */
+static void window_sync(orc_t *o, int k)
+{
+    int W = o->W, m = o->m;
+    if (o->finished[k]) return;
+    for (int j = 0; j < m; ++j)
+        for (int b = 0; b < W; ++b)
+            if (o->vis[(size_t)(k * m + j) * W + b]) o->visited[(size_t)k * W + b] = 1;
+    if (o->precision == 1) {
+        /* renormalise the (hi, lo) pairs with Dekker's Fast2Sum */
+        for (int j = 0; j < m; ++j)
+            for (int b = 0; b < W; ++b) {
+                size_t i = (size_t)(k * m + j) * W + b;
+                float s = o->lng_hi[i] + o->lng_lo[i];
+                float z = s - o->lng_hi[i];
+                o->lng_lo[i] = o->lng_lo[i] - z;
+                o->lng_hi[i] = s;
+            }
+    }
+    if (o->fixed_lnf) return;
+    double inv_t = (double)W / (double)o->step;
+    if (o->regime[k] == 0) {
+        int all_flat = 1;
+        for (int j = 0; j < m; ++j) {
+            uint64_t n_act = 0, sum = 0, mn = UINT64_MAX;
+            for (int b = 0; b < W; ++b) {
+                if (!o->visited[(size_t)k * W + b]) continue;
+                uint64_t hv = o->H[(size_t)(k * m + j) * W + b];
+                n_act += 1;
+                sum += hv;
+                if (hv < mn) mn = hv;
+            }
+            int flat = n_act > 0 && (uint64_t)o->flat_den * mn * n_act >= (uint64_t)o->flat_num * sum;
+            if (!flat) all_flat = 0;
+        }
+        if (!all_flat) return;
+        window_average(o, k);
+        memset(o->H + (size_t)k * m * W, 0, (size_t)m * W * sizeof(uint32_t));
+        o->lnf[k] = o->lnf[k] * 0.5;
+        o->iterations[k] += 1;
+        if (o->schedule == 1 && o->lnf[k] <= inv_t) {
+            o->regime[k] = 1;
+            o->lnf[k] = inv_t;
+        }
+    } else {
+        window_average(o, k);
+        memset(o->H + (size_t)k * m * W, 0, (size_t)m * W * sizeof(uint32_t));
+        o->lnf[k] = inv_t;
+        o->iterations[k] += 1;
+    }
+    if (o->lnf[k] < o->lnf_final) {
+        o->finished[k] = 1;
+        o->lnf_last[k] = o->lnf[k];
+        o->lnf[k] = 0.0;
+    }
+}
+
+/* One round of replica exchange (Sec. 2, Eq. (1)).  Round r pairs windows
+ * (k, k+1) with k = r mod 2, r mod 2 + 2, ...  Within a pair, walker j of
+ * window k is matched with walker pi(j) of window k+1 for a uniformly random
+ * permutation pi (Fisher-Yates).  Configurations X (walker a) and Y (walker b)
+ * swap with probability min[1, g_a(E_X)/g_a(E_Y) * g_b(E_Y)/g_b(E_X)]; the
+ * exchange is rejected if either energy lies outside the other window.
+ * ln g and H stay with their walkers.                                        */
+typedef struct { uint32_t ctr[4]; uint32_t buf[4]; int pos; const uint32_t *key; } word_stream;
+
+static uint32_t next_word(word_stream *ws)
+{
+    if (ws->pos == 4) {
+        philox4x32_10(ws->ctr, ws->key, ws->buf);
+        ws->ctr[2] += 1u;      /* block index n */
+        ws->pos = 0;
+    }
+    return ws->buf[ws->pos++];
+}
+
+int orc_exchange(orc_t *o)
+{
+    int h = o->h, m = o->m, W = o->W, N = o->N;
+    uint32_t r = (uint32_t)o->round;
+    int *perm = (int *)malloc((size_t)m * sizeof(int));
+    int8_t *tmp = (int8_t *)malloc((size_t)N);
+    if (!perm || !tmp) { free(perm); free(tmp); return ORC_ENOMEM; }
+    for (int k = (int)(r & 1u); k + 1 < h; k += 2) {
+        word_stream ws;
+        ws.ctr[0] = r; ws.ctr[1] = (uint32_t)k; ws.ctr[2] = 0u;
+        ws.ctr[3] = ((uint32_t)DOM_EXCH << 24) | o->instance;
+        ws.pos = 4; ws.key = o->key;
+        for (int j = 0; j < m; ++j) perm[j] = j;
+        for (int i = m - 1; i >= 1; --i) {
+            int j = (int)(((uint64_t)next_word(&ws) * (uint64_t)(i + 1)) >> 32);
+            int t = perm[i]; perm[i] = perm[j]; perm[j] = t;
+        }
+        int lo_a = o->start[k], hi_a = o->start[k] + W - 1;
+        int lo_b = o->start[k + 1], hi_b = o->start[k + 1] + W - 1;
+        for (int j = 0; j < m; ++j) {
+            int a = k * m + j, b = (k + 1) * m + perm[j];
+            uint32_t u = next_word(&ws);
+            int ex = o->E[a], ey = o->E[b];
+            int acc = 0;
+            o->x_att[k] += 1;
+            if (ey >= lo_a && ey <= hi_a && ex >= lo_b && ex <= hi_b) {
+                double d = ((lng_get(o, a, ex - lo_a) - lng_get(o, a, ey - lo_a))
+                            + lng_get(o, b, ey - lo_b)) - lng_get(o, b, ex - lo_b);
+                acc = accept64(d, u);
+            }
+            if (acc) {
+                o->x_acc[k] += 1;
+                memcpy(tmp, o->spin + (size_t)a * N, (size_t)N);
+                memcpy(o->spin + (size_t)a * N, o->spin + (size_t)b * N, (size_t)N);
+                memcpy(o->spin + (size_t)b * N, tmp, (size_t)N);
+                o->E[a] = ey; o->E[b] = ex;
+                uint32_t t = o->replica[a]; o->replica[a] = o->replica[b]; o->replica[b] = t;
+            }
+        }
+    }
+    o->round += 1;
+    free(perm); free(tmp);
+    return ORC_OK;
+}
+
+/* Run `attempts` more Wang-Landau attempts per walker.  Sync points (flatness,
+ * averaging, ln f update, then an exchange round) fall at every multiple of S
+ * attempts counted from the start of the main phase, so splitting a run into
+ * several calls gives the same result.  Stops at the first sync point at
+ * which every window is finished (Sec. 2: the simulation terminates when all
+ * h windows reached f_final).                                               */
+int orc_run(orc_t *o, int64_t attempts, int64_t walkin_budget)
+{
+    if (!o->walked_in) {
+        int st = orc_walkin(o, walkin_budget);
+        if (st != ORC_OK) return st;
+    }
+    if (o->converged) return ORC_CONVERGED;
+    int nt = o->threads;
+    (void)nt;
+    while (attempts > 0) {
+        int64_t seg = o->S - (o->step % o->S);
+        if (seg > attempts) seg = attempts;
+        int64_t s0 = o->step;
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+        for (int w = 0; w < o->nw; ++w) {
+            int k = w / o->m;
+            double lnf = o->lnf[k];
+            for (int64_t t = 0; t < seg; ++t)
+                potts_attempt(o, w, k, lnf, DOM_MOVE, (uint64_t)(s0 + t));
+        }
+        o->step += seg;
+        attempts -= seg;
+        if (o->step % o->S == 0) {
+            for (int k = 0; k < o->h; ++k) window_sync(o, k);
+            if (o->exchange) orc_exchange(o);
+            int all = 1;
+            for (int k = 0; k < o->h; ++k) all = all && o->finished[k];
+            if (all) { o->converged = 1; return ORC_CONVERGED; }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accessors for the tests.                                                  */
+void orc_info(const orc_t *o, int64_t *out)
+{
+    out[0] = o->N; out[1] = o->W; out[2] = o->B; out[3] = o->e_lo; out[4] = o->nw;
+    out[5] = o->step; out[6] = o->round; out[7] = o->converged; out[8] = o->walked_in;
+}
+
+void orc_starts(const orc_t *o, int32_t *out)
+{
+    for (int k = 0; k < o->h; ++k) out[k] = o->start[k];
+}
+
+void orc_get_walker(const orc_t *o, int w, int8_t *spins, int32_t *E, uint32_t *H, double *lng,
+                    float *lng_hi, float *lng_lo, uint32_t *replica, int64_t *walkin_attempts)
+{
+    size_t N = (size_t)o->N, W = (size_t)o->W;
+    if (spins) memcpy(spins, o->spin + (size_t)w * N, N);
+    if (E) *E = o->E[w];
+    if (H) memcpy(H, o->H + (size_t)w * W, W * sizeof(uint32_t));
+    if (lng) for (size_t b = 0; b < W; ++b) lng[b] = lng_get(o, w, (int)b);
+    if (lng_hi && o->precision == 1) memcpy(lng_hi, o->lng_hi + (size_t)w * W, W * sizeof(float));
+    if (lng_lo && o->precision == 1) memcpy(lng_lo, o->lng_lo + (size_t)w * W, W * sizeof(float));
+    if (replica) *replica = o->replica[w];
+    if (walkin_attempts) *walkin_attempts = o->walkin_att[w];
+}
+
+/* Window state; visited is the union of the walkers' visited bins so far.   */
+void orc_get_window(const orc_t *o, int k, double *lnf, double *lnf_last, int32_t *regime,
+                    int32_t *finished, int64_t *iterations, uint8_t *visited, uint64_t *xatt,
+                    uint64_t *xacc)
+{
+    int W = o->W, m = o->m;
+    if (lnf) *lnf = o->lnf[k];
+    if (lnf_last) *lnf_last = o->lnf_last[k];
+    if (regime) *regime = o->regime[k];
+    if (finished) *finished = o->finished[k];
+    if (iterations) *iterations = o->iterations[k];
+    if (visited) {
+        for (int b = 0; b < W; ++b) {
+            uint8_t v = o->visited[(size_t)k * W + b];
+            if (!o->finished[k])
+                for (int j = 0; j < m; ++j) v |= o->vis[(size_t)(k * m + j) * W + b];
+            visited[b] = v;
+        }
+    }
+    if (xatt) *xatt = o->x_att[k];
+    if (xacc) *xacc = o->x_acc[k];
+}
+
+/* Test hook: overwrite the ln g of walker w (precision 0 or 1).             */
+void orc_set_lng(orc_t *o, int w, const double *lng)
+{
+    size_t W = (size_t)o->W;
+    for (size_t b = 0; b < W; ++b) {
+        if (o->precision == 0) o->lng[(size_t)w * W + b] = lng[b];
+        else {
+            float hi = (float)lng[b];
+            o->lng_hi[(size_t)w * W + b] = hi;
+            o->lng_lo[(size_t)w * W + b] = (float)(lng[b] - (double)hi);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Joining the h pieces (Sec. 2, Fig. 2): for neighbouring windows k, k+1
+ * the joining energy E* is the energy of their overlap at which the
+ * microcanonical inverse temperatures beta(E) = d ln g / dE of the two pieces
+ * agree best; beta is the finite difference between the nearest visited bins
+ * above and below E inside the piece.  Ties go to the lowest E*, and E* must
+ * lie above the previous joining point.  Piece k+1 is shifted to equal piece
+ * k at E*; the joined curve takes piece k up to E* and piece k+1 above it.
+ * Finally ln g is normalised so that sum_E g(E) = q^N.
+ * pieces: [h][W] ln g, vis: [h][W] visited flags.  out: [B] (unvisited bins
+ * are -inf).  cuts: [h-1] joining energies.  Returns ORC_ESTATE if two
+ * neighbouring pieces share no visited energy.                              */
+static int beta_at(const double *g, const uint8_t *v, int W, int b, double *beta)
+{
+    if (!v[b]) return 0;
+    int bp = -1, bm = -1;
+    for (int t = b + 1; t < W; ++t) if (v[t]) { bp = t; break; }
+    for (int t = b - 1; t >= 0; --t) if (v[t]) { bm = t; break; }
+    if (bp < 0 || bm < 0) return 0;
+    *beta = (g[bp] - g[bm]) / (double)(bp - bm);
+    return 1;
+}
+
+int orc_join_pieces(int h, int W, const int32_t *start, int e_lo, int B, const double *pieces,
+                    const uint8_t *vis, double log_total, double *out, int32_t *cuts)
+{
+    double *shift = (double *)calloc((size_t)h, sizeof(double));
+    if (!shift) return ORC_ENOMEM;
+    int prev_cut = INT32_MIN;
+    for (int k = 0; k + 1 < h; ++k) {
+        const double *ga = pieces + (size_t)k * W, *gb = pieces + (size_t)(k + 1) * W;
+        const uint8_t *va = vis + (size_t)k * W, *vb = vis + (size_t)(k + 1) * W;
+        int lo = start[k + 1], hi = start[k] + W - 1;
+        if (prev_cut != INT32_MIN && prev_cut + 1 > lo) lo = prev_cut + 1;
+        int best = INT32_MIN;
+        double bestd = 0.0;
+        for (int e = lo; e <= hi; ++e) {
+            double ba, bb;
+            if (!beta_at(ga, va, W, e - start[k], &ba)) continue;
+            if (!beta_at(gb, vb, W, e - start[k + 1], &bb)) continue;
+            double d = fabs(ba - bb);
+            if (best == INT32_MIN || d < bestd) { best = e; bestd = d; }
+        }
+        if (best == INT32_MIN)
+            for (int e = lo; e <= hi; ++e)
+                if (va[e - start[k]] && vb[e - start[k + 1]]) { best = e; break; }
+        if (best == INT32_MIN) { free(shift); return ORC_ESTATE; }
+        cuts[k] = best;
+        shift[k + 1] = (ga[best - start[k]] + shift[k]) - gb[best - start[k + 1]];
+        prev_cut = best;
+    }
+    for (int b = 0; b < B; ++b) out[b] = -INFINITY;
+    for (int k = 0; k < h; ++k) {
+        int from = (k == 0) ? start[0] : cuts[k - 1] + 1;
+        int to = (k == h - 1) ? start[h - 1] + W - 1 : cuts[k];
+        for (int e = from; e <= to; ++e) {
+            int b = e - start[k];
+            if (b < 0 || b >= W || !vis[(size_t)k * W + b]) continue;
+            out[e - e_lo] = pieces[(size_t)k * W + b] + shift[k];
+        }
+    }
+    free(shift);
+    /* normalisation: ln g <- ln g - ln(sum_E g(E)) + ln(total) */
+    double mx = -INFINITY;
+    for (int b = 0; b < B; ++b) if (out[b] > mx) mx = out[b];
+    if (mx == -INFINITY) return ORC_ESTATE;
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) if (out[b] != -INFINITY) s += exp(out[b] - mx);
+    double lse = mx + log(s);
+    for (int b = 0; b < B; ++b) if (out[b] != -INFINITY) out[b] = (out[b] - lse) + log_total;
+    return ORC_OK;
+}
+
+/* Joined ln g of a run, from walker 0 of every window. */
+int orc_join(const orc_t *o, double *out, int32_t *cuts)
+{
+    int h = o->h, W = o->W;
+    double *pieces = (double *)malloc((size_t)h * W * sizeof(double));
+    uint8_t *vis = (uint8_t *)malloc((size_t)h * W);
+    int32_t *st = (int32_t *)malloc((size_t)h * sizeof(int32_t));
+    if (!pieces || !vis || !st) { free(pieces); free(vis); free(st); return ORC_ENOMEM; }
+    for (int k = 0; k < h; ++k) {
+        st[k] = o->start[k];
+        orc_get_window(o, k, NULL, NULL, NULL, NULL, NULL, vis + (size_t)k * W, NULL, NULL);
+        for (int b = 0; b < W; ++b) pieces[(size_t)k * W + b] = lng_get(o, k * o->m, b);
+    }
+    int st_code = orc_join_pieces(h, W, st, o->e_lo, o->B, pieces, vis,
+                                  (double)o->N * log((double)o->q), out, cuts);
+    free(pieces); free(vis); free(st);
+    return st_code;
+}
+
+/* Canonical averages from g(E) (Sec. 3.1, Fig. 3b): P(E,T) = g(E) e^{-E/T}/Z.
+ * ln Z = LSE_E(ln g(E) - E/T), U = <E>, C_v = (<E^2> - <E>^2)/T^2, with the
+ * variance summed as sum P (E - U)^2.  Bins with ln g = -inf are skipped.    */
+void orc_thermo(const double *lng, int B, int e_first, const double *T, int nT,
+                double *lnZ, double *U, double *C)
+{
+    for (int t = 0; t < nT; ++t) {
+        double mx = -INFINITY;
+        for (int b = 0; b < B; ++b) {
+            if (lng[b] == -INFINITY) continue;
+            double x = lng[b] - (double)(e_first + b) / T[t];
+            if (x > mx) mx = x;
+        }
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) {
+            if (lng[b] == -INFINITY) continue;
+            s += exp((lng[b] - (double)(e_first + b) / T[t]) - mx);
+        }
+        double lz = mx + log(s);
+        double u = 0.0;
+        for (int b = 0; b < B; ++b) {
+            if (lng[b] == -INFINITY) continue;
+            double p = exp((lng[b] - (double)(e_first + b) / T[t]) - lz);
+            u += p * (double)(e_first + b);
+        }
+        double var = 0.0;
+        for (int b = 0; b < B; ++b) {
+            if (lng[b] == -INFINITY) continue;
+            double p = exp((lng[b] - (double)(e_first + b) / T[t]) - lz);
+            double d = (double)(e_first + b) - u;
+            var += p * d * d;
+        }
+        lnZ[t] = lz;
+        U[t] = u;
+        C[t] = var / (T[t] * T[t]);
+    }
+}

@@ -1,0 +1,415 @@
+"""Pins of the CPU oracle against facts it does not compute itself.
+
+Each test ties one oracle routine to something independent: rocRAND's
+Philox, mpmath's exp, complete enumeration of tiny lattices, closed forms of
+the Potts model, the exchange rule of Eq. (1) under exact weights, and the
+numbers the paper prints.  A plausible slip anywhere in the oracle (a wrong
+sign in the acceptance, a swapped index in Eq. (1), a dropped bond in the
+energy, a wrong shift in the join) fails at least one of them.
+"""
+import json
+import math
+import os
+import subprocess
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def exact_lng(L, q):
+    g = bruteforce.potts_dos(L, q)
+    out = np.full(g.size, -np.inf)
+    out[g > 0] = np.log(g[g > 0].astype(np.float64))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 against rocRAND (black box through its public API).
+
+def test_philox_matches_rocrand(rocrand_ref):
+    rng = np.random.default_rng(12345)
+    cases = []
+    for _ in range(300):
+        seed = int(rng.integers(0, 2**63))
+        c = [int(x) for x in rng.integers(0, 2**32, size=4, dtype=np.uint64)]
+        c[1] &= (1 << 30) - 1          # keep 4 * (low 64 bits) inside the offset range
+        cases.append((seed, c))
+    # the counters the library actually uses: small steps, walker ids, domains
+    for seed in (0, 1, 2**32 + 7):
+        for c in ([0, 0, 0, 0], [1, 0, 3, 0], [9999, 0, 63, 2 << 24], [5, 0, 7, (3 << 24) | 17]):
+            cases.append((seed, c))
+    stdin = "".join(f"{s} {c[2] | (c[3] << 32)} {4 * (c[0] | (c[1] << 32))}\n" for s, c in cases)
+    res = subprocess.run([rocrand_ref], input=stdin, capture_output=True, text=True, check=True)
+    ref = [list(map(int, line.split())) for line in res.stdout.strip().splitlines()]
+    assert len(ref) == len(cases)
+    for (seed, c), want in zip(cases, ref):
+        got = oracle.philox(c, [seed & 0xFFFFFFFF, seed >> 32])
+        assert list(got) == want, (seed, c)
+
+
+# --------------------------------------------------------------------------
+# exp_poly against mpmath.
+
+def test_exp_poly_constants():
+    mp.mp.prec = 200
+    ln2 = mp.log(2)
+    inv, c1, c2 = oracle.constants()
+    assert inv == float(1 / ln2)
+    # C1 has at most 40 significant bits and C1 + C2 = ln 2 to double-double accuracy
+    m, e = math.frexp(c1)
+    assert (m * 2**40) == int(m * 2**40)
+    assert c2 == float(ln2 - mp.mpf(c1))
+    invf, c1f, c2f = oracle.constants32()
+    assert np.float32(invf) == np.float32(float(1 / ln2))
+    assert float(c2f) == float(np.float32(float(ln2 - mp.mpf(float(c1f)))))
+
+
+def ulp(x):
+    return math.ulp(x)
+
+
+def test_exp_poly_accuracy():
+    mp.mp.prec = 120
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([-rng.uniform(0, 64, 6000), -rng.uniform(0, 1e-3, 500),
+                         -np.array([1e-300, 1e-20, 0.5 * math.log(2), math.log(2), 1.0, 10.0, 63.999999,
+                                    64.0, 0.34657359027997264, 0.3465735902799727])])
+    worst = 0.0
+    for x in xs:
+        got = oracle.exp_poly(float(x))
+        want = mp.exp(mp.mpf(float(x)))
+        err = abs(mp.mpf(got) - want) / mp.mpf(ulp(float(want)))
+        worst = max(worst, float(err))
+    assert worst <= 2.0, worst
+    assert oracle.exp_poly(-64.0000001) == 0.0
+    assert oracle.exp_poly(-1000.0) == 0.0
+
+
+def test_exp_poly32_accuracy():
+    mp.mp.prec = 80
+    rng = np.random.default_rng(2)
+    xs = np.concatenate([-rng.uniform(0, 64, 4000), -rng.uniform(0, 1e-3, 300)]).astype(np.float32)
+    worst = 0.0
+    for x in xs:
+        got = oracle.exp_poly32(float(x))
+        want = mp.exp(mp.mpf(float(x)))
+        u = float(np.spacing(np.float32(float(want))))
+        worst = max(worst, float(abs(mp.mpf(got) - want) / mp.mpf(u)))
+    assert worst <= 2.0, worst
+
+
+def test_twosum_pair_keeps_small_increments():
+    # Plain binary32 loses every increment below half an ulp of the running
+    # value; the (hi, lo) pair must keep them.  1000 increments is more than a
+    # bin receives between two sync points (where the pair is renormalised).
+    hi, lo = oracle.twosum_accumulate(16384.0, 0.0, 1e-4, 1000)
+    exact = 16384.0 + 1000 * float(np.float32(1e-4))
+    assert abs((hi + lo) - exact) < 5e-6
+    hi, lo = oracle.twosum_accumulate(1.0, 0.0, 0.3, 1000)      # increments above an ulp
+    assert abs((hi + lo) - (1.0 + 1000 * float(np.float32(0.3)))) < 1e-9
+    plain = np.float32(16384.0)
+    for _ in range(1000):
+        plain = np.float32(plain + np.float32(1e-4))
+    assert plain == np.float32(16384.0)  # the failure the pair avoids
+
+
+# --------------------------------------------------------------------------
+# Window layout (Sec. 2, Fig. 1) against the paper's L=300 setup.
+
+def test_window_layout_paper_L300():
+    paper = json.load(open(os.path.join(GOLDEN, "paper_values.json")))["potts_L300"]
+    L, h, o = paper["L"], paper["windows"], paper["overlap"]
+    N = L * L
+    W, starts = oracle.window_layout(2 * N + 1, h, o, -2 * N)
+    assert starts[0] == -2 * N and starts[-1] + W - 1 == 0
+    strides = np.diff(starts)
+    # 717 equal windows at 75% overlap over 180,001 energies: W = 1001, stride 250
+    assert W == 1001 and np.all(strides == 250)
+    assert abs((W - 250) / W - o) < 1e-3
+    assert h * paper["walkers_per_window"] == 2151  # "approximately 2000 walkers"
+
+
+@pytest.mark.parametrize("L,h,o", [(8, 4, 0.75), (32, 16, 0.75), (80, 64, 0.75), (16, 8, 0.75),
+                                   (48, 8, 0.75), (5, 3, 0.5), (7, 1, 0.75), (10, 9, 0.9)])
+def test_window_layout_properties(L, h, o):
+    N = L * L
+    B = 2 * N + 1
+    W, starts = oracle.window_layout(B, h, o, -2 * N)
+    assert starts[0] == -2 * N and starts[-1] + W - 1 == 0
+    assert np.all(np.diff(starts) >= 0)
+    if h > 1:
+        # each overlap is within one bin of the requested fraction
+        ov = (starts[:-1] + W - starts[1:]) / W
+        assert np.all(np.abs(ov - o) <= 1.0 / W + (1 - o) / (h - 1)), ov
+        # W is the smallest width for which h windows at overlap o cover B
+        assert W - 1 < B / (1 + (h - 1) * (1 - o)) <= W
+
+
+def test_window_layout_cfg_values():
+    W, starts = oracle.window_layout(129, 4, 0.75, -128)
+    assert W == 74 and list(starts) == [-128, -110, -91, -73]
+    assert oracle.window_layout(2049, 16, 0.75, -2048)[0] == 432
+    assert oracle.window_layout(12801, 64, 0.75, -12800)[0] == 765
+
+
+# --------------------------------------------------------------------------
+# Potts energy (Eq. 2) and the brute-force density of states.
+
+def test_potts_energy_matches_enumeration():
+    for L, q in [(3, 3), (4, 2)]:
+        e = bruteforce.potts_energies(L, q)
+        rng = np.random.default_rng(L)
+        idx = rng.integers(0, q ** (L * L), 200)
+        for i in idx:
+            digits = [(int(i) // q**k) % q for k in range(L * L)]
+            assert oracle.potts_energy(np.array(digits, dtype=np.int8), L) == e[i]
+    for L in (3, 4, 8, 9):
+        assert oracle.potts_energy(np.zeros(L * L, np.int8), L) == -2 * L * L
+    cb = (np.add.outer(np.arange(8), np.arange(8)) % 2).astype(np.int8)
+    assert oracle.potts_energy(cb.reshape(-1), 8) == 0
+
+
+@pytest.mark.parametrize("L,q", [(3, 3), (4, 2), (3, 2), (3, 4)])
+def test_bruteforce_closed_forms(L, q):
+    N = L * L
+    g = bruteforce.potts_dos(L, q)
+    assert g.sum() == q ** N                       # every configuration counted once
+    assert g[0] == q                               # ground states: all spins equal
+    assert g[1] == g[2] == g[3] == 0               # a domain wall on a torus costs >= 4 bonds
+    assert g[4] == N * q * (q - 1)                 # single flipped spin
+    if q == 2:
+        assert np.all(g[1::2] == 0)                # Ising: broken bonds come in pairs per cycle
+        if L % 2 == 0:
+            assert np.array_equal(g, g[::-1])      # bipartite lattice: E <-> -2N - E
+
+
+def test_thermo_matches_direct_sums():
+    for L, q in [(4, 2), (3, 3)]:
+        lng = exact_lng(L, q)
+        T = np.array([0.3, 0.7, 1.0, 2.27, 5.0])
+        lnZ, U, C = oracle.thermo(lng, -2 * L * L, T)
+        ref = bruteforce.potts_partition(L, q, T)
+        np.testing.assert_allclose(lnZ, ref[:, 0], rtol=1e-12)
+        np.testing.assert_allclose(U, ref[:, 1], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(C, ref[:, 2], rtol=1e-9)
+    # infinite temperature: every bond is satisfied with probability 1/q
+    lng = exact_lng(3, 3)
+    _, U, _ = oracle.thermo(lng, -18, np.array([1e9]))
+    assert abs(U[0] - (-18 / 3)) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# The full REWL protocol against the exact density of states.
+
+def converged(L, q, h, m, precision=0, seed=3, threads=4):
+    spins = workloads.init_spins(L, q, h * m, seed)
+    o = oracle.Rewl(L, q, h, 0.75, m, spins, seed=seed, lnf_final=1e-6, schedule=1,
+                    sync_attempts=20000, precision=precision, threads=threads)
+    st = o.run(10**10)
+    assert st == oracle.CONVERGED
+    return o
+
+
+@pytest.mark.parametrize("L,q,h", [(4, 2, 2), (3, 3, 2)])
+def test_converged_dos_matches_enumeration(L, q, h):
+    o = converged(L, q, h, 4)
+    st, lng, cuts = o.join()
+    assert st == oracle.OK
+    ex = exact_lng(L, q)
+    reach = np.isfinite(ex)
+    assert np.array_equal(np.isfinite(lng), reach)   # visited bins = reachable energies
+    assert np.max(np.abs(lng[reach] - ex[reach])) <= 0.02
+    if q == 2:
+        assert np.max(np.abs(lng[reach] - lng[::-1][reach])) <= 0.02
+    for k in range(h):
+        w = o.window(k)
+        assert w["finished"] == 1 and w["regime"] == 1 and w["lnf_last"] < 1e-6
+    # every walker's energy still agrees with a full recount of its lattice
+    for w in range(o.nw):
+        d = o.walker(w)
+        assert d["E"] == oracle.potts_energy(d["spins"], L)
+        k = w // o.m
+        assert o.starts[k] <= d["E"] <= o.starts[k] + o.W - 1
+
+
+def test_converged_dos_fp32_pair():
+    o = converged(4, 2, 2, 4, precision=1)
+    st, lng, _ = o.join()
+    ex = exact_lng(4, 2)
+    reach = np.isfinite(ex)
+    assert st == oracle.OK and np.array_equal(np.isfinite(lng), reach)
+    assert np.max(np.abs(lng[reach] - ex[reach])) <= 0.02
+
+
+def test_fixed_exact_weights_give_flat_histogram():
+    # With ln g fixed at the exact values (ln f = 0) the walk samples every
+    # reachable energy equally often (the WL acceptance of Sec. 2).  A sign
+    # or index slip in the acceptance makes H far from flat.
+    L, q = 4, 2
+    ex = exact_lng(L, q)
+    spins = workloads.init_spins(L, q, 1, 5)
+    o = oracle.Rewl(L, q, 1, 0.75, 1, spins, seed=9, lnf_init=0.0, fixed_lnf=1, sync_attempts=10**6)
+    lng = np.where(np.isfinite(ex), ex, 0.0)
+    o.set_lng(0, lng)
+    o.run(3_000_000)
+    H = o.walker(0)["H"].astype(np.float64)
+    reach = np.isfinite(ex)
+    assert np.all(H[~reach] == 0)
+    rel = H[reach] / H[reach].mean()
+    assert np.max(np.abs(rel - 1.0)) < 0.05, rel
+
+
+def test_exchange_accepts_everything_under_exact_weights():
+    # Eq. (1): if every walker's ln g is the exact ln g up to a per-walker
+    # constant, the exchange ratio is 1 and every exchange whose energies lie
+    # in both windows is accepted; others are rejected.
+    L, q, h = 4, 2, 3
+    ex = exact_lng(L, q)
+    spins = workloads.init_spins(L, q, h, 11)
+    o = oracle.Rewl(L, q, h, 0.75, 1, spins, seed=4, lnf_init=0.0, fixed_lnf=1, exchange=0,
+                    sync_attempts=500)
+    rng = np.random.default_rng(0)
+    for w in range(h):
+        k = w
+        seg = ex[o.starts[k] - o.e_lo: o.starts[k] - o.e_lo + o.W]
+        o.set_lng(w, np.where(np.isfinite(seg), seg, 0.0) + rng.normal() * 50)
+    o.walkin()
+    eligible_total = 0
+    for rnd in range(60):
+        o.run(97)
+        E = [o.walker(w)["E"] for w in range(h)]
+        k = rnd % 2
+        if k + 1 < h:
+            inside = (o.starts[k] <= E[k + 1] <= o.starts[k] + o.W - 1 and
+                      o.starts[k + 1] <= E[k] <= o.starts[k + 1] + o.W - 1)
+            before = o.window(k)["x_acc"]
+            reps = (o.walker(k)["replica"], o.walker(k + 1)["replica"])
+            o.exchange()
+            after = o.window(k)["x_acc"]
+            assert after - before == int(inside)
+            eligible_total += int(inside)
+            if inside:
+                assert (o.walker(k)["replica"], o.walker(k + 1)["replica"]) == reps[::-1]
+                assert o.walker(k)["E"] == E[k + 1] and o.walker(k + 1)["E"] == E[k]
+        else:
+            o.exchange()
+    assert eligible_total > 5
+
+
+@pytest.mark.parametrize("bias,accepted", [(-100.0, 0), (100.0, 1), (-1e-12, 1)])
+def test_exchange_planted_weights(bias, accepted):
+    # Walker a carries X at E_X = -24 and walker b carries Y at E_Y = -20 (4x4
+    # Ising, two windows [-32,-6] and [-26,0], both energies in the overlap).
+    # With ln g_b = 0, Eq. (1) gives ln P = ln g_a(E_X) - ln g_a(E_Y) = bias:
+    # -100 must be rejected (exp(-100) underflows the 2^-32 grid), +100 accepted,
+    # and a ratio a hair below one accepted unless u = 1 - 2^-32.
+    L, q = 4, 2
+    x = np.zeros(16, np.int8); x[[0, 10]] = 1            # two isolated flips: E = -24
+    y = np.zeros(16, np.int8); y[[0, 2, 9]] = 1          # three isolated flips: E = -20
+    assert oracle.potts_energy(x, L) == -24 and oracle.potts_energy(y, L) == -20
+    o = oracle.Rewl(L, q, 2, 0.75, 1, np.stack([x, y]), seed=4, lnf_init=0.0, fixed_lnf=1, exchange=0)
+    assert list(o.starts) == [-32, -26] and o.W == 27
+    a = np.zeros(o.W)
+    a[-24 - o.starts[0]] = bias
+    o.set_lng(0, a)
+    assert o.walkin() == oracle.OK
+    o.exchange()
+    assert o.window(0)["x_att"] == 1 and o.window(0)["x_acc"] == accepted
+    assert o.walker(0)["E"] == (-20 if accepted else -24)
+    assert o.walker(1)["replica"] == (0 if accepted else 1)
+
+
+# --------------------------------------------------------------------------
+# Joining (Sec. 2, Fig. 2) and determinism.
+
+def test_join_recovers_exact_dos_from_shifted_pieces():
+    for L, q, h in [(4, 2, 3), (3, 3, 2), (4, 2, 4)]:
+        ex = exact_lng(L, q)
+        N = L * L
+        B = 2 * N + 1
+        W, starts = oracle.window_layout(B, h, 0.75, -2 * N)
+        rng = np.random.default_rng(h)
+        pieces = np.zeros((h, W))
+        vis = np.zeros((h, W), np.uint8)
+        for k in range(h):
+            seg = ex[starts[k] + 2 * N: starts[k] + 2 * N + W]
+            vis[k] = np.isfinite(seg)
+            pieces[k] = np.where(np.isfinite(seg), seg, 0.0) + rng.uniform(-100, 100)
+        st, out, cuts = oracle.join_pieces(pieces, vis, starts, -2 * N, B, N * math.log(q))
+        assert st == oracle.OK
+        fin = np.isfinite(ex)
+        assert np.array_equal(np.isfinite(out), fin)
+        np.testing.assert_allclose(out[fin], ex[fin], atol=1e-9)
+        for k in range(h - 1):
+            assert starts[k + 1] <= cuts[k] <= starts[k] + W - 1
+
+
+def test_join_picks_best_matching_slope():
+    # Two pieces that agree in slope only at one energy: the join must cut there.
+    W = 20
+    starts = np.array([0, 10], np.int32)
+    e = np.arange(30, dtype=np.float64)
+    a = 0.1 * e[:W] ** 2 / 2           # beta_a(E) = 0.1 E
+    b = 1.5 * e[10:30] + 7.0           # beta_b(E) = 1.5 -> equal at E = 15
+    vis = np.ones((2, W), np.uint8)
+    st, out, cuts = oracle.join_pieces(np.stack([a, b]), vis, starts, 0, 30, 0.0)
+    assert st == oracle.OK and cuts[0] == 15
+
+
+def test_split_runs_and_thread_count_are_bitwise_identical():
+    L, q, h, m = 4, 3, 3, 2
+    spins = workloads.init_spins(L, q, h * m, 21)
+    kw = dict(seed=77, sync_attempts=700, lnf_final=1e-3)
+    a = oracle.Rewl(L, q, h, 0.75, m, spins, threads=1, **kw)
+    b = oracle.Rewl(L, q, h, 0.75, m, spins, threads=4, **kw)
+    a.run(12345)
+    for n in (1000, 345, 7000, 4000):
+        b.run(n)
+    assert a.step == b.step and a.round == b.round
+    for w in range(h * m):
+        da, db = a.walker(w), b.walker(w)
+        for key in ("spins", "H", "lng"):
+            assert np.array_equal(da[key], db[key]), key
+        assert da["E"] == db["E"] and da["replica"] == db["replica"]
+    for k in range(h):
+        wa, wb = a.window(k), b.window(k)
+        assert wa["lnf"] == wb["lnf"] and wa["iterations"] == wb["iterations"]
+
+
+def test_walkin_places_every_walker_in_its_window():
+    L, q, h, m = 8, 10, 4, 2
+    spins = workloads.init_spins(L, q, h * m, 1)
+    o = oracle.Rewl(L, q, h, 0.75, m, spins, seed=1)
+    assert o.walkin() == oracle.OK
+    for w in range(h * m):
+        d = o.walker(w)
+        k = w // m
+        assert o.starts[k] <= d["E"] <= o.starts[k] + o.W - 1
+        assert d["E"] == oracle.potts_energy(d["spins"], L)
+
+
+def test_walkin_budget_error():
+    L, q = 8, 10
+    spins = np.zeros((4, 64), np.int8)                 # all at the ground state
+    o = oracle.Rewl(L, q, 4, 0.75, 1, spins, seed=1)
+    assert o.walkin(budget=3) == oracle.EBUDGET
+
+
+def test_invalid_parameters_are_rejected():
+    s = np.zeros((1, 4), np.int8)
+    with pytest.raises(ValueError):
+        oracle.Rewl(2, 2, 1, 0.5, 1, s)
+    s = np.zeros((1, 9), np.int8)
+    with pytest.raises(ValueError):
+        oracle.Rewl(3, 1, 1, 0.5, 1, s)
+    with pytest.raises(ValueError):
+        oracle.Rewl(3, 2, 1, 1.0, 1, s)
+    with pytest.raises(ValueError):
+        oracle.Rewl(3, 3, 1, 0.5, 1, np.full((1, 9), 3, np.int8))

@@ -1,0 +1,49 @@
+"""Seeded synthetic inputs shared by the GPU library's tests/benchmark and the
+CPU oracle.
+
+This module holds no arithmetic of the method: only the named problem
+configurations and the starting lattices (uniform random spins drawn with
+numpy's PCG64 from a seed).  Everything the method itself draws during a run
+comes from the Philox4x32-10 stream that each side implements on its own.
+"""
+import numpy as np
+
+# Named workloads.  sync_attempts = attempts per walker between sync points.
+CONFIGS = {
+    # 2D q=10 Potts, 8x8, h=4 at 75% overlap, m=1, flat 0.8, ln f 1 -> 1e-6 by
+    # halving, exchange every 1000 sweeps (64,000 attempts), binary64 ln g.
+    "potts_q10_L8": dict(model="potts", L=8, q=10, windows=4, overlap=0.75, walkers=1,
+                         flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
+                         sync_attempts=1000 * 64, exchange=1, precision=0, seed=1),
+    # 2D q=10 Potts, 32x32, h=16 at 75% overlap, m=4, flat 0.8, ln f 1 -> 1e-8
+    # (halving, then 1/t), exchange every 10^4 attempts per walker, binary64.
+    "potts_q10_L32": dict(model="potts", L=32, q=10, windows=16, overlap=0.75, walkers=4,
+                          flat=(4, 5), lnf_init=1.0, lnf_final=1e-8, schedule=1,
+                          sync_attempts=10_000, exchange=1, precision=0, seed=1),
+    # 2D q=10 Potts, 80x80, h=64 at 75% overlap, m=16, ln f 1 -> 1e-9 by halving;
+    # run in binary64 and in the binary32 (hi, lo) form.
+    "potts_q10_L80": dict(model="potts", L=80, q=10, windows=64, overlap=0.75, walkers=16,
+                          flat=(4, 5), lnf_init=1.0, lnf_final=1e-9, schedule=0,
+                          sync_attempts=10_000, exchange=1, precision=0, seed=1),
+}
+
+# Batched workload: 256 independent instances, L from {16,24,32,48} and q from
+# {2,4,8,10} drawn per instance, h=8 at 75% overlap, m=4, binary64, the
+# schedule of the L=8 workload (halving to 1e-6, flat 0.8, sync every 1000 sweeps).
+BATCHED = dict(instances=256, L_choices=(16, 24, 32, 48), q_choices=(2, 4, 8, 10), windows=8,
+               overlap=0.75, walkers=4, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
+               sweeps_per_sync=1000, exchange=1, precision=0, seed=1)
+
+
+def init_spins(L, q, n_walkers, seed):
+    """One uniformly random L x L lattice per walker, values in [0, q), int8."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, q, size=(n_walkers, L * L), dtype=np.int8)
+
+
+def batched_instances(cfg=BATCHED):
+    """(L, q) of every instance of the batched workload, drawn from its seed."""
+    rng = np.random.Generator(np.random.PCG64(cfg["seed"]))
+    Ls = rng.choice(np.array(cfg["L_choices"]), size=cfg["instances"])
+    qs = rng.choice(np.array(cfg["q_choices"]), size=cfg["instances"])
+    return [(int(a), int(b)) for a, b in zip(Ls, qs)]
