@@ -1,0 +1,184 @@
+/*
+ * rewl.h -- C ABI of the MI355X Replica-Exchange Wang-Landau library.
+ *
+ * Method: T. Vogel, Y. W. Li, T. Wuest, D. P. Landau, "Exploring new
+ * frontiers in statistical physics with a new, parallel Wang-Landau
+ * framework", J. Phys.: Conf. Ser. (2014), Sec. 2.  The global energy range
+ * is split into h overlapping windows (Fig. 1); m independent Wang-Landau
+ * walkers sample each window, each with its own ln g(E) and H(E); walkers in
+ * neighbouring windows exchange configurations with the probability of
+ * Eq. (1); when all m walkers of a window are flat their ln g are averaged
+ * and ln f is reduced; the run ends when every window reached ln f_final, and
+ * the pieces are joined where d ln g/dE agree best (Fig. 2).
+ *
+ * Model: the 2D q-state Potts model of Eq. (2) on an L x L periodic lattice,
+ * single-spin-flip moves (Sec. 3.1); energies are the integers [-2N, 0].
+ *
+ * Conventions
+ *  - Every function returns a rewl_status: 0 (REWL_OK) or 1
+ *    (REWL_CONVERGED) on success, a negative code on failure; the message of
+ *    the last failure in the calling thread is rewl_last_error().
+ *  - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *    pointers are GPU global memory.  The library never frees caller memory.
+ *  - All GPU work is enqueued on the caller's HIP stream given to
+ *    rewl_create; calls that return host data synchronise that stream.
+ *  - One handle must not be used from two threads at once; distinct handles
+ *    are independent.
+ *  - Walker w = k*m + j is walker j of window k.  Window k covers the
+ *    energies [start_k, start_k + W - 1]; bin b of a window is energy
+ *    start_k + b.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed
+ *    and counter (step_lo, step_hi, walker, domain << 24 | instance).
+ *  - Identical inputs give bitwise-identical results, and rewl_run(a)
+ *    followed by rewl_run(b) equals rewl_run(a + b).
+ */
+#ifndef REWL_H
+#define REWL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rewl rewl_t; /* opaque handle, owned by the library */
+
+enum rewl_model { REWL_POTTS2D = 0 };
+
+enum rewl_status {
+    REWL_OK = 0,
+    REWL_CONVERGED = 1, /* every window reached ln f_final                    */
+    REWL_EINVAL = -1,   /* argument out of range                               */
+    REWL_ENOMEM = -2,   /* workspace too small / host allocation failed        */
+    REWL_EDEVICE = -3,  /* a HIP call failed (message in rewl_last_error)      */
+    REWL_ESTATE = -4,   /* call not valid in the current state                 */
+    REWL_EBUDGET = -5   /* walk-in exceeded its attempt budget                 */
+};
+
+/* Run options.  rewl_default_opts fills the values in brackets. */
+typedef struct {
+    uint64_t seed;          /* [1] Philox key                                       */
+    uint32_t instance;      /* [0] low 24 bits enter the Philox counter             */
+    uint32_t flat_num;      /* [4] flatness: H is flat when                          */
+    uint32_t flat_den;      /* [5]   flat_den*min(H)*n >= flat_num*sum(H) (n = bins) */
+    double lnf_init;        /* [1.0] initial ln f                                   */
+    double lnf_final;       /* [1e-6] a window is finished once ln f < lnf_final    */
+    int32_t schedule;       /* [0] 0: ln f halves (f -> sqrt f) at each flat sync;   */
+                            /*     1: halving until ln f <= 1/t, then ln f = 1/t    */
+                            /*     with t = attempts per walker / W                 */
+    int32_t exchange;       /* [1] replica-exchange round at every sync point        */
+    int64_t sync_attempts;  /* [1000] attempts per walker between sync points        */
+    int32_t precision;      /* [0] 0: ln g in binary64; 1: binary32 (hi, lo) pair    */
+    int32_t fixed_lnf;      /* [0] 1: sync points never change ln f (fixed weights) */
+} rewl_opts;
+
+void rewl_default_opts(rewl_opts *o);
+
+/* Energy-range splitting of Sec. 2 / Fig. 1 for the L x L Potts model:
+ * h windows of equal width W at overlap fraction o over the 2N+1 energies;
+ * W = ceil((2N+1) / (1 + (h-1)(1-o))), start_k = -2N + round(k(2N+1-W)/(h-1)).
+ * starts: host int32[windows].  REWL_EINVAL for L < 3, windows < 1,
+ * o outside [0, 1) or W < 8.                                                 */
+int rewl_window_layout(int L, int windows, double overlap, int32_t *W, int32_t *starts);
+
+/* Device workspace needed by rewl_create for these parameters (bytes), or 0
+ * if the parameters are invalid.                                             */
+size_t rewl_workspace_bytes(int model, int L, int q, int windows, double overlap, int walkers,
+                            const rewl_opts *opts);
+
+/* Create a run: `windows` windows at `overlap`, `walkers` walkers per window.
+ * init_spins: host int8[windows*walkers][L*L], values in [0, q): the starting
+ *   lattice of every walker (copied; the caller keeps ownership).
+ * dev_workspace: device memory of at least rewl_workspace_bytes(...) bytes,
+ *   owned by the caller and required to outlive the handle.
+ * hip_stream: the hipStream_t all work is enqueued on (NULL = default stream).
+ * Limits: 3 <= L <= 724, 2 <= q <= 127, 1 <= windows, 1 <= walkers,
+ *   windows*walkers <= 65535, 0 <= overlap < 1, W >= 8, 1 <= flat_den <= 1000,
+ *   flat_num <= flat_den, sync_attempts >= 1.  The handle is written to *out. */
+int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overlap, int walkers,
+                const rewl_opts *opts, const int8_t *init_spins, void *dev_workspace,
+                size_t ws_bytes, void *hip_stream);
+
+void rewl_destroy(rewl_t *r);
+
+/* Walk-in: move every walker whose energy lies outside its window into it
+ * (each walker starts inside its own window, Sec. 3.2 on Fig. 7) by a global
+ * Wang-Landau walk with ln f = 1 over all energies.  REWL_EBUDGET if some
+ * walker needs more than max_attempts attempts (its state is left where the
+ * walk stopped).  Called implicitly with a budget of 2^40 by the first run. */
+int rewl_walkin(rewl_t *r, int64_t max_attempts);
+
+/* Main phase: attempts per walker (rewl_run: sweeps * L*L attempts).  Sync
+ * points (flatness, averaging and ln f update per window, then an exchange
+ * round) fall at every multiple of sync_attempts counted from the start of
+ * the main phase.  Returns REWL_CONVERGED, and stops at that sync point, once
+ * every window is finished; later calls return REWL_CONVERGED at once.       */
+int rewl_run(rewl_t *r, int64_t sweeps);
+int rewl_run_attempts(rewl_t *r, int64_t attempts);
+
+/* One replica-exchange round now (Eq. (1)); round r pairs windows (k, k+1)
+ * with k = r mod 2, r mod 2 + 2, ...                                          */
+int rewl_exchange(rewl_t *r);
+
+/* Progress counters: main-phase attempts per walker, exchange rounds done,
+ * and whether the run converged.  Any pointer may be NULL.                   */
+int rewl_get_progress(rewl_t *r, int64_t *step, int64_t *round, int32_t *converged);
+
+/* State of walker w into host buffers (any pointer may be NULL):
+ * spins int8[L*L], E, H uint32[W], lng double[W] (the (hi, lo) pair summed in
+ * binary64 when precision = 1), replica id, walk-in attempts.                */
+int rewl_get_walker(rewl_t *r, int walker, int8_t *spins, int32_t *E, uint32_t *H, double *lng,
+                    uint32_t *replica, int64_t *walkin_attempts);
+
+/* State of window k (any pointer may be NULL): current ln f (0 once
+ * finished), the ln f that finished it, regime (0 halving, 1 1/t), finished
+ * flag, number of ln f reductions, visited flags uint8[W] (union over the
+ * window's walkers), and the exchange attempts/accepts of pair (k, k+1).     */
+int rewl_get_window(rewl_t *r, int window, double *lnf, double *lnf_last, int32_t *regime,
+                    int32_t *finished, int64_t *iterations, uint8_t *visited, uint64_t *x_att,
+                    uint64_t *x_acc);
+
+/* Overwrite ln g of walker w from host double[W] (fixed-weight sampling,
+ * Sec. 3.2: "continued generating data with fixed weights 1/g(E)").         */
+int rewl_set_lng(rewl_t *r, int walker, const double *lng);
+
+/* ln g of window k (walker 0 of the window) into host double[W], or with
+ * window = -1 the joined and normalised ln g over all 2N+1 energies (see
+ * rewl_join).  Unvisited bins are -INFINITY.  *n_out = number of values,
+ * *e_first_out = energy of the first value.  REWL_EINVAL if cap is too small. */
+int rewl_get_lng(rewl_t *r, int window, double *host_out, int64_t cap, int64_t *n_out,
+                 int64_t *e_first_out);
+
+/* Join the h pieces on the GPU in binary64 (Sec. 2, Fig. 2): for each pair of
+ * neighbouring windows the joining energy E* is where the finite-difference
+ * slopes d ln g/dE of the two pieces agree best (ties: lowest E, and E* above
+ * the previous joining energy); piece k+1 is shifted to meet piece k at E*;
+ * the result is normalised to sum_E g(E) = q^N.  host_out: double[2N+1]
+ * (may be NULL), cuts: int32[windows-1] (may be NULL).  REWL_ESTATE if two
+ * neighbouring pieces share no visited energy.  The joined ln g stays on the
+ * device for rewl_thermo.                                                    */
+int rewl_join(rewl_t *r, double *host_out, int32_t *cuts);
+
+/* Canonical thermodynamics from the joined ln g (Sec. 3.1, Fig. 3b), binary64
+ * on the GPU: ln Z(T) = log-sum-exp_E (ln g(E) - E/T), U = <E>,
+ * C_v = (<E^2> - <E>^2)/T^2.  T, lnZ, U, C: host double[nT].  Requires a
+ * previous rewl_join (REWL_ESTATE otherwise).                                */
+int rewl_thermo(rewl_t *r, const double *T, int nT, double *lnZ, double *U, double *C);
+
+/* Kernel timing.  While enabled, HIP events on the run's stream bracket every
+ * launch of the attempt kernel and every sync point (flatness, averaging,
+ * exchange, termination test); rewl_get_timing returns the summed elapsed
+ * milliseconds and launch counts since timing was last enabled.            */
+int rewl_set_timing(rewl_t *r, int enable);
+int rewl_get_timing(rewl_t *r, double *sweep_ms, int64_t *sweep_launches, double *sync_ms,
+                    int64_t *sync_points);
+
+/* Message of the last failing call in this thread ("" if none). */
+const char *rewl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REWL_H */

@@ -1,0 +1,254 @@
+"""MI355X Replica-Exchange Wang-Landau (REWL) sampling.
+
+Python binding of librewl.so, the HIP (gfx950) implementation of the parallel
+Wang-Landau scheme of Vogel, Li, Wuest and Landau (J. Phys.: Conf. Ser.,
+2014, Sec. 2): h overlapping energy windows, m walkers per window, replica
+exchange between neighbouring windows (Eq. 1), window averaging at flat
+histograms, and joining of the pieces (Fig. 2) -- here for the 2D q-state
+Potts model of Eq. (2).
+
+This module only marshals arguments.  Every step of the method runs in the
+library's kernels; PyTorch provides the device workspace and the HIP stream.
+The library must be built (``python -m paper_1312_3004_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librewl.so")
+
+OK, CONVERGED, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET = 0, 1, -1, -2, -3, -4, -5
+POTTS2D = 0
+
+
+class RewlError(RuntimeError):
+    pass
+
+
+class Opts(ctypes.Structure):
+    """Mirror of rewl_opts in include/rewl.h."""
+    _fields_ = [("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
+                ("flat_num", ctypes.c_uint32), ("flat_den", ctypes.c_uint32),
+                ("lnf_init", ctypes.c_double), ("lnf_final", ctypes.c_double),
+                ("schedule", ctypes.c_int32), ("exchange", ctypes.c_int32),
+                ("sync_attempts", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("fixed_lnf", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librewl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1312_3004_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        L.rewl_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.rewl_default_opts.restype = None
+        L.rewl_window_layout.argtypes = [i32, i32, dbl, P, P]
+        L.rewl_workspace_bytes.argtypes = [i32, i32, i32, i32, dbl, i32, ctypes.POINTER(Opts)]
+        L.rewl_workspace_bytes.restype = ctypes.c_size_t
+        L.rewl_create.argtypes = [ctypes.POINTER(P), i32, i32, i32, i32, dbl, i32, ctypes.POINTER(Opts),
+                                  P, P, ctypes.c_size_t, P]
+        L.rewl_destroy.argtypes = [P]
+        L.rewl_destroy.restype = None
+        L.rewl_walkin.argtypes = [P, i64]
+        L.rewl_run.argtypes = [P, i64]
+        L.rewl_run_attempts.argtypes = [P, i64]
+        L.rewl_exchange.argtypes = [P]
+        L.rewl_get_progress.argtypes = [P, P, P, P]
+        L.rewl_get_walker.argtypes = [P, i32, P, P, P, P, P, P]
+        L.rewl_get_window.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+        L.rewl_set_lng.argtypes = [P, i32, P]
+        L.rewl_get_lng.argtypes = [P, i32, P, i64, P, P]
+        L.rewl_join.argtypes = [P, P, P]
+        L.rewl_thermo.argtypes = [P, P, i32, P, P, P]
+        L.rewl_set_timing.argtypes = [P, i32]
+        L.rewl_get_timing.argtypes = [P, P, P, P, P]
+        L.rewl_last_error.argtypes = []
+        L.rewl_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(status):
+    if status < 0:
+        raise RewlError(f"librewl error {status}: {lib().rewl_last_error().decode()}")
+    return status
+
+
+def default_opts():
+    o = Opts()
+    lib().rewl_default_opts(ctypes.byref(o))
+    return o
+
+
+def window_layout(L, windows, overlap):
+    """(W, starts) of the energy-range splitting (Sec. 2, Fig. 1)."""
+    W = ctypes.c_int32(0)
+    starts = np.zeros(windows, dtype=np.int32)
+    _check(lib().rewl_window_layout(L, windows, overlap, ctypes.byref(W), _ptr(starts)))
+    return W.value, starts
+
+
+def make_opts(seed=1, instance=0, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
+              sync_attempts=1000, exchange=1, precision=0, fixed_lnf=0):
+    o = default_opts()
+    o.seed, o.instance = seed, instance
+    o.flat_num, o.flat_den = flat
+    o.lnf_init, o.lnf_final = lnf_init, lnf_final
+    o.schedule, o.sync_attempts, o.exchange = schedule, sync_attempts, exchange
+    o.precision, o.fixed_lnf = precision, fixed_lnf
+    return o
+
+
+def workspace_bytes(L, q, windows, overlap, walkers, opts):
+    return lib().rewl_workspace_bytes(POTTS2D, L, q, windows, overlap, walkers, ctypes.byref(opts))
+
+
+class Rewl:
+    """One REWL run of the 2D q-state Potts model on the GPU.
+
+    ``init_spins``: int8 array [windows*walkers, L*L] of starting lattices.
+    Keyword options mirror rewl_opts.  ``device``: torch device of the
+    workspace (default cuda:0); ``stream``: torch.cuda.Stream to enqueue on
+    (default: the device's current stream).
+    """
+
+    def __init__(self, L, q, windows, overlap, walkers, init_spins, device=None, stream=None, **opts):
+        import torch
+
+        self.L, self.q, self.h, self.m = L, q, windows, walkers
+        self.N = L * L
+        self.nw = windows * walkers
+        self.opts = make_opts(**opts)
+        self.precision = self.opts.precision
+        self.W, self.starts = window_layout(L, windows, overlap)
+        self.B = 2 * self.N + 1
+        self.e_lo = -2 * self.N
+        spins = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(-1)
+        if spins.size != self.nw * self.N:
+            raise ValueError("init_spins must hold one L*L lattice per walker")
+        nbytes = workspace_bytes(L, q, windows, overlap, walkers, self.opts)
+        if nbytes == 0:
+            _check(lib().rewl_create(ctypes.byref(ctypes.c_void_p()), POTTS2D, L, q, windows, overlap,
+                                     walkers, ctypes.byref(self.opts), None, None, 0, None))
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().rewl_create(ctypes.byref(h), POTTS2D, L, q, windows, overlap, walkers,
+                                     ctypes.byref(self.opts), _ptr(spins),
+                                     ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rewl_destroy(h)
+            self._h = None
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def walkin(self, budget=1 << 40):
+        return _check(lib().rewl_walkin(self._h, int(budget)))
+
+    def run(self, attempts):
+        """Run `attempts` more attempts per walker; returns OK or CONVERGED."""
+        return _check(lib().rewl_run_attempts(self._h, int(attempts)))
+
+    def run_sweeps(self, sweeps):
+        return _check(lib().rewl_run(self._h, int(sweeps)))
+
+    def exchange(self):
+        return _check(lib().rewl_exchange(self._h))
+
+    def progress(self):
+        s, r, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(lib().rewl_get_progress(self._h, ctypes.byref(s), ctypes.byref(r), ctypes.byref(c)))
+        return s.value, r.value, bool(c.value)
+
+    @property
+    def step(self):
+        return self.progress()[0]
+
+    @property
+    def round(self):
+        return self.progress()[1]
+
+    def walker(self, w):
+        spins = np.zeros(self.N, dtype=np.int8)
+        E = ctypes.c_int32(0)
+        H = np.zeros(self.W, dtype=np.uint32)
+        lng = np.zeros(self.W)
+        rep = ctypes.c_uint32(0)
+        wa = ctypes.c_int64(0)
+        _check(lib().rewl_get_walker(self._h, w, _ptr(spins), ctypes.byref(E), _ptr(H), _ptr(lng),
+                                     ctypes.byref(rep), ctypes.byref(wa)))
+        return dict(spins=spins, E=E.value, H=H, lng=lng, replica=rep.value, walkin_attempts=wa.value)
+
+    def window(self, k):
+        lnf, lnf_last = ctypes.c_double(0), ctypes.c_double(0)
+        regime, fin = ctypes.c_int32(0), ctypes.c_int32(0)
+        it = ctypes.c_int64(0)
+        vis = np.zeros(self.W, dtype=np.uint8)
+        xa, xc = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(lib().rewl_get_window(self._h, k, ctypes.byref(lnf), ctypes.byref(lnf_last),
+                                     ctypes.byref(regime), ctypes.byref(fin), ctypes.byref(it), _ptr(vis),
+                                     ctypes.byref(xa), ctypes.byref(xc)))
+        return dict(lnf=lnf.value, lnf_last=lnf_last.value, regime=regime.value, finished=fin.value,
+                    iterations=it.value, visited=vis, x_att=xa.value, x_acc=xc.value)
+
+    def set_lng(self, w, lng):
+        a = np.ascontiguousarray(lng, dtype=np.float64)
+        if a.size != self.W:
+            raise ValueError("ln g must have W entries")
+        _check(lib().rewl_set_lng(self._h, w, _ptr(a)))
+
+    def get_lng(self, k):
+        """ln g of window k (walker 0), -inf where unvisited; k = -1: joined."""
+        n = self.B if k == -1 else self.W
+        out = np.zeros(n)
+        nn, ef = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().rewl_get_lng(self._h, k, _ptr(out), n, ctypes.byref(nn), ctypes.byref(ef)))
+        return out[: nn.value], ef.value
+
+    def join(self):
+        """(status, joined ln g over 2N+1 energies, joining energies)."""
+        out = np.zeros(self.B)
+        cuts = np.zeros(max(self.h - 1, 1), dtype=np.int32)
+        st = lib().rewl_join(self._h, _ptr(out), _ptr(cuts))
+        if st < 0 and st != ESTATE:
+            _check(st)
+        return st, out, cuts[: self.h - 1]
+
+    def set_timing(self, enable=True):
+        _check(lib().rewl_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self):
+        """(attempt-kernel ms, launches, sync-point ms, sync points) since set_timing."""
+        a, b = ctypes.c_double(0), ctypes.c_int64(0)
+        c, d = ctypes.c_double(0), ctypes.c_int64(0)
+        _check(lib().rewl_get_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                     ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def thermo(self, T):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        lnZ, U, C = np.zeros_like(T), np.zeros_like(T), np.zeros_like(T)
+        _check(lib().rewl_thermo(self._h, _ptr(T), len(T), _ptr(lnZ), _ptr(U), _ptr(C)))
+        return lnZ, U, C

@@ -1,0 +1,42 @@
+"""Compile librewl.so (HIP kernels + C-ABI host runtime) for gfx950, in-tree."""
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "librewl.so")
+SOURCES = [os.path.join(CSRC, "rewl_kernels.hip"), os.path.join(CSRC, "rewl_runtime.hip")]
+HEADERS = [os.path.join(CSRC, "rewl_device.h"),
+           os.path.join(os.path.dirname(HERE), "include", "rewl.h")]
+
+# -ffp-contract=off: the acceptance test must round every binary64/binary32
+# operation separately, in source order, exactly like a plain IEEE evaluation.
+# -packed-fp32-ops off: no packed FP32 instructions are generated.
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
+         "-Wno-unused-function", "-Wno-unknown-pragmas"]
+
+
+def hipcc():
+    return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+def build(force=True, verbose=False):
+    if not force and os.path.exists(LIB):
+        newest = max(os.path.getmtime(p) for p in SOURCES + HEADERS)
+        if os.path.getmtime(LIB) >= newest:
+            return LIB
+    tmp = LIB + ".tmp"
+    cmd = [hipcc()] + FLAGS + SOURCES + ["-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("librewl build failed:\n" + res.stderr[-8000:])
+    if verbose and res.stderr:
+        print(res.stderr[-4000:])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,167 @@
+// rewl_device.h -- device-side building blocks of the REWL walker update and
+// the state layout shared by the kernels and the host runtime of librewl.
+//
+// Method: Vogel, Li, Wuest, Landau, J. Phys.: Conf. Ser. (2014), Sec. 2
+// (Wang-Landau walkers in overlapping windows with replica exchange).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rewl_gpu {
+
+constexpr uint32_t kDomMove = 0;    // main-phase attempts
+constexpr uint32_t kDomWalkin = 2;  // walk-in attempts
+constexpr uint32_t kDomExch = 3;    // exchange permutation and acceptance words
+
+// Everything a kernel needs to find one run's state in the device workspace.
+// Per-walker rows are padded so every row starts on a 256-byte boundary.
+struct DevState {
+    int L, q, N, h, m, nw, W, B, e_lo;
+    int Npad, Wpad, Bpad;        // row strides (elements)
+    uint32_t key0, key1, ctr3;   // Philox key and instance bits of counter word 3
+    uint32_t flat_num, flat_den;
+    double lnf_final;
+    int schedule, precision, fixed_lnf;
+    const int32_t *start;        // [h] lowest energy of each window
+    int8_t *spins;               // [nw][Npad]
+    int32_t *E;                  // [nw]
+    double *lng;                 // [nw][Wpad]            (precision 0)
+    float *lng_hi, *lng_lo;      // [nw][Wpad] each       (precision 1)
+    uint32_t *H;                 // [nw][Wpad]
+    uint32_t *replica;           // [nw]
+    int64_t *walkin_att;         // [nw]
+    int32_t *walkin_done;        // [nw]
+    uint32_t *walkin_cnt;        // [nw][Bpad] visit counts of the walk-in ln g (ln f = 1)
+    double *lnf, *lnf_last;      // [h]
+    int32_t *regime, *finished;  // [h]
+    int64_t *iterations;         // [h]
+    uint8_t *visited;            // [h][Wpad]
+    unsigned long long *x_att, *x_acc;  // [h] exchange attempts / accepts of pair (k, k+1)
+    int32_t *converged;          // [1]
+    int64_t *stop;               // [2] main-phase step and exchange round at convergence
+    double *joined;              // [Bpad] joined ln g
+    int32_t *cuts;               // [h]
+    int32_t *join_status;        // [1]
+    double *scratch;             // [max(h, 4096)] small reduction scratch
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each
+// multiplying counter words 0 and 2 by fixed 32-bit constants, xor-ing the
+// high halves with the other words and the round key, then bumping the key by
+// the Weyl constants.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1) {
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t lo0 = M0 * c0, hi0 = __umulhi(M0, c0);
+        const uint32_t lo1 = M1 * c2, hi1 = __umulhi(M1, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// floor(r * n / 2^32): Lemire's multiply-shift map of a 32-bit word to [0, n).
+__device__ __forceinline__ uint32_t mul_shift(uint32_t r, uint32_t n) { return __umulhi(r, n); }
+
+// ---------------------------------------------------------------------------
+// exp(x) for x < 0, the acceptance ratio min[1, g_old/g_new] of Sec. 2 written
+// as exp(ln g_old - ln g_new).  Cody-Waite reduction x = k ln2 + r with ln 2
+// split as C1 (40 significant bits, so k*C1 is exact) + C2, then the degree-13
+// Taylor polynomial of exp(r) by Horner's rule with coefficients 1/n! rounded
+// to binary64, then scaling by 2^k.  Every operation is a separately rounded
+// binary64 operation (no contraction), so the result is reproducible bit for
+// bit on any IEEE machine that follows the same order.
+__device__ __forceinline__ double exp_neg(double x) {
+#pragma clang fp contract(off)
+    if (x < -64.0) return 0.0;
+    const double inv_ln2 = 0x1.71547652b82fep+0;
+    const double c1 = 0x1.62e42fefa4000p-1;
+    const double c2 = -0x1.8432a1b0e2634p-43;
+    const double kd = __builtin_rint(x * inv_ln2);
+    const double r = (x - kd * c1) - kd * c2;
+    double p = 0x1.6124613a86d09p-33;            // 1/13!
+    p = 0x1.1eed8eff8d898p-29 + r * p;           // 1/12!
+    p = 0x1.ae64567f544e4p-26 + r * p;           // 1/11!
+    p = 0x1.27e4fb7789f5cp-22 + r * p;           // 1/10!
+    p = 0x1.71de3a556c734p-19 + r * p;           // 1/9!
+    p = 0x1.a01a01a01a01ap-16 + r * p;           // 1/8!
+    p = 0x1.a01a01a01a01ap-13 + r * p;           // 1/7!
+    p = 0x1.6c16c16c16c17p-10 + r * p;           // 1/6!
+    p = 0x1.1111111111111p-7 + r * p;            // 1/5!
+    p = 0x1.5555555555555p-5 + r * p;            // 1/4!
+    p = 0x1.5555555555555p-3 + r * p;            // 1/3!
+    p = 0x1.0000000000000p-1 + r * p;            // 1/2!
+    p = 1.0 + r * p;                             // 1/1!
+    p = 1.0 + r * p;                             // 1/0!
+    return __builtin_ldexp(p, (int)kd);
+}
+
+// Binary32 twin for the (hi, lo) ln g variant: C1 of 16 bits, degree 7.
+__device__ __forceinline__ float exp_neg32(float x) {
+#pragma clang fp contract(off)
+    if (x < -64.0f) return 0.0f;
+    const float inv_ln2 = 0x1.715476p+0f;
+    const float c1 = 0x1.62e4p-1f;
+    const float c2 = 0x1.7f7d1cp-20f;
+    const float kf = __builtin_rintf(x * inv_ln2);
+    const float r = (x - kf * c1) - kf * c2;
+    float p = 0x1.a01a02p-13f;                   // 1/7!
+    p = 0x1.6c16c2p-10f + r * p;                 // 1/6!
+    p = 0x1.111112p-7f + r * p;                  // 1/5!
+    p = 0x1.555556p-5f + r * p;                  // 1/4!
+    p = 0x1.555556p-3f + r * p;                  // 1/3!
+    p = 0x1.000000p-1f + r * p;                  // 1/2!
+    p = 1.0f + r * p;
+    p = 1.0f + r * p;
+    return __builtin_ldexpf(p, (int)kf);
+}
+
+// Wang-Landau acceptance (Sec. 2): accept iff d >= 0 or u < exp(d), with
+// d = ln g(E_old) - ln g(E_new) and u = r / 2^32.
+__device__ __forceinline__ bool accept64(double d, uint32_t r) {
+#pragma clang fp contract(off)
+    if (d >= 0.0) return true;
+    return (double)r * 0x1p-32 < exp_neg(d);
+}
+
+// Same decision in binary32 with a 24-bit uniform u = (r >> 8) / 2^24.
+__device__ __forceinline__ bool accept32(float d, uint32_t r) {
+#pragma clang fp contract(off)
+    if (d >= 0.0f) return true;
+    return (float)(r >> 8) * 0x1p-24f < exp_neg32(d);
+}
+
+// ln g(E) += ln f on a binary32 (hi, lo) pair by Knuth's TwoSum: the rounding
+// error of the high part is carried into the low part.
+__device__ __forceinline__ void two_sum_add(float &hi, float &lo, float x) {
+#pragma clang fp contract(off)
+    const float s = hi + x;
+    const float bb = s - hi;
+    const float err = (hi - (s - bb)) + (x - bb);
+    hi = s;
+    lo = lo + err;
+}
+
+}  // namespace rewl_gpu
+
+// Launchers implemented in rewl_kernels.hip, used by the host runtime.
+namespace rewl_gpu {
+hipError_t launch_init_energy(const DevState &st, hipStream_t s);
+hipError_t launch_walkin(const DevState &st, int64_t chunk, int64_t budget, hipStream_t s);
+hipError_t launch_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s);
+hipError_t launch_sync(const DevState &st, int64_t attempts, hipStream_t s);
+hipError_t launch_exchange(const DevState &st, uint32_t round, hipStream_t s);
+hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, hipStream_t s);
+hipError_t launch_join(const DevState &st, double log_total, hipStream_t s);
+hipError_t launch_thermo(const DevState &st, const double *T, int nT, double *out, hipStream_t s);
+size_t sweep_lds_bytes(const DevState &st);
+}  // namespace rewl_gpu

@@ -1,0 +1,776 @@
+// rewl_kernels.hip -- HIP kernels (gfx950) of the Replica-Exchange Wang-Landau
+// walker update and its sync points.
+//
+// Vogel, Li, Wuest, Landau, J. Phys.: Conf. Ser. (2014):
+//   Sec. 2      Wang-Landau acceptance, refinement g -> f g, H(E)++, flatness,
+//               averaging within a window, replica exchange (Eq. 1), joining.
+//   Sec. 3.1    2D q-state Potts model (Eq. 2), single-spin-flip moves.
+//
+// Mapping: one walker per 64-lane wavefront (one workgroup).  Its lattice
+// (int8), ln g and H live in LDS for the whole launch; global memory is
+// touched only at launch start and end.  Attempts of one walker form a strict
+// sequence (each decision depends on the previous energy and ln g), so the
+// lanes first draw the Philox words and site neighbourhoods of the next 64
+// attempts in parallel and then walk through them in order.
+#include "rewl_device.h"
+
+namespace rewl_gpu {
+
+namespace {
+
+__device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double rfl(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ float rfl(float x) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x)));
+}
+
+// Proposal of one attempt, computed by one lane: site i uniform in [0, N),
+// new value uniform among the q-1 others (offset), u word, and the four
+// periodic neighbours of i (Sec. 3.1 single spin flips on the L x L torus).
+struct Proposal {
+    int site, off, nb0, nb1, nb2, nb3;
+    uint32_t u;
+};
+
+__device__ __forceinline__ Proposal propose(const DevState &st, uint32_t domain, uint64_t t,
+                                            uint32_t walker) {
+    const U4 r = philox10((uint32_t)t, (uint32_t)(t >> 32), walker, st.ctr3 | (domain << 24),
+                          st.key0, st.key1);
+    Proposal p;
+    p.site = (int)mul_shift(r.x, (uint32_t)st.N);
+    p.off = (int)mul_shift(r.y, (uint32_t)(st.q - 1));
+    p.u = r.z;
+    const int L = st.L;
+    const int y = p.site / L;
+    const int x = p.site - y * L;
+    const int row = y * L;
+    p.nb0 = row + (x + 1 == L ? 0 : x + 1);
+    p.nb1 = row + (x == 0 ? L - 1 : x - 1);
+    p.nb2 = (y + 1 == L ? 0 : row + L) + x;
+    p.nb3 = (y == 0 ? (L - 1) * L : row - L) + x;
+    return p;
+}
+
+// Energy change of setting site to nv, from the lattice in LDS (Eq. 2).
+__device__ __forceinline__ int delta_e(const int8_t *sp, int sc, int nv, int n0, int n1, int n2,
+                                       int n3) {
+    const int a0 = sp[n0], a1 = sp[n1], a2 = sp[n2], a3 = sp[n3];
+    return (int)(sc == a0) + (int)(sc == a1) + (int)(sc == a2) + (int)(sc == a3) -
+           (int)(nv == a0) - (int)(nv == a1) - (int)(nv == a2) - (int)(nv == a3);
+}
+
+// ---------------------------------------------------------------------------
+// Energy of every walker's starting lattice (Eq. 2, each bond once).
+__global__ __launch_bounds__(256) void k_init_energy(DevState st) {
+    const int w = blockIdx.x;
+    const int8_t *s = st.spins + (size_t)w * st.Npad;
+    const int L = st.L;
+    int e = 0;
+    for (int i = threadIdx.x; i < st.N; i += blockDim.x) {
+        const int y = i / L, x = i - y * L;
+        const int right = y * L + (x + 1 == L ? 0 : x + 1);
+        const int down = (y + 1 == L ? 0 : (y + 1) * L) + x;
+        e -= (s[i] == s[right]) + (s[i] == s[down]);
+    }
+    __shared__ int part[256];
+    part[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st.E[w] = part[0];
+}
+
+// ---------------------------------------------------------------------------
+// Walk-in: a global Wang-Landau walk with ln f = 1 over all 2N+1 energies, run
+// until the walker's energy first lies in its own window (every walker must
+// start inside its window, Sec. 3.2).  With ln f = 1 every ln g entry is an
+// integer visit count, kept exactly as uint32 in LDS.  Runs at most `chunk`
+// attempts per launch; the host relaunches until every walker is placed.
+__global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64_t budget) {
+    const int w = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (st.walkin_done[w]) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int8_t *sp = (int8_t *)smem;
+    uint32_t *cnt = (uint32_t *)(smem + st.Npad);
+    const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
+    for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)sp)[i] = gsp[i];
+    const uint32_t *gcnt = st.walkin_cnt + (size_t)w * st.Bpad;
+    for (int b = lane; b < st.B; b += 64) cnt[b] = gcnt[b];
+    __syncthreads();
+
+    const int k = w / st.m;
+    const int lo = st.start[k], hi = lo + st.W - 1;
+    const int e_lo = st.e_lo, q = st.q;
+    int E = st.E[w];
+    int64_t t = st.walkin_att[w];
+    const int64_t end = (t + chunk < budget) ? t + chunk : budget;
+    bool done = (E >= lo && E <= hi);
+    while (!done && t < end) {
+        const Proposal p = propose(st, kDomWalkin, (uint64_t)(t + lane), (uint32_t)w);
+        const int todo = (int)((end - t) < 64 ? (end - t) : 64);
+        for (int j = 0; j < todo; ++j) {
+            const int site = __builtin_amdgcn_readlane(p.site, j);
+            const int off = __builtin_amdgcn_readlane(p.off, j);
+            const uint32_t u = __builtin_amdgcn_readlane(p.u, j);
+            const int n0 = __builtin_amdgcn_readlane(p.nb0, j);
+            const int n1 = __builtin_amdgcn_readlane(p.nb1, j);
+            const int n2 = __builtin_amdgcn_readlane(p.nb2, j);
+            const int n3 = __builtin_amdgcn_readlane(p.nb3, j);
+            const int sc = rfl((int)sp[site]);
+            int nv = sc + 1 + off;
+            if (nv >= q) nv -= q;
+            const int En = E + rfl(delta_e(sp, sc, nv, n0, n1, n2, n3));
+            const int64_t ci = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(cnt[E - e_lo]);
+            const int64_t cn = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(cnt[En - e_lo]);
+            const double d = (double)(ci - cn);
+            if (accept64(d, u)) {
+                if (lane == 0) sp[site] = (int8_t)nv;
+                E = En;
+            }
+            if (lane == 0) cnt[E - e_lo] += 1u;
+            ++t;
+            if (E >= lo && E <= hi) { done = true; break; }
+        }
+    }
+    __syncthreads();
+    uint32_t *osp = (uint32_t *)(st.spins + (size_t)w * st.Npad);
+    for (int i = lane; i < st.Npad / 4; i += 64) osp[i] = ((uint32_t *)sp)[i];
+    uint32_t *ocnt = st.walkin_cnt + (size_t)w * st.Bpad;
+    for (int b = lane; b < st.B; b += 64) ocnt[b] = cnt[b];
+    if (lane == 0) {
+        st.E[w] = E;
+        st.walkin_att[w] = t;
+        st.walkin_done[w] = done ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Main-phase Wang-Landau attempts (Sec. 2): n attempts of every walker,
+// attempt indices s0 .. s0+n-1.  Per attempt: propose a single spin flip,
+// reject it if the new energy leaves the window, else accept with
+// min[1, g(E_old)/g(E_new)]; then ln g(E) += ln f and H(E) += 1 at the
+// energy after the decision.
+template <int PREC>
+__global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n) {
+    if (*st.converged) return;
+    const int w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int k = w / st.m;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int8_t *sp = (int8_t *)smem;
+    const int W = st.W, Wpad = st.Wpad;
+    double *g = (double *)(smem + st.Npad);
+    float *gh = (float *)(smem + st.Npad);
+    float *gl = gh + Wpad;
+    uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
+
+    const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
+    for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)sp)[i] = gsp[i];
+    const size_t row = (size_t)w * Wpad;
+    for (int b = lane; b < W; b += 64) {
+        if (PREC == 0) {
+            g[b] = st.lng[row + b];
+        } else {
+            gh[b] = st.lng_hi[row + b];
+            gl[b] = st.lng_lo[row + b];
+        }
+        H[b] = st.H[row + b];
+    }
+    __syncthreads();
+
+    const int lo = st.start[k], hi = lo + W - 1;
+    const int q = st.q;
+    const double lnf = st.lnf[k];
+    if (st.E[w] < lo || st.E[w] > hi) return;  // not walked in: leave the walker untouched
+    const float lnf32 = (float)lnf;
+    int E = st.E[w];
+    // ln g at the current energy, kept in registers (identical in all lanes)
+    double gE = 0.0;
+    float gEh = 0.0f, gEl = 0.0f;
+    if (PREC == 0) gE = rfl(g[E - lo]);
+    else { gEh = rfl(gh[E - lo]); gEl = rfl(gl[E - lo]); }
+
+    for (int64_t base = 0; base < n; base += 64) {
+        const Proposal p = propose(st, kDomMove, (uint64_t)(s0 + base + lane), (uint32_t)w);
+        const int todo = (int)((n - base) < 64 ? (n - base) : 64);
+        for (int j = 0; j < todo; ++j) {
+            const int site = __builtin_amdgcn_readlane(p.site, j);
+            const int off = __builtin_amdgcn_readlane(p.off, j);
+            const uint32_t u = __builtin_amdgcn_readlane(p.u, j);
+            const int n0 = __builtin_amdgcn_readlane(p.nb0, j);
+            const int n1 = __builtin_amdgcn_readlane(p.nb1, j);
+            const int n2 = __builtin_amdgcn_readlane(p.nb2, j);
+            const int n3 = __builtin_amdgcn_readlane(p.nb3, j);
+            const int sc = rfl((int)sp[site]);
+            int nv = sc + 1 + off;
+            if (nv >= q) nv -= q;
+            const int En = E + rfl(delta_e(sp, sc, nv, n0, n1, n2, n3));
+            if (En >= lo && En <= hi) {
+                if (PREC == 0) {
+                    const double gN = rfl(g[En - lo]);
+                    if (accept64(gE - gN, u)) {
+                        if (lane == 0) sp[site] = (int8_t)nv;
+                        E = En;
+                        gE = gN;
+                    }
+                } else {
+                    const float gNh = rfl(gh[En - lo]);
+                    const float gNl = rfl(gl[En - lo]);
+                    if (accept32((gEh - gNh) + (gEl - gNl), u)) {
+                        if (lane == 0) sp[site] = (int8_t)nv;
+                        E = En;
+                        gEh = gNh;
+                        gEl = gNl;
+                    }
+                }
+            }
+            const int b = E - lo;
+            if (PREC == 0) {
+                gE = gE + lnf;
+                if (lane == 0) { g[b] = gE; H[b] += 1u; }
+            } else {
+                two_sum_add(gEh, gEl, lnf32);
+                if (lane == 0) { gh[b] = gEh; gl[b] = gEl; H[b] += 1u; }
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *osp = (uint32_t *)(st.spins + (size_t)w * st.Npad);
+    for (int i = lane; i < st.Npad / 4; i += 64) osp[i] = ((uint32_t *)sp)[i];
+    for (int b = lane; b < W; b += 64) {
+        if (PREC == 0) {
+            st.lng[row + b] = g[b];
+        } else {
+            st.lng_hi[row + b] = gh[b];
+            st.lng_lo[row + b] = gl[b];
+        }
+        st.H[row + b] = H[b];
+    }
+    if (lane == 0) st.E[w] = E;
+}
+
+// ---------------------------------------------------------------------------
+// Sync point of one window (Sec. 2), one workgroup per window:
+//  1. visited bins of the window |= bins with H > 0 of any of its walkers;
+//  2. (hi, lo) pairs renormalised with Fast2Sum (binary32 variant);
+//  3. halving regime: every walker flat (flat_den*min H*n >= flat_num*sum H
+//     over the visited bins)?  Then average ln g over the m walkers (summed in
+//     walker order, divided by m), hand the mean to all, reset H, ln f /= 2,
+//     and switch to ln f = 1/t once ln f <= 1/t (schedule 1);
+//     1/t regime: average and reset H at every sync, ln f = 1/t;
+//  4. ln f < ln f_final: the window is finished and continues with ln f = 0.
+// t = attempts per walker / W (Belardinelli-Pereyra's 1/t rule, cited Sec. 2).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_sync(DevState st, int64_t attempts) {
+#pragma clang fp contract(off)
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (*st.converged || st.finished[k]) return;
+    const int W = st.W, m = st.m, Wpad = st.Wpad;
+    const size_t base = (size_t)k * m * Wpad;
+    uint8_t *vis = st.visited + (size_t)k * Wpad;
+    for (int b = tid; b < W; b += 256) {
+        uint8_t v = vis[b];
+        for (int j = 0; j < m; ++j) v |= (st.H[base + (size_t)j * Wpad + b] != 0u) ? 1 : 0;
+        vis[b] = v;
+    }
+    if (PREC == 1) {
+        for (int idx = tid; idx < m * W; idx += 256) {
+            const int j = idx / W, b = idx - j * W;
+            const size_t i = base + (size_t)j * Wpad + b;
+            const float h0 = st.lng_hi[i], l0 = st.lng_lo[i];
+            const float s = h0 + l0;
+            const float z = s - h0;
+            st.lng_lo[i] = l0 - z;
+            st.lng_hi[i] = s;
+        }
+    }
+    if (st.fixed_lnf) return;
+    __syncthreads();
+
+    __shared__ unsigned long long s_sum[256];
+    __shared__ unsigned int s_n[256], s_min[256];
+    __shared__ int s_avg;
+    const int regime = st.regime[k];
+    if (regime == 0) {
+        int all_flat = 1;
+        for (int j = 0; j < m; ++j) {
+            unsigned long long sum = 0;
+            unsigned int cnt = 0, mn = 0xFFFFFFFFu;
+            for (int b = tid; b < W; b += 256) {
+                if (!vis[b]) continue;
+                const unsigned int hv = st.H[base + (size_t)j * Wpad + b];
+                cnt += 1;
+                sum += hv;
+                mn = hv < mn ? hv : mn;
+            }
+            s_sum[tid] = sum; s_n[tid] = cnt; s_min[tid] = mn;
+            __syncthreads();
+            for (int o = 128; o > 0; o >>= 1) {
+                if (tid < o) {
+                    s_sum[tid] += s_sum[tid + o];
+                    s_n[tid] += s_n[tid + o];
+                    s_min[tid] = s_min[tid + o] < s_min[tid] ? s_min[tid + o] : s_min[tid];
+                }
+                __syncthreads();
+            }
+            const unsigned long long n_act = s_n[0], tot = s_sum[0], hmin = s_min[0];
+            const bool flat = n_act > 0 &&
+                              (unsigned long long)st.flat_den * hmin * n_act >=
+                                  (unsigned long long)st.flat_num * tot;
+            all_flat = all_flat && flat;
+            __syncthreads();
+        }
+        if (tid == 0) s_avg = all_flat;
+    } else {
+        if (tid == 0) s_avg = 1;
+    }
+    __syncthreads();
+    if (!s_avg) return;
+    for (int b = tid; b < W; b += 256) {
+        double sum;
+        if (PREC == 0) {
+            sum = st.lng[base + b];
+            for (int j = 1; j < m; ++j) sum = sum + st.lng[base + (size_t)j * Wpad + b];
+        } else {
+            sum = (double)st.lng_hi[base + b] + (double)st.lng_lo[base + b];
+            for (int j = 1; j < m; ++j) {
+                const size_t i = base + (size_t)j * Wpad + b;
+                sum = sum + ((double)st.lng_hi[i] + (double)st.lng_lo[i]);
+            }
+        }
+        const double mean = sum / (double)m;
+        for (int j = 0; j < m; ++j) {
+            const size_t i = base + (size_t)j * Wpad + b;
+            if (PREC == 0) {
+                st.lng[i] = mean;
+            } else {
+                const float h0 = (float)mean;
+                st.lng_hi[i] = h0;
+                st.lng_lo[i] = (float)(mean - (double)h0);
+            }
+            st.H[i] = 0u;
+        }
+    }
+    if (tid == 0) {
+        const double inv_t = (double)W / (double)attempts;
+        double lnf = st.lnf[k];
+        if (regime == 0) {
+            lnf = lnf * 0.5;
+            if (st.schedule == 1 && lnf <= inv_t) {
+                st.regime[k] = 1;
+                lnf = inv_t;
+            }
+        } else {
+            lnf = inv_t;
+        }
+        st.iterations[k] += 1;
+        if (lnf < st.lnf_final) {
+            st.finished[k] = 1;
+            st.lnf_last[k] = lnf;
+            lnf = 0.0;
+        }
+        st.lnf[k] = lnf;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One replica-exchange round (Sec. 2, Eq. 1).  Workgroup b handles the window
+// pair (k, k+1), k = (r mod 2) + 2b.  Walker j of window k meets walker pi(j)
+// of window k+1, pi a Fisher-Yates permutation; configurations X (walker a)
+// and Y (walker b) swap with probability
+//   min[1, g_a(E_X)/g_a(E_Y) * g_b(E_Y)/g_b(E_X)],
+// rejected outright if E_Y is outside window k or E_X outside window k+1.
+// Random words: Philox blocks with counter (r, k, n, EXCH), read in order:
+// m-1 words for the permutation, then one word per pair.
+__device__ __forceinline__ double lng_at(const DevState &st, int w, int b, int prec) {
+    const size_t i = (size_t)w * st.Wpad + b;
+    if (prec == 0) return st.lng[i];
+    return (double)st.lng_hi[i] + (double)st.lng_lo[i];
+}
+
+__global__ __launch_bounds__(64) void k_exchange(DevState st, uint32_t r) {
+#pragma clang fp contract(off)
+    if (*st.converged) return;
+    const int k = (int)(r & 1u) + 2 * (int)blockIdx.x;
+    if (k + 1 >= st.h) return;
+    const int m = st.m;
+    __shared__ int s_perm[1024];
+    __shared__ int s_acc[1024];
+    if (threadIdx.x == 0) {
+        uint32_t buf[4];
+        int pos = 4;
+        uint32_t n = 0;
+        auto next = [&]() -> uint32_t {
+            if (pos == 4) {
+                const U4 v = philox10(r, (uint32_t)k, n, st.ctr3 | (kDomExch << 24), st.key0, st.key1);
+                buf[0] = v.x; buf[1] = v.y; buf[2] = v.z; buf[3] = v.w;
+                ++n;
+                pos = 0;
+            }
+            return buf[pos++];
+        };
+        for (int j = 0; j < m; ++j) s_perm[j] = j;
+        for (int i = m - 1; i >= 1; --i) {
+            const int j = (int)mul_shift(next(), (uint32_t)(i + 1));
+            const int t = s_perm[i]; s_perm[i] = s_perm[j]; s_perm[j] = t;
+        }
+        const int lo_a = st.start[k], hi_a = lo_a + st.W - 1;
+        const int lo_b = st.start[k + 1], hi_b = lo_b + st.W - 1;
+        unsigned long long nacc = 0;
+        for (int j = 0; j < m; ++j) {
+            const int a = k * m + j, b = (k + 1) * m + s_perm[j];
+            const uint32_t u = next();
+            const int ex = st.E[a], ey = st.E[b];
+            int acc = 0;
+            if (ey >= lo_a && ey <= hi_a && ex >= lo_b && ex <= hi_b) {
+                const double d = ((lng_at(st, a, ex - lo_a, st.precision) -
+                                   lng_at(st, a, ey - lo_a, st.precision)) +
+                                  lng_at(st, b, ey - lo_b, st.precision)) -
+                                 lng_at(st, b, ex - lo_b, st.precision);
+                acc = accept64(d, u) ? 1 : 0;
+            }
+            s_acc[j] = acc;
+            nacc += (unsigned long long)acc;
+        }
+        st.x_att[k] += (unsigned long long)m;
+        st.x_acc[k] += nacc;
+    }
+    __syncthreads();
+    const int words = st.Npad / 4;
+    for (int j = 0; j < m; ++j) {
+        if (!s_acc[j]) continue;
+        const int a = k * m + j, b = (k + 1) * m + s_perm[j];
+        uint32_t *pa = (uint32_t *)(st.spins + (size_t)a * st.Npad);
+        uint32_t *pb = (uint32_t *)(st.spins + (size_t)b * st.Npad);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) {
+            const uint32_t t = pa[i]; pa[i] = pb[i]; pb[i] = t;
+        }
+        if (threadIdx.x == 0) {
+            const int t = st.E[a]; st.E[a] = st.E[b]; st.E[b] = t;
+            const uint32_t rr = st.replica[a]; st.replica[a] = st.replica[b]; st.replica[b] = rr;
+        }
+    }
+}
+
+// Termination (Sec. 2): the run ends once every window reached ln f_final.
+__global__ void k_check(DevState st, int64_t step, int64_t round_after) {
+    if (threadIdx.x != 0 || *st.converged) return;
+    for (int k = 0; k < st.h; ++k)
+        if (!st.finished[k]) return;
+    *st.converged = 1;
+    st.stop[0] = step;
+    st.stop[1] = round_after;
+}
+
+// ---------------------------------------------------------------------------
+// Joining the pieces (Sec. 2, Fig. 2) in binary64.
+// (a) visited flags of unfinished windows absorb the current histograms;
+// (b) beta_k(E) = (ln g_k(E+) - ln g_k(E-)) / (E+ - E-) with E+-, the nearest
+//     visited bins above and below E inside window k (NaN when undefined);
+// (c) one workgroup walks the pairs in order: the joining energy of pair
+//     (k, k+1) minimises |beta_k - beta_{k+1}| over the overlap above the
+//     previous joining energy (ties: lowest E); piece k+1 is shifted to meet
+//     piece k there;
+// (d) every energy takes the piece whose range (cut_{k-1}, cut_k] holds it;
+// (e) normalisation to sum_E g(E) = q^N by log-sum-exp.
+__global__ __launch_bounds__(256) void k_fold_visited(DevState st) {
+    const int k = blockIdx.x;
+    if (st.finished[k]) return;
+    const size_t base = (size_t)k * st.m * st.Wpad;
+    uint8_t *vis = st.visited + (size_t)k * st.Wpad;
+    for (int b = threadIdx.x; b < st.W; b += blockDim.x) {
+        uint8_t v = vis[b];
+        for (int j = 0; j < st.m; ++j) v |= (st.H[base + (size_t)j * st.Wpad + b] != 0u) ? 1 : 0;
+        vis[b] = v;
+    }
+}
+
+__device__ __forceinline__ double piece_at(const DevState &st, int k, int b) {
+    return lng_at(st, k * st.m, b, st.precision);
+}
+
+__global__ __launch_bounds__(256) void k_beta(DevState st, double *beta) {
+#pragma clang fp contract(off)
+    const int k = blockIdx.y;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= st.W) return;
+    const uint8_t *vis = st.visited + (size_t)k * st.Wpad;
+    double out = __builtin_nan("");
+    if (vis[b]) {
+        int bp = -1, bm = -1;
+        for (int t = b + 1; t < st.W; ++t) if (vis[t]) { bp = t; break; }
+        for (int t = b - 1; t >= 0; --t) if (vis[t]) { bm = t; break; }
+        if (bp >= 0 && bm >= 0)
+            out = (piece_at(st, k, bp) - piece_at(st, k, bm)) / (double)(bp - bm);
+    }
+    beta[(size_t)k * st.Wpad + b] = out;
+}
+
+__global__ __launch_bounds__(256) void k_join_cuts(DevState st, const double *beta, double *shift) {
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    __shared__ double s_d[256];
+    __shared__ int s_e[256];
+    __shared__ int s_prev;
+    if (tid == 0) { s_prev = INT32_MIN; shift[0] = 0.0; *st.join_status = 0; }
+    __syncthreads();
+    const int W = st.W;
+    for (int k = 0; k + 1 < st.h; ++k) {
+        const int sa = st.start[k], sb = st.start[k + 1];
+        int lo = sb;
+        if (s_prev != INT32_MIN && s_prev + 1 > lo) lo = s_prev + 1;
+        const int hi = sa + W - 1;
+        double bestd = 0.0;
+        int beste = INT32_MIN;
+        for (int e = lo + tid; e <= hi; e += 256) {
+            const double ba = beta[(size_t)k * st.Wpad + (e - sa)];
+            const double bb = beta[(size_t)(k + 1) * st.Wpad + (e - sb)];
+            if (ba != ba || bb != bb) continue;
+            const double d = fabs(ba - bb);
+            if (beste == INT32_MIN || d < bestd) { bestd = d; beste = e; }
+        }
+        s_d[tid] = bestd; s_e[tid] = beste;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) {
+                const int e2 = s_e[tid + o];
+                if (e2 != INT32_MIN) {
+                    const double d2 = s_d[tid + o];
+                    const int e1 = s_e[tid];
+                    if (e1 == INT32_MIN || d2 < s_d[tid] || (d2 == s_d[tid] && e2 < e1)) {
+                        s_d[tid] = d2; s_e[tid] = e2;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            int best = s_e[0];
+            if (best == INT32_MIN) {
+                const uint8_t *va = st.visited + (size_t)k * st.Wpad;
+                const uint8_t *vb = st.visited + (size_t)(k + 1) * st.Wpad;
+                for (int e = lo; e <= hi; ++e)
+                    if (va[e - sa] && vb[e - sb]) { best = e; break; }
+            }
+            if (best == INT32_MIN) {
+                *st.join_status = -1;
+                best = hi;
+            }
+            st.cuts[k] = best;
+            shift[k + 1] = (piece_at(st, k, best - sa) + shift[k]) - piece_at(st, k + 1, best - sb);
+            s_prev = best;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_join_assemble(DevState st, const double *shift) {
+#pragma clang fp contract(off)
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= st.B) return;
+    const int e = st.e_lo + b;
+    const int h = st.h;
+    // piece k holds (cut_{k-1}, cut_k]
+    int k = 0;
+    while (k < h - 1 && e > st.cuts[k]) ++k;
+    const int bb = e - st.start[k];
+    double out = -__builtin_inf();
+    if (bb >= 0 && bb < st.W && st.visited[(size_t)k * st.Wpad + bb])
+        out = piece_at(st, k, bb) + shift[k];
+    st.joined[b] = out;
+}
+
+// log-sum-exp over the joined curve in one workgroup, then the shift to
+// sum_E g(E) = exp(log_total).
+__global__ __launch_bounds__(256) void k_join_normalise(DevState st, double log_total) {
+    const int tid = threadIdx.x;
+    __shared__ double s[256];
+    double mx = -__builtin_inf();
+    for (int b = tid; b < st.B; b += 256) mx = fmax(mx, st.joined[b]);
+    s[tid] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] = fmax(s[tid], s[tid + o]);
+        __syncthreads();
+    }
+    mx = s[0];
+    __syncthreads();
+    double acc = 0.0;
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v != -__builtin_inf()) acc += exp(v - mx);
+    }
+    s[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] += s[tid + o];
+        __syncthreads();
+    }
+    const double lse = mx + log(s[0]);
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v != -__builtin_inf()) st.joined[b] = (v - lse) + log_total;
+    }
+}
+
+// Canonical averages (Sec. 3.1, Fig. 3b) from the joined ln g, one workgroup
+// per temperature: ln Z = LSE_E(ln g(E) - E/T), U = sum P E,
+// C_v = sum P (E - U)^2 / T^2 with P = exp(ln g(E) - E/T - ln Z).
+__global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, double *out) {
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const double temp = T[t];
+    __shared__ double s[256];
+    double mx = -__builtin_inf();
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v == -__builtin_inf()) continue;
+        mx = fmax(mx, v - (double)(st.e_lo + b) / temp);
+    }
+    s[tid] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] = fmax(s[tid], s[tid + o]);
+        __syncthreads();
+    }
+    mx = s[0];
+    __syncthreads();
+    double z = 0.0;
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v == -__builtin_inf()) continue;
+        z += exp((v - (double)(st.e_lo + b) / temp) - mx);
+    }
+    s[tid] = z;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] += s[tid + o];
+        __syncthreads();
+    }
+    const double lnz = mx + log(s[0]);
+    __syncthreads();
+    double u = 0.0;
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v == -__builtin_inf()) continue;
+        const double e = (double)(st.e_lo + b);
+        u += exp((v - e / temp) - lnz) * e;
+    }
+    s[tid] = u;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] += s[tid + o];
+        __syncthreads();
+    }
+    const double U = s[0];
+    __syncthreads();
+    double var = 0.0;
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v == -__builtin_inf()) continue;
+        const double e = (double)(st.e_lo + b);
+        const double d = e - U;
+        var += exp((v - e / temp) - lnz) * d * d;
+    }
+    s[tid] = var;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] += s[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[3 * t + 0] = lnz;
+        out[3 * t + 1] = U;
+        out[3 * t + 2] = s[0] / (temp * temp);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+size_t sweep_lds_bytes(const DevState &st) {
+    return (size_t)st.Npad + (size_t)st.Wpad * 8 + (size_t)st.Wpad * 4;
+}
+
+static size_t walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
+
+static hipError_t allow_lds(const void *fn, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_init_energy(const DevState &st, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_energy, dim3(st.nw), dim3(256), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_walkin(const DevState &st, int64_t chunk, int64_t budget, hipStream_t s) {
+    const size_t lds = walkin_lds_bytes(st);
+    hipError_t e = allow_lds((const void *)k_walkin, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_walkin, dim3(st.nw), dim3(64), lds, s, st, chunk, budget);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s) {
+    const size_t lds = sweep_lds_bytes(st);
+    if (st.precision == 0) {
+        hipError_t e = allow_lds((const void *)k_sweep<0>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sweep<0>, dim3(st.nw), dim3(64), lds, s, st, s0, n);
+    } else {
+        hipError_t e = allow_lds((const void *)k_sweep<1>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sweep<1>, dim3(st.nw), dim3(64), lds, s, st, s0, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sync(const DevState &st, int64_t attempts, hipStream_t s) {
+    if (st.precision == 0)
+        hipLaunchKernelGGL(k_sync<0>, dim3(st.h), dim3(256), 0, s, st, attempts);
+    else
+        hipLaunchKernelGGL(k_sync<1>, dim3(st.h), dim3(256), 0, s, st, attempts);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(const DevState &st, uint32_t round, hipStream_t s) {
+    const int pairs = (st.h - (int)(round & 1u)) / 2;
+    if (pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exchange, dim3(pairs), dim3(64), 0, s, st, round);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, hipStream_t s) {
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, s, st, step, round_after);
+    return hipGetLastError();
+}
+
+hipError_t launch_join(const DevState &st, double log_total, hipStream_t s) {
+    double *beta = st.scratch;                                  // [h][Wpad]
+    double *shift = st.scratch + (size_t)st.h * st.Wpad;        // [h]
+    hipLaunchKernelGGL(k_fold_visited, dim3(st.h), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_beta, dim3((st.W + 255) / 256, st.h), dim3(256), 0, s, st, beta);
+    hipLaunchKernelGGL(k_join_cuts, dim3(1), dim3(256), 0, s, st, (const double *)beta, shift);
+    hipLaunchKernelGGL(k_join_assemble, dim3((st.B + 255) / 256), dim3(256), 0, s, st,
+                       (const double *)shift);
+    hipLaunchKernelGGL(k_join_normalise, dim3(1), dim3(256), 0, s, st, log_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_thermo(const DevState &st, const double *T, int nT, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_thermo, dim3(nT), dim3(256), 0, s, st, T, out);
+    return hipGetLastError();
+}
+
+}  // namespace rewl_gpu

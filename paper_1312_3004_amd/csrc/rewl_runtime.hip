@@ -1,0 +1,614 @@
+// rewl_runtime.hip -- host side of librewl: the C ABI declared in
+// include/rewl.h.  Validates arguments, carves the caller's device workspace
+// into the run's state arrays, and enqueues the kernels of rewl_kernels.hip
+// on the caller's stream in the order of the method (Sec. 2 of Vogel, Li,
+// Wuest, Landau): attempts, then at every sync point flatness/averaging/ln f
+// per window, a replica-exchange round, and the termination test.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rewl.h"
+#include "rewl_device.h"
+
+using rewl_gpu::DevState;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(REWL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxLds = 160 * 1024;
+constexpr int kMaxThermo = 4096;
+constexpr int64_t kWalkinChunk = int64_t(1) << 20;
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Params {
+    int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad;
+};
+
+struct Layout {
+    size_t start, spins, E, lng, lng_hi, lng_lo, H, replica, walkin_att, walkin_done, walkin_cnt,
+        lnf, lnf_last, regime, finished, iterations, visited, x_att, x_acc, converged, stop, joined,
+        cuts, join_status, scratch, T, thermo_out, total;
+};
+
+Layout make_layout(const Params &p, int precision) {
+    Layout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = round_up(off + bytes, kAlign);
+        return at;
+    };
+    l.start = take(sizeof(int32_t) * p.h);
+    l.spins = take((size_t)p.nw * p.Npad);
+    l.E = take(sizeof(int32_t) * p.nw);
+    l.lng = precision == 0 ? take(sizeof(double) * p.nw * p.Wpad) : 0;
+    l.lng_hi = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
+    l.lng_lo = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
+    l.H = take(sizeof(uint32_t) * p.nw * p.Wpad);
+    l.replica = take(sizeof(uint32_t) * p.nw);
+    l.walkin_att = take(sizeof(int64_t) * p.nw);
+    l.walkin_done = take(sizeof(int32_t) * p.nw);
+    l.walkin_cnt = take(sizeof(uint32_t) * (size_t)p.nw * p.Bpad);
+    l.lnf = take(sizeof(double) * p.h);
+    l.lnf_last = take(sizeof(double) * p.h);
+    l.regime = take(sizeof(int32_t) * p.h);
+    l.finished = take(sizeof(int32_t) * p.h);
+    l.iterations = take(sizeof(int64_t) * p.h);
+    l.visited = take((size_t)p.h * p.Wpad);
+    l.x_att = take(sizeof(uint64_t) * p.h);
+    l.x_acc = take(sizeof(uint64_t) * p.h);
+    l.converged = take(sizeof(int32_t));
+    l.stop = take(sizeof(int64_t) * 2);
+    l.joined = take(sizeof(double) * p.Bpad);
+    l.cuts = take(sizeof(int32_t) * p.h);
+    l.join_status = take(sizeof(int32_t));
+    l.scratch = take(sizeof(double) * ((size_t)p.h * p.Wpad + p.h + 16));
+    l.T = take(sizeof(double) * kMaxThermo);
+    l.thermo_out = take(sizeof(double) * 3 * kMaxThermo);
+    l.total = off;
+    return l;
+}
+
+int layout_windows(int L, int h, double o, int *W_out, int32_t *starts) {
+    if (L < 3 || L > 724) return fail(REWL_EINVAL, "L must be in [3, 724]");
+    if (h < 1) return fail(REWL_EINVAL, "windows must be >= 1");
+    if (!(o >= 0.0 && o < 1.0)) return fail(REWL_EINVAL, "overlap must be in [0, 1)");
+    const int N = L * L, B = 2 * N + 1;
+    int W = B;
+    if (h > 1) {
+        const double denom = 1.0 + (double)(h - 1) * (1.0 - o);
+        W = (int)std::ceil((double)B / denom);
+        if (W > B) W = B;
+    }
+    if (W < 8) return fail(REWL_EINVAL, "windows narrower than 8 energies");
+    for (int k = 0; k < h; ++k) {
+        if (h == 1) { starts[k] = -2 * N; continue; }
+        const int64_t num = 2 * (int64_t)k * (B - W) + (h - 1);
+        starts[k] = -2 * N + (int32_t)(num / (2 * (int64_t)(h - 1)));
+    }
+    *W_out = W;
+    return REWL_OK;
+}
+
+int check_params(int model, int L, int q, int h, double o, int m, const rewl_opts &op, Params *p,
+                 std::vector<int32_t> *starts) {
+    if (model != REWL_POTTS2D) return fail(REWL_EINVAL, "unknown model");
+    if (q < 2 || q > 127) return fail(REWL_EINVAL, "q must be in [2, 127]");
+    if (m < 1 || m > 1024) return fail(REWL_EINVAL, "walkers per window must be in [1, 1024]");
+    if ((int64_t)h * m > 65535) return fail(REWL_EINVAL, "at most 65535 walkers");
+    if (op.flat_den == 0 || op.flat_den > 1000 || op.flat_num > op.flat_den)
+        return fail(REWL_EINVAL, "flatness must satisfy flat_num <= flat_den <= 1000");
+    if (op.sync_attempts < 1) return fail(REWL_EINVAL, "sync_attempts must be >= 1");
+    if (op.precision < 0 || op.precision > 1) return fail(REWL_EINVAL, "precision must be 0 or 1");
+    if (op.schedule < 0 || op.schedule > 1) return fail(REWL_EINVAL, "schedule must be 0 or 1");
+    if (!(op.lnf_init >= 0.0) || !(op.lnf_final >= 0.0)) return fail(REWL_EINVAL, "ln f must be >= 0");
+    starts->assign((size_t)std::max(h, 1), 0);
+    int W = 0;
+    const int st = layout_windows(L, h, o, &W, starts->data());
+    if (st != REWL_OK) return st;
+    p->L = L; p->q = q; p->N = L * L; p->h = h; p->m = m; p->nw = h * m; p->W = W;
+    p->B = 2 * p->N + 1; p->e_lo = -2 * p->N;
+    p->Npad = (int)round_up((size_t)p->N, kAlign);
+    p->Wpad = (int)round_up((size_t)W, 64);
+    p->Bpad = (int)round_up((size_t)p->B, 64);
+    if ((size_t)p->Npad + (size_t)p->Wpad * 12 > (size_t)kMaxLds)
+        return fail(REWL_EINVAL, "lattice plus window state exceed the 160 KiB LDS of a CU");
+    if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
+        return fail(REWL_EINVAL, "walk-in ln g over all energies exceeds the 160 KiB LDS (L too large)");
+    return REWL_OK;
+}
+
+}  // namespace
+
+// HIP event pairs around launches, folded into running sums when the pool
+// fills up or when the totals are read.
+struct Timer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+    std::vector<hipEvent_t> pool;
+    double ms[2] = {0.0, 0.0};
+    int64_t count[2] = {0, 0};
+};
+
+struct rewl {
+    DevState st;
+    Timer timer;
+    Layout lay;
+    unsigned char *ws;
+    hipStream_t stream;
+    rewl_opts opts;
+    std::vector<int32_t> starts;
+    int64_t step = 0, round = 0;
+    bool walked_in = false, converged = false, joined = false;
+};
+
+namespace {
+
+hipError_t timer_event(Timer &t, hipEvent_t *ev) {
+    if (!t.pool.empty()) {
+        *ev = t.pool.back();
+        t.pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+hipError_t timer_fold(Timer &t) {
+    for (int kind = 0; kind < 2; ++kind) {
+        for (auto &pr : t.pending[kind]) {
+            hipError_t e = hipEventSynchronize(pr.second);
+            if (e != hipSuccess) return e;
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, pr.first, pr.second);
+            if (e != hipSuccess) return e;
+            t.ms[kind] += ms;
+            t.count[kind] += 1;
+            t.pool.push_back(pr.first);
+            t.pool.push_back(pr.second);
+        }
+        t.pending[kind].clear();
+    }
+    return hipSuccess;
+}
+
+// Record the start event of a timed region of the given kind (0 attempts,
+// 1 sync point) on the run's stream.
+hipError_t timer_begin(rewl *r, hipEvent_t *ev) {
+    if (!r->timer.on) return hipSuccess;
+    if (r->timer.pending[0].size() + r->timer.pending[1].size() >= 4096) {
+        hipError_t e = timer_fold(r->timer);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = timer_event(r->timer, ev);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(*ev, r->stream);
+}
+
+hipError_t timer_end(rewl *r, int kind, hipEvent_t start) {
+    if (!r->timer.on) return hipSuccess;
+    hipEvent_t stop;
+    hipError_t e = timer_event(r->timer, &stop);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(stop, r->stream);
+    if (e != hipSuccess) return e;
+    r->timer.pending[kind].push_back({start, stop});
+    return hipSuccess;
+}
+
+void timer_destroy(Timer &t) {
+    (void)timer_fold(t);
+    for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);
+    t.pool.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+void rewl_default_opts(rewl_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->seed = 1;
+    o->instance = 0;
+    o->flat_num = 4;
+    o->flat_den = 5;
+    o->lnf_init = 1.0;
+    o->lnf_final = 1e-6;
+    o->schedule = 0;
+    o->exchange = 1;
+    o->sync_attempts = 1000;
+    o->precision = 0;
+    o->fixed_lnf = 0;
+}
+
+const char *rewl_last_error(void) { return g_err.c_str(); }
+
+int rewl_window_layout(int L, int windows, double overlap, int32_t *W, int32_t *starts) {
+    if (!W || !starts) return fail(REWL_EINVAL, "null output pointer");
+    int w = 0;
+    const int st = layout_windows(L, windows, overlap, &w, starts);
+    if (st == REWL_OK) *W = w;
+    return st;
+}
+
+size_t rewl_workspace_bytes(int model, int L, int q, int windows, double overlap, int walkers,
+                            const rewl_opts *opts) {
+    rewl_opts op;
+    if (opts) op = *opts; else rewl_default_opts(&op);
+    Params p;
+    std::vector<int32_t> starts;
+    if (check_params(model, L, q, windows, overlap, walkers, op, &p, &starts) != REWL_OK) return 0;
+    return make_layout(p, op.precision).total;
+}
+
+int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overlap, int walkers,
+                const rewl_opts *opts, const int8_t *init_spins, void *dev_workspace, size_t ws_bytes,
+                void *hip_stream) {
+    if (!out) return fail(REWL_EINVAL, "null handle pointer");
+    *out = nullptr;
+    rewl_opts op;
+    if (opts) op = *opts; else rewl_default_opts(&op);
+    Params p;
+    std::vector<int32_t> starts;
+    int st = check_params(model, L, q, windows, overlap, walkers, op, &p, &starts);
+    if (st != REWL_OK) return st;
+    if (!init_spins) return fail(REWL_EINVAL, "init_spins is required");
+    for (size_t i = 0; i < (size_t)p.nw * p.N; ++i)
+        if (init_spins[i] < 0 || init_spins[i] >= q) return fail(REWL_EINVAL, "spin value outside [0, q)");
+    const Layout lay = make_layout(p, op.precision);
+    if (!dev_workspace) return fail(REWL_EINVAL, "null device workspace");
+    if (ws_bytes < lay.total) return fail(REWL_ENOMEM, "device workspace smaller than rewl_workspace_bytes");
+    if (((uintptr_t)dev_workspace) % kAlign != 0) return fail(REWL_EINVAL, "workspace must be 256-byte aligned");
+
+    rewl *r = new (std::nothrow) rewl();
+    if (!r) return fail(REWL_ENOMEM, "host allocation failed");
+    r->ws = (unsigned char *)dev_workspace;
+    r->lay = lay;
+    r->stream = (hipStream_t)hip_stream;
+    r->opts = op;
+    r->starts = starts;
+    unsigned char *b = r->ws;
+    DevState &d = r->st;
+    std::memset(&d, 0, sizeof(d));
+    d.L = p.L; d.q = p.q; d.N = p.N; d.h = p.h; d.m = p.m; d.nw = p.nw; d.W = p.W; d.B = p.B;
+    d.e_lo = p.e_lo; d.Npad = p.Npad; d.Wpad = p.Wpad; d.Bpad = p.Bpad;
+    d.key0 = (uint32_t)op.seed; d.key1 = (uint32_t)(op.seed >> 32);
+    d.ctr3 = op.instance & 0xFFFFFFu;
+    d.flat_num = op.flat_num; d.flat_den = op.flat_den;
+    d.lnf_final = op.lnf_final;
+    d.schedule = op.schedule; d.precision = op.precision; d.fixed_lnf = op.fixed_lnf;
+    d.start = (const int32_t *)(b + lay.start);
+    d.spins = (int8_t *)(b + lay.spins);
+    d.E = (int32_t *)(b + lay.E);
+    d.lng = op.precision == 0 ? (double *)(b + lay.lng) : nullptr;
+    d.lng_hi = op.precision == 1 ? (float *)(b + lay.lng_hi) : nullptr;
+    d.lng_lo = op.precision == 1 ? (float *)(b + lay.lng_lo) : nullptr;
+    d.H = (uint32_t *)(b + lay.H);
+    d.replica = (uint32_t *)(b + lay.replica);
+    d.walkin_att = (int64_t *)(b + lay.walkin_att);
+    d.walkin_done = (int32_t *)(b + lay.walkin_done);
+    d.walkin_cnt = (uint32_t *)(b + lay.walkin_cnt);
+    d.lnf = (double *)(b + lay.lnf);
+    d.lnf_last = (double *)(b + lay.lnf_last);
+    d.regime = (int32_t *)(b + lay.regime);
+    d.finished = (int32_t *)(b + lay.finished);
+    d.iterations = (int64_t *)(b + lay.iterations);
+    d.visited = (uint8_t *)(b + lay.visited);
+    d.x_att = (unsigned long long *)(b + lay.x_att);
+    d.x_acc = (unsigned long long *)(b + lay.x_acc);
+    d.converged = (int32_t *)(b + lay.converged);
+    d.stop = (int64_t *)(b + lay.stop);
+    d.joined = (double *)(b + lay.joined);
+    d.cuts = (int32_t *)(b + lay.cuts);
+    d.join_status = (int32_t *)(b + lay.join_status);
+    d.scratch = (double *)(b + lay.scratch);
+
+    auto bail = [&](int code) { delete r; return code; };
+    hipError_t e = hipMemsetAsync(r->ws, 0, lay.total, r->stream);
+    if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e)));
+    std::vector<int8_t> sp((size_t)p.nw * p.Npad, 0);
+    for (int w = 0; w < p.nw; ++w) std::memcpy(&sp[(size_t)w * p.Npad], init_spins + (size_t)w * p.N, p.N);
+    std::vector<uint32_t> rep(p.nw);
+    for (int w = 0; w < p.nw; ++w) rep[w] = (uint32_t)w;
+    std::vector<double> lnf(p.h, op.lnf_init);
+    e = hipMemcpyAsync((void *)d.start, starts.data(), sizeof(int32_t) * p.h, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.spins, sp.data(), sp.size(), hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.replica, rep.data(), sizeof(uint32_t) * p.nw, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.lnf, lnf.data(), sizeof(double) * p.h, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = rewl_gpu::launch_init_energy(d, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("rewl_create: ") + hipGetErrorString(e)));
+    *out = r;
+    return REWL_OK;
+}
+
+void rewl_destroy(rewl_t *r) {
+    if (!r) return;
+    timer_destroy(r->timer);
+    delete r;
+}
+
+int rewl_set_timing(rewl_t *r, int enable) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    HIP_TRY(timer_fold(r->timer));
+    r->timer.on = enable != 0;
+    r->timer.ms[0] = r->timer.ms[1] = 0.0;
+    r->timer.count[0] = r->timer.count[1] = 0;
+    return REWL_OK;
+}
+
+int rewl_get_timing(rewl_t *r, double *sweep_ms, int64_t *sweep_launches, double *sync_ms,
+                    int64_t *sync_points) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    HIP_TRY(timer_fold(r->timer));
+    if (sweep_ms) *sweep_ms = r->timer.ms[0];
+    if (sweep_launches) *sweep_launches = r->timer.count[0];
+    if (sync_ms) *sync_ms = r->timer.ms[1];
+    if (sync_points) *sync_points = r->timer.count[1];
+    return REWL_OK;
+}
+
+int rewl_walkin(rewl_t *r, int64_t max_attempts) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    if (r->walked_in) return REWL_OK;
+    if (max_attempts < 0) return fail(REWL_EINVAL, "negative walk-in budget");
+    const int nw = r->st.nw;
+    std::vector<int32_t> done(nw);
+    std::vector<int64_t> att(nw);
+    for (;;) {
+        HIP_TRY(rewl_gpu::launch_walkin(r->st, kWalkinChunk, max_attempts, r->stream));
+        HIP_TRY(hipMemcpyAsync(done.data(), r->st.walkin_done, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipMemcpyAsync(att.data(), r->st.walkin_att, sizeof(int64_t) * nw, hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+        bool all = true, stuck = false;
+        for (int w = 0; w < nw; ++w) {
+            if (!done[w]) {
+                all = false;
+                if (att[w] >= max_attempts) stuck = true;
+            }
+        }
+        if (all) break;
+        if (stuck) return fail(REWL_EBUDGET, "walk-in exceeded its attempt budget");
+    }
+    r->walked_in = true;
+    return REWL_OK;
+}
+
+static int read_converged(rewl_t *r) {
+    int32_t conv = 0;
+    int64_t stop[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&conv, r->st.converged, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipMemcpyAsync(stop, r->st.stop, sizeof(stop), hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    if (conv) {
+        r->converged = true;
+        r->step = stop[0];
+        r->round = stop[1];
+    }
+    return REWL_OK;
+}
+
+int rewl_run_attempts(rewl_t *r, int64_t attempts) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    if (attempts < 0) return fail(REWL_EINVAL, "negative attempt count");
+    if (!r->walked_in) {
+        const int st = rewl_walkin(r, int64_t(1) << 40);
+        if (st != REWL_OK) return st;
+    }
+    if (r->converged) return REWL_CONVERGED;
+    r->joined = false;
+    const int64_t S = r->opts.sync_attempts;
+    int syncs_since_read = 0;
+    while (attempts > 0) {
+        int64_t seg = S - (r->step % S);
+        if (seg > attempts) seg = attempts;
+        hipEvent_t ev = nullptr;
+        HIP_TRY(timer_begin(r, &ev));
+        HIP_TRY(rewl_gpu::launch_sweep(r->st, r->step, seg, r->stream));
+        HIP_TRY(timer_end(r, 0, ev));
+        r->step += seg;
+        attempts -= seg;
+        if (r->step % S == 0) {
+            HIP_TRY(timer_begin(r, &ev));
+            HIP_TRY(rewl_gpu::launch_sync(r->st, r->step, r->stream));
+            if (r->opts.exchange) {
+                HIP_TRY(rewl_gpu::launch_exchange(r->st, (uint32_t)r->round, r->stream));
+                r->round += 1;
+            }
+            HIP_TRY(rewl_gpu::launch_check(r->st, r->step, r->round, r->stream));
+            HIP_TRY(timer_end(r, 1, ev));
+            if (!r->opts.fixed_lnf && ++syncs_since_read >= 64) {
+                syncs_since_read = 0;
+                const int st = read_converged(r);
+                if (st != REWL_OK) return st;
+                if (r->converged) return REWL_CONVERGED;
+            }
+        }
+    }
+    const int st = read_converged(r);
+    if (st != REWL_OK) return st;
+    return r->converged ? REWL_CONVERGED : REWL_OK;
+}
+
+int rewl_run(rewl_t *r, int64_t sweeps) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    if (sweeps < 0) return fail(REWL_EINVAL, "negative sweep count");
+    return rewl_run_attempts(r, sweeps * (int64_t)r->st.N);
+}
+
+int rewl_exchange(rewl_t *r) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    if (r->converged) return REWL_CONVERGED;
+    HIP_TRY(rewl_gpu::launch_exchange(r->st, (uint32_t)r->round, r->stream));
+    r->round += 1;
+    r->joined = false;
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return REWL_OK;
+}
+
+int rewl_get_progress(rewl_t *r, int64_t *step, int64_t *round, int32_t *converged) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    if (step) *step = r->step;
+    if (round) *round = r->round;
+    if (converged) *converged = r->converged ? 1 : 0;
+    return REWL_OK;
+}
+
+int rewl_get_walker(rewl_t *r, int w, int8_t *spins, int32_t *E, uint32_t *H, double *lng,
+                    uint32_t *replica, int64_t *walkin_attempts) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    const DevState &d = r->st;
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    const size_t row = (size_t)w * d.Wpad;
+    std::vector<float> hi, lo;
+    if (spins) HIP_TRY(hipMemcpyAsync(spins, d.spins + (size_t)w * d.Npad, d.N, hipMemcpyDeviceToHost, r->stream));
+    if (E) HIP_TRY(hipMemcpyAsync(E, d.E + w, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
+    if (H) HIP_TRY(hipMemcpyAsync(H, d.H + row, sizeof(uint32_t) * d.W, hipMemcpyDeviceToHost, r->stream));
+    if (lng && d.precision == 0)
+        HIP_TRY(hipMemcpyAsync(lng, d.lng + row, sizeof(double) * d.W, hipMemcpyDeviceToHost, r->stream));
+    if (lng && d.precision == 1) {
+        hi.resize(d.W); lo.resize(d.W);
+        HIP_TRY(hipMemcpyAsync(hi.data(), d.lng_hi + row, sizeof(float) * d.W, hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipMemcpyAsync(lo.data(), d.lng_lo + row, sizeof(float) * d.W, hipMemcpyDeviceToHost, r->stream));
+    }
+    if (replica) HIP_TRY(hipMemcpyAsync(replica, d.replica + w, sizeof(uint32_t), hipMemcpyDeviceToHost, r->stream));
+    if (walkin_attempts)
+        HIP_TRY(hipMemcpyAsync(walkin_attempts, d.walkin_att + w, sizeof(int64_t), hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    if (lng && d.precision == 1)
+        for (int b = 0; b < d.W; ++b) lng[b] = (double)hi[b] + (double)lo[b];
+    return REWL_OK;
+}
+
+int rewl_get_window(rewl_t *r, int k, double *lnf, double *lnf_last, int32_t *regime, int32_t *finished,
+                    int64_t *iterations, uint8_t *visited, uint64_t *x_att, uint64_t *x_acc) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    const DevState &d = r->st;
+    if (k < 0 || k >= d.h) return fail(REWL_EINVAL, "window index out of range");
+    int32_t fin = 0;
+    HIP_TRY(hipMemcpyAsync(&fin, d.finished + k, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
+    if (lnf) HIP_TRY(hipMemcpyAsync(lnf, d.lnf + k, sizeof(double), hipMemcpyDeviceToHost, r->stream));
+    if (lnf_last) HIP_TRY(hipMemcpyAsync(lnf_last, d.lnf_last + k, sizeof(double), hipMemcpyDeviceToHost, r->stream));
+    if (regime) HIP_TRY(hipMemcpyAsync(regime, d.regime + k, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
+    if (iterations) HIP_TRY(hipMemcpyAsync(iterations, d.iterations + k, sizeof(int64_t), hipMemcpyDeviceToHost, r->stream));
+    if (x_att) HIP_TRY(hipMemcpyAsync(x_att, d.x_att + k, sizeof(uint64_t), hipMemcpyDeviceToHost, r->stream));
+    if (x_acc) HIP_TRY(hipMemcpyAsync(x_acc, d.x_acc + k, sizeof(uint64_t), hipMemcpyDeviceToHost, r->stream));
+    std::vector<uint32_t> Hs;
+    if (visited) {
+        HIP_TRY(hipMemcpyAsync(visited, d.visited + (size_t)k * d.Wpad, d.W, hipMemcpyDeviceToHost, r->stream));
+        Hs.resize((size_t)d.m * d.Wpad);
+        HIP_TRY(hipMemcpyAsync(Hs.data(), d.H + (size_t)k * d.m * d.Wpad, sizeof(uint32_t) * Hs.size(),
+                               hipMemcpyDeviceToHost, r->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    if (finished) *finished = fin;
+    if (visited && !fin)
+        for (int j = 0; j < d.m; ++j)
+            for (int b = 0; b < d.W; ++b)
+                if (Hs[(size_t)j * d.Wpad + b]) visited[b] = 1;
+    return REWL_OK;
+}
+
+int rewl_set_lng(rewl_t *r, int w, const double *lng) {
+    if (!r || !lng) return fail(REWL_EINVAL, "null argument");
+    const DevState &d = r->st;
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    const size_t row = (size_t)w * d.Wpad;
+    if (d.precision == 0) {
+        HIP_TRY(hipMemcpyAsync(d.lng + row, lng, sizeof(double) * d.W, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    } else {
+        std::vector<float> hi(d.W), lo(d.W);
+        for (int b = 0; b < d.W; ++b) {
+            hi[b] = (float)lng[b];
+            lo[b] = (float)(lng[b] - (double)hi[b]);
+        }
+        HIP_TRY(hipMemcpyAsync(d.lng_hi + row, hi.data(), sizeof(float) * d.W, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipMemcpyAsync(d.lng_lo + row, lo.data(), sizeof(float) * d.W, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    }
+    r->joined = false;
+    return REWL_OK;
+}
+
+int rewl_join(rewl_t *r, double *host_out, int32_t *cuts) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    const DevState &d = r->st;
+    const double log_total = (double)d.N * std::log((double)d.q);
+    HIP_TRY(rewl_gpu::launch_join(d, log_total, r->stream));
+    int32_t status = 0;
+    HIP_TRY(hipMemcpyAsync(&status, d.join_status, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
+    if (host_out) HIP_TRY(hipMemcpyAsync(host_out, d.joined, sizeof(double) * d.B, hipMemcpyDeviceToHost, r->stream));
+    if (cuts && d.h > 1)
+        HIP_TRY(hipMemcpyAsync(cuts, d.cuts, sizeof(int32_t) * (d.h - 1), hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    if (status != 0) return fail(REWL_ESTATE, "two neighbouring windows share no visited energy");
+    r->joined = true;
+    return REWL_OK;
+}
+
+int rewl_get_lng(rewl_t *r, int k, double *host_out, int64_t cap, int64_t *n_out, int64_t *e_first_out) {
+    if (!r || !host_out) return fail(REWL_EINVAL, "null argument");
+    const DevState &d = r->st;
+    if (k == -1) {
+        if (cap < d.B) return fail(REWL_EINVAL, "output buffer too small");
+        const int st = rewl_join(r, host_out, nullptr);
+        if (n_out) *n_out = d.B;
+        if (e_first_out) *e_first_out = d.e_lo;
+        return st;
+    }
+    if (k < 0 || k >= d.h) return fail(REWL_EINVAL, "window index out of range");
+    if (cap < d.W) return fail(REWL_EINVAL, "output buffer too small");
+    std::vector<uint8_t> vis(d.W);
+    int st = rewl_get_window(r, k, nullptr, nullptr, nullptr, nullptr, nullptr, vis.data(), nullptr, nullptr);
+    if (st != REWL_OK) return st;
+    st = rewl_get_walker(r, k * d.m, nullptr, nullptr, nullptr, host_out, nullptr, nullptr);
+    if (st != REWL_OK) return st;
+    for (int b = 0; b < d.W; ++b)
+        if (!vis[b]) host_out[b] = -INFINITY;
+    if (n_out) *n_out = d.W;
+    if (e_first_out) *e_first_out = r->starts[k];
+    return REWL_OK;
+}
+
+int rewl_thermo(rewl_t *r, const double *T, int nT, double *lnZ, double *U, double *C) {
+    if (!r || !T) return fail(REWL_EINVAL, "null argument");
+    if (nT < 1 || nT > kMaxThermo) return fail(REWL_EINVAL, "nT must be in [1, 4096]");
+    if (!r->joined) return fail(REWL_ESTATE, "rewl_thermo needs a current rewl_join");
+    for (int i = 0; i < nT; ++i)
+        if (!(T[i] > 0.0)) return fail(REWL_EINVAL, "temperatures must be positive");
+    const DevState &d = r->st;
+    double *dT = (double *)(r->ws + r->lay.T);
+    double *dout = (double *)(r->ws + r->lay.thermo_out);
+    std::vector<double> out(3 * (size_t)nT);
+    HIP_TRY(hipMemcpyAsync(dT, T, sizeof(double) * nT, hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(rewl_gpu::launch_thermo(d, dT, nT, dout, r->stream));
+    HIP_TRY(hipMemcpyAsync(out.data(), dout, sizeof(double) * 3 * nT, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    for (int i = 0; i < nT; ++i) {
+        if (lnZ) lnZ[i] = out[3 * i + 0];
+        if (U) U[i] = out[3 * i + 1];
+        if (C) C[i] = out[3 * i + 2];
+    }
+    return REWL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""The C ABI of librewl on the CPU: the library loads, exports every function
+include/rewl.h declares, and its host-side logic (window layout, option
+defaults, workspace sizing, argument validation) behaves as documented.
+No GPU work is issued here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1312_3004_amd as pk
+from paper_1312_3004_amd import build as pkbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rewl.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pk.LIB_PATH):
+        pkbuild.build()
+    return pk.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rewl_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for need in ("rewl_create", "rewl_run", "rewl_exchange", "rewl_get_lng", "rewl_join", "rewl_thermo",
+                 "rewl_walkin", "rewl_destroy", "rewl_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_default_opts(lib):
+    o = pk.default_opts()
+    assert (o.seed, o.flat_num, o.flat_den, o.lnf_init, o.lnf_final) == (1, 4, 5, 1.0, 1e-6)
+    assert (o.schedule, o.exchange, o.sync_attempts, o.precision, o.fixed_lnf) == (0, 1, 1000, 0, 0)
+    assert ctypes.sizeof(pk.Opts) == 64
+
+
+@pytest.mark.parametrize("L,h,o", [(3, 1, 0.5), (4, 2, 0.75), (8, 4, 0.75), (32, 16, 0.75), (80, 64, 0.75),
+                                   (16, 8, 0.75), (24, 8, 0.75), (48, 8, 0.75), (10, 7, 0.6), (300, 717, 0.75)])
+def test_window_layout_matches_oracle(lib, L, h, o):
+    W, starts = pk.window_layout(L, h, o)
+    Wo, so = oracle.window_layout(2 * L * L + 1, h, o, -2 * L * L)
+    assert W == Wo and np.array_equal(starts, so)
+
+
+def test_workspace_and_validation(lib):
+    o = pk.make_opts()
+    assert pk.workspace_bytes(32, 10, 16, 0.75, 4, o) > 64 * 1024
+    assert pk.workspace_bytes(2, 10, 1, 0.75, 1, o) == 0          # L < 3
+    assert pk.workspace_bytes(8, 1, 4, 0.75, 1, o) == 0           # q < 2
+    assert pk.workspace_bytes(8, 10, 4, 1.0, 1, o) == 0           # overlap >= 1
+    assert pk.workspace_bytes(8, 10, 4, 0.75, 0, o) == 0          # no walkers
+    assert pk.workspace_bytes(200, 10, 4, 0.75, 1, o) == 0        # walk-in ln g exceeds LDS
+    bad = pk.make_opts(flat=(6, 5))
+    assert pk.workspace_bytes(8, 10, 4, 0.75, 1, bad) == 0
+    h = ctypes.c_void_p()
+    st = lib.rewl_create(ctypes.byref(h), 0, 8, 10, 4, 0.75, 1, ctypes.byref(o), None, None, 0, None)
+    assert st == pk.EINVAL and b"init_spins" in lib.rewl_last_error()
+    spins = np.zeros(4 * 64, np.int8)
+    st = lib.rewl_create(ctypes.byref(h), 0, 8, 10, 4, 0.75, 1, ctypes.byref(o),
+                         spins.ctypes.data_as(ctypes.c_void_p), None, 0, None)
+    assert st == pk.EINVAL and b"workspace" in lib.rewl_last_error()
+    spins[3] = 10
+    st = lib.rewl_create(ctypes.byref(h), 0, 8, 10, 4, 0.75, 1, ctypes.byref(o),
+                         spins.ctypes.data_as(ctypes.c_void_p), None, 0, None)
+    assert st == pk.EINVAL and b"spin value" in lib.rewl_last_error()
+
+
+def test_binding_raises_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(pk, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pk, "_lib", None)
+    with pytest.raises(ImportError):
+        pk.lib()

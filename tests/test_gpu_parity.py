@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer state (lattices, energies, histograms, replica ids, counters, joining
+energies) must be identical.  ln g must be identical bit for bit: both sides
+evaluate the same sequence of separately rounded IEEE operations.  Only the
+log-sum-exp normalisation and the thermodynamic sums (different summation
+order, library exp/log) carry a tolerance.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    import paper_1312_3004_amd as pk
+    return pk
+
+
+def make_pair(L, q, h, m, overlap=0.75, spins_seed=1, threads=8, **opts):
+    spins = workloads.init_spins(L, q, h * m, spins_seed)
+    print(f"[case] L={L} q={q} h={h} m={m} opts={opts}", flush=True)
+    sys.stdout.flush()
+    g = _pk().Rewl(L, q, h, overlap, m, spins, **opts)
+    o = oracle.Rewl(L, q, h, overlap, m, spins, threads=threads, **opts)
+    return g, o
+
+
+def assert_same_state(g, o):
+    assert g.step == o.step and g.round == o.round
+    for w in range(g.nw):
+        a, b = g.walker(w), o.walker(w)
+        assert np.array_equal(a["spins"], b["spins"]), f"spins of walker {w}"
+        assert a["E"] == b["E"], f"E of walker {w}"
+        assert np.array_equal(a["H"], b["H"]), f"H of walker {w}"
+        assert np.array_equal(a["lng"].view(np.uint64), b["lng"].view(np.uint64)), f"ln g of walker {w}"
+        assert a["replica"] == b["replica"], f"replica of walker {w}"
+        assert a["walkin_attempts"] == b["walkin_attempts"], f"walk-in of walker {w}"
+    for k in range(g.h):
+        a, b = g.window(k), o.window(k)
+        for key in ("lnf", "lnf_last", "regime", "finished", "iterations", "x_att", "x_acc"):
+            assert a[key] == b[key], (k, key, a[key], b[key])
+        assert np.array_equal(a["visited"], b["visited"]), f"visited of window {k}"
+
+
+FIXED_CASES = [
+    # (L, q, h, m, attempts, precision)
+    (3, 3, 2, 2, 20011, 0),
+    (4, 2, 3, 2, 30000, 0),
+    (8, 10, 4, 1, 64123, 0),
+    (8, 10, 4, 3, 50000, 1),
+    (32, 10, 16, 4, 40000, 0),
+    (32, 10, 16, 4, 40000, 1),
+    (13, 5, 5, 3, 25000, 0),
+]
+
+
+@pytest.mark.parametrize("L,q,h,m,attempts,precision", FIXED_CASES)
+def test_fixed_lnf_trajectories_bitexact(L, q, h, m, attempts, precision):
+    g, o = make_pair(L, q, h, m, lnf_init=0.05, fixed_lnf=1, sync_attempts=997, exchange=1,
+                     precision=precision, seed=5)
+    g.run(attempts)
+    o.run(attempts)
+    assert_same_state(g, o)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_protocol_L8_bitexact_to_convergence(precision):
+    c = workloads.CONFIGS["potts_q10_L8"]
+    g, o = make_pair(c["L"], c["q"], c["windows"], c["walkers"], seed=c["seed"], flat=c["flat"],
+                     lnf_init=c["lnf_init"], lnf_final=c["lnf_final"], schedule=c["schedule"],
+                     sync_attempts=c["sync_attempts"], exchange=c["exchange"], precision=precision)
+    assert g.run(10**10) == _pk().CONVERGED
+    assert o.run(10**10) == oracle.CONVERGED
+    assert_same_state(g, o)
+    sg, lg, cg = g.join()
+    so, lo, co = o.join()
+    assert sg == so == 0
+    assert np.array_equal(cg, co)
+    fin = np.isfinite(lo)
+    assert np.array_equal(np.isfinite(lg), fin)
+    assert np.max(np.abs(lg[fin] - lo[fin])) <= 1e-10
+    T = np.linspace(0.5, 1.0, 201)
+    zg, ug, cvg = g.thermo(T)
+    zo, uo, cvo = oracle.thermo(lo, -128, T)
+    np.testing.assert_allclose(zg, zo, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(ug, uo, rtol=1e-9, atol=1e-8)
+    np.testing.assert_allclose(cvg, cvo, rtol=1e-8, atol=1e-8)
+
+
+def test_full_protocol_L32_segment_bitexact():
+    # The benchmark workload (L=32, 16 windows x 4 walkers, 1/t schedule),
+    # element by element after walk-in and 3 x 10^5 attempts per walker.
+    c = workloads.CONFIGS["potts_q10_L32"]
+    g, o = make_pair(c["L"], c["q"], c["windows"], c["walkers"], seed=c["seed"], flat=c["flat"],
+                     lnf_init=c["lnf_init"], lnf_final=c["lnf_final"], schedule=c["schedule"],
+                     sync_attempts=c["sync_attempts"], exchange=c["exchange"])
+    for n in (123_457, 76_543, 100_000):
+        g.run(n)
+        o.run(n)
+    assert_same_state(g, o)
+
+
+def test_split_runs_equal_one_run():
+    args = dict(lnf_init=1.0, lnf_final=1e-3, sync_attempts=700, seed=3)
+    spins = workloads.init_spins(6, 4, 6, 2)
+    a = _pk().Rewl(6, 4, 3, 0.75, 2, spins, **args)
+    b = _pk().Rewl(6, 4, 3, 0.75, 2, spins, **args)
+    a.run(20_000)
+    for n in (1, 63, 64, 65, 699, 700, 701, 17_707):
+        b.run(n)
+    assert a.step == b.step == 20_000
+    for w in range(6):
+        da, db = a.walker(w), b.walker(w)
+        assert np.array_equal(da["spins"], db["spins"]) and da["E"] == db["E"]
+        assert np.array_equal(da["lng"], db["lng"]) and np.array_equal(da["H"], db["H"])
+
+
+def test_manual_exchange_rounds():
+    g, o = make_pair(8, 3, 5, 2, lnf_init=0.02, fixed_lnf=1, exchange=0, sync_attempts=500, seed=8)
+    for _ in range(7):
+        g.run(333)
+        o.run(333)
+        g.exchange()
+        o.exchange()
+    assert_same_state(g, o)
+
+
+def test_converged_dos_matches_enumeration_on_gpu():
+    L, q, h, m = 4, 2, 2, 4
+    g, o = make_pair(L, q, h, m, seed=3, lnf_final=1e-6, schedule=1, sync_attempts=20000, spins_seed=3)
+    assert g.run(10**10) == _pk().CONVERGED
+    st, lng, _ = g.join()
+    gex = bruteforce.potts_dos(L, q)
+    ex = np.full(gex.size, -np.inf)
+    ex[gex > 0] = np.log(gex[gex > 0].astype(float))
+    reach = np.isfinite(ex)
+    assert st == 0 and np.array_equal(np.isfinite(lng), reach)
+    assert np.max(np.abs(lng[reach] - ex[reach])) <= 0.02
+    assert o.run(10**10) == oracle.CONVERGED
+    assert_same_state(g, o)
+
+
+@pytest.mark.parametrize("L,q,h,m", [(3, 127, 1, 1), (3, 2, 1, 7), (5, 3, 1, 64), (128, 2, 8, 1)])
+def test_edge_shapes(L, q, h, m):
+    g, o = make_pair(L, q, h, m, lnf_init=0.5, lnf_final=1e-2, sync_attempts=300, seed=2)
+    n = 3000 if L < 100 else 1000
+    g.run(n)
+    o.run(n)
+    assert_same_state(g, o)
+
+
+def test_fixed_exact_weights_and_set_lng():
+    L, q = 4, 2
+    gex = bruteforce.potts_dos(L, q)
+    lng = np.where(gex > 0, np.log(np.maximum(gex, 1).astype(float)), 0.0)
+    g, o = make_pair(L, q, 1, 1, lnf_init=0.0, fixed_lnf=1, sync_attempts=10**6, seed=9, spins_seed=5)
+    g.set_lng(0, lng)
+    o.set_lng(0, lng)
+    g.run(500_000)
+    o.run(500_000)
+    assert_same_state(g, o)
+    H = g.walker(0)["H"].astype(float)
+    reach = gex > 0
+    assert np.max(np.abs(H[reach] / H[reach].mean() - 1)) < 0.1
+
+
+def test_walkin_budget_error_on_gpu():
+    spins = np.zeros((4, 64), np.int8)
+    g = _pk().Rewl(8, 10, 4, 0.75, 1, spins, seed=1)
+    with pytest.raises(_pk().RewlError):
+        g.walkin(budget=3)
