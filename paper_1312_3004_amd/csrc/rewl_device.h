@@ -19,6 +19,7 @@ constexpr uint32_t kDomExch = 3;    // exchange permutation and acceptance words
 struct DevState {
     int L, q, N, h, m, nw, W, B, e_lo;
     int Npad, Wpad, Bpad;        // row strides (elements)
+    int Ntag;                    // entries of the LDS conflict-tag table (power of two)
     uint32_t key0, key1, ctr3;   // Philox key and instance bits of counter word 3
     uint32_t flat_num, flat_den;
     double lnf_final;

@@ -18,6 +18,9 @@ namespace rewl_gpu {
 
 namespace {
 
+// v_writelane_b32: lane `lane` of `old` takes the uniform value `v`.
+extern "C" __device__ int writelane_i32(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 __device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ double rfl(double x) {
     const uint64_t b = (uint64_t)__double_as_longlong(x);
@@ -158,90 +161,379 @@ __global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64
 // reject it if the new energy leaves the window, else accept with
 // min[1, g(E_old)/g(E_new)]; then ln g(E) += ln f and H(E) += 1 at the
 // energy after the decision.
+//
+// The attempts of one walker are a strict sequence.  The kernel processes
+// them in blocks of 64 with a lane-parallel phase and a serial phase that
+// reproduces the sequential result exactly:
+//  * lanes draw the 64 proposals and compute their energy changes from the
+//    lattice at block start.  A proposal whose site or neighbours were hit by
+//    an earlier proposal of the same block carries a conflict mask (built by
+//    OR-ing lane bits into an LDS tag table); if any of those earlier
+//    proposals was accepted, its energy change is recomputed from LDS;
+//  * lanes compute ln u of their uniform word; u < exp(d) is then settled by
+//    comparing d with ln u up to a margin that covers the error of exp_neg
+//    and log; attempts inside the margin evaluate exp_neg exactly, as the
+//    sequential rule does;
+//  * ln g of 64 consecutive energies around the walker sit in VGPRs (lane b
+//    holds energy ebase + b; energies outside the window hold +inf, which
+//    makes any move there a certain reject).
+// Two serial modes:
+//  * exact mode (large ln f): the current ln g is carried through every
+//    attempt and compared with the cached ln g of the proposed energy;
+//  * table mode (ln f <= kTableMaxLnf, i.e. nearly all of a run): ln g is
+//    frozen at its block-start values during the block.  For every attempt
+//    the lanes (one per candidate energy e) compare d(e) = ln g(e) -
+//    ln g(e + dE) with ln u; one compare yields a 64-bit accept mask and a
+//    "decided" mask, and the serial step is a bit test on the walker's
+//    energy.  The margin also covers the drift of ln g within a block (at
+//    most 64 ln f) and the binary32 rounding of d, so every decided bit
+//    equals the sequential decision; undecided attempts rebuild the exact
+//    current ln g (block-start value plus the same sequence of ln f
+//    additions) and apply the exact rule.  At block end every bin receives
+//    its ln f additions in sequence, the result the sequential walk leaves.
+// H(E) increments and accepted spins are applied to LDS once per block (no
+// two pending spin writes share a site: a repeat hit is a conflict and is
+// written at once).
+constexpr double kMargin64 = 1e-10;   // log-domain slack of the exact-mode test (binary64)
+constexpr double kMargin32 = 1e-5;    // log-domain slack of the exact-mode test (binary32)
+constexpr double kTableMaxLnf = 2e-4; // table mode when ln f is at most this
+constexpr double kTableDmax = 64.0;   // table entries with |d| above this are left undecided
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, j);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double readlane_d(double v, int j) {
+    return __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), j));
+}
+__device__ __forceinline__ float readlane_f(float v, int j) {
+    return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), j));
+}
+// binary32 rounding of a finite x towards +inf / -inf (one ulp step when
+// round-to-nearest went the wrong way)
+__device__ __forceinline__ float f32_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) {
+        uint32_t b = __float_as_uint(f);
+        if (f == 0.0f) b = 1u;
+        else if (f > 0.0f) b += 1u;
+        else b -= 1u;
+        f = __uint_as_float(b);
+    }
+    return f;
+}
+__device__ __forceinline__ float f32_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) {
+        uint32_t b = __float_as_uint(f);
+        if (f == 0.0f) b = 0x80000001u;
+        else if (f > 0.0f) b -= 1u;
+        else b += 1u;
+        f = __uint_as_float(b);
+    }
+    return f;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n) {
+#pragma clang fp contract(off)
     if (*st.converged) return;
     const int w = blockIdx.x;
     const int lane = threadIdx.x;
     const int k = w / st.m;
     extern __shared__ __align__(16) unsigned char smem[];
-    int8_t *sp = (int8_t *)smem;
     const int W = st.W, Wpad = st.Wpad;
+    int8_t *sp = (int8_t *)smem;
     double *g = (double *)(smem + st.Npad);
     float *gh = (float *)(smem + st.Npad);
     float *gl = gh + Wpad;
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
+    unsigned long long *tag = (unsigned long long *)(smem + st.Npad + (size_t)Wpad * 12);
+    uint32_t *cnt = (uint32_t *)(tag + st.Ntag);
+    const uint32_t tag_mask = (uint32_t)st.Ntag - 1u;
 
     const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)sp)[i] = gsp[i];
     const size_t row = (size_t)w * Wpad;
+    double gmax = 0.0;
     for (int b = lane; b < W; b += 64) {
         if (PREC == 0) {
             g[b] = st.lng[row + b];
+            gmax = fmax(gmax, fabs(g[b]));
         } else {
             gh[b] = st.lng_hi[row + b];
             gl[b] = st.lng_lo[row + b];
+            gmax = fmax(gmax, fabs((double)gh[b]) + fabs((double)gl[b]));
         }
         H[b] = st.H[row + b];
     }
+    for (int i = lane; i < st.Ntag; i += 64) tag[i] = 0ull;
+    cnt[lane] = 0u;
     __syncthreads();
 
     const int lo = st.start[k], hi = lo + W - 1;
     const int q = st.q;
     const double lnf = st.lnf[k];
-    if (st.E[w] < lo || st.E[w] > hi) return;  // not walked in: leave the walker untouched
     const float lnf32 = (float)lnf;
     int E = st.E[w];
-    // ln g at the current energy, kept in registers (identical in all lanes)
-    double gE = 0.0;
+    if (E < lo || E > hi) return;  // not walked in: leave the walker untouched
+
+    // Table-mode margin: exp/log error and binary32 rounding of d (2e-5),
+    // drift of ln g within a block (64 ln f), and the rounding of up to 64
+    // additions on values bounded by gmax + n ln f.
+    for (int o = 32; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o));
+    const bool tbl = lnf <= kTableMaxLnf;
+    const double margin = 2e-5 + 64.5 * lnf + 0x1p-44 * (gmax + (double)n * lnf + 1.0);
+
+    // ln g cache: lane b holds energy ebase + b (+inf outside the window)
+    int ebase = E - 32;
+    double c64 = 0.0;
+    float ch = 0.0f, cl = 0.0f;
+    auto cache_load = [&]() {
+        const int b = ebase + lane - lo;
+        const bool in = b >= 0 && b < W;
+        if (PREC == 0) c64 = in ? g[b] : __builtin_inf();
+        else { ch = in ? gh[b] : __builtin_inff(); cl = in ? gl[b] : 0.0f; }
+    };
+    auto cache_store = [&]() {
+        const int b = ebase + lane - lo;
+        if (b >= 0 && b < W) {
+            if (PREC == 0) g[b] = c64;
+            else { gh[b] = ch; gl[b] = cl; }
+        }
+    };
+    cache_load();
+    int erel = 32;  // E - ebase
+    // ln f as a VGPR operand: the per-attempt add then reads one SGPR pair (ln g)
+    double lnf_v = lnf;
+    asm volatile("" : "+v"(lnf_v));
+    double gEv = 0.0, gEs = 0.0;
     float gEh = 0.0f, gEl = 0.0f;
-    if (PREC == 0) gE = rfl(g[E - lo]);
-    else { gEh = rfl(gh[E - lo]); gEl = rfl(gl[E - lo]); }
 
     for (int64_t base = 0; base < n; base += 64) {
-        const Proposal p = propose(st, kDomMove, (uint64_t)(s0 + base + lane), (uint32_t)w);
         const int todo = (int)((n - base) < 64 ? (n - base) : 64);
-        for (int j = 0; j < todo; ++j) {
-            const int site = __builtin_amdgcn_readlane(p.site, j);
-            const int off = __builtin_amdgcn_readlane(p.off, j);
-            const uint32_t u = __builtin_amdgcn_readlane(p.u, j);
-            const int n0 = __builtin_amdgcn_readlane(p.nb0, j);
-            const int n1 = __builtin_amdgcn_readlane(p.nb1, j);
-            const int n2 = __builtin_amdgcn_readlane(p.nb2, j);
-            const int n3 = __builtin_amdgcn_readlane(p.nb3, j);
-            const int sc = rfl((int)sp[site]);
-            int nv = sc + 1 + off;
-            if (nv >= q) nv -= q;
-            const int En = E + rfl(delta_e(sp, sc, nv, n0, n1, n2, n3));
+        const bool live = lane < todo;
+        if ((unsigned)(erel - 16) >= 32u) {   // keep the walker near the cache centre
+            cache_store();
+            ebase += erel - 32;
+            erel = 32;
+            cache_load();
+        }
+        if (!tbl) {   // exact mode carries the current ln g in registers
+            if (PREC == 0) { gEs = readlane_d(c64, erel); gEv = gEs; }
+            else { gEh = readlane_f(ch, erel); gEl = readlane_f(cl, erel); }
+        }
+        // ---- lane-parallel phase: proposal, energy change, conflicts, ln u
+        const Proposal p = propose(st, kDomMove, (uint64_t)(s0 + base + lane), (uint32_t)w);
+        const int sc = sp[p.site];
+        int nv = sc + 1 + p.off;
+        if (nv >= q) nv -= q;
+        const int dE = delta_e(sp, sc, nv, p.nb0, p.nb1, p.nb2, p.nb3);
+        const uint32_t ti = (uint32_t)p.site & tag_mask;
+        if (live) atomicOr(&tag[ti], 1ull << lane);
+        const unsigned long long hits = tag[ti] | tag[(uint32_t)p.nb0 & tag_mask] |
+                                        tag[(uint32_t)p.nb1 & tag_mask] |
+                                        tag[(uint32_t)p.nb2 & tag_mask] |
+                                        tag[(uint32_t)p.nb3 & tag_mask];
+        const unsigned long long conf = hits & ((1ull << lane) - 1ull);
+        if (live) tag[ti] = 0ull;
+        const unsigned long long anyconf = __ballot(conf != 0ull);
+        double lnu;
+        if (PREC == 0) lnu = p.u == 0u ? -64.0 : log((double)p.u * 0x1p-32);
+        else lnu = (p.u >> 8) == 0u ? -64.0 : log((double)(p.u >> 8) * 0x1p-24);
+
+        unsigned long long accepted = 0ull, flushed = 0ull;
+        int hist = 0;
+
+        // Exact decision of attempt j from the exact current ln g of the walker's
+        // energy and of the proposed one (table mode: rebuilt by replaying this
+        // block's ln f additions).  Also handles conflicts.  Returns acceptance
+        // and writes dE actually used.
+        auto slow_attempt = [&](int j, bool table_values) -> void {
+            int dEj = __builtin_amdgcn_readlane(dE, j);
+            bool now = false;
+            int nvj = 0;
+            if (((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
+                if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
+                flushed = accepted;
+                const int site = __builtin_amdgcn_readlane(p.site, j);
+                const int scj = rfl((int)sp[site]);
+                nvj = scj + 1 + __builtin_amdgcn_readlane(p.off, j);
+                if (nvj >= q) nvj -= q;
+                dEj = rfl(delta_e(sp, scj, nvj, __builtin_amdgcn_readlane(p.nb0, j),
+                                  __builtin_amdgcn_readlane(p.nb1, j),
+                                  __builtin_amdgcn_readlane(p.nb2, j),
+                                  __builtin_amdgcn_readlane(p.nb3, j)));
+                now = true;
+            }
+            const int Ecur = ebase + erel, En = Ecur + dEj;
+            bool acc = false;
             if (En >= lo && En <= hi) {
-                if (PREC == 0) {
-                    const double gN = rfl(g[En - lo]);
-                    if (accept64(gE - gN, u)) {
-                        if (lane == 0) sp[site] = (int8_t)nv;
-                        E = En;
-                        gE = gN;
+                const uint32_t u = __builtin_amdgcn_readlane(p.u, j);
+                if (table_values) {
+                    // exact current values: block-start value + this block's additions
+                    const unsigned long long before = (1ull << j) - 1ull;
+                    const int n_cur = __builtin_popcountll(__ballot(hist == Ecur) & before);
+                    const int n_new = __builtin_popcountll(__ballot(hist == En) & before);
+                    const int rc = Ecur - ebase, rn = En - ebase;
+                    if (PREC == 0) {
+                        double vc = (unsigned)rc < 64u ? readlane_d(c64, rc) : g[Ecur - lo];
+                        double vn = (unsigned)rn < 64u ? readlane_d(c64, rn) : g[En - lo];
+                        vc = rfl(vc);
+                        vn = rfl(vn);
+                        for (int i = 0; i < n_cur; ++i) vc = vc + lnf;
+                        for (int i = 0; i < n_new; ++i) vn = vn + lnf;
+                        acc = __ballot(accept64(vc - vn, u)) != 0ull;
+                    } else {
+                        float hc = (unsigned)rc < 64u ? readlane_f(ch, rc) : gh[Ecur - lo];
+                        float lc = (unsigned)rc < 64u ? readlane_f(cl, rc) : gl[Ecur - lo];
+                        float hn = (unsigned)rn < 64u ? readlane_f(ch, rn) : gh[En - lo];
+                        float ln_ = (unsigned)rn < 64u ? readlane_f(cl, rn) : gl[En - lo];
+                        hc = rfl(hc); lc = rfl(lc); hn = rfl(hn); ln_ = rfl(ln_);
+                        for (int i = 0; i < n_cur; ++i) two_sum_add(hc, lc, lnf32);
+                        for (int i = 0; i < n_new; ++i) two_sum_add(hn, ln_, lnf32);
+                        acc = __ballot(accept32((hc - hn) + (lc - ln_), u)) != 0ull;
                     }
                 } else {
-                    const float gNh = rfl(gh[En - lo]);
-                    const float gNl = rfl(gl[En - lo]);
-                    if (accept32((gEh - gNh) + (gEl - gNl), u)) {
-                        if (lane == 0) sp[site] = (int8_t)nv;
-                        E = En;
-                        gEh = gNh;
-                        gEl = gNl;
+                    int idx = erel + dEj;
+                    if ((unsigned)idx >= 64u) {
+                        cache_store();
+                        ebase += idx - 32;
+                        cache_load();
+                        erel = erel - idx + 32;
+                        idx = 32;
+                    }
+                    const double luj = readlane_d(lnu, j);
+                    if (PREC == 0) {
+                        const double gN = readlane_d(c64, idx);
+                        const double d = gEv - gN;
+                        const double t = d - luj;
+                        if (__ballot(fabs(t) > kMargin64) != 0ull) acc = __ballot(t > 0.0) != 0ull;
+                        else acc = __ballot(accept64(d, u)) != 0ull;
+                        gEs = acc ? gN : gEs;
+                    } else {
+                        const float gNh = readlane_f(ch, idx);
+                        const float gNl = readlane_f(cl, idx);
+                        const float d = (gEh - gNh) + (gEl - gNl);
+                        const double t = (double)d - luj;
+                        if (__ballot(fabs(t) > kMargin32) != 0ull) acc = __ballot(t > 0.0) != 0ull;
+                        else acc = __ballot(accept32(d, u)) != 0ull;
+                        gEh = acc ? gNh : gEh;
+                        gEl = acc ? gNl : gEl;
                     }
                 }
             }
-            const int b = E - lo;
-            if (PREC == 0) {
-                gE = gE + lnf;
-                if (lane == 0) { g[b] = gE; H[b] += 1u; }
-            } else {
-                two_sum_add(gEh, gEl, lnf32);
-                if (lane == 0) { gh[b] = gEh; gl[b] = gEl; H[b] += 1u; }
+            erel = acc ? En - ebase : erel;
+            accepted |= acc ? (1ull << j) : 0ull;
+            if (acc && now) {
+                if (lane == 0) sp[__builtin_amdgcn_readlane(p.site, j)] = (int8_t)nvj;
+                flushed |= 1ull << j;
+            }
+            if (!table_values) {
+                if (PREC == 0) {
+                    gEv = gEs + lnf_v;
+                    gEs = rfl(gEv);
+                    c64 = (lane == erel) ? gEv : c64;
+                } else {
+                    two_sum_add(gEh, gEl, lnf32);
+                    gEh = rfl(gEh);
+                    gEl = rfl(gEl);
+                    ch = (lane == erel) ? gEh : ch;
+                    cl = (lane == erel) ? gEl : cl;
+                }
+            }
+            hist = writelane_i32(ebase + erel, j, hist);
+        };
+
+        if (tbl) {
+            // ---- table mode.  Lane e: d_k(e) = ln g(ebase+e) - ln g(ebase+e+k-4)
+            // at block start (binary32; NaN = undecided), and per attempt lane j
+            // the thresholds ln u -+ margin rounded outwards.
+            f16v dtab;
+            double cself;
+            if (PREC == 0) cself = c64;
+            else cself = (double)ch + (double)cl;
+#pragma unroll
+            for (int kk = 0; kk < 9; ++kk) {
+                const int src = lane + kk - 4;
+                const double other = __shfl(cself, src & 63);
+                const double d = cself - other;
+                float v = __builtin_nanf("");
+                if (src >= 0 && src < 64) {
+                    if (fabs(d) <= kTableDmax) v = (float)d;
+                    else if (d == -__builtin_inf()) v = -__builtin_inff();
+                }
+                dtab[kk] = v;
+            }
+            const float th_hi = f32_up(lnu + margin);
+            const float th_lo = f32_down(lnu - margin);
+            bool outside = false;   // walker left the cached range in this block
+            int j = 0;
+            while (j < todo) {
+                const unsigned long long later = anyconf & (~0ull << j);
+                const int jstop = later ? min(todo, (int)__builtin_ctzll(later)) : todo;
+                if (!outside) {
+                    for (; j < jstop; ++j) {
+                        const int dEj = __builtin_amdgcn_readlane(dE, j);
+                        const float dsel = dtab[dEj + 4];
+                        const unsigned long long accm = __ballot(dsel > readlane_f(th_hi, j));
+                        const unsigned long long okm = __ballot(dsel < readlane_f(th_lo, j)) | accm;
+                        if (!((okm >> erel) & 1ull)) break;
+                        const bool acc = (accm >> erel) & 1ull;
+                        accepted |= acc ? (1ull << j) : 0ull;
+                        erel = acc ? erel + dEj : erel;
+                        hist = writelane_i32(ebase + erel, j, hist);
+                    }
+                }
+                if (j >= todo) break;
+                slow_attempt(j, true);
+                outside = outside || (unsigned)erel >= 64u;
+                ++j;
+            }
+        } else {
+            // ---- exact mode
+            for (int j = 0; j < todo; ++j) slow_attempt(j, false);
+        }
+
+        if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
+        if (live) atomicAdd(&H[hist - lo], 1u);
+        if (tbl) {
+            // replay this block's ln f additions, bin by bin
+            const int rb = hist - ebase;
+            const bool incache = (unsigned)rb < 64u;
+            if (live && incache) atomicAdd(&cnt[rb], 1u);
+            unsigned long long far = __ballot(live && !incache);
+            while (far) {      // visits outside the cached range (rare): LDS values
+                const int jj = (int)__builtin_ctzll(far);
+                far &= far - 1ull;
+                const int b = __builtin_amdgcn_readlane(hist, jj) - lo;
+                if (lane == 0) {
+                    if (PREC == 0) g[b] = g[b] + lnf;
+                    else { float a = gh[b], c = gl[b]; two_sum_add(a, c, lnf32); gh[b] = a; gl[b] = c; }
+                }
+            }
+            int nvis = (int)cnt[lane];
+            cnt[lane] = 0u;
+            while (__ballot(nvis > 0) != 0ull) {
+                if (nvis > 0) {
+                    if (PREC == 0) c64 = c64 + lnf;
+                    else two_sum_add(ch, cl, lnf32);
+                    --nvis;
+                }
+            }
+            if ((unsigned)erel >= 64u) {   // walker left the cached range: recentre
+                cache_store();
+                ebase += erel - 32;
+                erel = 32;
+                cache_load();
             }
         }
     }
+    cache_store();
+    E = ebase + erel;
     __syncthreads();
     uint32_t *osp = (uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = lane; i < st.Npad / 4; i += 64) osp[i] = ((uint32_t *)sp)[i];
@@ -699,7 +991,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
 // Launchers.
 
 size_t sweep_lds_bytes(const DevState &st) {
-    return (size_t)st.Npad + (size_t)st.Wpad * 8 + (size_t)st.Wpad * 4;
+    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)st.Ntag * 8 + 64 * 4;
 }
 
 static size_t walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }

@@ -39,8 +39,18 @@ constexpr int64_t kWalkinChunk = int64_t(1) << 20;
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Params {
-    int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad;
+    int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad, Ntag;
 };
+
+// Conflict-tag table of the attempt kernel: one 64-bit lane mask per site
+// (exact) up to 4096 sites, hashed by site mod the table size beyond or when
+// the LDS left after lattice and window state is smaller (a hash collision
+// only sends an attempt down the exact recomputation path).
+int tag_entries(int N, size_t lds_free) {
+    int t = 64;
+    while (t < N && t < 4096 && (size_t)t * 16 <= lds_free) t *= 2;
+    return t;
+}
 
 struct Layout {
     size_t start, spins, E, lng, lng_hi, lng_lo, H, replica, walkin_att, walkin_done, walkin_cnt,
@@ -129,7 +139,9 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     p->Npad = (int)round_up((size_t)p->N, kAlign);
     p->Wpad = (int)round_up((size_t)W, 64);
     p->Bpad = (int)round_up((size_t)p->B, 64);
-    if ((size_t)p->Npad + (size_t)p->Wpad * 12 > (size_t)kMaxLds)
+    const size_t lds_state = (size_t)p->Npad + (size_t)p->Wpad * 12 + 64 * 4;
+    p->Ntag = tag_entries(p->N, lds_state < (size_t)kMaxLds ? (size_t)kMaxLds - lds_state : 0);
+    if (lds_state + (size_t)p->Ntag * 8 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "lattice plus window state exceed the 160 KiB LDS of a CU");
     if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "walk-in ln g over all energies exceeds the 160 KiB LDS (L too large)");
@@ -289,7 +301,7 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     DevState &d = r->st;
     std::memset(&d, 0, sizeof(d));
     d.L = p.L; d.q = p.q; d.N = p.N; d.h = p.h; d.m = p.m; d.nw = p.nw; d.W = p.W; d.B = p.B;
-    d.e_lo = p.e_lo; d.Npad = p.Npad; d.Wpad = p.Wpad; d.Bpad = p.Bpad;
+    d.e_lo = p.e_lo; d.Npad = p.Npad; d.Wpad = p.Wpad; d.Bpad = p.Bpad; d.Ntag = p.Ntag;
     d.key0 = (uint32_t)op.seed; d.key1 = (uint32_t)(op.seed >> 32);
     d.ctr3 = op.instance & 0xFFFFFFu;
     d.flat_num = op.flat_num; d.flat_den = op.flat_den;

@@ -176,3 +176,39 @@ def test_walkin_budget_error_on_gpu():
     g = _pk().Rewl(8, 10, 4, 0.75, 1, spins, seed=1)
     with pytest.raises(_pk().RewlError):
         g.walkin(budget=3)
+
+
+TABLE_CASES = [
+    # (L, q, h, m, attempts, precision, lnf): ln f small enough for the
+    # block-table decision path of the attempt kernel
+    (8, 10, 4, 2, 40_000, 0, 1e-5),
+    (32, 10, 16, 4, 30_000, 0, 1e-7),
+    (32, 10, 16, 4, 30_000, 1, 1e-7),
+    (4, 2, 2, 3, 30_000, 0, 1e-4),
+    (13, 5, 5, 3, 25_000, 1, 2e-4),
+    (24, 3, 8, 2, 20_000, 0, 3e-6),
+]
+
+
+@pytest.mark.parametrize("L,q,h,m,attempts,precision,lnf", TABLE_CASES)
+def test_small_lnf_trajectories_bitexact(L, q, h, m, attempts, precision, lnf):
+    g, o = make_pair(L, q, h, m, lnf_init=lnf, fixed_lnf=1, sync_attempts=1009, exchange=1,
+                     precision=precision, seed=11)
+    g.run(attempts)
+    o.run(attempts)
+    assert_same_state(g, o)
+
+
+@pytest.mark.parametrize("tilt,precision", [(0.7, 0), (-0.7, 0), (0.7, 1), (0.05, 0)])
+def test_tilted_weights_drive_walker_across_cache(tilt, precision):
+    # A steep fixed ln g makes the walker drift through a wide window, so it
+    # leaves the 64-energy register cache inside a block.
+    L, q = 16, 4
+    g, o = make_pair(L, q, 1, 1, lnf_init=1e-6, fixed_lnf=1, sync_attempts=5000, seed=13,
+                     precision=precision)
+    lng = tilt * np.arange(g.W, dtype=np.float64)
+    g.set_lng(0, lng)
+    o.set_lng(0, lng)
+    g.run(20_011)
+    o.run(20_011)
+    assert_same_state(g, o)
