@@ -199,7 +199,6 @@ constexpr double kMargin32 = 1e-5;    // log-domain slack of the exact-mode test
 constexpr double kTableMaxLnf = 2e-4; // table mode when ln f is at most this
 constexpr double kTableDmax = 64.0;   // table entries with |d| above this are left undecided
 
-typedef float f16v __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, j);
@@ -253,6 +252,8 @@ __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
     unsigned long long *tag = (unsigned long long *)(smem + st.Npad + (size_t)Wpad * 12);
     uint32_t *cnt = (uint32_t *)(tag + st.Ntag);
+    float *dtab = (float *)(cnt + 64);   // [9][64] table-mode differences
+    uint4 *apar = (uint4 *)(dtab + 9 * 64);  // [64] per-attempt table offset, dE + 64, thresholds
     const uint32_t tag_mask = (uint32_t)st.Ntag - 1u;
 
     const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
@@ -348,25 +349,36 @@ __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n
         unsigned long long accepted = 0ull, flushed = 0ull;
         int hist = 0;
 
+        // An earlier accepted flip of this block touched attempt j's site or a
+        // neighbour: write the pending flips, then recompute the proposal's new
+        // value and energy change from the live lattice (five reads at once).
+        auto settle = [&](int j, int &nvj) -> int {
+            if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
+            flushed = accepted;
+            const int s0 = sp[__builtin_amdgcn_readlane(p.site, j)];
+            const int a0 = sp[__builtin_amdgcn_readlane(p.nb0, j)];
+            const int a1 = sp[__builtin_amdgcn_readlane(p.nb1, j)];
+            const int a2 = sp[__builtin_amdgcn_readlane(p.nb2, j)];
+            const int a3 = sp[__builtin_amdgcn_readlane(p.nb3, j)];
+            const int scj = rfl(s0);
+            int v = scj + 1 + __builtin_amdgcn_readlane(p.off, j);
+            if (v >= q) v -= q;
+            nvj = v;
+            return rfl((int)(scj == a0) + (int)(scj == a1) + (int)(scj == a2) + (int)(scj == a3) -
+                       (int)(v == a0) - (int)(v == a1) - (int)(v == a2) - (int)(v == a3));
+        };
+
         // Exact decision of attempt j from the exact current ln g of the walker's
         // energy and of the proposed one (table mode: rebuilt by replaying this
         // block's ln f additions).  Also handles conflicts.  Returns acceptance
         // and writes dE actually used.
-        auto slow_attempt = [&](int j, bool table_values) -> void {
-            int dEj = __builtin_amdgcn_readlane(dE, j);
-            bool now = false;
-            int nvj = 0;
-            if (((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
-                if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
-                flushed = accepted;
-                const int site = __builtin_amdgcn_readlane(p.site, j);
-                const int scj = rfl((int)sp[site]);
-                nvj = scj + 1 + __builtin_amdgcn_readlane(p.off, j);
-                if (nvj >= q) nvj -= q;
-                dEj = rfl(delta_e(sp, scj, nvj, __builtin_amdgcn_readlane(p.nb0, j),
-                                  __builtin_amdgcn_readlane(p.nb1, j),
-                                  __builtin_amdgcn_readlane(p.nb2, j),
-                                  __builtin_amdgcn_readlane(p.nb3, j)));
+        auto slow_attempt = [&](int j, bool table_values, int dEj_in = 0, bool now_in = false,
+                                int nvj_in = 0, bool resolve = true) -> void {
+            int dEj = resolve ? __builtin_amdgcn_readlane(dE, j) : dEj_in;
+            bool now = resolve ? false : now_in;
+            int nvj = resolve ? 0 : nvj_in;
+            if (resolve && ((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
+                dEj = settle(j, nvj);
                 now = true;
             }
             const int Ecur = ebase + erel, En = Ecur + dEj;
@@ -376,8 +388,8 @@ __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n
                 if (table_values) {
                     // exact current values: block-start value + this block's additions
                     const unsigned long long before = (1ull << j) - 1ull;
-                    const int n_cur = __builtin_popcountll(__ballot(hist == Ecur) & before);
-                    const int n_new = __builtin_popcountll(__ballot(hist == En) & before);
+                    const int n_cur = __builtin_popcountll(__ballot(hist == Ecur - ebase) & before);
+                    const int n_new = __builtin_popcountll(__ballot(hist == En - ebase) & before);
                     const int rc = Ecur - ebase, rn = En - ebase;
                     if (PREC == 0) {
                         double vc = (unsigned)rc < 64u ? readlane_d(c64, rc) : g[Ecur - lo];
@@ -445,14 +457,13 @@ __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n
                     cl = (lane == erel) ? gEl : cl;
                 }
             }
-            hist = writelane_i32(ebase + erel, j, hist);
+            hist = writelane_i32(table_values ? erel : ebase + erel, j, hist);
         };
 
         if (tbl) {
             // ---- table mode.  Lane e: d_k(e) = ln g(ebase+e) - ln g(ebase+e+k-4)
             // at block start (binary32; NaN = undecided), and per attempt lane j
             // the thresholds ln u -+ margin rounded outwards.
-            f16v dtab;
             double cself;
             if (PREC == 0) cself = c64;
             else cself = (double)ch + (double)cl;
@@ -466,57 +477,229 @@ __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n
                     if (fabs(d) <= kTableDmax) v = (float)d;
                     else if (d == -__builtin_inf()) v = -__builtin_inff();
                 }
-                dtab[kk] = v;
+                dtab[kk * 64 + lane] = v;
             }
             const float th_hi = f32_up(lnu + margin);
             const float th_lo = f32_down(lnu - margin);
+            apar[lane] = make_uint4((uint32_t)((dE + 4) * 256), (uint32_t)(dE + 64),
+                                    __float_as_uint(th_hi), __float_as_uint(th_lo));
+            const unsigned char *dtab_b = (const unsigned char *)dtab + lane * 4;
+            // Next-state table of one attempt: lane e holds the walker's cache
+            // offset after the attempt if it is at offset e before it, plus 64
+            // when the move is accepted, or e + 128 when the table cannot decide.
+            auto next_table = [&](uint4 P, float ds) -> int {
+                const int ma = (ds > __uint_as_float(P.z)) ? -1 : 0;
+                const int ml = (ds < __uint_as_float(P.w)) ? -1 : 0;
+                return lane + ((int)P.y & ma) + (128 & ~(ma | ml));
+            };
             bool outside = false;   // walker left the cached range in this block
+            int j = 0;
+            while (j < todo) {
+                if (outside) {   // rest of the block after leaving the cache range
+                    slow_attempt(j, true, 0, false, 0, true);
+                    ++j;
+                    continue;
+                }
+                // Attempt j's conflict is settled by the acceptances so far.
+                bool now = false;
+                int nvj = 0;
+                if (((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
+                    const int dEj = settle(j, nvj);
+                    if (lane == 0) {
+                        apar[j].x = (uint32_t)((dEj + 4) * 256);
+                        apar[j].y = (uint32_t)(dEj + 64);
+                    }
+                    now = true;
+                }
+                // Group of up to 8 attempts: tables (vector work), then the chain
+                // of lane lookups, one per attempt.
+                const int len = min(8, todo - j);
+                uint4 P8[8];
+                float ds8[8];
+                int lut[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) P8[i] = apar[(j + i) & 63];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) ds8[i] = *(const float *)(dtab_b + P8[i].x);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) lut[i] = next_table(P8[i], ds8[i]);
+                int chain[8];
+                int sc = erel;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    sc = __builtin_amdgcn_readlane(lut[i], sc);
+                    chain[i] = sc;
+                }
+                int rec = 0;   // lane i <- chain value of step i
+#pragma unroll
+                for (int i = 0; i < 8; ++i) rec = writelane_i32(chain[i], i, rec);
+                const unsigned long long gmask = (len >= 64) ? ~0ull : ((1ull << len) - 1ull);
+                const unsigned long long und = __ballot((rec & 128) != 0) & gmask;
+                const unsigned long long accl = __ballot((rec & 64) != 0) & gmask;
+                // first step whose speculation fails: undecided, or a later step of
+                // the group hit by an accepted flip earlier in the group
+                int bad = und ? (int)__builtin_ctzll(und) : len;
+                unsigned long long fl = (anyconf >> j) & gmask & ~1ull;
+                while (fl) {
+                    const int i = (int)__builtin_ctzll(fl);
+                    if (i >= bad) break;
+                    fl &= fl - 1ull;
+                    const unsigned long long acc_before = accepted | ((accl & ((1ull << i) - 1ull)) << j);
+                    if (readlane64(conf, j + i) & acc_before) { bad = i; break; }
+                }
+                if (bad == 0 && now) bad = -1;   // resolved conflict attempt: decide it singly
+                const int ncommit = bad < 0 ? 0 : bad;
+                if (ncommit > 0) {
+                    // commit steps 0 .. ncommit-1
+                    const int src = lane - j;
+                    const int moved = __shfl(rec, src & 63);
+                    const bool mine = src >= 0 && src < ncommit;
+                    hist = mine ? (moved & 63) : hist;
+                    accepted |= (accl & ((ncommit >= 64) ? ~0ull : ((1ull << ncommit) - 1ull))) << j;
+                    erel = __builtin_amdgcn_readlane(rec, ncommit - 1) & 63;
+                    if (now && (accl & 1ull)) {   // recomputed attempt accepted: write at once
+                        if (lane == 0) sp[__builtin_amdgcn_readlane(p.site, j)] = (int8_t)nvj;
+                        flushed |= 1ull << j;
+                    }
+                }
+                j += ncommit;
+                if (ncommit == len) continue;
+                // step j could not be taken with the group: settle its conflict
+                // (if the group did not already), then decide it from its table
+                // unless the table is undecided there
+                const bool was_now = (ncommit == 0) && now;
+                bool now2 = was_now;
+                int nvj2 = was_now ? nvj : 0;
+                if (!was_now && ((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
+                    const int dEr = settle(j, nvj2);
+                    if (lane == 0) {
+                        apar[j].x = (uint32_t)((dEr + 4) * 256);
+                        apar[j].y = (uint32_t)(dEr + 64);
+                    }
+                    now2 = true;
+                }
+                const uint4 Pj = apar[j];
+                const int dEj = (int)Pj.y - 64;
+                const int v = __builtin_amdgcn_readlane(next_table(Pj, *(const float *)(dtab_b + Pj.x)), erel);
+                if (v & 128) {
+                    slow_attempt(j, true, dEj, now2, nvj2, false);
+                    outside = outside || (unsigned)erel >= 64u;
+                } else {
+                    const bool acc = (v & 64) != 0;
+                    erel = v & 63;
+                    accepted |= acc ? (1ull << j) : 0ull;
+                    if (acc && now2) {
+                        if (lane == 0) sp[__builtin_amdgcn_readlane(p.site, j)] = (int8_t)nvj2;
+                        flushed |= 1ull << j;
+                    }
+                    hist = writelane_i32(erel, j, hist);
+                }
+                ++j;
+            }
+        } else {
+            // ---- exact mode: runs of attempts with no possible conflict take the
+            // inline path; the others go through slow_attempt (which settles the
+            // conflict first)
             int j = 0;
             while (j < todo) {
                 const unsigned long long later = anyconf & (~0ull << j);
                 const int jstop = later ? min(todo, (int)__builtin_ctzll(later)) : todo;
-                if (!outside) {
-                    for (; j < jstop; ++j) {
-                        const int dEj = __builtin_amdgcn_readlane(dE, j);
-                        const float dsel = dtab[dEj + 4];
-                        const unsigned long long accm = __ballot(dsel > readlane_f(th_hi, j));
-                        const unsigned long long okm = __ballot(dsel < readlane_f(th_lo, j)) | accm;
-                        if (!((okm >> erel) & 1ull)) break;
-                        const bool acc = (accm >> erel) & 1ull;
-                        accepted |= acc ? (1ull << j) : 0ull;
-                        erel = acc ? erel + dEj : erel;
-                        hist = writelane_i32(ebase + erel, j, hist);
+                for (; j < jstop; ++j) {
+                    const int dEj = __builtin_amdgcn_readlane(dE, j);
+                    const double luj = readlane_d(lnu, j);
+                    int idx = erel + dEj;
+                    if ((unsigned)idx >= 64u) {
+                        cache_store();
+                        ebase += idx - 32;
+                        cache_load();
+                        erel = erel - idx + 32;
+                        idx = 32;
                     }
+                    bool acc;
+                    if (PREC == 0) {
+                        const double gN = readlane_d(c64, idx);
+                        const double d = gEv - gN;
+                        const double t = d - luj;
+                        acc = __ballot(t > 0.0) != 0ull;
+                        if (__builtin_expect(__ballot(!(fabs(t) > kMargin64)) != 0ull, 0))
+                            acc = __ballot(ebase + idx >= lo && ebase + idx <= hi &&
+                                           accept64(d, __builtin_amdgcn_readlane(p.u, j))) != 0ull;
+                        gEs = acc ? gN : gEs;
+                        gEv = gEs + lnf_v;
+                        gEs = rfl(gEv);
+                        erel = acc ? idx : erel;
+                        c64 = (lane == erel) ? gEv : c64;
+                    } else {
+                        const float gNh = readlane_f(ch, idx);
+                        const float gNl = readlane_f(cl, idx);
+                        const float d = (gEh - gNh) + (gEl - gNl);
+                        const double t = (double)d - luj;
+                        acc = __ballot(t > 0.0) != 0ull;
+                        if (__builtin_expect(__ballot(!(fabs(t) > kMargin32)) != 0ull, 0))
+                            acc = __ballot(ebase + idx >= lo && ebase + idx <= hi &&
+                                           accept32(d, __builtin_amdgcn_readlane(p.u, j))) != 0ull;
+                        gEh = acc ? gNh : gEh;
+                        gEl = acc ? gNl : gEl;
+                        two_sum_add(gEh, gEl, lnf32);
+                        gEh = rfl(gEh);
+                        gEl = rfl(gEl);
+                        erel = acc ? idx : erel;
+                        ch = (lane == erel) ? gEh : ch;
+                        cl = (lane == erel) ? gEl : cl;
+                    }
+                    accepted |= acc ? (1ull << j) : 0ull;
+                    hist = writelane_i32(ebase + erel, j, hist);
                 }
                 if (j >= todo) break;
-                slow_attempt(j, true);
-                outside = outside || (unsigned)erel >= 64u;
+                slow_attempt(j, false);
                 ++j;
             }
-        } else {
-            // ---- exact mode
-            for (int j = 0; j < todo; ++j) slow_attempt(j, false);
         }
 
         if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
-        if (live) atomicAdd(&H[hist - lo], 1u);
-        if (tbl) {
-            // replay this block's ln f additions, bin by bin
+        if (!tbl) {
+            if (live) atomicAdd(&H[hist - lo], 1u);
+        } else {
+            // this block's visits per cached energy; H and ln g of the bin take
+            // them in sequence (visits outside the cached range, rare, go
+            // straight to LDS one by one)
+            hist += ebase;   // table mode records energies relative to ebase
             const int rb = hist - ebase;
             const bool incache = (unsigned)rb < 64u;
             if (live && incache) atomicAdd(&cnt[rb], 1u);
             unsigned long long far = __ballot(live && !incache);
-            while (far) {      // visits outside the cached range (rare): LDS values
+            while (far) {
                 const int jj = (int)__builtin_ctzll(far);
                 far &= far - 1ull;
                 const int b = __builtin_amdgcn_readlane(hist, jj) - lo;
                 if (lane == 0) {
+                    H[b] += 1u;
                     if (PREC == 0) g[b] = g[b] + lnf;
                     else { float a = gh[b], c = gl[b]; two_sum_add(a, c, lnf32); gh[b] = a; gl[b] = c; }
                 }
             }
             int nvis = (int)cnt[lane];
             cnt[lane] = 0u;
+            const int hb = ebase + lane - lo;
+            if (nvis > 0) H[hb] += (uint32_t)nvis;
+            if (PREC == 0) {
+                // n additions of ln f in sequence.  Inside one binade every
+                // addition adds the same exact step d = RN(x + ln f) - x, so the
+                // result is x + n d, unless ln f sits exactly halfway between two
+                // multiples of ulp(x) (ties round to even) or the sum leaves the
+                // binade; those lanes (and x = 0) add one by one.
+                if (nvis > 0 && c64 > 0.0) {
+                    const double x1 = c64 + lnf;
+                    const double d = x1 - c64;
+                    const int ex = ilogb(c64);
+                    const double u = __builtin_ldexp(1.0, ex - 52);
+                    const double xn = c64 + (double)nvis * d;
+                    if (fabs(lnf - d) != 0.5 * u && ilogb(xn) == ex) {
+                        c64 = xn;
+                        nvis = 0;
+                    }
+                }
+            }
             while (__ballot(nvis > 0) != 0ull) {
                 if (nvis > 0) {
                     if (PREC == 0) c64 = c64 + lnf;
@@ -991,7 +1174,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
 // Launchers.
 
 size_t sweep_lds_bytes(const DevState &st) {
-    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)st.Ntag * 8 + 64 * 4;
+    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)st.Ntag * 8 + 64 * 4 + 9 * 64 * 4 + 64 * 16;
 }
 
 static size_t walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }

@@ -139,7 +139,7 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     p->Npad = (int)round_up((size_t)p->N, kAlign);
     p->Wpad = (int)round_up((size_t)W, 64);
     p->Bpad = (int)round_up((size_t)p->B, 64);
-    const size_t lds_state = (size_t)p->Npad + (size_t)p->Wpad * 12 + 64 * 4;
+    const size_t lds_state = (size_t)p->Npad + (size_t)p->Wpad * 12 + 64 * 4 + 9 * 64 * 4 + 64 * 16;
     p->Ntag = tag_entries(p->N, lds_state < (size_t)kMaxLds ? (size_t)kMaxLds - lds_state : 0);
     if (lds_state + (size_t)p->Ntag * 8 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "lattice plus window state exceed the 160 KiB LDS of a CU");

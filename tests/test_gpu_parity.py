@@ -147,7 +147,7 @@ def test_converged_dos_matches_enumeration_on_gpu():
     assert_same_state(g, o)
 
 
-@pytest.mark.parametrize("L,q,h,m", [(3, 127, 1, 1), (3, 2, 1, 7), (5, 3, 1, 64), (128, 2, 8, 1)])
+@pytest.mark.parametrize("L,q,h,m", [(3, 127, 1, 1), (3, 2, 1, 7), (5, 3, 1, 64), (128, 2, 16, 1)])
 def test_edge_shapes(L, q, h, m):
     g, o = make_pair(L, q, h, m, lnf_init=0.5, lnf_final=1e-2, sync_attempts=300, seed=2)
     n = 3000 if L < 100 else 1000
