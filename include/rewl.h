@@ -177,6 +177,98 @@ int rewl_get_timing(rewl_t *r, double *sweep_ms, int64_t *sweep_launches, double
 /* Message of the last failing call in this thread ("" if none). */
 const char *rewl_last_error(void);
 
+/* ---- Batched form ---------------------------------------------------------
+ * A batch holds n independent runs ("instances") of the method above, each
+ * with its own L, q, windows, walkers and options, in one device workspace.
+ * One batched step advances every unconverged instance by one sync interval:
+ * sync_attempts attempts for each of its walkers, then its sync point and
+ * exchange round, exactly as rewl_run_attempts does at a sync point.  The
+ * attempts of all walkers of all instances run in one persistent launch: a
+ * grid of walkers_per_cu x (compute units) one-wavefront workgroups takes
+ * walker tasks, longest first, from a device-side queue.  The step (queue
+ * reset, attempts, sync points, exchange rounds, counters) is captured once
+ * in a HIP graph and replayed.  Whatever the plan, every instance ends in the
+ * bit-identical state rewl_run_attempts gives it alone (the plan changes only
+ * where and when a walker's attempts run).
+ * Instances must share `precision`; each keeps its own seed and `instance`
+ * counter bits (give instances distinct `instance` values or seeds, else
+ * equal inputs give equal streams).                                          */
+typedef struct rewl_batch rewl_batch_t; /* opaque, owned by the library */
+
+typedef struct {
+    int32_t model;          /* REWL_POTTS2D */
+    int32_t L, q, windows, walkers;
+    int32_t reserved;
+    double overlap;
+    rewl_opts opts;
+} rewl_instance;
+
+typedef struct {
+    int32_t walkers_per_cu; /* persistent grid = walkers_per_cu x CUs workgroups    */
+    int32_t tag_policy;     /* 0: each instance's conflict-tag table as large as the */
+                            /*    LDS share 160 KiB / walkers_per_cu allows;         */
+                            /*    1: 64-entry tables (least LDS, more recomputation) */
+    int32_t use_graph;      /* 1: replay a captured HIP graph per step; 0: launch    */
+    int32_t lds_bytes;      /* out: LDS per workgroup of the attempt kernel          */
+    int32_t grid;           /* out: workgroups of the attempt kernel                 */
+    int32_t resident;       /* out: workgroups per CU the occupancy calculator allows */
+    double ms_per_step;     /* out (rewl_batch_tune): measured ms per batched step   */
+} rewl_batch_plan;
+
+/* Device workspace for these instances (bytes), 0 if any is invalid.        */
+size_t rewl_batch_workspace_bytes(int n, const rewl_instance *inst);
+
+/* Create a batch of n instances.  init_spins: host int8, the starting lattices
+ * of instance 0's walkers, then instance 1's, ... (windows*walkers*L*L values
+ * per instance).  dev_workspace / ws_bytes / hip_stream as for rewl_create.
+ * The initial plan is the one rewl_batch_set_plan picks for walkers_per_cu =
+ * 0 (the most resident walkers per CU with tag_policy 0).                   */
+int rewl_batch_create(rewl_batch_t **out, int n, const rewl_instance *inst, const int8_t *init_spins,
+                      void *dev_workspace, size_t ws_bytes, void *hip_stream);
+void rewl_batch_destroy(rewl_batch_t *b);
+
+/* Handle of instance i, for every single-run query (rewl_get_walker,
+ * rewl_get_window, rewl_get_lng, rewl_join, rewl_thermo, ...).  The batch
+ * owns it: rewl_destroy ignores it, and it dies with the batch.             */
+int rewl_batch_instance(rewl_batch_t *b, int i, rewl_t **out);
+
+/* Walk-in of every walker of every instance in one launch per chunk (see
+ * rewl_walkin).  Called with a budget of 2^40 by the first batched step.    */
+int rewl_batch_walkin(rewl_batch_t *b, int64_t max_attempts);
+
+/* Set the launch plan (walkers_per_cu = 0: the largest count the occupancy
+ * calculator allows).  Fills the out fields.  REWL_EINVAL if the LDS of an
+ * instance does not fit the share or the CU cannot hold that many walkers.  */
+int rewl_batch_set_plan(rewl_batch_t *b, rewl_batch_plan *plan);
+int rewl_batch_get_plan(rewl_batch_t *b, rewl_batch_plan *plan);
+
+/* Autotuner: time `steps_per_plan` batched steps under every feasible plan
+ * (walkers per CU from 1 to the occupancy limit x both tag policies), keep the
+ * fastest (with use_graph = 1).  The trial steps are ordinary steps of the
+ * runs (results do not depend on the plan).  tried: host array of `cap`
+ * plans (may be NULL) receiving every trial with its ms_per_step; *n_tried
+ * the number of trials.                                                      */
+int rewl_batch_tune(rewl_batch_t *b, int steps_per_plan, rewl_batch_plan *tried, int cap, int *n_tried);
+
+/* `steps` batched steps under the current plan.  Every instance's step must
+ * be a multiple of its sync_attempts (true unless the instance handles were
+ * run on their own).  REWL_CONVERGED once every instance has converged.     */
+int rewl_batch_run(rewl_batch_t *b, int64_t steps);
+
+/* Same steps with one launch per instance for each kernel (attempts, sync
+ * point, exchange, counters): the one-run-at-a-time baseline of the batched
+ * form.  Results are identical to rewl_batch_run.                           */
+int rewl_batch_run_per_instance(rewl_batch_t *b, int64_t steps);
+
+/* Batched steps done by the batch, and how many instances have converged.   */
+int rewl_batch_progress(rewl_batch_t *b, int64_t *steps, int32_t *converged);
+
+/* While enabled, HIP events on the batch's stream bracket every batched step
+ * (graph replay or launches); rewl_batch_get_timing returns the summed
+ * milliseconds and step count since timing was last enabled.                */
+int rewl_batch_set_timing(rewl_batch_t *b, int enable);
+int rewl_batch_get_timing(rewl_batch_t *b, double *ms, int64_t *steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,23 @@ class Opts(ctypes.Structure):
                 ("fixed_lnf", ctypes.c_int32)]
 
 
+class Instance(ctypes.Structure):
+    """Mirror of rewl_instance in include/rewl.h."""
+    _fields_ = [("model", ctypes.c_int32), ("L", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("windows", ctypes.c_int32), ("walkers", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("overlap", ctypes.c_double), ("opts", Opts)]
+
+
+class Plan(ctypes.Structure):
+    """Mirror of rewl_batch_plan in include/rewl.h."""
+    _fields_ = [("walkers_per_cu", ctypes.c_int32), ("tag_policy", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("resident", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -73,6 +90,22 @@ def lib():
         L.rewl_get_timing.argtypes = [P, P, P, P, P]
         L.rewl_last_error.argtypes = []
         L.rewl_last_error.restype = ctypes.c_char_p
+        IP, PP = ctypes.POINTER(Instance), ctypes.POINTER(Plan)
+        L.rewl_batch_workspace_bytes.argtypes = [i32, IP]
+        L.rewl_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.rewl_batch_create.argtypes = [ctypes.POINTER(P), i32, IP, P, P, ctypes.c_size_t, P]
+        L.rewl_batch_destroy.argtypes = [P]
+        L.rewl_batch_destroy.restype = None
+        L.rewl_batch_instance.argtypes = [P, i32, ctypes.POINTER(P)]
+        L.rewl_batch_walkin.argtypes = [P, i64]
+        L.rewl_batch_set_plan.argtypes = [P, PP]
+        L.rewl_batch_get_plan.argtypes = [P, PP]
+        L.rewl_batch_tune.argtypes = [P, i32, PP, i32, ctypes.POINTER(i32)]
+        L.rewl_batch_run.argtypes = [P, i64]
+        L.rewl_batch_run_per_instance.argtypes = [P, i64]
+        L.rewl_batch_progress.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+        L.rewl_batch_set_timing.argtypes = [P, i32]
+        L.rewl_batch_get_timing.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         _lib = L
     return _lib
 
@@ -128,14 +161,7 @@ class Rewl:
     def __init__(self, L, q, windows, overlap, walkers, init_spins, device=None, stream=None, **opts):
         import torch
 
-        self.L, self.q, self.h, self.m = L, q, windows, walkers
-        self.N = L * L
-        self.nw = windows * walkers
-        self.opts = make_opts(**opts)
-        self.precision = self.opts.precision
-        self.W, self.starts = window_layout(L, windows, overlap)
-        self.B = 2 * self.N + 1
-        self.e_lo = -2 * self.N
+        self._describe(L, q, windows, overlap, walkers, make_opts(**opts))
         spins = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(-1)
         if spins.size != self.nw * self.N:
             raise ValueError("init_spins must hold one L*L lattice per walker")
@@ -154,9 +180,28 @@ class Rewl:
                                      ctypes.c_void_p(self._stream.cuda_stream)))
         self._h = h
 
+    def _describe(self, L, q, windows, overlap, walkers, opts):
+        self.L, self.q, self.h, self.m = L, q, windows, walkers
+        self.N = L * L
+        self.nw = windows * walkers
+        self.opts = opts
+        self.precision = self.opts.precision
+        self.W, self.starts = window_layout(L, windows, overlap)
+        self.B = 2 * self.N + 1
+        self.e_lo = -2 * self.N
+
+    @classmethod
+    def _view(cls, handle, L, q, windows, overlap, walkers, opts, owner):
+        """A Rewl over an instance handle owned by a Batch."""
+        self = cls.__new__(cls)
+        self._describe(L, q, windows, overlap, walkers, opts)
+        self._h = handle
+        self._owner = owner
+        return self
+
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and getattr(self, "_owner", None) is None:
             lib().rewl_destroy(h)
             self._h = None
 
@@ -252,3 +297,102 @@ class Rewl:
         lnZ, U, C = np.zeros_like(T), np.zeros_like(T), np.zeros_like(T)
         _check(lib().rewl_thermo(self._h, _ptr(T), len(T), _ptr(lnZ), _ptr(U), _ptr(C)))
         return lnZ, U, C
+
+
+class Batch:
+    """Many independent REWL runs advanced together (the batched form).
+
+    ``instances``: list of dicts with keys L, q, windows, overlap, walkers and
+    any rewl_opts option (seed, instance, flat, lnf_init, ...).
+    ``init_spins``: list of int8 arrays, one [windows*walkers, L*L] per instance.
+    """
+
+    def __init__(self, instances, init_spins, device=None, stream=None):
+        import torch
+
+        n = len(instances)
+        arr = (Instance * n)()
+        self._desc = []
+        for i, d in enumerate(instances):
+            d = dict(d)
+            geo = {k: d.pop(k) for k in ("L", "q", "windows", "overlap", "walkers")}
+            o = make_opts(**d)
+            arr[i].model = POTTS2D
+            arr[i].L, arr[i].q, arr[i].windows, arr[i].walkers = geo["L"], geo["q"], geo["windows"], geo["walkers"]
+            arr[i].overlap = geo["overlap"]
+            arr[i].opts = o
+            self._desc.append((geo, o))
+        self._arr = arr
+        self.n = n
+        spins = np.concatenate([np.ascontiguousarray(s, dtype=np.int8).reshape(-1) for s in init_spins])
+        nbytes = lib().rewl_batch_workspace_bytes(n, arr)
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if nbytes == 0:
+            _check(lib().rewl_batch_create(ctypes.byref(ctypes.c_void_p()), n, arr, _ptr(spins), None, 0, None))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().rewl_batch_create(ctypes.byref(h), n, arr, _ptr(spins),
+                                           ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                           ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+        self._views = [None] * n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rewl_batch_destroy(h)
+            self._h = None
+
+    def instance(self, i):
+        """Rewl view of instance i (walker/window/join/thermo queries)."""
+        if self._views[i] is None:
+            ih = ctypes.c_void_p()
+            _check(lib().rewl_batch_instance(self._h, i, ctypes.byref(ih)))
+            geo, o = self._desc[i]
+            self._views[i] = Rewl._view(ih, geo["L"], geo["q"], geo["windows"], geo["overlap"], geo["walkers"],
+                                        o, self)
+        return self._views[i]
+
+    def walkin(self, budget=1 << 40):
+        return _check(lib().rewl_batch_walkin(self._h, int(budget)))
+
+    def run(self, steps):
+        """`steps` batched steps (one sync interval of every instance each)."""
+        return _check(lib().rewl_batch_run(self._h, int(steps)))
+
+    def run_per_instance(self, steps):
+        return _check(lib().rewl_batch_run_per_instance(self._h, int(steps)))
+
+    def plan(self):
+        p = Plan()
+        _check(lib().rewl_batch_get_plan(self._h, ctypes.byref(p)))
+        return p.as_dict()
+
+    def set_plan(self, walkers_per_cu=0, tag_policy=0, use_graph=1):
+        p = Plan()
+        p.walkers_per_cu, p.tag_policy, p.use_graph = walkers_per_cu, tag_policy, use_graph
+        _check(lib().rewl_batch_set_plan(self._h, ctypes.byref(p)))
+        return p.as_dict()
+
+    def tune(self, steps_per_plan=1, cap=256):
+        """Autotune the launch plan; returns (chosen plan, list of trials)."""
+        tried = (Plan * cap)()
+        nt = ctypes.c_int32(0)
+        _check(lib().rewl_batch_tune(self._h, int(steps_per_plan), tried, cap, ctypes.byref(nt)))
+        return self.plan(), [tried[i].as_dict() for i in range(nt.value)]
+
+    def progress(self):
+        s, c = ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(lib().rewl_batch_progress(self._h, ctypes.byref(s), ctypes.byref(c)))
+        return s.value, c.value
+
+    def set_timing(self, enable=True):
+        _check(lib().rewl_batch_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self):
+        """(milliseconds, batched steps) since set_timing."""
+        ms, n = ctypes.c_double(0), ctypes.c_int64(0)
+        _check(lib().rewl_batch_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -6,8 +6,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librewl.so")
-SOURCES = [os.path.join(CSRC, "rewl_kernels.hip"), os.path.join(CSRC, "rewl_runtime.hip")]
-HEADERS = [os.path.join(CSRC, "rewl_device.h"),
+SOURCES = [os.path.join(CSRC, "rewl_kernels.hip"), os.path.join(CSRC, "rewl_runtime.hip"),
+           os.path.join(CSRC, "rewl_batch.hip")]
+HEADERS = [os.path.join(CSRC, "rewl_device.h"), os.path.join(CSRC, "rewl_host.h"),
            os.path.join(os.path.dirname(HERE), "include", "rewl.h")]
 
 # -ffp-contract=off: the acceptance test must round every binary64/binary32

@@ -23,7 +23,10 @@ struct DevState {
     uint32_t key0, key1, ctr3;   // Philox key and instance bits of counter word 3
     uint32_t flat_num, flat_den;
     double lnf_final;
-    int schedule, precision, fixed_lnf;
+    int schedule, precision, fixed_lnf, exchange;
+    int64_t sync_attempts;       // S: attempts per walker between sync points
+    int64_t *ctl;                // [2] main-phase step and exchange round, kept on the
+                                 // device by the batched form (null otherwise)
     const int32_t *start;        // [h] lowest energy of each window
     int8_t *spins;               // [nw][Npad]
     int32_t *E;                  // [nw]
@@ -45,6 +48,19 @@ struct DevState {
     int32_t *cuts;               // [h]
     int32_t *join_status;        // [1]
     double *scratch;             // [max(h, 4096)] small reduction scratch
+};
+
+// One unit of work of the batched form: walker, window or window pair `idx`
+// of instance `inst`.
+struct BatchTask {
+    int32_t inst, idx;
+};
+
+// Per-instance progress gathered after batched steps.
+struct BatchStatus {
+    int64_t step, round;    // device-side counters (or the stop point once converged)
+    int32_t converged;      // every window reached ln f_final
+    int32_t walkin;         // walk-in: 0 all placed, 1 pending, 2 some walker hit the budget
 };
 
 // ---------------------------------------------------------------------------
@@ -165,4 +181,24 @@ hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, h
 hipError_t launch_join(const DevState &st, double log_total, hipStream_t s);
 hipError_t launch_thermo(const DevState &st, const double *T, int nT, double *out, hipStream_t s);
 size_t sweep_lds_bytes(const DevState &st);
+size_t walkin_lds_bytes(const DevState &st);
+
+// Batched form: many independent runs, each described by one DevState in
+// device memory (`descs`).  Tasks are (instance, index) pairs.
+hipError_t launch_walkin_batch(const DevState *descs, const BatchTask *tasks, int ntasks,
+                               size_t lds_bytes, int64_t chunk, int64_t budget, hipStream_t s);
+hipError_t launch_walkin_status(const DevState *descs, int n, int64_t budget, BatchStatus *out,
+                                hipStream_t s);
+hipError_t launch_queue_reset(int *queue, hipStream_t s);
+// persistent (queue != null): `grid` workgroups pull tasks [0, ntasks) from the
+// queue; otherwise one workgroup per task of [task_lo, task_lo + ntasks).
+hipError_t launch_sweep_batch(int precision, const DevState *descs, const BatchTask *tasks, int task_lo,
+                              int ntasks, int *queue, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_sync_batch(int precision, const DevState *descs, const BatchTask *wtasks, int lo, int n,
+                             hipStream_t s);
+hipError_t launch_exchange_batch(const DevState *descs, const BatchTask *xtasks, int lo, int n,
+                                 hipStream_t s);
+hipError_t launch_advance_batch(const DevState *descs, int lo, int n, hipStream_t s);
+hipError_t launch_status_batch(const DevState *descs, int n, BatchStatus *out, hipStream_t s);
+hipError_t sweep_batch_occupancy(int precision, size_t lds_bytes, int *blocks_per_cu);
 }  // namespace rewl_gpu

@@ -96,11 +96,10 @@ __global__ __launch_bounds__(256) void k_init_energy(DevState st) {
 // start inside its window, Sec. 3.2).  With ln f = 1 every ln g entry is an
 // integer visit count, kept exactly as uint32 in LDS.  Runs at most `chunk`
 // attempts per launch; the host relaunches until every walker is placed.
-__global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64_t budget) {
-    const int w = blockIdx.x;
+__device__ __forceinline__ void walkin_walker(const DevState &st, int w, int64_t chunk, int64_t budget,
+                                              unsigned char *smem) {
     const int lane = threadIdx.x;
     if (st.walkin_done[w]) return;
-    extern __shared__ __align__(16) unsigned char smem[];
     int8_t *sp = (int8_t *)smem;
     uint32_t *cnt = (uint32_t *)(smem + st.Npad);
     const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
@@ -153,6 +152,11 @@ __global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64
         st.walkin_att[w] = t;
         st.walkin_done[w] = done ? 1 : 0;
     }
+}
+
+__global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64_t budget) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    walkin_walker(st, blockIdx.x, chunk, budget, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,13 +241,12 @@ __device__ __forceinline__ float f32_down(double x) {
 }
 
 template <int PREC>
-__global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n) {
+__device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t s0, int64_t n,
+                                             unsigned char *smem) {
 #pragma clang fp contract(off)
     if (*st.converged) return;
-    const int w = blockIdx.x;
     const int lane = threadIdx.x;
     const int k = w / st.m;
-    extern __shared__ __align__(16) unsigned char smem[];
     const int W = st.W, Wpad = st.Wpad;
     int8_t *sp = (int8_t *)smem;
     double *g = (double *)(smem + st.Npad);
@@ -732,6 +735,12 @@ __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n
     if (lane == 0) st.E[w] = E;
 }
 
+template <int PREC>
+__global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_walker<PREC>(st, blockIdx.x, s0, n, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Sync point of one window (Sec. 2), one workgroup per window:
 //  1. visited bins of the window |= bins with H > 0 of any of its walkers;
@@ -744,9 +753,8 @@ __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n
 //  4. ln f < ln f_final: the window is finished and continues with ln f = 0.
 // t = attempts per walker / W (Belardinelli-Pereyra's 1/t rule, cited Sec. 2).
 template <int PREC>
-__global__ __launch_bounds__(256) void k_sync(DevState st, int64_t attempts) {
+__device__ __forceinline__ void sync_window(const DevState &st, int k, int64_t attempts) {
 #pragma clang fp contract(off)
-    const int k = blockIdx.x;
     const int tid = threadIdx.x;
     if (*st.converged || st.finished[k]) return;
     const int W = st.W, m = st.m, Wpad = st.Wpad;
@@ -857,6 +865,11 @@ __global__ __launch_bounds__(256) void k_sync(DevState st, int64_t attempts) {
     }
 }
 
+template <int PREC>
+__global__ __launch_bounds__(256) void k_sync(DevState st, int64_t attempts) {
+    sync_window<PREC>(st, blockIdx.x, attempts);
+}
+
 // ---------------------------------------------------------------------------
 // One replica-exchange round (Sec. 2, Eq. 1).  Workgroup b handles the window
 // pair (k, k+1), k = (r mod 2) + 2b.  Walker j of window k meets walker pi(j)
@@ -872,10 +885,10 @@ __device__ __forceinline__ double lng_at(const DevState &st, int w, int b, int p
     return (double)st.lng_hi[i] + (double)st.lng_lo[i];
 }
 
-__global__ __launch_bounds__(64) void k_exchange(DevState st, uint32_t r) {
+__device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t r, int pair) {
 #pragma clang fp contract(off)
     if (*st.converged) return;
-    const int k = (int)(r & 1u) + 2 * (int)blockIdx.x;
+    const int k = (int)(r & 1u) + 2 * pair;
     if (k + 1 >= st.h) return;
     const int m = st.m;
     __shared__ int s_perm[1024];
@@ -936,14 +949,22 @@ __global__ __launch_bounds__(64) void k_exchange(DevState st, uint32_t r) {
     }
 }
 
+__global__ __launch_bounds__(64) void k_exchange(DevState st, uint32_t r) {
+    exchange_pair(st, r, blockIdx.x);
+}
+
 // Termination (Sec. 2): the run ends once every window reached ln f_final.
-__global__ void k_check(DevState st, int64_t step, int64_t round_after) {
-    if (threadIdx.x != 0 || *st.converged) return;
+__device__ __forceinline__ void check_instance(const DevState &st, int64_t step, int64_t round_after) {
+    if (*st.converged) return;
     for (int k = 0; k < st.h; ++k)
         if (!st.finished[k]) return;
     *st.converged = 1;
     st.stop[0] = step;
     st.stop[1] = round_after;
+}
+
+__global__ void k_check(DevState st, int64_t step, int64_t round_after) {
+    if (threadIdx.x == 0) check_instance(st, step, round_after);
 }
 
 // ---------------------------------------------------------------------------
@@ -1168,6 +1189,117 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched form: many independent REWL runs (instances) in the same launches.
+// Each instance is one DevState in device memory; its main-phase step and
+// exchange round live on the device (ctl), so a captured graph of one batched
+// step can be replayed.  A batched step advances every unconverged instance
+// by one sync interval (its own S attempts per walker): attempts, sync point,
+// exchange round, then the counters and the termination test.  Every kernel
+// does per instance exactly what the single-run kernels do, so the results
+// are bit-identical to running each instance on its own.
+
+__device__ __forceinline__ int wave_broadcast(int v) { return __builtin_amdgcn_readlane(v, 0); }
+
+__global__ __launch_bounds__(64) void k_walkin_batch(const DevState *__restrict__ descs,
+                                                     const BatchTask *__restrict__ tasks, int64_t chunk,
+                                                     int64_t budget) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchTask t = tasks[blockIdx.x];
+    const DevState st = descs[t.inst];
+    walkin_walker(st, t.idx, chunk, budget, smem);
+}
+
+// One thread per instance: 0 every walker placed, 1 some still walking,
+// 2 some walker exhausted the budget.
+__global__ void k_walkin_status(const DevState *__restrict__ descs, int n, int64_t budget,
+                                BatchStatus *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevState &st = descs[i];
+    int status = 0;
+    for (int w = 0; w < st.nw; ++w) {
+        if (st.walkin_done[w]) continue;
+        status = st.walkin_att[w] >= budget ? 2 : (status == 2 ? 2 : 1);
+    }
+    out[i].walkin = status;
+}
+
+__global__ void k_queue_reset(int *queue) {
+    if (threadIdx.x == 0) queue[0] = 0;
+}
+
+// Attempts of one sync interval for every walker of every instance.  With a
+// queue the grid is persistent: each workgroup (one wavefront, one walker at
+// a time) takes the next task until none is left, so the launch shape (and
+// with it walkers per CU and LDS per walker) is free of the task count.
+// Tasks are ordered longest first.  Every workgroup leaves once the queue
+// index passes ntasks.
+template <int PREC, bool PERSISTENT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(const DevState *__restrict__ descs,
+                                                    const BatchTask *__restrict__ tasks, int task_lo,
+                                                    int ntasks, int *queue) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (!PERSISTENT) {
+        const BatchTask t = tasks[task_lo + (int)blockIdx.x];
+        const DevState st = descs[t.inst];
+        sweep_walker<PREC>(st, t.idx, st.ctl[0], st.sync_attempts, smem);
+        return;
+    }
+    for (;;) {
+        int ti = 0;
+        if (threadIdx.x == 0) ti = atomicAdd(queue, 1);
+        ti = wave_broadcast(ti);
+        if (ti >= ntasks) break;
+        const BatchTask t = tasks[ti];
+        const DevState &st = descs[t.inst];
+        sweep_walker<PREC>(st, t.idx, st.ctl[0], st.sync_attempts, smem);
+        __syncthreads();
+    }
+}
+
+// Sync point of window t.idx of instance t.inst, at the attempt count the
+// instance reaches with this step.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_sync_batch(const DevState *__restrict__ descs,
+                                                    const BatchTask *__restrict__ wtasks, int lo) {
+    const BatchTask t = wtasks[lo + (int)blockIdx.x];
+    const DevState st = descs[t.inst];
+    sync_window<PREC>(st, t.idx, st.ctl[0] + st.sync_attempts);
+}
+
+// Exchange round of instance t.inst (at its own round counter), pair slot t.idx.
+__global__ __launch_bounds__(64) void k_exchange_batch(const DevState *__restrict__ descs,
+                                                       const BatchTask *__restrict__ xtasks, int lo) {
+    const BatchTask t = xtasks[lo + (int)blockIdx.x];
+    const DevState st = descs[t.inst];
+    if (!st.exchange) return;
+    exchange_pair(st, (uint32_t)st.ctl[1], t.idx);
+}
+
+// Step and round counters of every unconverged instance, then termination.
+__global__ void k_advance_batch(const DevState *__restrict__ descs, int lo, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevState &st = descs[lo + i];
+    if (*st.converged) return;
+    const int64_t step = st.ctl[0] + st.sync_attempts;
+    const int64_t round = st.ctl[1] + (st.exchange ? 1 : 0);
+    st.ctl[0] = step;
+    st.ctl[1] = round;
+    check_instance(st, step, round);
+}
+
+__global__ void k_status_batch(const DevState *__restrict__ descs, int n, BatchStatus *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevState &st = descs[i];
+    const int conv = *st.converged;
+    out[i].converged = conv;
+    out[i].step = conv ? st.stop[0] : st.ctl[0];
+    out[i].round = conv ? st.stop[1] : st.ctl[1];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1177,7 +1309,7 @@ size_t sweep_lds_bytes(const DevState &st) {
     return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)st.Ntag * 8 + 64 * 4 + 9 * 64 * 4 + 64 * 16;
 }
 
-static size_t walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
+size_t walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
 
 static hipError_t allow_lds(const void *fn, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
@@ -1246,6 +1378,89 @@ hipError_t launch_join(const DevState &st, double log_total, hipStream_t s) {
 hipError_t launch_thermo(const DevState &st, const double *T, int nT, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_thermo, dim3(nT), dim3(256), 0, s, st, T, out);
     return hipGetLastError();
+}
+
+hipError_t launch_walkin_batch(const DevState *descs, const BatchTask *tasks, int ntasks,
+                               size_t lds_bytes, int64_t chunk, int64_t budget, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    hipError_t e = allow_lds((const void *)k_walkin_batch, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_walkin_batch, dim3(ntasks), dim3(64), lds_bytes, s, descs, tasks, chunk, budget);
+    return hipGetLastError();
+}
+
+hipError_t launch_walkin_status(const DevState *descs, int n, int64_t budget, BatchStatus *out,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walkin_status, dim3((n + 255) / 256), dim3(256), 0, s, descs, n, budget, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_queue_reset(int *queue, hipStream_t s) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(int precision, const DevState *descs, const BatchTask *tasks, int task_lo,
+                              int ntasks, int *queue, int grid, size_t lds_bytes, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    const void *fn = queue ? (precision == 0 ? (const void *)k_sweep_batch<0, true>
+                                             : (const void *)k_sweep_batch<1, true>)
+                           : (precision == 0 ? (const void *)k_sweep_batch<0, false>
+                                             : (const void *)k_sweep_batch<1, false>);
+    hipError_t e = allow_lds(fn, lds_bytes);
+    if (e != hipSuccess) return e;
+    if (queue && precision == 0)
+        hipLaunchKernelGGL((k_sweep_batch<0, true>), dim3(grid), dim3(64), lds_bytes, s, descs, tasks, task_lo,
+                           ntasks, queue);
+    else if (queue)
+        hipLaunchKernelGGL((k_sweep_batch<1, true>), dim3(grid), dim3(64), lds_bytes, s, descs, tasks, task_lo,
+                           ntasks, queue);
+    else if (precision == 0)
+        hipLaunchKernelGGL((k_sweep_batch<0, false>), dim3(ntasks), dim3(64), lds_bytes, s, descs, tasks,
+                           task_lo, ntasks, queue);
+    else
+        hipLaunchKernelGGL((k_sweep_batch<1, false>), dim3(ntasks), dim3(64), lds_bytes, s, descs, tasks,
+                           task_lo, ntasks, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_sync_batch(int precision, const DevState *descs, const BatchTask *wtasks, int lo, int n,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_sync_batch<0>, dim3(n), dim3(256), 0, s, descs, wtasks, lo);
+    else
+        hipLaunchKernelGGL(k_sync_batch<1>, dim3(n), dim3(256), 0, s, descs, wtasks, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange_batch(const DevState *descs, const BatchTask *xtasks, int lo, int n,
+                                 hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exchange_batch, dim3(n), dim3(64), 0, s, descs, xtasks, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_batch(const DevState *descs, int lo, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_advance_batch, dim3((n + 255) / 256), dim3(256), 0, s, descs, lo, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_batch(const DevState *descs, int n, BatchStatus *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_status_batch, dim3((n + 255) / 256), dim3(256), 0, s, descs, n, out);
+    return hipGetLastError();
+}
+
+hipError_t sweep_batch_occupancy(int precision, size_t lds_bytes, int *blocks_per_cu) {
+    const void *fn = precision == 0 ? (const void *)k_sweep_batch<0, true> : (const void *)k_sweep_batch<1, true>;
+    hipError_t e = allow_lds(fn, lds_bytes);
+    if (e != hipSuccess) return e;
+    if (precision == 0)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_batch<0, true>, 64, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_batch<1, true>, 64, lds_bytes);
 }
 
 }  // namespace rewl_gpu

@@ -10,12 +10,12 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rewl.h"
-#include "rewl_device.h"
+#include "rewl_host.h"
 
 using rewl_gpu::DevState;
+using namespace rewl_host;
 
-namespace {
+namespace rewl_host {
 
 thread_local std::string g_err;
 
@@ -24,23 +24,7 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(REWL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr int kMaxLds = 160 * 1024;
-constexpr int kMaxThermo = 4096;
-constexpr int64_t kWalkinChunk = int64_t(1) << 20;
-
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-struct Params {
-    int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad, Ntag;
-};
 
 // Conflict-tag table of the attempt kernel: one 64-bit lane mask per site
 // (exact) up to 4096 sites, hashed by site mod the table size beyond or when
@@ -52,10 +36,19 @@ int tag_entries(int N, size_t lds_free) {
     return t;
 }
 
-struct Layout {
-    size_t start, spins, E, lng, lng_hi, lng_lo, H, replica, walkin_att, walkin_done, walkin_cnt,
-        lnf, lnf_last, regime, finished, iterations, visited, x_att, x_acc, converged, stop, joined,
-        cuts, join_status, scratch, T, thermo_out, total;
+size_t sweep_state_lds(int Npad, int Wpad) {
+    return (size_t)Npad + (size_t)Wpad * 12 + 64 * 4 + 9 * 64 * 4 + 64 * 16;
+}
+
+}  // namespace rewl_host
+
+namespace {
+
+constexpr int kMaxThermo = 4096;
+constexpr int64_t kWalkinChunk = int64_t(1) << 20;
+
+struct Params {
+    int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad, Ntag;
 };
 
 Layout make_layout(const Params &p, int precision) {
@@ -139,7 +132,7 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     p->Npad = (int)round_up((size_t)p->N, kAlign);
     p->Wpad = (int)round_up((size_t)W, 64);
     p->Bpad = (int)round_up((size_t)p->B, 64);
-    const size_t lds_state = (size_t)p->Npad + (size_t)p->Wpad * 12 + 64 * 4 + 9 * 64 * 4 + 64 * 16;
+    const size_t lds_state = sweep_state_lds(p->Npad, p->Wpad);
     p->Ntag = tag_entries(p->N, lds_state < (size_t)kMaxLds ? (size_t)kMaxLds - lds_state : 0);
     if (lds_state + (size_t)p->Ntag * 8 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "lattice plus window state exceed the 160 KiB LDS of a CU");
@@ -149,28 +142,6 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
 }
 
 }  // namespace
-
-// HIP event pairs around launches, folded into running sums when the pool
-// fills up or when the totals are read.
-struct Timer {
-    bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
-    std::vector<hipEvent_t> pool;
-    double ms[2] = {0.0, 0.0};
-    int64_t count[2] = {0, 0};
-};
-
-struct rewl {
-    DevState st;
-    Timer timer;
-    Layout lay;
-    unsigned char *ws;
-    hipStream_t stream;
-    rewl_opts opts;
-    std::vector<int32_t> starts;
-    int64_t step = 0, round = 0;
-    bool walked_in = false, converged = false, joined = false;
-};
 
 namespace {
 
@@ -307,6 +278,7 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     d.flat_num = op.flat_num; d.flat_den = op.flat_den;
     d.lnf_final = op.lnf_final;
     d.schedule = op.schedule; d.precision = op.precision; d.fixed_lnf = op.fixed_lnf;
+    d.exchange = op.exchange; d.sync_attempts = op.sync_attempts; d.ctl = nullptr;
     d.start = (const int32_t *)(b + lay.start);
     d.spins = (int8_t *)(b + lay.spins);
     d.E = (int32_t *)(b + lay.E);
@@ -353,7 +325,7 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
 }
 
 void rewl_destroy(rewl_t *r) {
-    if (!r) return;
+    if (!r || r->in_batch) return;
     timer_destroy(r->timer);
     delete r;
 }

@@ -1,0 +1,20 @@
+"""State comparison of a GPU run (librewl) and an oracle run, element by element."""
+import numpy as np
+
+
+def assert_same_state(g, o):
+    """Every integer and binary64 field of every walker and window must match exactly."""
+    assert g.step == o.step and g.round == o.round
+    for w in range(g.nw):
+        a, b = g.walker(w), o.walker(w)
+        assert np.array_equal(a["spins"], b["spins"]), f"spins of walker {w}"
+        assert a["E"] == b["E"], f"E of walker {w}"
+        assert np.array_equal(a["H"], b["H"]), f"H of walker {w}"
+        assert np.array_equal(a["lng"].view(np.uint64), b["lng"].view(np.uint64)), f"ln g of walker {w}"
+        assert a["replica"] == b["replica"], f"replica of walker {w}"
+        assert a["walkin_attempts"] == b["walkin_attempts"], f"walk-in of walker {w}"
+    for k in range(g.h):
+        a, b = g.window(k), o.window(k)
+        for key in ("lnf", "lnf_last", "regime", "finished", "iterations", "x_att", "x_acc"):
+            assert a[key] == b[key], (k, key, a[key], b[key])
+        assert np.array_equal(a["visited"], b["visited"]), f"visited of window {k}"

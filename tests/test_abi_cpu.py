@@ -85,3 +85,31 @@ def test_binding_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pk, "_lib", None)
     with pytest.raises(ImportError):
         pk.lib()
+
+
+def _instances(specs):
+    arr = (pk.Instance * len(specs))()
+    for i, (L, q, h, m) in enumerate(specs):
+        arr[i].model, arr[i].L, arr[i].q, arr[i].windows, arr[i].walkers = 0, L, q, h, m
+        arr[i].overlap = 0.75
+        arr[i].opts = pk.make_opts(instance=i)
+    return arr
+
+
+def test_batch_structs_and_workspace(lib):
+    assert ctypes.sizeof(pk.Instance) == 96 and ctypes.sizeof(pk.Plan) == 32
+    specs = [(16, 2, 8, 4), (24, 4, 8, 4), (48, 10, 8, 4)]
+    arr = _instances(specs)
+    total = lib.rewl_batch_workspace_bytes(3, arr)
+    singles = sum(pk.workspace_bytes(L, q, h, 0.75, m, pk.make_opts()) for L, q, h, m in specs)
+    assert total > singles and total % 256 == 0
+    assert lib.rewl_batch_workspace_bytes(0, arr) == 0
+    bad = _instances([(16, 2, 8, 4), (2, 2, 1, 1)])
+    assert lib.rewl_batch_workspace_bytes(2, bad) == 0
+    h = ctypes.c_void_p()
+    st = lib.rewl_batch_create(ctypes.byref(h), 2, bad, None, None, 0, None)
+    assert st == pk.EINVAL and b"instance 1" in lib.rewl_last_error()
+    mixed = _instances(specs[:2])
+    mixed[1].opts.precision = 1
+    st = lib.rewl_batch_create(ctypes.byref(h), 2, mixed, None, None, 0, None)
+    assert st == pk.EINVAL and b"precision" in lib.rewl_last_error()

@@ -14,6 +14,7 @@ import pytest
 import oracle
 from oracle import bruteforce
 import workloads
+from statecmp import assert_same_state
 
 pytestmark = pytest.mark.gpu
 
@@ -30,23 +31,6 @@ def make_pair(L, q, h, m, overlap=0.75, spins_seed=1, threads=8, **opts):
     g = _pk().Rewl(L, q, h, overlap, m, spins, **opts)
     o = oracle.Rewl(L, q, h, overlap, m, spins, threads=threads, **opts)
     return g, o
-
-
-def assert_same_state(g, o):
-    assert g.step == o.step and g.round == o.round
-    for w in range(g.nw):
-        a, b = g.walker(w), o.walker(w)
-        assert np.array_equal(a["spins"], b["spins"]), f"spins of walker {w}"
-        assert a["E"] == b["E"], f"E of walker {w}"
-        assert np.array_equal(a["H"], b["H"]), f"H of walker {w}"
-        assert np.array_equal(a["lng"].view(np.uint64), b["lng"].view(np.uint64)), f"ln g of walker {w}"
-        assert a["replica"] == b["replica"], f"replica of walker {w}"
-        assert a["walkin_attempts"] == b["walkin_attempts"], f"walk-in of walker {w}"
-    for k in range(g.h):
-        a, b = g.window(k), o.window(k)
-        for key in ("lnf", "lnf_last", "regime", "finished", "iterations", "x_att", "x_acc"):
-            assert a[key] == b[key], (k, key, a[key], b[key])
-        assert np.array_equal(a["visited"], b["visited"]), f"visited of window {k}"
 
 
 FIXED_CASES = [
