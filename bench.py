@@ -55,6 +55,210 @@ def cpu_baseline(cfg, spins, attempts_per_walker):
                         f"{threads} OpenMP threads"))
 
 
+def batched(args):
+    """The 256-instance batched workload: autotuned persistent launch (graph
+    replay) against one launch per instance, alternating step by step."""
+    import torch
+
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    cfg = workloads.BATCHED
+    pairs = workloads.batched_instances(cfg)
+    insts, spins = [], []
+    for i, (L, q) in enumerate(pairs):
+        insts.append(dict(L=L, q=q, windows=cfg["windows"], overlap=cfg["overlap"], walkers=cfg["walkers"],
+                          seed=cfg["seed"], instance=i, flat=cfg["flat"], lnf_init=cfg["lnf_init"],
+                          lnf_final=cfg["lnf_final"], schedule=cfg["schedule"],
+                          sync_attempts=cfg["sweeps_per_sync"] * L * L, exchange=cfg["exchange"],
+                          precision=cfg["precision"]))
+        spins.append(workloads.init_spins(L, q, cfg["windows"] * cfg["walkers"], cfg["seed"] + i))
+    attempts_per_step = sum(d["windows"] * d["walkers"] * d["sync_attempts"] for d in insts)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    b = pk.Batch(insts, spins, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.walkin()
+    torch.cuda.synchronize()
+    walkin_s = time.perf_counter() - t0
+    log(f"[bench] batched walk-in done in {walkin_s:.2f} s")
+    t0 = time.perf_counter()
+    plan, trials = b.tune(steps_per_plan=1)
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] tuned in {tune_s:.1f} s over {len(trials)} plans: {plan}")
+    if args.warmup:
+        b.run(args.warmup)
+    torch.cuda.synchronize()
+    # persistent steps, with one step of one-launch-per-instance in the middle
+    t_batch = t_single = 0.0
+    for i in range(args.steps):
+        if i == args.steps // 2:
+            t0 = time.perf_counter()
+            b.run_per_instance(1)
+            torch.cuda.synchronize()
+            t_single = time.perf_counter() - t0
+            log(f"[bench] one launch per instance: {1e3 * t_single:.1f} ms per step")
+        t0 = time.perf_counter()
+        b.run(1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_batch += dt
+        log(f"[bench] persistent step {i}: {1e3 * dt:.1f} ms")
+    steps, conv = b.progress()
+    value = attempts_per_step * args.steps / t_batch
+    out = {
+        "metric": "spin-flip attempts/s (1 GPU), 256 batched REWL instances",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_batch / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "256 instances of 2D Potts, L in {16,24,32,48} and q in {2,4,8,10} drawn "
+                               "from a seed, 8 windows at 75% overlap, 4 walkers each, sync every 1000 sweeps",
+                   "instances": len(insts), "walkers": sum(d["windows"] * d["walkers"] for d in insts),
+                   "attempts_per_step": attempts_per_step},
+        "plan": plan,
+        "tuner_trials": trials,
+        "per_instance_launches": {"value": attempts_per_step / t_single, "ms_per_step": 1e3 * t_single,
+                                  "steps": 1},
+        "speedup_vs_per_instance": t_single / (t_batch / args.steps),
+        "walkin_s": walkin_s,
+        "tune_s": tune_s,
+        "converged_instances": conv,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def walkin_with_progress(g, tag):
+    """Walk-in in growing attempt budgets, logging progress (placed walkers)."""
+    import paper_1312_3004_amd as pk
+
+    budget = 1 << 22
+    t0 = time.perf_counter()
+    while True:
+        try:
+            g.walkin(budget=budget)
+            break
+        except pk.RewlError:
+            placed = sum(1 for w in range(g.nw)
+                         if g.starts[w // g.m] <= g.walker(w)["E"] <= g.starts[w // g.m] + g.W - 1)
+            log(f"[bench] {tag} walk-in: {placed}/{g.nw} placed after {budget:,} attempts budget, "
+                f"{time.perf_counter() - t0:.1f} s")
+            budget *= 2
+    return time.perf_counter() - t0
+
+
+def precision_study(args):
+    """The L=80 workload in binary64 and in the binary32 (hi, lo) form: both
+    start from the same walked-in lattices; throughput of each, and the error
+    of each format's ln g against its exact (double-double) shadow."""
+    import numpy as np
+    import torch
+
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    cfg = dict(workloads.CONFIGS["potts_q10_L80"])
+    L, q, h, m = cfg["L"], cfg["q"], cfg["windows"], cfg["walkers"]
+    nw, S = h * m, cfg["sync_attempts"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    kw = dict(device=dev, seed=cfg["seed"], flat=cfg["flat"], lnf_init=cfg["lnf_init"],
+              lnf_final=cfg["lnf_final"], schedule=cfg["schedule"], sync_attempts=S,
+              exchange=cfg["exchange"], shadow=1)
+    spins = workloads.init_spins(L, q, nw, cfg["seed"])
+    runs, out = {}, {}
+    g0 = pk.Rewl(L, q, h, cfg["overlap"], m, spins, precision=0, **kw)
+    walkin_s = walkin_with_progress(g0, "L=80")
+    log(f"[bench] L=80 walk-in done in {walkin_s:.1f} s")
+    placed = np.stack([g0.walker(w)["spins"] for w in range(nw)])
+    runs[0] = g0
+    runs[1] = pk.Rewl(L, q, h, cfg["overlap"], m, placed, precision=1, **kw)
+    runs[1].walkin()
+    for prec in (0, 1):
+        g = runs[prec]
+        if args.warmup:
+            g.run(args.warmup * S)
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        t0 = time.perf_counter()
+        g.run(args.steps * S)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sweep_ms, launches, sync_ms, syncs = g.timing()
+        g.set_timing(False)
+        err, iters = [], []
+        for k in range(h):
+            iters.append(g.window(k)["iterations"])
+            worst = 0.0
+            for j in range(m):
+                w = k * m + j
+                hi, lo = g.shadow(w)
+                lng = g.walker(w)["lng"]
+                worst = max(worst, float(np.max(np.abs((lng - hi) - lo))))
+            err.append(worst)
+        out["f64" if prec == 0 else "f32x2"] = {
+            "attempts_per_s": nw * S * args.steps / el,
+            "k_sweep_avg_ms": sweep_ms / max(launches, 1),
+            "sync_point_avg_ms": sync_ms / max(syncs, 1),
+            "max_abs_lng_minus_exact": max(err),
+            "median_window_max_abs_err": float(np.median(err)),
+            "ln_f_reductions_min_median_max": [int(min(iters)), int(np.median(iters)), int(max(iters))],
+        }
+        log(f"[bench] precision {prec}: {out['f64' if prec == 0 else 'f32x2']}")
+    # Late-phase segment: the halving schedule's increments are powers of two,
+    # which both formats add exactly.  From the binary64 run's ln g (values of
+    # a few thousand), both formats add a fixed ln f that is not a binary
+    # fraction (about the schedule's value after 18 halvings) for the same
+    # number of steps; each is compared with its own exact shadow.
+    lnf_late = 1.0 / (3 * 2**17)
+    src = [runs[0].walker(w)["lng"] for w in range(nw)]
+    late = {}
+    for prec in (0, 1):
+        g = pk.Rewl(L, q, h, cfg["overlap"], m, placed, precision=prec, device=dev, seed=cfg["seed"] + 1,
+                    lnf_init=lnf_late, fixed_lnf=1, sync_attempts=S, exchange=cfg["exchange"], shadow=1)
+        g.walkin()
+        for w in range(nw):
+            g.set_lng(w, src[w])
+        g.run(args.steps * S)
+        torch.cuda.synchronize()
+        worst, vals = 0.0, 0.0
+        for w in range(nw):
+            hi, lo = g.shadow(w)
+            lng = g.walker(w)["lng"]
+            worst = max(worst, float(np.max(np.abs((lng - hi) - lo))))
+            vals = max(vals, float(np.max(np.abs(lng))))
+        late["f64" if prec == 0 else "f32x2"] = {"max_abs_lng_minus_exact": worst, "max_abs_lng": vals}
+        log(f"[bench] late segment precision {prec}: max |ln g - exact| = {worst:.3e} (|ln g| <= {vals:.1f})")
+    out["late_segment"] = {"lnf": lnf_late, "steps": args.steps, **late}
+    res = {
+        "metric": "spin-flip attempts/s (1 GPU), q=10 Potts L=80 REWL, binary64 vs binary32 (hi, lo) ln g",
+        "value": out["f32x2"]["attempts_per_s"],
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32x2",
+        "data": "synthetic",
+        "config": {"workload": "potts_q10_L80: 2D q=10 Potts 80x80 periodic, 64 windows at 75% overlap, "
+                               "16 walkers/window, ln f halving to 1e-9",
+                   "walkers": nw, "attempts_per_step_per_walker": S},
+        "precisions": out,
+        "walkin_s": walkin_s,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,11 +267,18 @@ def main():
     ap.add_argument("--config", default="potts_q10_L32")
     ap.add_argument("--cpu-attempts", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("potts", "batched", "precision"), default="potts",
+                    help="potts: the single-run workload (--config); batched: 256 instances; "
+                         "precision: the L=80 workload in binary64 and in the binary32 pair form")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole REWL hot path on a single "
-              "MI355X (multi-GPU window sharding is a design note, not implemented).", file=sys.stderr)
+        print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
+              "(multi-GPU window sharding is a design note, not implemented).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return batched(args)
+    if args.workload == "precision":
+        return precision_study(args)
 
     import torch
 

@@ -71,6 +71,9 @@ typedef struct {
     int64_t sync_attempts;  /* [1000] attempts per walker between sync points        */
     int32_t precision;      /* [0] 0: ln g in binary64; 1: binary32 (hi, lo) pair    */
     int32_t fixed_lnf;      /* [0] 1: sync points never change ln f (fixed weights) */
+    int32_t shadow;         /* [0] 1: keep an exact reference of ln g (see           */
+                            /*     rewl_get_shadow); costs 20 bytes per bin and walker */
+    int32_t walkin_slack;   /* [16] walk-in lid width (energy units), 0 = no lid    */
 } rewl_opts;
 
 void rewl_default_opts(rewl_opts *o);
@@ -103,8 +106,11 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
 void rewl_destroy(rewl_t *r);
 
 /* Walk-in: move every walker whose energy lies outside its window into it
- * (each walker starts inside its own window, Sec. 3.2 on Fig. 7) by a global
- * Wang-Landau walk with ln f = 1 over all energies.  REWL_EBUDGET if some
+ * (each walker starts inside its own window, Sec. 3.2 on Fig. 7) by a
+ * Wang-Landau walk with ln f = 1 over all energies, under a lid: a walker
+ * above its window rejects moves to energies more than walkin_slack above the
+ * lowest energy it has reached (a walker below, symmetrically, stays above a
+ * floor), so it floods a band of that width instead of the whole range.  REWL_EBUDGET if some
  * walker needs more than max_attempts attempts (its state is left where the
  * walk stopped).  Called implicitly with a budget of 2^40 by the first run. */
 int rewl_walkin(rewl_t *r, int64_t max_attempts);
@@ -138,6 +144,16 @@ int rewl_get_walker(rewl_t *r, int walker, int8_t *spins, int32_t *E, uint32_t *
 int rewl_get_window(rewl_t *r, int window, double *lnf, double *lnf_last, int32_t *regime,
                     int32_t *finished, int64_t *iterations, uint8_t *visited, uint64_t *x_att,
                     uint64_t *x_acc);
+
+/* Shadow of walker w's ln g (runs created with opts.shadow = 1): an exact
+ * reference of the values ln g should hold along the walker's own trajectory.
+ * At every sync point each bin receives (visits since the previous sync
+ * point) x ln f in double-double arithmetic (Knuth TwoSum, Dekker Fast2Sum,
+ * exact products by fused multiply-add), and window averages are taken the
+ * same way; (hi + lo) - ln g is the rounding error the ln g format has
+ * accumulated (binary64, or the binary32 pair).  Valid at sync points.
+ * hi, lo: host double[W].  REWL_ESTATE if the run keeps no shadow.          */
+int rewl_get_shadow(rewl_t *r, int walker, double *hi, double *lo);
 
 /* Overwrite ln g of walker w from host double[W] (fixed-weight sampling,
  * Sec. 3.2: "continued generating data with fixed weights 1/g(E)").         */

@@ -29,7 +29,13 @@ def lib():
         i32, i64, u32, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
         L.orc_create.restype = P
         L.orc_create.argtypes = [i32, i32, i32, dbl, i32, u64, u32, u32, u32, dbl, dbl, i32, i64,
-                                 i32, i32, i32, P]
+                                 i32, i32, i32, i32, i32, P]
+        L.orc_get_shadow.argtypes = [P, i32, P, P]
+        L.orc_get_shadow.restype = None
+        for name, args in (("orc_dd_add", [P, P, dbl, dbl]), ("orc_dd_div_int", [P, P, i32]),
+                           ("orc_dd_mul_count", [u32, dbl, P, P])):
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = None
         L.orc_destroy.argtypes = [P]
         L.orc_set_threads.argtypes = [P, i32]
         L.orc_walkin.argtypes = [P, i64]
@@ -104,6 +110,25 @@ def twosum_accumulate(hi, lo, x, n):
     return float(a[0]), float(b[0])
 
 
+def dd_add(a, b):
+    """Double-double sum of (hi, lo) pairs a and b."""
+    hi, lo = ctypes.c_double(a[0]), ctypes.c_double(a[1])
+    lib().orc_dd_add(ctypes.byref(hi), ctypes.byref(lo), b[0], b[1])
+    return hi.value, lo.value
+
+
+def dd_div_int(a, m):
+    hi, lo = ctypes.c_double(a[0]), ctypes.c_double(a[1])
+    lib().orc_dd_div_int(ctypes.byref(hi), ctypes.byref(lo), m)
+    return hi.value, lo.value
+
+
+def dd_mul_count(n, x):
+    hi, lo = ctypes.c_double(0), ctypes.c_double(0)
+    lib().orc_dd_mul_count(n, x, ctypes.byref(hi), ctypes.byref(lo))
+    return hi.value, lo.value
+
+
 def window_layout(B, h, overlap, e_lo):
     W = ctypes.c_int(0)
     starts = np.zeros(h, dtype=np.int32)
@@ -143,7 +168,7 @@ class Rewl:
 
     def __init__(self, L, q, windows, overlap, walkers, init_spins, seed=1, instance=0,
                  flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0, sync_attempts=1000,
-                 exchange=1, precision=0, fixed_lnf=0, threads=1):
+                 exchange=1, precision=0, fixed_lnf=0, shadow=0, walkin_slack=16, threads=1):
         self.L, self.q, self.h, self.m = L, q, windows, walkers
         self.precision = precision
         spins = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(-1)
@@ -152,7 +177,7 @@ class Rewl:
         self._keep = spins
         self.h_ = lib().orc_create(L, q, windows, overlap, walkers, seed, instance, flat[0], flat[1],
                                    lnf_init, lnf_final, schedule, sync_attempts, exchange, precision,
-                                   fixed_lnf, _ptr(spins))
+                                   fixed_lnf, shadow, walkin_slack, _ptr(spins))
         if not self.h_:
             raise ValueError("oracle rejected the parameters")
         lib().orc_set_threads(self.h_, threads)
@@ -219,6 +244,12 @@ class Rewl:
                              ctypes.byref(xc))
         return dict(lnf=lnf.value, lnf_last=lnf_last.value, regime=regime.value, finished=fin.value,
                     iterations=it.value, visited=vis, x_att=xa.value, x_acc=xc.value)
+
+    def shadow(self, w):
+        """(hi, lo): double-double exact reference of walker w's ln g."""
+        hi, lo = np.zeros(self.W), np.zeros(self.W)
+        lib().orc_get_shadow(self.h_, w, _ptr(hi), _ptr(lo))
+        return hi, lo
 
     def set_lng(self, w, lng):
         a = np.ascontiguousarray(lng, dtype=np.float64)

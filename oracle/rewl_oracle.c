@@ -196,6 +196,8 @@ typedef struct {
     int exchange;          /* exchange round at every sync point             */
     int precision;         /* 0: binary64 ln g; 1: binary32 (hi, lo) pair    */
     int fixed_lnf;         /* 1: sync points never change ln f or average    */
+    int shadow;            /* 1: keep the exact reference of ln g (below)    */
+    int walkin_slack;      /* walk-in lid/floor distance (0: no lid)          */
     int threads;
     /* walker state, walker w = k*m + j */
     int8_t *spin;          /* [nw][N] */
@@ -203,6 +205,8 @@ typedef struct {
     double *lng;           /* [nw][W] (precision 0) */
     float *lng_hi, *lng_lo;/* [nw][W] (precision 1) */
     uint32_t *H;           /* [nw][W] */
+    double *sh_hi, *sh_lo; /* [nw][W] shadow: ln g in double-double          */
+    uint32_t *hprev;       /* [nw][W] H at the previous sync point           */
     uint8_t *vis;          /* [nw][W] bins this walker reached since creation */
     uint32_t *replica;     /* [nw] */
     int64_t *walkin_att;   /* [nw] */
@@ -224,7 +228,7 @@ static void orc_free(orc_t *o)
 {
     if (!o) return;
     free(o->start); free(o->spin); free(o->E); free(o->lng); free(o->lng_hi);
-    free(o->lng_lo); free(o->H); free(o->vis); free(o->replica); free(o->walkin_att);
+    free(o->lng_lo); free(o->H); free(o->sh_hi); free(o->sh_lo); free(o->hprev); free(o->vis); free(o->replica); free(o->walkin_att);
     free(o->lnf); free(o->lnf_last); free(o->regime); free(o->finished);
     free(o->iterations); free(o->visited); free(o->x_att); free(o->x_acc);
     free(o);
@@ -250,12 +254,13 @@ void orc_constants32(float *c) { c[0] = ORC_INV_LN2_F; c[1] = ORC_LN2_C1_F; c[2]
 orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uint32_t instance,
                   uint32_t flat_num, uint32_t flat_den, double lnf_init, double lnf_final,
                   int schedule, int64_t sync_attempts, int exchange, int precision, int fixed_lnf,
-                  const int8_t *init_spins)
+                  int shadow, int walkin_slack, const int8_t *init_spins)
 {
     if (L < 3 || L > 724 || q < 2 || q > 127 || h < 1 || m < 1) return NULL;
     if (!(overlap >= 0.0 && overlap < 1.0)) return NULL;
     if (flat_den == 0 || flat_den > 1000 || flat_num > flat_den) return NULL;
     if (sync_attempts < 1 || precision < 0 || precision > 1 || schedule < 0 || schedule > 1) return NULL;
+    if (walkin_slack < 0) return NULL;
     if (!init_spins) return NULL;
     orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
     if (!o) return NULL;
@@ -271,13 +276,20 @@ orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uin
     o->flat_num = flat_num; o->flat_den = flat_den;
     o->lnf_init = lnf_init; o->lnf_final = lnf_final;
     o->schedule = schedule; o->S = sync_attempts; o->exchange = exchange;
-    o->precision = precision; o->fixed_lnf = fixed_lnf; o->threads = 1;
+    o->precision = precision; o->fixed_lnf = fixed_lnf; o->shadow = shadow != 0; o->threads = 1;
+    o->walkin_slack = walkin_slack;
     size_t nw = (size_t)o->nw, N = (size_t)o->N, W = (size_t)o->W;
     o->spin = (int8_t *)malloc(nw * N);
     o->E = (int32_t *)calloc(nw, sizeof(int32_t));
     if (precision == 0) o->lng = (double *)calloc(nw * W, sizeof(double));
     else { o->lng_hi = (float *)calloc(nw * W, sizeof(float)); o->lng_lo = (float *)calloc(nw * W, sizeof(float)); }
     o->H = (uint32_t *)calloc(nw * W, sizeof(uint32_t));
+    if (o->shadow) {
+        o->sh_hi = (double *)calloc(nw * W, sizeof(double));
+        o->sh_lo = (double *)calloc(nw * W, sizeof(double));
+        o->hprev = (uint32_t *)calloc(nw * W, sizeof(uint32_t));
+        if (!o->sh_hi || !o->sh_lo || !o->hprev) { orc_free(o); return NULL; }
+    }
     o->vis = (uint8_t *)calloc(nw * W, 1);
     o->replica = (uint32_t *)calloc(nw, sizeof(uint32_t));
     o->walkin_att = (int64_t *)calloc(nw, sizeof(int64_t));
@@ -400,10 +412,16 @@ static void potts_attempt(orc_t *o, int w, int k, double lnf, uint32_t domain, u
 
 /* Placement before the run: each walker must carry a configuration whose
  * energy lies inside its own window (Sec. 3.2, discussion of Fig. 7).  The
- * paper does not say how; here a global Wang-Landau walk with its own ln g
- * over all B energies and ln f = 1 moves the configuration until its energy
- * first lies in the window.  Returns ORC_EBUDGET if a walker needs more than
- * max_attempts attempts.                                                    */
+ * paper does not say how; here a Wang-Landau walk with its own ln g over all
+ * B energies and ln f = 1 moves the configuration until its energy first
+ * lies in the window.  A walker above its window walks under a lid: moves to
+ * energies more than `walkin_slack` above the lowest energy it has reached
+ * are rejected (a walker below its window, symmetrically, walks above a
+ * floor).  Without the lid the walk floods the whole range between the start
+ * and the window, at a cost that grows with the square of that range; with
+ * it the flooded band stays `walkin_slack` wide.  walkin_slack = 0 means no
+ * lid.  Returns ORC_EBUDGET if a walker needs more than max_attempts
+ * attempts.                                                                 */
 int orc_walkin(orc_t *o, int64_t max_attempts)
 {
     if (o->walked_in) return ORC_OK;
@@ -418,6 +436,9 @@ int orc_walkin(orc_t *o, int64_t max_attempts)
         int8_t *s = o->spin + (size_t)w * N;
         double *g = (double *)calloc((size_t)o->B, sizeof(double));
         int64_t t = 0;
+        int slack = o->walkin_slack;
+        int down = o->E[w] > hi;
+        int bound = down ? o->E[w] + slack : o->E[w] - slack;   /* lid, or floor */
         while (!(o->E[w] >= lo && o->E[w] <= hi)) {
             if (t >= max_attempts || !g) {
 #pragma omp atomic write
@@ -434,9 +455,12 @@ int orc_walkin(orc_t *o, int64_t max_attempts)
             if (nv >= q) nv -= q;
             int e_new = o->E[w] + potts_delta_e(s, L, i, nv);
             double d = g[o->E[w] - o->e_lo] - g[e_new - o->e_lo];
-            if (accept64(d, r[2])) {
+            int inside = slack == 0 || (down ? e_new <= bound : e_new >= bound);
+            if (inside && accept64(d, r[2])) {
                 s[i] = (int8_t)nv;
                 o->E[w] = e_new;
+                if (slack && down && o->E[w] + slack < bound) bound = o->E[w] + slack;
+                if (slack && !down && o->E[w] - slack > bound) bound = o->E[w] - slack;
             }
             g[o->E[w] - o->e_lo] += 1.0;
             ++t;
@@ -446,6 +470,103 @@ int orc_walkin(orc_t *o, int64_t max_attempts)
     }
     if (status == ORC_OK) o->walked_in = 1;
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shadow: an exact reference of every walker's ln g along its own trajectory.
+ * Between two sync points ln f of a window is constant, so bin b of walker w
+ * received (H - H_prev) additions of ln f; the shadow adds that product in
+ * double-double arithmetic (about 106 significant bits) and follows the
+ * window averages the same way.  The difference between ln g and its shadow
+ * is then the rounding error the ln g format accumulated (binary64, or the
+ * binary32 (hi, lo) pair).  It plays no part in the sampling.
+ * Double-double routines: Knuth's TwoSum, Dekker's Fast2Sum, and the exact
+ * product residual by fused multiply-add, combined as in the accurate
+ * double-double addition of Hida, Li and Bailey (QD library, 2001).          */
+static void dd_two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    double bb = x - a;
+    *e = (a - (x - bb)) + (b - bb);
+    *s = x;
+}
+
+static void dd_fast_two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    *e = b - (x - a);
+    *s = x;
+}
+
+static void dd_add(double *hi, double *lo, double bh, double bl)
+{
+    double s, e, t, f;
+    dd_two_sum(*hi, bh, &s, &e);
+    dd_two_sum(*lo, bl, &t, &f);
+    e = e + t;
+    dd_fast_two_sum(s, e, &s, &e);
+    e = e + f;
+    dd_fast_two_sum(s, e, hi, lo);
+}
+
+/* (hi, lo) / m for a small positive integer m */
+static void dd_div_int(double *hi, double *lo, int m)
+{
+    double dm = (double)m;
+    double q1 = *hi / dm;
+    double r = fma(-q1, dm, *hi);
+    r = r + *lo;
+    double q2 = r / dm;
+    dd_fast_two_sum(q1, q2, hi, lo);
+}
+
+/* test exports of the double-double steps */
+void orc_dd_add(double *hi, double *lo, double bh, double bl) { dd_add(hi, lo, bh, bl); }
+void orc_dd_div_int(double *hi, double *lo, int m) { dd_div_int(hi, lo, m); }
+void orc_dd_mul_count(uint32_t n, double x, double *hi, double *lo)
+{
+    double dn = (double)n;
+    *hi = dn * x;
+    *lo = fma(dn, x, -*hi);
+}
+
+/* sync point of window k: the interval's additions, n * ln f, into the shadow */
+static void shadow_accumulate(orc_t *o, int k, double lnf)
+{
+    int W = o->W, m = o->m;
+    for (int j = 0; j < m; ++j)
+        for (int b = 0; b < W; ++b) {
+            size_t i = (size_t)(k * m + j) * W + b;
+            uint32_t n = o->H[i] - o->hprev[i];
+            if (n) {
+                double dn = (double)n;
+                double ph = dn * lnf;
+                double pl = fma(dn, lnf, -ph);
+                dd_add(&o->sh_hi[i], &o->sh_lo[i], ph, pl);
+            }
+            o->hprev[i] = o->H[i];
+        }
+}
+
+/* window average of the shadows (walker order, then / m), H_prev reset */
+static void shadow_average(orc_t *o, int k)
+{
+    int W = o->W, m = o->m;
+    for (int b = 0; b < W; ++b) {
+        size_t i0 = (size_t)(k * m) * W + b;
+        double hi = o->sh_hi[i0], lo = o->sh_lo[i0];
+        for (int j = 1; j < m; ++j) {
+            size_t i = (size_t)(k * m + j) * W + b;
+            dd_add(&hi, &lo, o->sh_hi[i], o->sh_lo[i]);
+        }
+        dd_div_int(&hi, &lo, m);
+        for (int j = 0; j < m; ++j) {
+            size_t i = (size_t)(k * m + j) * W + b;
+            o->sh_hi[i] = hi;
+            o->sh_lo[i] = lo;
+            o->hprev[i] = 0;
+        }
+    }
 }
 
 /* Average the m estimators of window k and hand the mean back to every
@@ -493,6 +614,7 @@ static void window_sync(orc_t *o, int k)
                 o->lng_hi[i] = s;
             }
     }
+    if (o->shadow) shadow_accumulate(o, k, o->lnf[k]);
     if (o->fixed_lnf) return;
     double inv_t = (double)W / (double)o->step;
     if (o->regime[k] == 0) {
@@ -511,6 +633,7 @@ static void window_sync(orc_t *o, int k)
         }
         if (!all_flat) return;
         window_average(o, k);
+        if (o->shadow) shadow_average(o, k);
         memset(o->H + (size_t)k * m * W, 0, (size_t)m * W * sizeof(uint32_t));
         o->lnf[k] = o->lnf[k] * 0.5;
         o->iterations[k] += 1;
@@ -520,6 +643,7 @@ static void window_sync(orc_t *o, int k)
         }
     } else {
         window_average(o, k);
+        if (o->shadow) shadow_average(o, k);
         memset(o->H + (size_t)k * m * W, 0, (size_t)m * W * sizeof(uint32_t));
         o->lnf[k] = inv_t;
         o->iterations[k] += 1;
@@ -684,11 +808,27 @@ void orc_get_window(const orc_t *o, int k, double *lnf, double *lnf_last, int32_
     if (xacc) *xacc = o->x_acc[k];
 }
 
-/* Test hook: overwrite the ln g of walker w (precision 0 or 1).             */
+/* Shadow of walker w (zeros if the run keeps none).                        */
+void orc_get_shadow(const orc_t *o, int w, double *hi, double *lo)
+{
+    size_t W = (size_t)o->W;
+    for (size_t b = 0; b < W; ++b) {
+        hi[b] = o->shadow ? o->sh_hi[(size_t)w * W + b] : 0.0;
+        lo[b] = o->shadow ? o->sh_lo[(size_t)w * W + b] : 0.0;
+    }
+}
+
+/* Test hook: overwrite the ln g of walker w (precision 0 or 1); the shadow
+ * restarts from the given values.                                           */
 void orc_set_lng(orc_t *o, int w, const double *lng)
 {
     size_t W = (size_t)o->W;
     for (size_t b = 0; b < W; ++b) {
+        if (o->shadow) {
+            o->sh_hi[(size_t)w * W + b] = lng[b];
+            o->sh_lo[(size_t)w * W + b] = 0.0;
+            o->hprev[(size_t)w * W + b] = o->H[(size_t)w * W + b];
+        }
         if (o->precision == 0) o->lng[(size_t)w * W + b] = lng[b];
         else {
             float hi = (float)lng[b];

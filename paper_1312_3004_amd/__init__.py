@@ -35,7 +35,8 @@ class Opts(ctypes.Structure):
                 ("lnf_init", ctypes.c_double), ("lnf_final", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("exchange", ctypes.c_int32),
                 ("sync_attempts", ctypes.c_int64), ("precision", ctypes.c_int32),
-                ("fixed_lnf", ctypes.c_int32)]
+                ("fixed_lnf", ctypes.c_int32), ("shadow", ctypes.c_int32),
+                ("walkin_slack", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -83,6 +84,7 @@ def lib():
         L.rewl_get_walker.argtypes = [P, i32, P, P, P, P, P, P]
         L.rewl_get_window.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.rewl_set_lng.argtypes = [P, i32, P]
+        L.rewl_get_shadow.argtypes = [P, i32, P, P]
         L.rewl_get_lng.argtypes = [P, i32, P, i64, P, P]
         L.rewl_join.argtypes = [P, P, P]
         L.rewl_thermo.argtypes = [P, P, i32, P, P, P]
@@ -135,13 +137,14 @@ def window_layout(L, windows, overlap):
 
 
 def make_opts(seed=1, instance=0, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
-              sync_attempts=1000, exchange=1, precision=0, fixed_lnf=0):
+              sync_attempts=1000, exchange=1, precision=0, fixed_lnf=0, shadow=0, walkin_slack=16):
     o = default_opts()
     o.seed, o.instance = seed, instance
     o.flat_num, o.flat_den = flat
     o.lnf_init, o.lnf_final = lnf_init, lnf_final
     o.schedule, o.sync_attempts, o.exchange = schedule, sync_attempts, exchange
-    o.precision, o.fixed_lnf = precision, fixed_lnf
+    o.precision, o.fixed_lnf, o.shadow = precision, fixed_lnf, shadow
+    o.walkin_slack = walkin_slack
     return o
 
 
@@ -257,6 +260,12 @@ class Rewl:
                                      ctypes.byref(xa), ctypes.byref(xc)))
         return dict(lnf=lnf.value, lnf_last=lnf_last.value, regime=regime.value, finished=fin.value,
                     iterations=it.value, visited=vis, x_att=xa.value, x_acc=xc.value)
+
+    def shadow(self, w):
+        """(hi, lo): double-double exact reference of walker w's ln g (opts shadow=1)."""
+        hi, lo = np.zeros(self.W), np.zeros(self.W)
+        _check(lib().rewl_get_shadow(self._h, w, _ptr(hi), _ptr(lo)))
+        return hi, lo
 
     def set_lng(self, w, lng):
         a = np.ascontiguousarray(lng, dtype=np.float64)

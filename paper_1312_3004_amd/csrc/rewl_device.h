@@ -23,8 +23,9 @@ struct DevState {
     uint32_t key0, key1, ctr3;   // Philox key and instance bits of counter word 3
     uint32_t flat_num, flat_den;
     double lnf_final;
-    int schedule, precision, fixed_lnf, exchange;
+    int schedule, precision, fixed_lnf, exchange, shadow;
     int64_t sync_attempts;       // S: attempts per walker between sync points
+    int walkin_slack;            // walk-in lid/floor distance (0: no lid)
     int64_t *ctl;                // [2] main-phase step and exchange round, kept on the
                                  // device by the batched form (null otherwise)
     const int32_t *start;        // [h] lowest energy of each window
@@ -33,9 +34,12 @@ struct DevState {
     double *lng;                 // [nw][Wpad]            (precision 0)
     float *lng_hi, *lng_lo;      // [nw][Wpad] each       (precision 1)
     uint32_t *H;                 // [nw][Wpad]
+    double *sh_hi, *sh_lo;       // [nw][Wpad] exact reference of ln g (double-double), if kept
+    uint32_t *hprev;             // [nw][Wpad] H at the previous sync point (shadow only)
     uint32_t *replica;           // [nw]
     int64_t *walkin_att;         // [nw]
     int32_t *walkin_done;        // [nw]
+    int32_t *walkin_bound;       // [nw] walk-in lid (walker above its window) or floor
     uint32_t *walkin_cnt;        // [nw][Bpad] visit counts of the walk-in ln g (ln f = 1)
     double *lnf, *lnf_last;      // [h]
     int32_t *regime, *finished;  // [h]
@@ -166,6 +170,52 @@ __device__ __forceinline__ void two_sum_add(float &hi, float &lo, float x) {
     const float err = (hi - (s - bb)) + (x - bb);
     hi = s;
     lo = lo + err;
+}
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic of the ln g shadow (an exact reference of the
+// accumulated ln g, kept at sync points): TwoSum (Knuth), Fast2Sum (Dekker),
+// product residuals by fused multiply-add, and the accurate double-double
+// addition of Hida, Li and Bailey.  Every step is one rounded binary64 op.
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD dd_sum(double a, double b) {
+#pragma clang fp contract(off)
+    const double s = a + b;
+    const double bb = s - a;
+    return DD{s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ DD dd_quick(double a, double b) {
+#pragma clang fp contract(off)
+    const double s = a + b;
+    return DD{s, b - (s - a)};
+}
+
+__device__ __forceinline__ DD dd_add(DD x, DD y) {
+#pragma clang fp contract(off)
+    DD s = dd_sum(x.hi, y.hi);
+    const DD t = dd_sum(x.lo, y.lo);
+    s = dd_quick(s.hi, s.lo + t.hi);
+    return dd_quick(s.hi, s.lo + t.lo);
+}
+
+// exact n * x as a double-double (n < 2^32)
+__device__ __forceinline__ DD dd_mul_count(uint32_t n, double x) {
+#pragma clang fp contract(off)
+    const double dn = (double)n;
+    const double p = dn * x;
+    return DD{p, __builtin_fma(dn, x, -p)};
+}
+
+__device__ __forceinline__ DD dd_div_count(DD x, int m) {
+#pragma clang fp contract(off)
+    const double dm = (double)m;
+    const double q1 = x.hi / dm;
+    const double r = __builtin_fma(-q1, dm, x.hi) + x.lo;
+    return dd_quick(q1, r / dm);
 }
 
 }  // namespace rewl_gpu

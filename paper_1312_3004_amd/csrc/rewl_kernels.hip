@@ -91,10 +91,13 @@ __global__ __launch_bounds__(256) void k_init_energy(DevState st) {
 }
 
 // ---------------------------------------------------------------------------
-// Walk-in: a global Wang-Landau walk with ln f = 1 over all 2N+1 energies, run
-// until the walker's energy first lies in its own window (every walker must
-// start inside its window, Sec. 3.2).  With ln f = 1 every ln g entry is an
-// integer visit count, kept exactly as uint32 in LDS.  Runs at most `chunk`
+// Walk-in: a Wang-Landau walk over all 2N+1 energies with ln f = 1, run until
+// the walker's energy first lies in its own window (every walker must start
+// inside its window, Sec. 3.2).  With ln f = 1 every ln g entry is an integer
+// visit count, kept exactly as uint32 in LDS.  A walker above its window
+// walks under a lid (moves more than walkin_slack above the lowest energy
+// reached are rejected), a walker below it above a floor; the flooded band
+// then stays walkin_slack wide instead of spanning the whole way down.  Runs at most `chunk`
 // attempts per launch; the host relaunches until every walker is placed.
 __device__ __forceinline__ void walkin_walker(const DevState &st, int w, int64_t chunk, int64_t budget,
                                               unsigned char *smem) {
@@ -113,6 +116,9 @@ __device__ __forceinline__ void walkin_walker(const DevState &st, int w, int64_t
     const int e_lo = st.e_lo, q = st.q;
     int E = st.E[w];
     int64_t t = st.walkin_att[w];
+    const int slack = st.walkin_slack;
+    const bool down = E > hi;
+    int bound = t == 0 ? (down ? E + slack : E - slack) : st.walkin_bound[w];
     const int64_t end = (t + chunk < budget) ? t + chunk : budget;
     bool done = (E >= lo && E <= hi);
     while (!done && t < end) {
@@ -133,9 +139,12 @@ __device__ __forceinline__ void walkin_walker(const DevState &st, int w, int64_t
             const int64_t ci = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(cnt[E - e_lo]);
             const int64_t cn = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(cnt[En - e_lo]);
             const double d = (double)(ci - cn);
-            if (accept64(d, u)) {
+            const bool inside = slack == 0 || (down ? En <= bound : En >= bound);
+            if (inside && accept64(d, u)) {
                 if (lane == 0) sp[site] = (int8_t)nv;
                 E = En;
+                if (slack && down && E + slack < bound) bound = E + slack;
+                if (slack && !down && E - slack > bound) bound = E - slack;
             }
             if (lane == 0) cnt[E - e_lo] += 1u;
             ++t;
@@ -151,6 +160,7 @@ __device__ __forceinline__ void walkin_walker(const DevState &st, int w, int64_t
         st.E[w] = E;
         st.walkin_att[w] = t;
         st.walkin_done[w] = done ? 1 : 0;
+        st.walkin_bound[w] = bound;
     }
 }
 
@@ -776,6 +786,21 @@ __device__ __forceinline__ void sync_window(const DevState &st, int k, int64_t a
             st.lng_hi[i] = s;
         }
     }
+    if (st.shadow) {   // this interval's additions, (H - H_prev) * ln f, into the shadow
+        const double lnf = st.lnf[k];
+        for (int idx = tid; idx < m * W; idx += 256) {
+            const int j = idx / W, b = idx - j * W;
+            const size_t i = base + (size_t)j * Wpad + b;
+            const uint32_t hv = st.H[i];
+            const uint32_t n = hv - st.hprev[i];
+            if (n) {
+                const DD r = dd_add(DD{st.sh_hi[i], st.sh_lo[i]}, dd_mul_count(n, lnf));
+                st.sh_hi[i] = r.hi;
+                st.sh_lo[i] = r.lo;
+            }
+            st.hprev[i] = hv;
+        }
+    }
     if (st.fixed_lnf) return;
     __syncthreads();
 
@@ -841,6 +866,20 @@ __device__ __forceinline__ void sync_window(const DevState &st, int k, int64_t a
                 st.lng_lo[i] = (float)(mean - (double)h0);
             }
             st.H[i] = 0u;
+        }
+        if (st.shadow) {
+            DD acc{st.sh_hi[base + b], st.sh_lo[base + b]};
+            for (int j = 1; j < m; ++j) {
+                const size_t i = base + (size_t)j * Wpad + b;
+                acc = dd_add(acc, DD{st.sh_hi[i], st.sh_lo[i]});
+            }
+            acc = dd_div_count(acc, m);
+            for (int j = 0; j < m; ++j) {
+                const size_t i = base + (size_t)j * Wpad + b;
+                st.sh_hi[i] = acc.hi;
+                st.sh_lo[i] = acc.lo;
+                st.hprev[i] = 0u;
+            }
         }
     }
     if (tid == 0) {

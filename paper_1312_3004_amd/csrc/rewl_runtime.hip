@@ -4,6 +4,7 @@
 // on the caller's stream in the order of the method (Sec. 2 of Vogel, Li,
 // Wuest, Landau): attempts, then at every sync point flatness/averaging/ln f
 // per window, a replica-exchange round, and the termination test.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,7 +52,7 @@ struct Params {
     int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad, Ntag;
 };
 
-Layout make_layout(const Params &p, int precision) {
+Layout make_layout(const Params &p, int precision, int shadow) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -66,9 +67,13 @@ Layout make_layout(const Params &p, int precision) {
     l.lng_hi = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
     l.lng_lo = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
     l.H = take(sizeof(uint32_t) * p.nw * p.Wpad);
+    l.sh_hi = shadow ? take(sizeof(double) * p.nw * p.Wpad) : 0;
+    l.sh_lo = shadow ? take(sizeof(double) * p.nw * p.Wpad) : 0;
+    l.hprev = shadow ? take(sizeof(uint32_t) * p.nw * p.Wpad) : 0;
     l.replica = take(sizeof(uint32_t) * p.nw);
     l.walkin_att = take(sizeof(int64_t) * p.nw);
     l.walkin_done = take(sizeof(int32_t) * p.nw);
+    l.walkin_bound = take(sizeof(int32_t) * p.nw);
     l.walkin_cnt = take(sizeof(uint32_t) * (size_t)p.nw * p.Bpad);
     l.lnf = take(sizeof(double) * p.h);
     l.lnf_last = take(sizeof(double) * p.h);
@@ -122,6 +127,8 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     if (op.sync_attempts < 1) return fail(REWL_EINVAL, "sync_attempts must be >= 1");
     if (op.precision < 0 || op.precision > 1) return fail(REWL_EINVAL, "precision must be 0 or 1");
     if (op.schedule < 0 || op.schedule > 1) return fail(REWL_EINVAL, "schedule must be 0 or 1");
+    if (op.shadow < 0 || op.shadow > 1) return fail(REWL_EINVAL, "shadow must be 0 or 1");
+    if (op.walkin_slack < 0) return fail(REWL_EINVAL, "walkin_slack must be >= 0");
     if (!(op.lnf_init >= 0.0) || !(op.lnf_final >= 0.0)) return fail(REWL_EINVAL, "ln f must be >= 0");
     starts->assign((size_t)std::max(h, 1), 0);
     int W = 0;
@@ -220,6 +227,8 @@ void rewl_default_opts(rewl_opts *o) {
     o->sync_attempts = 1000;
     o->precision = 0;
     o->fixed_lnf = 0;
+    o->shadow = 0;
+    o->walkin_slack = 16;
 }
 
 const char *rewl_last_error(void) { return g_err.c_str(); }
@@ -239,7 +248,7 @@ size_t rewl_workspace_bytes(int model, int L, int q, int windows, double overlap
     Params p;
     std::vector<int32_t> starts;
     if (check_params(model, L, q, windows, overlap, walkers, op, &p, &starts) != REWL_OK) return 0;
-    return make_layout(p, op.precision).total;
+    return make_layout(p, op.precision, op.shadow).total;
 }
 
 int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overlap, int walkers,
@@ -256,7 +265,7 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     if (!init_spins) return fail(REWL_EINVAL, "init_spins is required");
     for (size_t i = 0; i < (size_t)p.nw * p.N; ++i)
         if (init_spins[i] < 0 || init_spins[i] >= q) return fail(REWL_EINVAL, "spin value outside [0, q)");
-    const Layout lay = make_layout(p, op.precision);
+    const Layout lay = make_layout(p, op.precision, op.shadow);
     if (!dev_workspace) return fail(REWL_EINVAL, "null device workspace");
     if (ws_bytes < lay.total) return fail(REWL_ENOMEM, "device workspace smaller than rewl_workspace_bytes");
     if (((uintptr_t)dev_workspace) % kAlign != 0) return fail(REWL_EINVAL, "workspace must be 256-byte aligned");
@@ -279,6 +288,8 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     d.lnf_final = op.lnf_final;
     d.schedule = op.schedule; d.precision = op.precision; d.fixed_lnf = op.fixed_lnf;
     d.exchange = op.exchange; d.sync_attempts = op.sync_attempts; d.ctl = nullptr;
+    d.shadow = op.shadow;
+    d.walkin_slack = op.walkin_slack;
     d.start = (const int32_t *)(b + lay.start);
     d.spins = (int8_t *)(b + lay.spins);
     d.E = (int32_t *)(b + lay.E);
@@ -286,9 +297,13 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     d.lng_hi = op.precision == 1 ? (float *)(b + lay.lng_hi) : nullptr;
     d.lng_lo = op.precision == 1 ? (float *)(b + lay.lng_lo) : nullptr;
     d.H = (uint32_t *)(b + lay.H);
+    d.sh_hi = op.shadow ? (double *)(b + lay.sh_hi) : nullptr;
+    d.sh_lo = op.shadow ? (double *)(b + lay.sh_lo) : nullptr;
+    d.hprev = op.shadow ? (uint32_t *)(b + lay.hprev) : nullptr;
     d.replica = (uint32_t *)(b + lay.replica);
     d.walkin_att = (int64_t *)(b + lay.walkin_att);
     d.walkin_done = (int32_t *)(b + lay.walkin_done);
+    d.walkin_bound = (int32_t *)(b + lay.walkin_bound);
     d.walkin_cnt = (uint32_t *)(b + lay.walkin_cnt);
     d.lnf = (double *)(b + lay.lnf);
     d.lnf_last = (double *)(b + lay.lnf_last);
@@ -306,7 +321,21 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     d.scratch = (double *)(b + lay.scratch);
 
     auto bail = [&](int code) { delete r; return code; };
-    hipError_t e = hipMemsetAsync(r->ws, 0, lay.total, r->stream);
+    // Conflict-tag table: as large as fits when every walker of the run is to
+    // be resident at once (walkers per CU = walkers / CUs, at most 16, the
+    // register limit of the attempt kernel), so no workgroup waits for a slot.
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("device query: ") + hipGetErrorString(e)));
+    if (ncu > 0) {
+        const int per_cu = std::min((p.nw + ncu - 1) / ncu, 16);
+        const size_t share = (size_t)kMaxLds / (size_t)per_cu;
+        const size_t state = sweep_state_lds(p.Npad, p.Wpad);
+        if (share > state + 64 * 8) d.Ntag = std::min(d.Ntag, tag_entries(p.N, share - state));
+        else d.Ntag = 64;
+    }
+    e = hipMemsetAsync(r->ws, 0, lay.total, r->stream);
     if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e)));
     std::vector<int8_t> sp((size_t)p.nw * p.Npad, 0);
     for (int w = 0; w < p.nw; ++w) std::memcpy(&sp[(size_t)w * p.Npad], init_spins + (size_t)w * p.N, p.N);
@@ -511,11 +540,29 @@ int rewl_get_window(rewl_t *r, int k, double *lnf, double *lnf_last, int32_t *re
     return REWL_OK;
 }
 
+int rewl_get_shadow(rewl_t *r, int w, double *hi, double *lo) {
+    if (!r || !hi || !lo) return fail(REWL_EINVAL, "null argument");
+    const DevState &d = r->st;
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    if (!d.shadow) return fail(REWL_ESTATE, "the run keeps no shadow (opts.shadow = 0)");
+    const size_t row = (size_t)w * d.Wpad;
+    HIP_TRY(hipMemcpyAsync(hi, d.sh_hi + row, sizeof(double) * d.W, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipMemcpyAsync(lo, d.sh_lo + row, sizeof(double) * d.W, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return REWL_OK;
+}
+
 int rewl_set_lng(rewl_t *r, int w, const double *lng) {
     if (!r || !lng) return fail(REWL_EINVAL, "null argument");
     const DevState &d = r->st;
     if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
     const size_t row = (size_t)w * d.Wpad;
+    if (d.shadow) {   // the shadow restarts from the given values
+        HIP_TRY(hipMemcpyAsync(d.sh_hi + row, lng, sizeof(double) * d.W, hipMemcpyHostToDevice, r->stream));
+        HIP_TRY(hipMemsetAsync(d.sh_lo + row, 0, sizeof(double) * d.W, r->stream));
+        HIP_TRY(hipMemcpyAsync(d.hprev + row, d.H + row, sizeof(uint32_t) * d.W, hipMemcpyDeviceToDevice,
+                               r->stream));
+    }
     if (d.precision == 0) {
         HIP_TRY(hipMemcpyAsync(d.lng + row, lng, sizeof(double) * d.W, hipMemcpyHostToDevice, r->stream));
         HIP_TRY(hipStreamSynchronize(r->stream));

@@ -196,3 +196,41 @@ def test_tilted_weights_drive_walker_across_cache(tilt, precision):
     g.run(20_011)
     o.run(20_011)
     assert_same_state(g, o)
+
+
+def assert_same_shadow(g, o):
+    for w in range(g.nw):
+        gh, gl = g.shadow(w)
+        oh, ol = o.shadow(w)
+        assert np.array_equal(gh.view(np.uint64), oh.view(np.uint64)), f"shadow hi of walker {w}"
+        assert np.array_equal(gl.view(np.uint64), ol.view(np.uint64)), f"shadow lo of walker {w}"
+
+
+@pytest.mark.parametrize("precision,lnf", [(0, 0.1), (1, 0.1), (1, 3e-6)])
+def test_shadow_fixed_lnf_bitexact(precision, lnf):
+    g, o = make_pair(12, 4, 4, 3, lnf_init=lnf, fixed_lnf=1, sync_attempts=1000, exchange=1,
+                     precision=precision, seed=21, shadow=1)
+    g.run(30_000)
+    o.run(30_000)
+    assert_same_state(g, o)
+    assert_same_shadow(g, o)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_shadow_full_protocol_L8_bitexact(precision):
+    c = workloads.CONFIGS["potts_q10_L8"]
+    g, o = make_pair(c["L"], c["q"], c["windows"], 2, seed=c["seed"], flat=c["flat"],
+                     lnf_init=c["lnf_init"], lnf_final=1e-4, schedule=1, sync_attempts=20_000,
+                     exchange=c["exchange"], precision=precision, shadow=1)
+    assert g.run(10**10) == _pk().CONVERGED
+    assert o.run(10**10) == oracle.CONVERGED
+    assert_same_state(g, o)
+    assert_same_shadow(g, o)
+
+
+@pytest.mark.parametrize("slack", [0, 4, 16])
+def test_walkin_lid_bitexact(slack):
+    g, o = make_pair(20, 10, 6, 2, lnf_init=0.5, sync_attempts=2000, seed=17, walkin_slack=slack)
+    g.run(6000)
+    o.run(6000)
+    assert_same_state(g, o)

@@ -413,3 +413,101 @@ def test_invalid_parameters_are_rejected():
         oracle.Rewl(3, 2, 1, 1.0, 1, s)
     with pytest.raises(ValueError):
         oracle.Rewl(3, 3, 1, 0.5, 1, np.full((1, 9), 3, np.int8))
+
+
+# ---------------------------------------------------------------------------
+# The ln g shadow (exact reference of the accumulated ln g along a trajectory).
+from fractions import Fraction as Fr
+
+
+def _dd(p):
+    return Fr(p[0]) + Fr(p[1])
+
+
+def test_double_double_steps_against_exact_rationals():
+    rng = np.random.default_rng(5)
+    for _ in range(2000):
+        a = float(rng.uniform(-1e4, 1e4))
+        a = oracle.dd_add((a, 0.0), (float(rng.uniform(-1e-12, 1e-12)), 0.0))   # a genuine pair
+        b = (float(rng.uniform(-1e4, 1e4)), 0.0)
+        b = oracle.dd_add(b, (float(rng.uniform(-1e-12, 1e-12)), 0.0))
+        s = oracle.dd_add(a, b)
+        exact = _dd(a) + _dd(b)
+        if exact != 0:
+            assert abs(_dd(s) - exact) <= abs(exact) * Fr(1, 2**100)
+        n = int(rng.integers(1, 2**32))
+        x = float(rng.uniform(0, 1))
+        assert _dd(oracle.dd_mul_count(n, x)) == n * Fr(x)          # exact product
+        m = int(rng.integers(1, 1025))
+        q = oracle.dd_div_int(a, m)
+        assert abs(_dd(q) - _dd(a) / m) <= abs(_dd(a) / m) * Fr(1, 2**100)
+
+
+def test_shadow_is_exact_for_fixed_increments():
+    # Fixed ln f = 0.1 (not a binary fraction): no averaging, so bin b of a
+    # walker holds H(b) additions of the same double ln f.
+    spins = workloads.init_spins(5, 3, 4, 3)
+    o = oracle.Rewl(5, 3, 2, 0.75, 2, spins, seed=4, lnf_init=0.1, fixed_lnf=1, sync_attempts=500,
+                    shadow=1)
+    o.run(20_000)
+    lnf = Fr(0.1)
+    worst64 = Fr(0)
+    for w in range(4):
+        d = o.walker(w)
+        hi, lo = o.shadow(w)
+        for b in range(o.W):
+            exact = int(d["H"][b]) * lnf
+            assert abs(Fr(hi[b]) + Fr(lo[b]) - exact) <= exact * Fr(1, 2**100)
+            worst64 = max(worst64, abs(Fr(d["lng"][b]) - exact))
+    # the binary64 sums of 0.1 do round, by far less than the count times an ulp
+    assert 0 < worst64 < Fr(1, 10**9)
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_shadow_equals_binary64_where_the_arithmetic_is_exact(m):
+    # Halving from ln f = 1 keeps every increment a power of two, and the
+    # average over m = 2 or 4 walkers divides by a power of two: binary64 ln g
+    # is then exact, and its shadow must equal it bit for bit.
+    spins = workloads.init_spins(4, 2, 2 * m, 7)
+    o = oracle.Rewl(4, 2, 2, 0.75, m, spins, seed=6, lnf_init=1.0, lnf_final=1e-3, sync_attempts=400,
+                    shadow=1, threads=4)
+    assert o.run(10**8) == oracle.CONVERGED
+    assert min(o.window(k)["iterations"] for k in range(2)) >= 5
+    for w in range(2 * m):
+        hi, lo = o.shadow(w)
+        assert np.array_equal(hi, o.walker(w)["lng"]) and not np.any(lo)
+
+
+def test_shadow_measures_the_pair_rounding():
+    # binary32 (hi, lo) ln g adds ln f rounded to binary32 (TwoSum keeps the
+    # rest exact), so along the same trajectory ln g - shadow must be
+    # H(b) * (f32(ln f) - ln f) plus the pair's own (tiny) rounding.
+    spins = workloads.init_spins(6, 4, 3, 9)
+    o = oracle.Rewl(6, 4, 1, 0.75, 3, spins, seed=2, lnf_init=0.1, fixed_lnf=1, sync_attempts=1000,
+                    precision=1, shadow=1)
+    o.run(50_000)
+    step = float(np.float32(0.1)) - 0.1
+    for w in range(3):
+        hi, lo = o.shadow(w)
+        g = o.walker(w)["lng"]
+        err = (g - hi) - lo
+        expect = o.walker(w)["H"].astype(np.float64) * step
+        assert np.max(np.abs(expect)) > 1e-6
+        assert np.max(np.abs(err - expect)) < 1e-11
+
+
+def test_walkin_lid_places_walkers_and_shortens_the_walk():
+    # The lid keeps the walk-in's flooded band narrow: every walker still ends
+    # inside its window, after far fewer attempts than the unbounded walk.
+    spins = workloads.init_spins(32, 10, 16, 4)
+    att = {}
+    for slack in (0, 16):
+        o = oracle.Rewl(32, 10, 16, 0.75, 1, spins, seed=3, walkin_slack=slack, threads=8)
+        assert o.walkin() == 0
+        for w in range(16):
+            E = o.walker(w)["E"]
+            assert o.starts[w] <= E <= o.starts[w] + o.W - 1
+        att[slack] = max(o.walker(w)["walkin_attempts"] for w in range(16))
+    assert att[16] * 10 < att[0]
+    with pytest.raises(ValueError):
+        oracle.Rewl(16, 10, 8, 0.75, 1, workloads.init_spins(16, 10, 8, 4), walkin_slack=-1)
