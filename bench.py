@@ -26,6 +26,10 @@ if ROOT not in sys.path:
 LDS_BYTES_PER_ATTEMPT = 38
 # MI355X LDS bandwidth: 256 CUs x 128 B/clk x 2.4 GHz.
 LDS_PEAK_GBS = 256 * 128 * 2.4
+# HBM bytes per k_sweep launch of the potts_q10_L32 workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg copy of known size
+# (profiles/k_sweep_potts_q10_L32_pmc.md).  Valid for the kernel as profiled.
+K_SWEEP_L32_HBM_BYTES = 975_000
 # 1/t phase ends once W/t < 1e-8, i.e. after W/1e-8 attempts per walker.
 
 
@@ -267,6 +271,9 @@ def main():
     ap.add_argument("--config", default="potts_q10_L32")
     ap.add_argument("--cpu-attempts", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
+                         "times first: the reference for the HBM byte counters of a profiler run")
     ap.add_argument("--workload", choices=("potts", "batched", "precision"), default="potts",
                     help="potts: the single-run workload (--config); batched: 256 instances; "
                          "precision: the L=80 workload in binary64 and in the binary32 pair form")
@@ -275,6 +282,18 @@ def main():
         print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
               "(multi-GPU window sharding is a design note, not implemented).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration_mib:
+        import torch
+
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x torch.neg over {args.copy_calibration_mib} MiB "
+            f"(reads and writes {4 * n} bytes per launch)")
+        del src, dst
     if args.workload == "batched":
         return batched(args)
     if args.workload == "precision":
@@ -346,7 +365,8 @@ def main():
                    "L": L, "q": q, "windows": h, "walkers_per_window": m, "walkers": nw,
                    "attempts_per_step_per_walker": S, "attempts_per_step": nw * S},
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                     "frac": achieved / LDS_PEAK_GBS,
+                     "traffic": K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" else None,
                      "kernel": "k_sweep", "kernel_avg_ms": avg_ms, "kernel_launches": launches,
                      "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT},
         "per_walker_attempts_per_s": per_walker,
