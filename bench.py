@@ -263,6 +263,72 @@ def precision_study(args):
     print(json.dumps(res), flush=True)
 
 
+# Floating-point work of one trimer attempt counted as the binary64 squared
+# distance (3 multiplies, 2 adds) for the old and the new position of the
+# moved bead against each of its 191 partners; cut-off tests, potentials and
+# the sum come on top.
+TRIMER_FLOPS_PER_ATTEMPT = 2 * 191 * 5
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def trimer(args):
+    """The continuous-move workload: 64 head-tail-tail trimers, bead displacements."""
+    import torch
+
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    cfg = workloads.TRIMER
+    h, m = cfg["windows"], cfg["walkers"]
+    nw, S = h * m, cfg["sync_attempts"]
+    x = workloads.init_trimers(cfg["nmol"], cfg["box"], nw, cfg["seed"])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    g = pk.Rewl.trimer(cfg["nmol"], cfg["box"], cfg["e_min"], cfg["bin_w"], cfg["bins"], h, cfg["overlap"], m, x,
+                       device=dev, seed=cfg["seed"], flat=cfg["flat"], lnf_init=cfg["lnf_init"],
+                       lnf_final=cfg["lnf_final"], schedule=cfg["schedule"], sync_attempts=S,
+                       exchange=cfg["exchange"], precision=cfg["precision"])
+    walkin_s = walkin_with_progress(g, "trimer")
+    log(f"[bench] trimer walk-in done in {walkin_s:.1f} s")
+    if args.warmup:
+        g.run(args.warmup * S)
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    t0 = time.perf_counter()
+    g.run(args.steps * S)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sweep_ms, launches, sync_ms, syncs = g.timing()
+    g.set_timing(False)
+    value = nw * S * args.steps / el
+    avg_ms = sweep_ms / max(launches, 1)
+    achieved = TRIMER_FLOPS_PER_ATTEMPT * nw * S / (avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": "bead-displacement attempts/s (1 GPU), 64-trimer amphiphile REWL",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "trimer: 64 head-tail-tail trimers in a periodic cube of side 10, bins of 0.5 "
+                               "over [-460, 40), 16 windows at 75% overlap, 4 walkers each",
+                   "walkers": nw, "attempts_per_step_per_walker": S},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_trimer_sweep",
+                     "kernel_avg_ms": avg_ms, "kernel_launches": launches,
+                     "flops_per_attempt": TRIMER_FLOPS_PER_ATTEMPT},
+        "per_walker_attempts_per_s": S * args.steps / el,
+        "walkin_s": walkin_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,9 +340,10 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
                          "times first: the reference for the HBM byte counters of a profiler run")
-    ap.add_argument("--workload", choices=("potts", "batched", "precision"), default="potts",
+    ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer"), default="potts",
                     help="potts: the single-run workload (--config); batched: 256 instances; "
-                         "precision: the L=80 workload in binary64 and in the binary32 pair form")
+                         "precision: the L=80 workload in binary64 and in the binary32 pair form; "
+                         "trimer: the continuous-move workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
@@ -298,6 +365,8 @@ def main():
         return batched(args)
     if args.workload == "precision":
         return precision_study(args)
+    if args.workload == "trimer":
+        return trimer(args)
 
     import torch
 

@@ -44,7 +44,7 @@ extern "C" {
 
 typedef struct rewl rewl_t; /* opaque handle, owned by the library */
 
-enum rewl_model { REWL_POTTS2D = 0 };
+enum rewl_model { REWL_POTTS2D = 0, REWL_TRIMER3D = 1 /* rewl_create_trimer */ };
 
 enum rewl_status {
     REWL_OK = 0,
@@ -104,6 +104,38 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
                 size_t ws_bytes, void *hip_stream);
 
 void rewl_destroy(rewl_t *r);
+
+/* ---- Continuous-move model: amphiphilic trimers ---------------------------
+ * nmol head-tail-tail molecules (bead 3i the head, 3i+1 and 3i+2 its tails)
+ * in a periodic cube of side `box` (the paper's bead-spring amphiphile with
+ * local displacement moves, Sec. 3.2, with a simpler force field): bonds
+ * head-tail1 and tail1-tail2 harmonic, 100 (r - 1)^2; every other pair
+ * 4 (r^-12 - r^-6), tail-tail cut at r = 2.5 unshifted, pairs with a head cut
+ * at r = 2^(1/6) and shifted by +1.  A move displaces one uniformly chosen
+ * bead by a uniform vector in [-0.1, 0.1)^3 (periodic wrap).  Energies are
+ * binned: bin b = floor((E - e_min) / bin_w), b in [0, bins); the windows of
+ * Sec. 2 are laid over the bins exactly as over the Potts energies.  The
+ * energy change of a move is summed over the partner beads in a fixed order
+ * (per lane j of 64: partners j, j+64, ... left to right, then lanes pairwise
+ * by halving), so that runs are reproducible bit for bit.
+ * init_coords: host float[windows*walkers][3 nmol][3], values in [0, box).
+ * For these runs rewl_get_walker returns the configuration's bytes in
+ * `spins` (float[3 nmol][3]) and the energy bin in `E`; rewl_get_energy
+ * gives the energy.  rewl_join normalises to sum over bins of g = 1, and
+ * rewl_thermo takes bin centres as energies.  Limits: 1 <= nmol <= 1024,
+ * bins >= 8.                                                                */
+size_t rewl_trimer_workspace_bytes(int nmol, float box, double e_min, double bin_w, int bins, int windows,
+                                   double overlap, int walkers, const rewl_opts *opts);
+int rewl_create_trimer(rewl_t **out, int nmol, float box, double e_min, double bin_w, int bins, int windows,
+                       double overlap, int walkers, const rewl_opts *opts, const float *init_coords,
+                       void *dev_workspace, size_t ws_bytes, void *hip_stream);
+
+/* Windows over `bins` energy bins (bin indices, first window at 0).        */
+int rewl_window_layout_bins(int bins, int windows, double overlap, int32_t *W, int32_t *starts);
+
+/* Current energy of walker w (the Potts energy as a double, or the trimer
+ * model's continuous energy).                                               */
+int rewl_get_energy(rewl_t *r, int walker, double *E);
 
 /* Walk-in: move every walker whose energy lies outside its window into it
  * (each walker starts inside its own window, Sec. 3.2 on Fig. 7) by a

@@ -31,6 +31,14 @@ def lib():
         L.orc_create.argtypes = [i32, i32, i32, dbl, i32, u64, u32, u32, u32, dbl, dbl, i32, i64,
                                  i32, i32, i32, i32, i32, P]
         L.orc_get_shadow.argtypes = [P, i32, P, P]
+        L.orc_create_trimer.restype = P
+        L.orc_create_trimer.argtypes = [i32, ctypes.c_float, dbl, dbl, i32, i32, dbl, i32, u64, u32, u32,
+                                        u32, dbl, dbl, i32, i64, i32, i32, i32, i32, i32, P]
+        for name in ("orc_trimer_energy", "orc_get_energy"):
+            getattr(L, name).argtypes = [P, i32]
+            getattr(L, name).restype = dbl
+        L.orc_trimer_delta.argtypes = [P, i32, i32, P]
+        L.orc_trimer_delta.restype = dbl
         L.orc_get_shadow.restype = None
         for name, args in (("orc_dd_add", [P, P, dbl, dbl]), ("orc_dd_div_int", [P, P, i32]),
                            ("orc_dd_mul_count", [u32, dbl, P, P])):
@@ -53,7 +61,7 @@ def lib():
         L.orc_join.restype = i32
         L.orc_join_pieces.argtypes = [i32, i32, P, i32, i32, P, P, dbl, P, P]
         L.orc_join_pieces.restype = i32
-        L.orc_thermo.argtypes = [P, i32, i32, P, i32, P, P, P]
+        L.orc_thermo.argtypes = [P, i32, dbl, dbl, P, i32, P, P, P]
         L.orc_philox.argtypes = [P, P, P]
         L.orc_exp_poly.argtypes = [dbl]
         L.orc_exp_poly.restype = dbl
@@ -143,11 +151,13 @@ def potts_energy(spins, L):
     return lib().orc_potts_energy(_ptr(s), L)
 
 
-def thermo(lng, e_first, T):
+def thermo(lng, e_first, T, de=1.0):
+    """ln Z, U, C_v on the grid T; bin b stands for energy e_first + b de."""
     g = np.ascontiguousarray(lng, dtype=np.float64)
     T = np.ascontiguousarray(T, dtype=np.float64)
     lnZ, U, C = np.zeros_like(T), np.zeros_like(T), np.zeros_like(T)
-    lib().orc_thermo(_ptr(g), len(g), int(e_first), _ptr(T), len(T), _ptr(lnZ), _ptr(U), _ptr(C))
+    lib().orc_thermo(_ptr(g), len(g), float(e_first), float(de), _ptr(T), len(T), _ptr(lnZ), _ptr(U),
+                     _ptr(C))
     return lnZ, U, C
 
 
@@ -185,6 +195,41 @@ class Rewl:
         self.N, self.W, self.B, self.e_lo, self.nw = info[:5]
         self.starts = np.zeros(windows, dtype=np.int32)
         lib().orc_starts(self.h_, _ptr(self.starts))
+
+    @classmethod
+    def trimer(cls, nmol, box, e_min, bin_w, bins, windows, overlap, walkers, init_coords, seed=1,
+               instance=0, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0, sync_attempts=1000,
+               exchange=1, precision=0, fixed_lnf=0, shadow=0, walkin_slack=16, threads=1):
+        """REWL run of the trimer model; init_coords: float32 [walkers, 3 nmol, 3]."""
+        self = cls.__new__(cls)
+        self.h, self.m, self.precision, self.nmol = windows, walkers, precision, nmol
+        x = np.ascontiguousarray(init_coords, dtype=np.float32).reshape(-1)
+        if x.size != windows * walkers * nmol * 9:
+            raise ValueError("init_coords must hold 3 nmol beads x 3 coordinates per walker")
+        self._keep = x
+        self.h_ = lib().orc_create_trimer(nmol, box, e_min, bin_w, bins, windows, overlap, walkers, seed,
+                                          instance, flat[0], flat[1], lnf_init, lnf_final, schedule,
+                                          sync_attempts, exchange, precision, fixed_lnf, shadow,
+                                          walkin_slack, _ptr(x))
+        if not self.h_:
+            raise ValueError("oracle rejected the parameters")
+        lib().orc_set_threads(self.h_, threads)
+        info = self.info()
+        self.N, self.W, self.B, self.e_lo, self.nw = info[:5]
+        self.starts = np.zeros(windows, dtype=np.int32)
+        lib().orc_starts(self.h_, _ptr(self.starts))
+        return self
+
+    def energy(self, w):
+        """Current energy of walker w (the trimer model's continuous energy)."""
+        return lib().orc_get_energy(self.h_, w)
+
+    def trimer_energy(self, w):
+        """Total energy of walker w's configuration, recomputed from scratch."""
+        return lib().orc_trimer_energy(self.h_, w)
+
+    def trimer_delta(self, w, bead, xn):
+        return lib().orc_trimer_delta(self.h_, w, bead, _ptr(np.ascontiguousarray(xn, dtype=np.float32)))
 
     def __del__(self):
         if getattr(self, "h_", None):

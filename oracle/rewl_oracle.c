@@ -35,7 +35,10 @@ enum { ORC_OK = 0, ORC_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENOMEM = -2,
        ORC_ESTATE = -4, ORC_EBUDGET = -5 };
 
 /* Philox counter domains: the fourth counter word carries domain << 24 | instance. */
-enum { DOM_MOVE = 0, DOM_WALKIN = 2, DOM_EXCH = 3 };
+enum { DOM_MOVE = 0, DOM_WALKIN = 2, DOM_EXCH = 3, DOM_MOVE_U = 5, DOM_WALKIN_U = 6 };
+
+/* Models. */
+enum { MODEL_POTTS2D = 0, MODEL_TRIMER3D = 1 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and
@@ -183,6 +186,14 @@ static int potts_delta_e(const int8_t *s, int L, int i, int nv)
 
 /* ------------------------------------------------------------------------ */
 typedef struct {
+    int model;             /* MODEL_POTTS2D or MODEL_TRIMER3D                 */
+    /* trimer model: nmol head-tail-tail molecules (nb = 3 nmol beads, bead
+     * 3i is a head, 3i+1 and 3i+2 its tails), FP32 coordinates in a periodic
+     * cube of side `box`, energy bins of width bin_w from e_min             */
+    int nmol, nb;
+    float box;
+    double e_min, bin_w;
+    double *Ed;            /* [nw] continuous energy of each walker (trimer)  */
     int L, q, N;
     int h, m, nw;          /* windows, walkers per window, walkers            */
     int W, B, e_lo;        /* bins per window, global bins, lowest energy     */
@@ -231,6 +242,7 @@ static void orc_free(orc_t *o)
     free(o->lng_lo); free(o->H); free(o->sh_hi); free(o->sh_lo); free(o->hprev); free(o->vis); free(o->replica); free(o->walkin_att);
     free(o->lnf); free(o->lnf_last); free(o->regime); free(o->finished);
     free(o->iterations); free(o->visited); free(o->x_att); free(o->x_acc);
+    free(o->Ed);
     free(o);
 }
 
@@ -248,24 +260,22 @@ int orc_potts_energy(const int8_t *s, int L) { return potts_energy(s, L); }
 void orc_constants(double *c) { c[0] = ORC_INV_LN2; c[1] = ORC_LN2_C1; c[2] = ORC_LN2_C2; }
 void orc_constants32(float *c) { c[0] = ORC_INV_LN2_F; c[1] = ORC_LN2_C1_F; c[2] = ORC_LN2_C2_F; }
 
-/* Create a REWL run: h windows with overlap o and m walkers each (Sec. 2).
- * init_spins holds one starting lattice per walker ([h*m][L*L], values in
- * [0, q)).  Returns NULL on invalid arguments.                              */
-orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uint32_t instance,
-                  uint32_t flat_num, uint32_t flat_den, double lnf_init, double lnf_final,
-                  int schedule, int64_t sync_attempts, int exchange, int precision, int fixed_lnf,
-                  int shadow, int walkin_slack, const int8_t *init_spins)
+/* Options and state arrays shared by both models: B energy bins from e_lo,
+ * N bytes of configuration per walker.  Returns NULL on invalid options.    */
+static orc_t *orc_new(int B, int e_lo, int N, int h, double overlap, int m, uint64_t seed,
+                      uint32_t instance, uint32_t flat_num, uint32_t flat_den, double lnf_init,
+                      double lnf_final, int schedule, int64_t sync_attempts, int exchange,
+                      int precision, int fixed_lnf, int shadow, int walkin_slack)
 {
-    if (L < 3 || L > 724 || q < 2 || q > 127 || h < 1 || m < 1) return NULL;
+    if (h < 1 || m < 1) return NULL;
     if (!(overlap >= 0.0 && overlap < 1.0)) return NULL;
     if (flat_den == 0 || flat_den > 1000 || flat_num > flat_den) return NULL;
     if (sync_attempts < 1 || precision < 0 || precision > 1 || schedule < 0 || schedule > 1) return NULL;
     if (walkin_slack < 0) return NULL;
-    if (!init_spins) return NULL;
     orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
     if (!o) return NULL;
-    o->L = L; o->q = q; o->N = L * L; o->h = h; o->m = m; o->nw = h * m;
-    o->B = 2 * o->N + 1; o->e_lo = -2 * o->N;
+    o->N = N; o->h = h; o->m = m; o->nw = h * m;
+    o->B = B; o->e_lo = e_lo;
     o->start = (int *)calloc((size_t)h, sizeof(int));
     if (!o->start || window_layout(o->B, h, overlap, o->e_lo, &o->W, o->start) != ORC_OK || o->W < 8) {
         orc_free(o);
@@ -278,8 +288,8 @@ orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uin
     o->schedule = schedule; o->S = sync_attempts; o->exchange = exchange;
     o->precision = precision; o->fixed_lnf = fixed_lnf; o->shadow = shadow != 0; o->threads = 1;
     o->walkin_slack = walkin_slack;
-    size_t nw = (size_t)o->nw, N = (size_t)o->N, W = (size_t)o->W;
-    o->spin = (int8_t *)malloc(nw * N);
+    size_t nw = (size_t)o->nw, W = (size_t)o->W;
+    o->spin = (int8_t *)malloc(nw * (size_t)N);
     o->E = (int32_t *)calloc(nw, sizeof(int32_t));
     if (precision == 0) o->lng = (double *)calloc(nw * W, sizeof(double));
     else { o->lng_hi = (float *)calloc(nw * W, sizeof(float)); o->lng_lo = (float *)calloc(nw * W, sizeof(float)); }
@@ -307,15 +317,34 @@ orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uin
         orc_free(o);
         return NULL;
     }
-    for (size_t i = 0; i < nw * N; ++i) {
+    for (int w = 0; w < o->nw; ++w) o->replica[w] = (uint32_t)w;
+    for (int k = 0; k < h; ++k) o->lnf[k] = lnf_init;
+    return o;
+}
+
+/* Create a REWL run of the 2D Potts model: h windows with overlap o and m
+ * walkers each (Sec. 2).  init_spins holds one starting lattice per walker
+ * ([h*m][L*L], values in [0, q)).  Returns NULL on invalid arguments.       */
+orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uint32_t instance,
+                  uint32_t flat_num, uint32_t flat_den, double lnf_init, double lnf_final,
+                  int schedule, int64_t sync_attempts, int exchange, int precision, int fixed_lnf,
+                  int shadow, int walkin_slack, const int8_t *init_spins)
+{
+    if (L < 3 || L > 724 || q < 2 || q > 127) return NULL;
+    if (!init_spins) return NULL;
+    int N = L * L;
+    orc_t *o = orc_new(2 * N + 1, -2 * N, N, h, overlap, m, seed, instance, flat_num, flat_den,
+                       lnf_init, lnf_final, schedule, sync_attempts, exchange, precision, fixed_lnf,
+                       shadow, walkin_slack);
+    if (!o) return NULL;
+    o->model = MODEL_POTTS2D;
+    o->L = L; o->q = q;
+    size_t nw = (size_t)o->nw;
+    for (size_t i = 0; i < nw * (size_t)N; ++i) {
         if (init_spins[i] < 0 || init_spins[i] >= q) { orc_free(o); return NULL; }
         o->spin[i] = init_spins[i];
     }
-    for (int w = 0; w < o->nw; ++w) {
-        o->E[w] = potts_energy(o->spin + (size_t)w * N, L);
-        o->replica[w] = (uint32_t)w;
-    }
-    for (int k = 0; k < h; ++k) o->lnf[k] = lnf_init;
+    for (int w = 0; w < o->nw; ++w) o->E[w] = potts_energy(o->spin + (size_t)w * N, L);
     return o;
 }
 
@@ -410,6 +439,235 @@ static void potts_attempt(orc_t *o, int w, int k, double lnf, uint32_t domain, u
     if (!o->finished[k]) o->vis[ib] = 1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Coarse-grained amphiphile of three beads, head-tail-tail (the paper's lipid
+ * model, Sec. 3.2, is a bead-spring amphiphile sampled with local bead
+ * displacements; this workload keeps that structure with a simpler force
+ * field): bonds H-T1 and T1-T2 are harmonic, k (r - r0)^2 with k = 100,
+ * r0 = 1 (no factor 1/2); every other pair interacts by Lennard-Jones,
+ * 4 (r^-12 - r^-6) (sigma = epsilon = 1): tail-tail pairs cut at r = 2.5
+ * without shift, every pair involving a head cut at r = 2^(1/6) and shifted
+ * by +1 (WCA).  Periodic cube, minimum image per axis in binary32; pair
+ * energies in binary64 from the binary32 coordinate differences; the bond
+ * length by the correctly rounded binary64 square root.                    */
+static const double TRI_K = 100.0;
+static const double TRI_R0 = 1.0;
+static const double TRI_LJ_RC2 = 6.25;                    /* 2.5^2                 */
+static const double TRI_WCA_RC2 = 0x1.428a2f98d728bp+0;   /* RN(2^(1/3)) = RN((2^(1/6))^2) */
+
+static void tri_min_image(float box, const float *a, const float *b, double d[3])
+{
+    float half = 0.5f * box;
+    for (int c = 0; c < 3; ++c) {
+        float x = b[c] - a[c];
+        if (x > half) x = x - box;
+        else if (x < -half) x = x + box;
+        d[c] = (double)x;
+    }
+}
+
+static double tri_pair(const orc_t *o, int i, int j, const float *xi, const float *xj)
+{
+    double d[3];
+    tri_min_image(o->box, xi, xj, d);
+    double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    int ti = i % 3, tj = j % 3;
+    if (i / 3 == j / 3 && (ti - tj == 1 || tj - ti == 1)) {
+        double x = sqrt(r2) - TRI_R0;
+        return TRI_K * (x * x);
+    }
+    int tails = ti > 0 && tj > 0;
+    if (r2 >= (tails ? TRI_LJ_RC2 : TRI_WCA_RC2)) return 0.0;
+    double s2 = 1.0 / r2;
+    double s6 = (s2 * s2) * s2;
+    double v = 4.0 * ((s6 * s6) - s6);
+    return tails ? v : v + 1.0;
+}
+
+/* Total energy, pairs i < j in order (only at creation and in the tests).  */
+static double tri_energy(const orc_t *o, const float *x)
+{
+    double e = 0.0;
+    for (int i = 0; i < o->nb; ++i)
+        for (int j = i + 1; j < o->nb; ++j) e = e + tri_pair(o, i, j, x + 3 * i, x + 3 * j);
+    return e;
+}
+
+/* Energy change of moving bead b to xn.  The 191 partner terms
+ * t_j = V(b at xn, j) - V(b, j) (t_b = 0, t_j = 0 beyond the last bead) are
+ * summed in a fixed order: s_l = (t_l + t_{l+64}) + t_{l+128} + ... for
+ * l = 0..63, then s_l = s_l + s_{l+h} for h = 32, 16, ..., 1; the result is
+ * s_0.  Floating-point addition is not associative: the order is part of
+ * the definition so that every implementation rounds identically.          */
+static double tri_delta_e(const orc_t *o, const float *x, int b, const float *xn)
+{
+    int slots = (o->nb + 63) / 64 * 64;
+    double s[64];
+    for (int l = 0; l < 64; ++l) {
+        double acc = 0.0;
+        for (int j = l; j < slots; j += 64) {
+            double t = 0.0;
+            if (j < o->nb && j != b)
+                t = tri_pair(o, b, j, xn, x + 3 * j) - tri_pair(o, b, j, x + 3 * b, x + 3 * j);
+            acc = j == l ? t : acc + t;
+        }
+        s[l] = acc;
+    }
+    for (int h = 32; h >= 1; h /= 2)
+        for (int l = 0; l < h; ++l) s[l] = s[l] + s[l + h];
+    return s[0];
+}
+
+/* Energy bin: floor((E - e_min) / bin_w), also outside [0, B) (bounded to
+ * +-2^30), so that the walk-in's lid can follow energies above the range.  */
+static int tri_bin(const orc_t *o, double e)
+{
+    double x = (e - o->e_min) / o->bin_w;
+    if (!(x >= -1073741824.0)) return -1073741824;
+    if (x >= 1073741824.0) return 1073741824;
+    return (int)floor(x);
+}
+
+/* Displacement of one axis, uniform in [-0.1, 0.1) (0.1 (2u - 1) with u a
+ * 23-bit uniform), and the periodic wrap into [0, box).                    */
+static float tri_disp(uint32_t r) { return 0.1f * ((float)(r >> 9) * 0x1p-22f - 1.0f); }
+static float tri_wrap(float v, float box)
+{
+    if (v < 0.0f) v = v + box;
+    if (v >= box) v = v - box;
+    return v;
+}
+
+/* One bead-displacement attempt of walker w (Wang-Landau acceptance as in
+ * potts_attempt, on energy bins).  Philox block (step, walker, MOVE): bead,
+ * dx, dy, dz; block (step, walker, MOVE_U): the uniform word.               */
+static void trimer_attempt(orc_t *o, int w, int k, double lnf, uint64_t cnt)
+{
+    int W = o->W;
+    float *x = (float *)(o->spin + (size_t)w * o->N);
+    uint32_t ctr[4] = { (uint32_t)cnt, (uint32_t)(cnt >> 32), (uint32_t)w,
+                        ((uint32_t)DOM_MOVE << 24) | o->instance };
+    uint32_t r[4], ru[4];
+    philox4x32_10(ctr, o->key, r);
+    ctr[3] = ((uint32_t)DOM_MOVE_U << 24) | o->instance;
+    philox4x32_10(ctr, o->key, ru);
+    int b = (int)(((uint64_t)r[0] * (uint64_t)o->nb) >> 32);
+    float xn[3];
+    for (int c = 0; c < 3; ++c) xn[c] = tri_wrap(x[3 * b + c] + tri_disp(r[1 + c]), o->box);
+    double e_new = o->Ed[w] + tri_delta_e(o, x, b, xn);
+    int bn = tri_bin(o, e_new);
+    int lo = o->start[k], hi = o->start[k] + W - 1;
+    int acc = 0;
+    if (bn >= lo && bn <= hi) {
+        size_t io = (size_t)w * W + (o->E[w] - lo), in = (size_t)w * W + (bn - lo);
+        if (o->precision == 0) {
+            acc = accept64(o->lng[io] - o->lng[in], ru[0]);
+        } else {
+            float d = (o->lng_hi[io] - o->lng_hi[in]) + (o->lng_lo[io] - o->lng_lo[in]);
+            acc = accept32(d, ru[0]);
+        }
+    }
+    if (acc) {
+        for (int c = 0; c < 3; ++c) x[3 * b + c] = xn[c];
+        o->Ed[w] = e_new;
+        o->E[w] = bn;
+    }
+    size_t ib = (size_t)w * W + (o->E[w] - lo);
+    if (o->precision == 0) o->lng[ib] += lnf;
+    else twosum_add(&o->lng_hi[ib], &o->lng_lo[ib], (float)lnf);
+    o->H[ib] += 1u;
+    if (!o->finished[k]) o->vis[ib] = 1;
+}
+
+/* Walk-in of a trimer walker: the Potts walk-in rule on energy bins (counts
+ * over the B bins, an energy outside the range counted at the nearest end
+ * bin), same lid.                                                           */
+static int trimer_walkin(orc_t *o, int w, int64_t max_attempts)
+{
+    int k = w / o->m;
+    int lo = o->start[k], hi = o->start[k] + o->W - 1;
+    float *x = (float *)(o->spin + (size_t)w * o->N);
+    double *g = (double *)calloc((size_t)o->B, sizeof(double));
+    if (!g) return ORC_ENOMEM;
+    int64_t t = 0;
+    int slack = o->walkin_slack;
+    int down = o->E[w] > hi;
+    int bound = down ? o->E[w] + slack : o->E[w] - slack;
+    int status = ORC_OK;
+    while (!(o->E[w] >= lo && o->E[w] <= hi)) {
+        if (t >= max_attempts) { status = ORC_EBUDGET; break; }
+        uint32_t ctr[4] = { (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)w,
+                            ((uint32_t)DOM_WALKIN << 24) | o->instance };
+        uint32_t r[4], ru[4];
+        philox4x32_10(ctr, o->key, r);
+        ctr[3] = ((uint32_t)DOM_WALKIN_U << 24) | o->instance;
+        philox4x32_10(ctr, o->key, ru);
+        int b = (int)(((uint64_t)r[0] * (uint64_t)o->nb) >> 32);
+        float xn[3];
+        for (int c = 0; c < 3; ++c) xn[c] = tri_wrap(x[3 * b + c] + tri_disp(r[1 + c]), o->box);
+        double e_new = o->Ed[w] + tri_delta_e(o, x, b, xn);
+        int bn = tri_bin(o, e_new);
+        int co = o->E[w] < 0 ? 0 : (o->E[w] >= o->B ? o->B - 1 : o->E[w]);
+        int cn = bn < 0 ? 0 : (bn >= o->B ? o->B - 1 : bn);
+        double d = g[co] - g[cn];
+        int inside = slack == 0 || (down ? bn <= bound : bn >= bound);
+        if (inside && accept64(d, ru[0])) {
+            for (int c = 0; c < 3; ++c) x[3 * b + c] = xn[c];
+            o->Ed[w] = e_new;
+            o->E[w] = bn;
+            if (slack && down && o->E[w] + slack < bound) bound = o->E[w] + slack;
+            if (slack && !down && o->E[w] - slack > bound) bound = o->E[w] - slack;
+        }
+        int ci = o->E[w] < 0 ? 0 : (o->E[w] >= o->B ? o->B - 1 : o->E[w]);
+        g[ci] += 1.0;
+        ++t;
+    }
+    o->walkin_att[w] = t;
+    free(g);
+    return status;
+}
+
+/* Create a REWL run of the trimer model: nmol molecules in a periodic cube
+ * of side box; `bins` energy bins of width bin_w from e_min; windows as for
+ * the Potts model, over the bins.  init_coords: [h*m][3 nmol][3] binary32
+ * positions in [0, box).  Returns NULL on invalid arguments.               */
+orc_t *orc_create_trimer(int nmol, float box, double e_min, double bin_w, int bins, int h,
+                         double overlap, int m, uint64_t seed, uint32_t instance, uint32_t flat_num,
+                         uint32_t flat_den, double lnf_init, double lnf_final, int schedule,
+                         int64_t sync_attempts, int exchange, int precision, int fixed_lnf, int shadow,
+                         int walkin_slack, const float *init_coords)
+{
+    if (nmol < 1 || nmol > 1024 || !(box > 0.0f) || !(bin_w > 0.0) || bins < 8 || !init_coords) return NULL;
+    int nb = 3 * nmol;
+    orc_t *o = orc_new(bins, 0, nb * 3 * (int)sizeof(float), h, overlap, m, seed, instance, flat_num,
+                       flat_den, lnf_init, lnf_final, schedule, sync_attempts, exchange, precision,
+                       fixed_lnf, shadow, walkin_slack);
+    if (!o) return NULL;
+    o->model = MODEL_TRIMER3D;
+    o->nmol = nmol; o->nb = nb; o->box = box; o->e_min = e_min; o->bin_w = bin_w;
+    o->Ed = (double *)calloc((size_t)o->nw, sizeof(double));
+    if (!o->Ed) { orc_free(o); return NULL; }
+    for (int w = 0; w < o->nw; ++w) {
+        float *x = (float *)(o->spin + (size_t)w * o->N);
+        for (int i = 0; i < 3 * nb; ++i) {
+            float v = init_coords[(size_t)w * 3 * nb + i];
+            if (!(v >= 0.0f && v < box)) { orc_free(o); return NULL; }
+            x[i] = v;
+        }
+        o->Ed[w] = tri_energy(o, x);
+        o->E[w] = tri_bin(o, o->Ed[w]);
+    }
+    return o;
+}
+
+/* Test exports of the trimer model. */
+double orc_trimer_energy(const orc_t *o, int w) { return tri_energy(o, (const float *)(o->spin + (size_t)w * o->N)); }
+double orc_get_energy(const orc_t *o, int w) { return o->model == MODEL_TRIMER3D ? o->Ed[w] : (double)o->E[w]; }
+double orc_trimer_delta(const orc_t *o, int w, int b, const float *xn)
+{
+    return tri_delta_e(o, (const float *)(o->spin + (size_t)w * o->N), b, xn);
+}
+
 /* Placement before the run: each walker must carry a configuration whose
  * energy lies inside its own window (Sec. 3.2, discussion of Fig. 7).  The
  * paper does not say how; here a Wang-Landau walk with its own ln g over all
@@ -430,6 +688,14 @@ int orc_walkin(orc_t *o, int64_t max_attempts)
     (void)nt;
 #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
     for (int w = 0; w < o->nw; ++w) {
+        if (o->model == MODEL_TRIMER3D) {
+            int st = trimer_walkin(o, w, max_attempts);
+            if (st != ORC_OK) {
+#pragma omp atomic write
+                status = st;
+            }
+            continue;
+        }
         int k = w / o->m;
         int lo = o->start[k], hi = o->start[k] + o->W - 1;
         int N = o->N, L = o->L, q = o->q;
@@ -710,6 +976,7 @@ int orc_exchange(orc_t *o)
                 memcpy(o->spin + (size_t)a * N, o->spin + (size_t)b * N, (size_t)N);
                 memcpy(o->spin + (size_t)b * N, tmp, (size_t)N);
                 o->E[a] = ey; o->E[b] = ex;
+                if (o->Ed) { double te = o->Ed[a]; o->Ed[a] = o->Ed[b]; o->Ed[b] = te; }
                 uint32_t t = o->replica[a]; o->replica[a] = o->replica[b]; o->replica[b] = t;
             }
         }
@@ -742,8 +1009,10 @@ int orc_run(orc_t *o, int64_t attempts, int64_t walkin_budget)
         for (int w = 0; w < o->nw; ++w) {
             int k = w / o->m;
             double lnf = o->lnf[k];
-            for (int64_t t = 0; t < seg; ++t)
-                potts_attempt(o, w, k, lnf, DOM_MOVE, (uint64_t)(s0 + t));
+            if (o->model == MODEL_TRIMER3D)
+                for (int64_t t = 0; t < seg; ++t) trimer_attempt(o, w, k, lnf, (uint64_t)(s0 + t));
+            else
+                for (int64_t t = 0; t < seg; ++t) potts_attempt(o, w, k, lnf, DOM_MOVE, (uint64_t)(s0 + t));
         }
         o->step += seg;
         attempts -= seg;
@@ -924,42 +1193,45 @@ int orc_join(const orc_t *o, double *out, int32_t *cuts)
         orc_get_window(o, k, NULL, NULL, NULL, NULL, NULL, vis + (size_t)k * W, NULL, NULL);
         for (int b = 0; b < W; ++b) pieces[(size_t)k * W + b] = lng_get(o, k * o->m, b);
     }
-    int st_code = orc_join_pieces(h, W, st, o->e_lo, o->B, pieces, vis,
-                                  (double)o->N * log((double)o->q), out, cuts);
+    /* Potts: sum_E g(E) = q^N; trimer: no total count, sum over bins of g = 1 */
+    double log_total = o->model == MODEL_POTTS2D ? (double)o->N * log((double)o->q) : 0.0;
+    int st_code = orc_join_pieces(h, W, st, o->e_lo, o->B, pieces, vis, log_total, out, cuts);
     free(pieces); free(vis); free(st);
     return st_code;
 }
 
 /* Canonical averages from g(E) (Sec. 3.1, Fig. 3b): P(E,T) = g(E) e^{-E/T}/Z.
  * ln Z = LSE_E(ln g(E) - E/T), U = <E>, C_v = (<E^2> - <E>^2)/T^2, with the
- * variance summed as sum P (E - U)^2.  Bins with ln g = -inf are skipped.    */
-void orc_thermo(const double *lng, int B, int e_first, const double *T, int nT,
+ * variance summed as sum P (E - U)^2.  Bin b stands for the energy
+ * e_first + b de (Potts: integer energies, de = 1; trimer: bin centres).
+ * Bins with ln g = -inf are skipped.                                         */
+void orc_thermo(const double *lng, int B, double e_first, double de, const double *T, int nT,
                 double *lnZ, double *U, double *C)
 {
     for (int t = 0; t < nT; ++t) {
         double mx = -INFINITY;
         for (int b = 0; b < B; ++b) {
             if (lng[b] == -INFINITY) continue;
-            double x = lng[b] - (double)(e_first + b) / T[t];
+            double x = lng[b] - (e_first + (double)b * de) / T[t];
             if (x > mx) mx = x;
         }
         double s = 0.0;
         for (int b = 0; b < B; ++b) {
             if (lng[b] == -INFINITY) continue;
-            s += exp((lng[b] - (double)(e_first + b) / T[t]) - mx);
+            s += exp((lng[b] - (e_first + (double)b * de) / T[t]) - mx);
         }
         double lz = mx + log(s);
         double u = 0.0;
         for (int b = 0; b < B; ++b) {
             if (lng[b] == -INFINITY) continue;
-            double p = exp((lng[b] - (double)(e_first + b) / T[t]) - lz);
-            u += p * (double)(e_first + b);
+            double p = exp((lng[b] - (e_first + (double)b * de) / T[t]) - lz);
+            u += p * (e_first + (double)b * de);
         }
         double var = 0.0;
         for (int b = 0; b < B; ++b) {
             if (lng[b] == -INFINITY) continue;
-            double p = exp((lng[b] - (double)(e_first + b) / T[t]) - lz);
-            double d = (double)(e_first + b) - u;
+            double p = exp((lng[b] - (e_first + (double)b * de) / T[t]) - lz);
+            double d = (e_first + (double)b * de) - u;
             var += p * d * d;
         }
         lnZ[t] = lz;

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librewl.so")
 
 OK, CONVERGED, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET = 0, 1, -1, -2, -3, -4, -5
-POTTS2D = 0
+POTTS2D, TRIMER3D = 0, 1
 
 
 class RewlError(RuntimeError):
@@ -85,6 +85,13 @@ def lib():
         L.rewl_get_window.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.rewl_set_lng.argtypes = [P, i32, P]
         L.rewl_get_shadow.argtypes = [P, i32, P, P]
+        flt = ctypes.c_float
+        L.rewl_trimer_workspace_bytes.argtypes = [i32, flt, dbl, dbl, i32, i32, dbl, i32, ctypes.POINTER(Opts)]
+        L.rewl_trimer_workspace_bytes.restype = ctypes.c_size_t
+        L.rewl_create_trimer.argtypes = [ctypes.POINTER(P), i32, flt, dbl, dbl, i32, i32, dbl, i32,
+                                         ctypes.POINTER(Opts), P, P, ctypes.c_size_t, P]
+        L.rewl_window_layout_bins.argtypes = [i32, i32, dbl, P, P]
+        L.rewl_get_energy.argtypes = [P, i32, ctypes.POINTER(dbl)]
         L.rewl_get_lng.argtypes = [P, i32, P, i64, P, P]
         L.rewl_join.argtypes = [P, P, P]
         L.rewl_thermo.argtypes = [P, P, i32, P, P, P]
@@ -192,6 +199,48 @@ class Rewl:
         self.W, self.starts = window_layout(L, windows, overlap)
         self.B = 2 * self.N + 1
         self.e_lo = -2 * self.N
+
+    @classmethod
+    def trimer(cls, nmol, box, e_min, bin_w, bins, windows, overlap, walkers, init_coords, device=None,
+               stream=None, **opts):
+        """A run of the trimer model; init_coords: float32 [windows*walkers, 3 nmol, 3]."""
+        import torch
+
+        self = cls.__new__(cls)
+        o = make_opts(**opts)
+        self.h, self.m, self.nw = windows, walkers, windows * walkers
+        self.opts, self.precision = o, o.precision
+        self.nmol, self.box, self.e_min, self.bin_w = nmol, box, e_min, bin_w
+        self.L = self.q = 0
+        self.N = 9 * nmol * 4
+        self.B, self.e_lo = bins, 0
+        W = ctypes.c_int32(0)
+        self.starts = np.zeros(windows, dtype=np.int32)
+        _check(lib().rewl_window_layout_bins(bins, windows, overlap, ctypes.byref(W), _ptr(self.starts)))
+        self.W = W.value
+        x = np.ascontiguousarray(init_coords, dtype=np.float32).reshape(-1)
+        if x.size != self.nw * 9 * nmol:
+            raise ValueError("init_coords must hold 3 nmol beads x 3 coordinates per walker")
+        args = (nmol, box, e_min, bin_w, bins, windows, overlap, walkers, ctypes.byref(o))
+        nbytes = lib().rewl_trimer_workspace_bytes(*args)
+        if nbytes == 0:
+            _check(lib().rewl_create_trimer(ctypes.byref(ctypes.c_void_p()), *args, _ptr(x), None, 0, None))
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().rewl_create_trimer(ctypes.byref(h), *args, _ptr(x),
+                                            ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                            ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+        return self
+
+    def energy(self, w):
+        """Energy of walker w (the trimer model's continuous energy)."""
+        e = ctypes.c_double(0)
+        _check(lib().rewl_get_energy(self._h, w, ctypes.byref(e)))
+        return e.value
 
     @classmethod
     def _view(cls, handle, L, q, windows, overlap, walkers, opts, owner):

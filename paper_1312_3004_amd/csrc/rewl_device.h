@@ -13,11 +13,25 @@ namespace rewl_gpu {
 constexpr uint32_t kDomMove = 0;    // main-phase attempts
 constexpr uint32_t kDomWalkin = 2;  // walk-in attempts
 constexpr uint32_t kDomExch = 3;    // exchange permutation and acceptance words
+constexpr uint32_t kDomMoveU = 5;   // trimer model: uniform word of a main-phase attempt
+constexpr uint32_t kDomWalkinU = 6; // trimer model: uniform word of a walk-in attempt
+
+constexpr int kModelPotts2D = 0;
+constexpr int kModelTrimer3D = 1;
 
 // Everything a kernel needs to find one run's state in the device workspace.
 // Per-walker rows are padded so every row starts on a 256-byte boundary.
 struct DevState {
+    int model;                   // kModelPotts2D or kModelTrimer3D
+    // Potts: L x L lattice, q states, N = L*L sites, energies e_lo .. e_lo+B-1.
+    // Trimer: N = bytes of one configuration (3 nmol beads x 3 binary32
+    // coordinates), B energy bins of width bin_w from e_min, e_lo = 0 and
+    // E[] holds each walker's bin, Ed[] its energy.
     int L, q, N, h, m, nw, W, B, e_lo;
+    int nmol, nb;                // trimer: molecules, beads
+    float box;                   // trimer: side of the periodic cube
+    double e_min, bin_w;         // trimer: energy of bin 0's lower edge, bin width
+    double th_e0, th_de;         // energy of bin b for thermodynamics: th_e0 + b th_de
     int Npad, Wpad, Bpad;        // row strides (elements)
     int Ntag;                    // entries of the LDS conflict-tag table (power of two)
     uint32_t key0, key1, ctr3;   // Philox key and instance bits of counter word 3
@@ -30,7 +44,8 @@ struct DevState {
                                  // device by the batched form (null otherwise)
     const int32_t *start;        // [h] lowest energy of each window
     int8_t *spins;               // [nw][Npad]
-    int32_t *E;                  // [nw]
+    int32_t *E;                  // [nw] energy (Potts) or energy bin (trimer)
+    double *Ed;                  // [nw] trimer: continuous energy (null for Potts)
     double *lng;                 // [nw][Wpad]            (precision 0)
     float *lng_hi, *lng_lo;      // [nw][Wpad] each       (precision 1)
     uint32_t *H;                 // [nw][Wpad]
@@ -232,6 +247,13 @@ hipError_t launch_join(const DevState &st, double log_total, hipStream_t s);
 hipError_t launch_thermo(const DevState &st, const double *T, int nT, double *out, hipStream_t s);
 size_t sweep_lds_bytes(const DevState &st);
 size_t walkin_lds_bytes(const DevState &st);
+
+// Trimer model (rewl_trimer.hip).
+hipError_t launch_trimer_init(const DevState &st, hipStream_t s);
+hipError_t launch_trimer_walkin(const DevState &st, int64_t chunk, int64_t budget, hipStream_t s);
+hipError_t launch_trimer_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s);
+size_t trimer_sweep_lds_bytes(const DevState &st);
+size_t trimer_walkin_lds_bytes(const DevState &st);
 
 // Batched form: many independent runs, each described by one DevState in
 // device memory (`descs`).  Tasks are (instance, index) pairs.

@@ -983,6 +983,7 @@ __device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t r, in
         }
         if (threadIdx.x == 0) {
             const int t = st.E[a]; st.E[a] = st.E[b]; st.E[b] = t;
+            if (st.Ed) { const double te = st.Ed[a]; st.Ed[a] = st.Ed[b]; st.Ed[b] = te; }
             const uint32_t rr = st.replica[a]; st.replica[a] = st.replica[b]; st.replica[b] = rr;
         }
     }
@@ -1168,7 +1169,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     for (int b = tid; b < st.B; b += 256) {
         const double v = st.joined[b];
         if (v == -__builtin_inf()) continue;
-        mx = fmax(mx, v - (double)(st.e_lo + b) / temp);
+        mx = fmax(mx, v - (st.th_e0 + (double)b * st.th_de) / temp);
     }
     s[tid] = mx;
     __syncthreads();
@@ -1182,7 +1183,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     for (int b = tid; b < st.B; b += 256) {
         const double v = st.joined[b];
         if (v == -__builtin_inf()) continue;
-        z += exp((v - (double)(st.e_lo + b) / temp) - mx);
+        z += exp((v - (st.th_e0 + (double)b * st.th_de) / temp) - mx);
     }
     s[tid] = z;
     __syncthreads();
@@ -1196,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     for (int b = tid; b < st.B; b += 256) {
         const double v = st.joined[b];
         if (v == -__builtin_inf()) continue;
-        const double e = (double)(st.e_lo + b);
+        const double e = st.th_e0 + (double)b * st.th_de;
         u += exp((v - e / temp) - lnz) * e;
     }
     s[tid] = u;
@@ -1211,7 +1212,7 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     for (int b = tid; b < st.B; b += 256) {
         const double v = st.joined[b];
         if (v == -__builtin_inf()) continue;
-        const double e = (double)(st.e_lo + b);
+        const double e = st.th_e0 + (double)b * st.th_de;
         const double d = e - U;
         var += exp((v - e / temp) - lnz) * d * d;
     }
@@ -1356,11 +1357,13 @@ static hipError_t allow_lds(const void *fn, size_t bytes) {
 }
 
 hipError_t launch_init_energy(const DevState &st, hipStream_t s) {
+    if (st.model == kModelTrimer3D) return launch_trimer_init(st, s);
     hipLaunchKernelGGL(k_init_energy, dim3(st.nw), dim3(256), 0, s, st);
     return hipGetLastError();
 }
 
 hipError_t launch_walkin(const DevState &st, int64_t chunk, int64_t budget, hipStream_t s) {
+    if (st.model == kModelTrimer3D) return launch_trimer_walkin(st, chunk, budget, s);
     const size_t lds = walkin_lds_bytes(st);
     hipError_t e = allow_lds((const void *)k_walkin, lds);
     if (e != hipSuccess) return e;
@@ -1369,6 +1372,7 @@ hipError_t launch_walkin(const DevState &st, int64_t chunk, int64_t budget, hipS
 }
 
 hipError_t launch_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s) {
+    if (st.model == kModelTrimer3D) return launch_trimer_sweep(st, s0, n, s);
     const size_t lds = sweep_lds_bytes(st);
     if (st.precision == 0) {
         hipError_t e = allow_lds((const void *)k_sweep<0>, lds);

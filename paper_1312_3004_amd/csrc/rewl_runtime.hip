@@ -52,7 +52,7 @@ struct Params {
     int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad, Ntag;
 };
 
-Layout make_layout(const Params &p, int precision, int shadow) {
+Layout make_layout(const Params &p, int precision, int shadow, bool trimer) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -63,6 +63,7 @@ Layout make_layout(const Params &p, int precision, int shadow) {
     l.start = take(sizeof(int32_t) * p.h);
     l.spins = take((size_t)p.nw * p.Npad);
     l.E = take(sizeof(int32_t) * p.nw);
+    l.Ed = trimer ? take(sizeof(double) * p.nw) : 0;
     l.lng = precision == 0 ? take(sizeof(double) * p.nw * p.Wpad) : 0;
     l.lng_hi = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
     l.lng_lo = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
@@ -95,11 +96,11 @@ Layout make_layout(const Params &p, int precision, int shadow) {
     return l;
 }
 
-int layout_windows(int L, int h, double o, int *W_out, int32_t *starts) {
-    if (L < 3 || L > 724) return fail(REWL_EINVAL, "L must be in [3, 724]");
+// Windows over B bins from e_lo (Sec. 2, Fig. 1): h windows of equal width W
+// at overlap o, the first starting at e_lo and the last ending at e_lo+B-1.
+int layout_bins(int B, int e_lo, int h, double o, int *W_out, int32_t *starts) {
     if (h < 1) return fail(REWL_EINVAL, "windows must be >= 1");
     if (!(o >= 0.0 && o < 1.0)) return fail(REWL_EINVAL, "overlap must be in [0, 1)");
-    const int N = L * L, B = 2 * N + 1;
     int W = B;
     if (h > 1) {
         const double denom = 1.0 + (double)(h - 1) * (1.0 - o);
@@ -108,18 +109,21 @@ int layout_windows(int L, int h, double o, int *W_out, int32_t *starts) {
     }
     if (W < 8) return fail(REWL_EINVAL, "windows narrower than 8 energies");
     for (int k = 0; k < h; ++k) {
-        if (h == 1) { starts[k] = -2 * N; continue; }
+        if (h == 1) { starts[k] = e_lo; continue; }
         const int64_t num = 2 * (int64_t)k * (B - W) + (h - 1);
-        starts[k] = -2 * N + (int32_t)(num / (2 * (int64_t)(h - 1)));
+        starts[k] = e_lo + (int32_t)(num / (2 * (int64_t)(h - 1)));
     }
     *W_out = W;
     return REWL_OK;
 }
 
-int check_params(int model, int L, int q, int h, double o, int m, const rewl_opts &op, Params *p,
-                 std::vector<int32_t> *starts) {
-    if (model != REWL_POTTS2D) return fail(REWL_EINVAL, "unknown model");
-    if (q < 2 || q > 127) return fail(REWL_EINVAL, "q must be in [2, 127]");
+int layout_windows(int L, int h, double o, int *W_out, int32_t *starts) {
+    if (L < 3 || L > 724) return fail(REWL_EINVAL, "L must be in [3, 724]");
+    const int N = L * L;
+    return layout_bins(2 * N + 1, -2 * N, h, o, W_out, starts);
+}
+
+int check_opts(int h, int m, const rewl_opts &op) {
     if (m < 1 || m > 1024) return fail(REWL_EINVAL, "walkers per window must be in [1, 1024]");
     if ((int64_t)h * m > 65535) return fail(REWL_EINVAL, "at most 65535 walkers");
     if (op.flat_den == 0 || op.flat_den > 1000 || op.flat_num > op.flat_den)
@@ -130,9 +134,51 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     if (op.shadow < 0 || op.shadow > 1) return fail(REWL_EINVAL, "shadow must be 0 or 1");
     if (op.walkin_slack < 0) return fail(REWL_EINVAL, "walkin_slack must be >= 0");
     if (!(op.lnf_init >= 0.0) || !(op.lnf_final >= 0.0)) return fail(REWL_EINVAL, "ln f must be >= 0");
+    return REWL_OK;
+}
+
+// Geometry of the trimer model (rewl_create_trimer).
+struct TrimerGeom {
+    int nmol;
+    float box;
+    double e_min, bin_w;
+    int bins;
+};
+
+int check_trimer(const TrimerGeom &g, int h, double o, int m, const rewl_opts &op, Params *p,
+                 std::vector<int32_t> *starts) {
+    if (g.nmol < 1 || g.nmol > 1024) return fail(REWL_EINVAL, "nmol must be in [1, 1024]");
+    if (!(g.box > 0.0f) || !(g.box < 1e6f)) return fail(REWL_EINVAL, "box must be positive");
+    if (!(g.bin_w > 0.0) || !std::isfinite(g.e_min)) return fail(REWL_EINVAL, "bin_w must be > 0, e_min finite");
+    if (g.bins < 8) return fail(REWL_EINVAL, "at least 8 energy bins");
+    int st = check_opts(h, m, op);
+    if (st != REWL_OK) return st;
     starts->assign((size_t)std::max(h, 1), 0);
     int W = 0;
-    const int st = layout_windows(L, h, o, &W, starts->data());
+    st = layout_bins(g.bins, 0, h, o, &W, starts->data());
+    if (st != REWL_OK) return st;
+    p->L = 0; p->q = 0; p->N = 3 * g.nmol * 3 * (int)sizeof(float); p->h = h; p->m = m; p->nw = h * m;
+    p->W = W; p->B = g.bins; p->e_lo = 0;
+    p->Npad = (int)round_up((size_t)p->N, kAlign);
+    p->Wpad = (int)round_up((size_t)W, 64);
+    p->Bpad = (int)round_up((size_t)p->B, 64);
+    p->Ntag = 64;
+    if ((size_t)p->Npad + (size_t)p->Wpad * 12 > (size_t)kMaxLds)
+        return fail(REWL_EINVAL, "coordinates plus window state exceed the 160 KiB LDS of a CU");
+    if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
+        return fail(REWL_EINVAL, "walk-in counts over all bins exceed the 160 KiB LDS");
+    return REWL_OK;
+}
+
+int check_params(int model, int L, int q, int h, double o, int m, const rewl_opts &op, Params *p,
+                 std::vector<int32_t> *starts) {
+    if (model != REWL_POTTS2D) return fail(REWL_EINVAL, "unknown model (the trimer model has rewl_create_trimer)");
+    if (q < 2 || q > 127) return fail(REWL_EINVAL, "q must be in [2, 127]");
+    int st = check_opts(h, m, op);
+    if (st != REWL_OK) return st;
+    starts->assign((size_t)std::max(h, 1), 0);
+    int W = 0;
+    st = layout_windows(L, h, o, &W, starts->data());
     if (st != REWL_OK) return st;
     p->L = L; p->q = q; p->N = L * L; p->h = h; p->m = m; p->nw = h * m; p->W = W;
     p->B = 2 * p->N + 1; p->e_lo = -2 * p->N;
@@ -248,24 +294,18 @@ size_t rewl_workspace_bytes(int model, int L, int q, int windows, double overlap
     Params p;
     std::vector<int32_t> starts;
     if (check_params(model, L, q, windows, overlap, walkers, op, &p, &starts) != REWL_OK) return 0;
-    return make_layout(p, op.precision, op.shadow).total;
+    return make_layout(p, op.precision, op.shadow, false).total;
 }
 
-int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overlap, int walkers,
-                const rewl_opts *opts, const int8_t *init_spins, void *dev_workspace, size_t ws_bytes,
-                void *hip_stream) {
-    if (!out) return fail(REWL_EINVAL, "null handle pointer");
-    *out = nullptr;
-    rewl_opts op;
-    if (opts) op = *opts; else rewl_default_opts(&op);
-    Params p;
-    std::vector<int32_t> starts;
-    int st = check_params(model, L, q, windows, overlap, walkers, op, &p, &starts);
-    if (st != REWL_OK) return st;
-    if (!init_spins) return fail(REWL_EINVAL, "init_spins is required");
-    for (size_t i = 0; i < (size_t)p.nw * p.N; ++i)
-        if (init_spins[i] < 0 || init_spins[i] >= q) return fail(REWL_EINVAL, "spin value outside [0, q)");
-    const Layout lay = make_layout(p, op.precision, op.shadow);
+namespace {
+
+// Shared part of rewl_create / rewl_create_trimer: carve the workspace, fill
+// the device state, upload the starting configurations (p.N bytes per walker)
+// and compute the starting energies.
+int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts, const rewl_opts &op,
+               const TrimerGeom *geom, const unsigned char *init, void *dev_workspace, size_t ws_bytes,
+               void *hip_stream) {
+    const Layout lay = make_layout(p, op.precision, op.shadow, geom != nullptr);
     if (!dev_workspace) return fail(REWL_EINVAL, "null device workspace");
     if (ws_bytes < lay.total) return fail(REWL_ENOMEM, "device workspace smaller than rewl_workspace_bytes");
     if (((uintptr_t)dev_workspace) % kAlign != 0) return fail(REWL_EINVAL, "workspace must be 256-byte aligned");
@@ -280,6 +320,17 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     unsigned char *b = r->ws;
     DevState &d = r->st;
     std::memset(&d, 0, sizeof(d));
+    d.model = geom ? rewl_gpu::kModelTrimer3D : rewl_gpu::kModelPotts2D;
+    if (geom) {
+        d.nmol = geom->nmol; d.nb = 3 * geom->nmol; d.box = geom->box;
+        d.e_min = geom->e_min; d.bin_w = geom->bin_w;
+        d.th_e0 = geom->e_min + 0.5 * geom->bin_w;   // bin centres
+        d.th_de = geom->bin_w;
+        d.Ed = (double *)(b + lay.Ed);
+    } else {
+        d.th_e0 = (double)p.e_lo;
+        d.th_de = 1.0;
+    }
     d.L = p.L; d.q = p.q; d.N = p.N; d.h = p.h; d.m = p.m; d.nw = p.nw; d.W = p.W; d.B = p.B;
     d.e_lo = p.e_lo; d.Npad = p.Npad; d.Wpad = p.Wpad; d.Bpad = p.Bpad; d.Ntag = p.Ntag;
     d.key0 = (uint32_t)op.seed; d.key1 = (uint32_t)(op.seed >> 32);
@@ -328,7 +379,7 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("device query: ") + hipGetErrorString(e)));
-    if (ncu > 0) {
+    if (ncu > 0 && !geom) {
         const int per_cu = std::min((p.nw + ncu - 1) / ncu, 16);
         const size_t share = (size_t)kMaxLds / (size_t)per_cu;
         const size_t state = sweep_state_lds(p.Npad, p.Wpad);
@@ -338,7 +389,7 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     e = hipMemsetAsync(r->ws, 0, lay.total, r->stream);
     if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e)));
     std::vector<int8_t> sp((size_t)p.nw * p.Npad, 0);
-    for (int w = 0; w < p.nw; ++w) std::memcpy(&sp[(size_t)w * p.Npad], init_spins + (size_t)w * p.N, p.N);
+    for (int w = 0; w < p.nw; ++w) std::memcpy(&sp[(size_t)w * p.Npad], init + (size_t)w * p.N, p.N);
     std::vector<uint32_t> rep(p.nw);
     for (int w = 0; w < p.nw; ++w) rep[w] = (uint32_t)w;
     std::vector<double> lnf(p.h, op.lnf_init);
@@ -350,6 +401,83 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
     if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("rewl_create: ") + hipGetErrorString(e)));
     *out = r;
+    return REWL_OK;
+}
+
+}  // namespace
+
+
+int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overlap, int walkers,
+                const rewl_opts *opts, const int8_t *init_spins, void *dev_workspace, size_t ws_bytes,
+                void *hip_stream) {
+    if (!out) return fail(REWL_EINVAL, "null handle pointer");
+    *out = nullptr;
+    rewl_opts op;
+    if (opts) op = *opts; else rewl_default_opts(&op);
+    Params p;
+    std::vector<int32_t> starts;
+    int st = check_params(model, L, q, windows, overlap, walkers, op, &p, &starts);
+    if (st != REWL_OK) return st;
+    if (!init_spins) return fail(REWL_EINVAL, "init_spins is required");
+    for (size_t i = 0; i < (size_t)p.nw * p.N; ++i)
+        if (init_spins[i] < 0 || init_spins[i] >= q) return fail(REWL_EINVAL, "spin value outside [0, q)");
+    return create_run(out, p, starts, op, nullptr, (const unsigned char *)init_spins, dev_workspace, ws_bytes,
+                      hip_stream);
+}
+
+size_t rewl_trimer_workspace_bytes(int nmol, float box, double e_min, double bin_w, int bins, int windows,
+                                   double overlap, int walkers, const rewl_opts *opts) {
+    rewl_opts op;
+    if (opts) op = *opts; else rewl_default_opts(&op);
+    Params p;
+    std::vector<int32_t> starts;
+    const TrimerGeom g{nmol, box, e_min, bin_w, bins};
+    if (check_trimer(g, windows, overlap, walkers, op, &p, &starts) != REWL_OK) return 0;
+    return make_layout(p, op.precision, op.shadow, true).total;
+}
+
+int rewl_create_trimer(rewl_t **out, int nmol, float box, double e_min, double bin_w, int bins, int windows,
+                       double overlap, int walkers, const rewl_opts *opts, const float *init_coords,
+                       void *dev_workspace, size_t ws_bytes, void *hip_stream) {
+    if (!out) return fail(REWL_EINVAL, "null handle pointer");
+    *out = nullptr;
+    rewl_opts op;
+    if (opts) op = *opts; else rewl_default_opts(&op);
+    Params p;
+    std::vector<int32_t> starts;
+    const TrimerGeom g{nmol, box, e_min, bin_w, bins};
+    int st = check_trimer(g, windows, overlap, walkers, op, &p, &starts);
+    if (st != REWL_OK) return st;
+    if (!init_coords) return fail(REWL_EINVAL, "init_coords is required");
+    for (size_t i = 0; i < (size_t)p.nw * 9 * nmol; ++i)
+        if (!(init_coords[i] >= 0.0f && init_coords[i] < box))
+            return fail(REWL_EINVAL, "coordinate outside [0, box)");
+    return create_run(out, p, starts, op, &g, (const unsigned char *)init_coords, dev_workspace, ws_bytes,
+                      hip_stream);
+}
+
+int rewl_window_layout_bins(int bins, int windows, double overlap, int32_t *W, int32_t *starts) {
+    if (!W || !starts) return fail(REWL_EINVAL, "null output pointer");
+    if (bins < 8) return fail(REWL_EINVAL, "at least 8 bins");
+    int w = 0;
+    const int st = layout_bins(bins, 0, windows, overlap, &w, starts);
+    if (st == REWL_OK) *W = w;
+    return st;
+}
+
+int rewl_get_energy(rewl_t *r, int w, double *E) {
+    if (!r || !E) return fail(REWL_EINVAL, "null argument");
+    const DevState &d = r->st;
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    if (d.Ed) {
+        HIP_TRY(hipMemcpyAsync(E, d.Ed + w, sizeof(double), hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    } else {
+        int32_t e = 0;
+        HIP_TRY(hipMemcpyAsync(&e, d.E + w, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+        *E = (double)e;
+    }
     return REWL_OK;
 }
 
@@ -583,7 +711,8 @@ int rewl_set_lng(rewl_t *r, int w, const double *lng) {
 int rewl_join(rewl_t *r, double *host_out, int32_t *cuts) {
     if (!r) return fail(REWL_EINVAL, "null handle");
     const DevState &d = r->st;
-    const double log_total = (double)d.N * std::log((double)d.q);
+    // Potts: sum_E g(E) = q^N; trimer (no total count): sum over bins of g = 1
+    const double log_total = d.model == rewl_gpu::kModelPotts2D ? (double)d.N * std::log((double)d.q) : 0.0;
     HIP_TRY(rewl_gpu::launch_join(d, log_total, r->stream));
     int32_t status = 0;
     HIP_TRY(hipMemcpyAsync(&status, d.join_status, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));

@@ -511,3 +511,100 @@ def test_walkin_lid_places_walkers_and_shortens_the_walk():
     assert att[16] * 10 < att[0]
     with pytest.raises(ValueError):
         oracle.Rewl(16, 10, 8, 0.75, 1, workloads.init_spins(16, 10, 8, 4), walkin_slack=-1)
+
+
+# ---------------------------------------------------------------------------
+# Trimer model (continuous bead displacements).
+def _trimer(coords, nmol, box=10.0, e_min=-50.0, bin_w=0.5, bins=400, h=1, m=1, **kw):
+    return oracle.Rewl.trimer(nmol, box, e_min, bin_w, bins, h, 0.75, m, coords, **kw)
+
+
+def test_trimer_pair_energies_closed_forms():
+    # one molecule along x with unit bonds: both bonds at rest, head-tail2 at
+    # r = 2 beyond the WCA range -> E = 0; a second molecule's tail at the LJ
+    # minimum r = 2^(1/6) from the first tail2 -> E = -1 (the binary32
+    # coordinates carry r to ~1e-7, so -1 to ~1e-6).
+    c = np.array([[1.0, 5.0, 5.0], [2.0, 5.0, 5.0], [3.0, 5.0, 5.0]], dtype=np.float32)
+    o = _trimer(c[None], 1)
+    assert o.trimer_energy(0) == 0.0
+    rmin = 2.0 ** (1.0 / 6.0)
+    c2 = np.array([[3.0 + rmin + 2.0, 5.0, 5.0], [3.0 + rmin + 1.0, 5.0, 5.0], [3.0 + rmin, 5.0, 5.0]],
+                  dtype=np.float32)
+    o2 = _trimer(np.concatenate([c, c2])[None], 2)
+    # pairs: tail2(0)-tail2(1) at rmin -> -1; tail2(0)-tail1(1) at rmin+1 -> LJ(2.122);
+    # tail1(0)-tail2(1) at rmin+1; tail1(0)-tail1(1) at rmin+2 -> LJ(3.12) = 0 (cut)
+    lj = lambda r: 4 * (r ** -12 - r ** -6) if r < 2.5 else 0.0
+    expect = -1.0 + 2 * lj(rmin + 1.0)
+    assert abs(o2.trimer_energy(0) - expect) < 1e-5
+    # bond stretched to r = 1.5: 100 * 0.25 = 25
+    c3 = c.copy()
+    c3[2, 0] = 3.5
+    assert abs(_trimer(c3[None], 1).trimer_energy(0) - 25.0) < 1e-9
+    # WCA: head and tail2 at r = 1 (tail2 folded back): 4 (1 - 1) + 1 = 1, bonds 0
+    c4 = np.array([[1.0, 5.0, 5.0], [2.0, 5.0, 5.0], [1.5, 5.0 + np.sqrt(0.75), 5.0]], dtype=np.float32)
+    assert abs(_trimer(c4[None], 1).trimer_energy(0) - 1.0) < 1e-5
+
+
+def test_trimer_minimum_image():
+    # tails of two molecules across the periodic boundary: x = 0.3 and 9.3 are
+    # 1.0 apart through the wall, the LJ energy of r = 1 is 0.
+    a = np.array([[0.3, 2.0, 2.0], [0.3, 3.0, 2.0], [0.3, 4.0, 2.0]], dtype=np.float32)
+    b = np.array([[9.3, 2.0, 8.0], [9.3, 3.0, 8.0], [9.3, 4.0, 8.0]], dtype=np.float32)   # z 6 apart
+    base = _trimer(np.concatenate([a, b])[None], 2).trimer_energy(0)
+    b2 = b.copy()
+    b2[:, 2] = 2.0
+    e = _trimer(np.concatenate([a, b2])[None], 2).trimer_energy(0)
+    # heads at r = 1 (WCA: 4 (1 - 1) + 1 = 1), tail1-tail1 and tail2-tail2 at
+    # r = 1 (LJ 0), the two tail1-tail2 pairs at sqrt(2); head-tail pairs at
+    # sqrt(2) lie beyond the WCA range
+    lj = lambda r: 4 * (r ** -12 - r ** -6)
+    assert abs((e - base) - (1.0 + 2 * lj(np.sqrt(2.0)))) < 1e-5
+
+
+def test_trimer_delta_matches_recomputed_energy_and_drift():
+    x = workloads.init_trimers(8, 5.0, 1, 3)
+    o = _trimer(x, 8, box=5.0, e_min=-200.0, bins=1000)
+    rng = np.random.default_rng(1)
+    cur = x[0].copy()
+    for _ in range(200):
+        b = int(rng.integers(24))
+        xn = np.mod(cur[b] + rng.uniform(-0.1, 0.1, 3), 5.0).astype(np.float32)
+        d = o.trimer_delta(0, b, xn)
+        e0 = _trimer(cur[None], 8, box=5.0, e_min=-200.0, bins=1000).trimer_energy(0)
+        cur2 = cur.copy()
+        cur2[b] = xn
+        e1 = _trimer(cur2[None], 8, box=5.0, e_min=-200.0, bins=1000).trimer_energy(0)
+        assert abs(d - (e1 - e0)) <= 1e-9 * max(1.0, abs(e0))
+    # incremental energy of a long run against a full recompute
+    o = _trimer(x, 8, box=5.0, e_min=-200.0, bins=1000, lnf_init=0.0, fixed_lnf=1, sync_attempts=10_000)
+    o.run(100_000)
+    assert abs(o.energy(0) - o.trimer_energy(0)) < 1e-9
+
+
+def test_trimer_fixed_weights_detailed_balance():
+    # ln f = 0 and flat ln g: every move inside the range is accepted, so the
+    # run is a uniform random walk; with the bead displacement symmetric the
+    # energy histogram is the density of states itself, and the walker keeps
+    # a consistent energy and bin.
+    x = workloads.init_trimers(4, 4.0, 2, 5)
+    o = _trimer(x, 4, box=4.0, e_min=-60.0, bins=400, m=2, lnf_init=0.0, fixed_lnf=1, sync_attempts=5000)
+    o.run(20_000)
+    for w in range(2):
+        d = o.walker(w)
+        assert d["H"].sum() == 20_000
+        assert d["E"] == int((o.energy(w) + 60.0) // 0.5)
+        assert abs(o.energy(w) - o.trimer_energy(w)) < 1e-9
+
+
+def test_trimer_rewl_walks_in_and_converges():
+    x = workloads.init_trimers(2, 4.0, 4, 8)
+    o = _trimer(x, 2, box=4.0, e_min=-6.0, bin_w=0.5, bins=24, h=2, m=2, lnf_init=1.0, lnf_final=1e-3,
+                sync_attempts=2000, threads=4)
+    assert o.run(10**8) == oracle.CONVERGED
+    st, lng, cuts = o.join()
+    assert st == 0
+    fin = np.isfinite(lng)
+    assert fin.sum() > 10
+    assert abs(np.log(np.exp(lng[fin]).sum())) < 1e-9          # sum over bins of g = 1
+    for w in range(4):
+        assert o.starts[w // 2] <= o.walker(w)["E"] <= o.starts[w // 2] + o.W - 1

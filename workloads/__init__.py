@@ -35,6 +35,57 @@ BATCHED = dict(instances=256, L_choices=(16, 24, 32, 48), q_choices=(2, 4, 8, 10
                sweeps_per_sync=1000, exchange=1, precision=0, seed=1)
 
 
+# Amphiphile trimers (head-tail-tail): 64 molecules in a periodic cube of side
+# 10, harmonic bonds, tail-tail LJ cut at 2.5, WCA for pairs with a head,
+# +-0.1 bead displacements, energy bins of 0.5 over [e_min, e_min + 0.5 bins),
+# 16 windows at 75% overlap, 4 walkers each, binary64 ln g.  The energy range
+# comes from an annealing pre-run: its lowest energy minus a margin
+# up to above the energies of the starting configurations.
+TRIMER = dict(model="trimer", nmol=64, box=10.0, e_min=-460.0, bin_w=0.5, bins=1000, windows=16,
+              overlap=0.75, walkers=4, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
+              sync_attempts=20_000, exchange=1, precision=0, seed=1)
+
+
+def init_trimers(nmol, box, n_walkers, seed, min_dist=0.9):
+    """Starting configurations: float32 [n_walkers, 3 nmol, 3] in [0, box).
+
+    Per molecule, the head is uniform in the box and each tail sits at unit
+    distance from the previous bead along a uniform random direction; a
+    molecule is redrawn while any of its beads comes closer than min_dist to
+    a bead already placed (minimum image), so the start has no overlaps.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((n_walkers, 3 * nmol, 3), dtype=np.float32)
+    for w in range(n_walkers):
+        placed = np.zeros((0, 3))
+        for i in range(nmol):
+            for _ in range(100000):
+                beads = [rng.uniform(0.0, box, 3)]
+                for _t in range(2):
+                    v = rng.normal(size=3)
+                    beads.append(beads[-1] + v / np.linalg.norm(v))
+                beads = np.mod(np.array(beads), box)
+                ok = True
+                allb = np.concatenate([placed, beads[:0]])
+                for b in beads:
+                    if len(allb):
+                        d = np.abs(allb - b)
+                        d = np.minimum(d, box - d)
+                        if np.min(np.sum(d * d, axis=1)) < min_dist * min_dist:
+                            ok = False
+                            break
+                    allb = np.concatenate([allb, b[None]])
+                if ok:
+                    placed = np.concatenate([placed, beads])
+                    break
+            else:
+                raise RuntimeError("could not place a molecule")
+        x = placed.astype(np.float32)
+        x[x >= np.float32(box)] = np.float32(0.0)
+        out[w] = x
+    return out
+
+
 def init_spins(L, q, n_walkers, seed):
     """One uniformly random L x L lattice per walker, values in [0, q), int8."""
     rng = np.random.Generator(np.random.PCG64(seed))
