@@ -241,12 +241,51 @@ __global__ __launch_bounds__(64) void k_trimer_walkin(DevState st, int64_t chunk
 // displacement, reject it if the new energy bin leaves the window, else
 // accept with min[1, g(bin_old)/g(bin_new)]; then ln g += ln f and H += 1 at
 // the bin after the decision.
+//
+// One workgroup per walker with one wavefront per 64 partner beads: wave c
+// evaluates the partner terms t_j of j = 64c + lane and leaves them in LDS;
+// wave 0 adds them per lane in chunk order, sums the lanes by halving (lane l
+// adds lane l+h: permlane swaps for h = 32, 16, row shifts for h <= 8), and
+// takes the decision.  Every wave draws the same random words.
+
+// Lane l's copy of lane l+STEP (for the lanes that use it): permlane swaps
+// for STEP = 32, 16, a row shift inside rows of 16 lanes for STEP <= 8.
+template <int STEP>
+__device__ __forceinline__ unsigned pull_u32(unsigned v) {
+    if constexpr (STEP == 32) return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+    else if constexpr (STEP == 16) return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
+    else return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + STEP, 0xf, 0xf, false);
+}
+
+template <int STEP>
+__device__ __forceinline__ double pull(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = pull_u32<STEP>((unsigned)b);
+    const unsigned hi = pull_u32<STEP>((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// s_l + s_{l+h} for h = 32, 16, ..., 1 (lanes l < h carry the sum; the
+// others don't matter); returns lane 0's total.
+__device__ __forceinline__ double halving_sum(double s) {
+#pragma clang fp contract(off)
+    s = s + pull<32>(s);
+    s = s + pull<16>(s);
+    s = s + pull<8>(s);
+    s = s + pull<4>(s);
+    s = s + pull<2>(s);
+    s = s + pull<1>(s);
+    return lane0_d(s);
+}
+
 template <int PREC>
-__global__ __launch_bounds__(64) void k_trimer_sweep(DevState st, int64_t s0, int64_t n) {
+__global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, int64_t n) {
 #pragma clang fp contract(off)
     if (*st.converged) return;
     const int w = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
     const int k = w / st.m;
     extern __shared__ __align__(16) unsigned char smem[];
     const int W = st.W, Wpad = st.Wpad;
@@ -255,10 +294,11 @@ __global__ __launch_bounds__(64) void k_trimer_sweep(DevState st, int64_t s0, in
     float *gh = (float *)(smem + st.Npad);
     float *gl = gh + Wpad;
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
+    double *tbuf = (double *)(smem + st.Npad + (size_t)Wpad * 12);   // [nwaves][64]
     const uint32_t *gx = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
-    for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)x)[i] = gx[i];
+    for (int i = threadIdx.x; i < st.Npad / 4; i += blockDim.x) ((uint32_t *)x)[i] = gx[i];
     const size_t row = (size_t)w * Wpad;
-    for (int b = lane; b < W; b += 64) {
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
         if (PREC == 0) {
             g[b] = st.lng[row + b];
         } else {
@@ -274,54 +314,70 @@ __global__ __launch_bounds__(64) void k_trimer_sweep(DevState st, int64_t s0, in
     if (E < lo || E > hi) return;   // not walked in: leave the walker untouched
     const double lnf = st.lnf[k];
     const float lnf32 = (float)lnf;
+    const float box = st.box, half = 0.5f * st.box;
+    const int j = wave * 64 + lane;          // this lane's partner bead
+    const bool real = j < st.nb;
+    const float *xj = x + 3 * (real ? j : 0);
     for (int64_t base = 0; base < n; base += 64) {
         const int todo = (int)((n - base) < 64 ? (n - base) : 64);
         const Draw dr = draw(st, kDomMove, kDomMoveU, (uint64_t)(s0 + base + lane), (uint32_t)w);
-        for (int j = 0; j < todo; ++j) {
-            const int b = __builtin_amdgcn_readlane(dr.bead, j);
-            const float d0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(dr.d0), j));
-            const float d1 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(dr.d1), j));
-            const float d2 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(dr.d2), j));
-            const uint32_t u = __builtin_amdgcn_readlane(dr.u, j);
-            const float n0 = wrap(x[3 * b] + d0, st.box);
-            const float n1 = wrap(x[3 * b + 1] + d1, st.box);
-            const float n2 = wrap(x[3 * b + 2] + d2, st.box);
-            const double e_new = Ed + delta_e(st, x, b, n0, n1, n2, lane);
-            const int bn = energy_bin(st, e_new);
-            bool acc = false;
-            if (bn >= lo && bn <= hi) {
-                const int io = E - lo, in = bn - lo;
-                if (PREC == 0) acc = accept64(g[io] - g[in], u);
-                else acc = accept32((gh[io] - gh[in]) + (gl[io] - gl[in]), u);
+        for (int a = 0; a < todo; ++a) {
+            const int b = __builtin_amdgcn_readlane(dr.bead, a);
+            const float d0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(dr.d0), a));
+            const float d1 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(dr.d1), a));
+            const float d2 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(dr.d2), a));
+            const float o0 = x[3 * b], o1 = x[3 * b + 1], o2 = x[3 * b + 2];
+            const float n0 = wrap(o0 + d0, box);
+            const float n1 = wrap(o1 + d1, box);
+            const float n2 = wrap(o2 + d2, box);
+            double t = 0.0;
+            if (real && j != b) {
+                const float r0 = xj[0], r1 = xj[1], r2 = xj[2];
+                t = pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half) -
+                    pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half);
             }
-            if (acc) {
+            tbuf[wave * 64 + lane] = t;
+            __syncthreads();
+            if (wave == 0) {
+                double sl = tbuf[lane];
+                for (int c = 1; c < nwaves; ++c) sl = sl + tbuf[c * 64 + lane];
+                const double e_new = Ed + halving_sum(sl);
+                const int bn = energy_bin(st, e_new);
+                const uint32_t u = __builtin_amdgcn_readlane(dr.u, a);
+                bool acc = false;
+                if (bn >= lo && bn <= hi) {
+                    const int io = E - lo, in = bn - lo;
+                    if (PREC == 0) acc = accept64(g[io] - g[in], u);
+                    else acc = accept32((gh[io] - gh[in]) + (gl[io] - gl[in]), u);
+                }
+                if (acc) {
+                    if (lane == 0) {
+                        x[3 * b] = n0;
+                        x[3 * b + 1] = n1;
+                        x[3 * b + 2] = n2;
+                    }
+                    Ed = e_new;
+                    E = bn;
+                }
                 if (lane == 0) {
-                    x[3 * b] = n0;
-                    x[3 * b + 1] = n1;
-                    x[3 * b + 2] = n2;
+                    const int ib = E - lo;
+                    if (PREC == 0) {
+                        g[ib] = g[ib] + lnf;
+                    } else {
+                        float hh = gh[ib], ll = gl[ib];
+                        two_sum_add(hh, ll, lnf32);
+                        gh[ib] = hh;
+                        gl[ib] = ll;
+                    }
+                    H[ib] += 1u;
                 }
-                Ed = e_new;
-                E = bn;
-            }
-            if (lane == 0) {
-                const int ib = E - lo;
-                if (PREC == 0) {
-                    g[ib] = g[ib] + lnf;
-                } else {
-                    float hh = gh[ib], ll = gl[ib];
-                    two_sum_add(hh, ll, lnf32);
-                    gh[ib] = hh;
-                    gl[ib] = ll;
-                }
-                H[ib] += 1u;
             }
             __syncthreads();
         }
     }
-    __syncthreads();
     uint32_t *ox = (uint32_t *)(st.spins + (size_t)w * st.Npad);
-    for (int i = lane; i < st.Npad / 4; i += 64) ox[i] = ((uint32_t *)x)[i];
-    for (int b = lane; b < W; b += 64) {
+    for (int i = threadIdx.x; i < st.Npad / 4; i += blockDim.x) ox[i] = ((uint32_t *)x)[i];
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
         if (PREC == 0) {
             st.lng[row + b] = g[b];
         } else {
@@ -330,7 +386,7 @@ __global__ __launch_bounds__(64) void k_trimer_sweep(DevState st, int64_t s0, in
         }
         st.H[row + b] = H[b];
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         st.E[w] = E;
         st.Ed[w] = Ed;
     }
@@ -343,7 +399,10 @@ hipError_t allow(const void *fn, size_t bytes) {
 
 }  // namespace
 
-size_t trimer_sweep_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Wpad * 12; }
+static int trimer_waves(const DevState &st) { return (st.nb + 63) / 64; }
+size_t trimer_sweep_lds_bytes(const DevState &st) {
+    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)trimer_waves(st) * 64 * 8;
+}
 size_t trimer_walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
 
 hipError_t launch_trimer_init(const DevState &st, hipStream_t s) {
@@ -364,11 +423,11 @@ hipError_t launch_trimer_sweep(const DevState &st, int64_t s0, int64_t n, hipStr
     if (st.precision == 0) {
         hipError_t e = allow((const void *)k_trimer_sweep<0>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_trimer_sweep<0>, dim3(st.nw), dim3(64), lds, s, st, s0, n);
+        hipLaunchKernelGGL(k_trimer_sweep<0>, dim3(st.nw), dim3(64 * trimer_waves(st)), lds, s, st, s0, n);
     } else {
         hipError_t e = allow((const void *)k_trimer_sweep<1>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_trimer_sweep<1>, dim3(st.nw), dim3(64), lds, s, st, s0, n);
+        hipLaunchKernelGGL(k_trimer_sweep<1>, dim3(st.nw), dim3(64 * trimer_waves(st)), lds, s, st, s0, n);
     }
     return hipGetLastError();
 }
