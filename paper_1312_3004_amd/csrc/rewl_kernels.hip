@@ -211,7 +211,7 @@ __global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64
 constexpr double kMargin64 = 1e-10;   // log-domain slack of the exact-mode test (binary64)
 constexpr double kMargin32 = 1e-5;    // log-domain slack of the exact-mode test (binary32)
 constexpr double kTableMaxLnf = 2e-4; // table mode when ln f is at most this
-constexpr double kTableDmax = 64.0;   // table entries with |d| above this are left undecided
+constexpr double kTableDmax = 64.0;   // |d| in (64, 65]: undecided; beyond: decided by its sign
 
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
@@ -488,7 +488,10 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 float v = __builtin_nanf("");
                 if (src >= 0 && src < 64) {
                     if (fabs(d) <= kTableDmax) v = (float)d;
-                    else if (d == -__builtin_inf()) v = -__builtin_inff();
+                    // beyond 65 the block's drift (<= 64 ln f) cannot cross the
+                    // cut-off of exp at -64: d > 0 always accepts, d < 0 never
+                    else if (d > kTableDmax + 1.0) v = __builtin_inff();
+                    else if (d < -(kTableDmax + 1.0)) v = -__builtin_inff();
                 }
                 dtab[kk * 64 + lane] = v;
             }

@@ -183,7 +183,7 @@ def test_small_lnf_trajectories_bitexact(L, q, h, m, attempts, precision, lnf):
     assert_same_state(g, o)
 
 
-@pytest.mark.parametrize("tilt,precision", [(0.7, 0), (-0.7, 0), (0.7, 1), (0.05, 0)])
+@pytest.mark.parametrize("tilt,precision", [(0.7, 0), (-0.7, 0), (0.7, 1), (0.05, 0), (17.0, 0), (-17.0, 1)])
 def test_tilted_weights_drive_walker_across_cache(tilt, precision):
     # A steep fixed ln g makes the walker drift through a wide window, so it
     # leaves the 64-energy register cache inside a block.
