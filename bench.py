@@ -329,6 +329,50 @@ def trimer(args):
     print(json.dumps(out), flush=True)
 
 
+def trajectory(g, S, seconds, converge_attempts, walkin_s, early_rate):
+    """Continue the protocol of the run for `seconds` of wall time (from where
+    the measurement left it, 2,000 sync intervals per call), logging the
+    windows' ln f; returns when every window entered the 1/t regime, the rate
+    there, and the time to ln f_final from those measured parts (the 1/t phase
+    is deterministic: ln f = W / t)."""
+    import torch
+
+    import paper_1312_3004_amd as pk
+
+    t0 = time.perf_counter()
+    first_all_1t = None
+    rates = []
+    start_step = g.step
+    last_t, last_s = t0, g.step
+    while time.perf_counter() - t0 < seconds:
+        st = g.run(2000 * S)
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        ws = [g.window(k) for k in range(g.h)]
+        lnf = [w["lnf"] if not w["finished"] else w["lnf_last"] for w in ws]
+        n1t = sum(1 for w in ws if w["regime"] == 1 or w["finished"])
+        rate = (g.step - last_s) / (now - last_t)
+        if n1t == g.h:
+            rates.append(rate)
+            if first_all_1t is None:
+                first_all_1t = {"attempts_per_walker": g.step, "wall_s": now - t0}
+        log(f"[bench] trajectory t={now - t0:.0f} s step={g.step} rate/walker={rate:.4g} "
+            f"ln f max={max(lnf):.3g} min={min(lnf):.3g} windows in 1/t: {n1t}")
+        last_t, last_s = now, g.step
+        if st == pk.CONVERGED:
+            break
+    out = {"seconds": time.perf_counter() - t0, "start_attempts_per_walker": start_step,
+           "end_attempts_per_walker": g.step, "all_windows_in_1_over_t": first_all_1t}
+    if first_all_1t and rates and converge_attempts:
+        r1t = sum(rates) / len(rates)
+        # the part before (walk-in, warm-up and timed steps) at the measured rate
+        before = walkin_s + start_step / early_rate
+        out["rate_1_over_t_per_walker"] = r1t
+        out["time_to_lnf_final_s"] = (before + first_all_1t["wall_s"] +
+                                      (converge_attempts - first_all_1t["attempts_per_walker"]) / r1t)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +381,9 @@ def main():
     ap.add_argument("--config", default="potts_q10_L32")
     ap.add_argument("--cpu-attempts", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--trajectory", type=float, default=0.0,
+                    help="after the measurement, continue the run for this many seconds and report "
+                         "when every window reached the 1/t regime and the time to ln f_final")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
                          "times first: the reference for the HBM byte counters of a profiler run")
@@ -445,6 +492,8 @@ def main():
     if converge_attempts:
         out["time_to_lnf_final_s_projected"] = walkin_s + converge_attempts / per_walker
         out["attempts_per_walker_to_lnf_final"] = converge_attempts
+    if args.trajectory > 0:
+        out["trajectory"] = trajectory(g, S, args.trajectory, converge_attempts, walkin_s, per_walker)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg, spins, args.cpu_attempts)

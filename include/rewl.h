@@ -187,6 +187,16 @@ int rewl_get_window(rewl_t *r, int window, double *lnf, double *lnf_last, int32_
  * hi, lo: host double[W].  REWL_ESTATE if the run keeps no shadow.          */
 int rewl_get_shadow(rewl_t *r, int walker, double *hi, double *lo);
 
+/* Checkpoint / resume.  rewl_save writes the whole state of the run (its
+ * device workspace and the host-side counters, behind a header that records
+ * the run's parameters) into host memory: with buf = NULL it only stores the
+ * required size in *n; with cap smaller than that it fails with REWL_ENOMEM.
+ * rewl_load restores such a checkpoint into a handle created with the same
+ * model, sizes and options (REWL_EINVAL otherwise); the run then continues
+ * bit for bit as the saved one would have.  Both synchronise the stream.     */
+int rewl_save(rewl_t *r, void *buf, size_t cap, size_t *n);
+int rewl_load(rewl_t *r, const void *buf, size_t n);
+
 /* Overwrite ln g of walker w from host double[W] (fixed-weight sampling,
  * Sec. 3.2: "continued generating data with fixed weights 1/g(E)").         */
 int rewl_set_lng(rewl_t *r, int walker, const double *lng);

@@ -92,6 +92,8 @@ def lib():
                                          ctypes.POINTER(Opts), P, P, ctypes.c_size_t, P]
         L.rewl_window_layout_bins.argtypes = [i32, i32, dbl, P, P]
         L.rewl_get_energy.argtypes = [P, i32, ctypes.POINTER(dbl)]
+        L.rewl_save.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.rewl_load.argtypes = [P, P, ctypes.c_size_t]
         L.rewl_get_lng.argtypes = [P, i32, P, i64, P, P]
         L.rewl_join.argtypes = [P, P, P]
         L.rewl_thermo.argtypes = [P, P, i32, P, P, P]
@@ -236,6 +238,19 @@ class Rewl:
         self._h = h
         return self
 
+    def save(self):
+        """Checkpoint of the whole run (bytes)."""
+        n = ctypes.c_size_t(0)
+        _check(lib().rewl_save(self._h, None, 0, ctypes.byref(n)))
+        buf = np.zeros(n.value, dtype=np.uint8)
+        _check(lib().rewl_save(self._h, _ptr(buf), n.value, ctypes.byref(n)))
+        return buf.tobytes()
+
+    def load(self, blob):
+        """Restore a checkpoint written by save() of a run with the same sizes and options."""
+        buf = np.frombuffer(blob, dtype=np.uint8)
+        _check(lib().rewl_load(self._h, _ptr(buf), buf.size))
+
     def energy(self, w):
         """Energy of walker w (the trimer model's continuous energy)."""
         e = ctypes.c_double(0)
@@ -253,8 +268,8 @@ class Rewl:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and getattr(self, "_owner", None) is None:
-            lib().rewl_destroy(h)
+        if h is not None and h.value and getattr(self, "_owner", None) is None and _lib is not None:
+            _lib.rewl_destroy(h)
             self._h = None
 
     @property
@@ -399,8 +414,8 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().rewl_batch_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            _lib.rewl_batch_destroy(h)
             self._h = None
 
     def instance(self, i):

@@ -668,6 +668,83 @@ int rewl_get_window(rewl_t *r, int k, double *lnf, double *lnf_last, int32_t *re
     return REWL_OK;
 }
 
+namespace {
+
+// Checkpoint header: the run's identity (sizes and options that fix the
+// workspace layout and the trajectory) and its host-side counters.
+struct SaveHeader {
+    char magic[8];          // "REWLCKP1"
+    uint64_t ws_bytes;
+    int32_t model, L, q, N, h, m, W, B, nmol, precision, shadow, fixed_lnf, schedule, exchange;
+    float box;
+    int32_t walkin_slack;
+    double e_min, bin_w, lnf_init, lnf_final;
+    uint64_t seed;
+    uint32_t instance, flat_num, flat_den, reserved;
+    int64_t sync_attempts, step, round;
+    int32_t walked_in, converged;
+};
+
+SaveHeader make_header(const rewl *r) {
+    SaveHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, "REWLCKP1", 8);
+    const DevState &d = r->st;
+    h.ws_bytes = r->lay.total;
+    h.model = d.model; h.L = d.L; h.q = d.q; h.N = d.N; h.h = d.h; h.m = d.m; h.W = d.W; h.B = d.B;
+    h.nmol = d.nmol; h.precision = d.precision; h.shadow = d.shadow; h.fixed_lnf = d.fixed_lnf;
+    h.schedule = d.schedule; h.exchange = d.exchange; h.box = d.box; h.walkin_slack = d.walkin_slack;
+    h.e_min = d.e_min; h.bin_w = d.bin_w;
+    h.lnf_init = r->opts.lnf_init; h.lnf_final = r->opts.lnf_final;
+    h.seed = r->opts.seed; h.instance = r->opts.instance;
+    h.flat_num = r->opts.flat_num; h.flat_den = r->opts.flat_den;
+    h.sync_attempts = r->opts.sync_attempts;
+    h.step = r->step; h.round = r->round;
+    h.walked_in = r->walked_in ? 1 : 0;
+    h.converged = r->converged ? 1 : 0;
+    return h;
+}
+
+}  // namespace
+
+int rewl_save(rewl_t *r, void *buf, size_t cap, size_t *n) {
+    if (!r || !n) return fail(REWL_EINVAL, "null argument");
+    const size_t need = sizeof(SaveHeader) + r->lay.total;
+    *n = need;
+    if (!buf) return REWL_OK;
+    if (cap < need) return fail(REWL_ENOMEM, "checkpoint buffer smaller than the required size");
+    const SaveHeader h = make_header(r);
+    std::memcpy(buf, &h, sizeof(h));
+    HIP_TRY(hipMemcpyAsync((unsigned char *)buf + sizeof(h), r->ws, r->lay.total, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return REWL_OK;
+}
+
+int rewl_load(rewl_t *r, const void *buf, size_t n) {
+    if (!r || !buf) return fail(REWL_EINVAL, "null argument");
+    if (n < sizeof(SaveHeader)) return fail(REWL_EINVAL, "checkpoint too short");
+    SaveHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    SaveHeader mine = make_header(r);
+    if (std::memcmp(h.magic, "REWLCKP1", 8) != 0) return fail(REWL_EINVAL, "not a checkpoint");
+    // everything but the counters must match the handle
+    SaveHeader a = h, b = mine;
+    a.step = b.step = 0; a.round = b.round = 0;
+    a.walked_in = b.walked_in = 0; a.converged = b.converged = 0;
+    if (std::memcmp(&a, &b, sizeof(a)) != 0)
+        return fail(REWL_EINVAL, "checkpoint of a run with other sizes or options");
+    if (n < sizeof(SaveHeader) + h.ws_bytes) return fail(REWL_EINVAL, "checkpoint truncated");
+    HIP_TRY(hipMemcpyAsync(r->ws, (const unsigned char *)buf + sizeof(h), r->lay.total, hipMemcpyHostToDevice,
+                           r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    r->step = h.step;
+    r->round = h.round;
+    r->walked_in = h.walked_in != 0;
+    r->converged = h.converged != 0;
+    r->joined = false;
+    return REWL_OK;
+}
+
 int rewl_get_shadow(rewl_t *r, int w, double *hi, double *lo) {
     if (!r || !hi || !lo) return fail(REWL_EINVAL, "null argument");
     const DevState &d = r->st;

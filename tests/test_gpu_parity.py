@@ -234,3 +234,23 @@ def test_walkin_lid_bitexact(slack):
     g.run(6000)
     o.run(6000)
     assert_same_state(g, o)
+
+
+def test_checkpoint_resume_bitexact():
+    # save after a segment, restore into a fresh run of the same parameters,
+    # continue both: identical to the oracle's uninterrupted run
+    args = dict(lnf_init=1.0, lnf_final=1e-4, schedule=1, sync_attempts=1500, seed=12, shadow=1)
+    g, o = make_pair(10, 6, 4, 2, **args)
+    g.run(30_000)
+    blob = g.save()
+    spins = workloads.init_spins(10, 6, 8, 1)
+    g2 = _pk().Rewl(10, 6, 4, 0.75, 2, spins, **args)
+    g2.load(blob)
+    assert g2.step == 30_000
+    g2.run(25_000)
+    o.run(55_000)
+    assert_same_state(g2, o)
+    assert_same_shadow(g2, o)
+    bad = _pk().Rewl(10, 6, 4, 0.75, 2, spins, **dict(args, seed=13))
+    with pytest.raises(_pk().RewlError):
+        bad.load(blob)
