@@ -271,6 +271,16 @@ typedef struct {
     int32_t grid;           /* out: workgroups of the attempt kernel                 */
     int32_t resident;       /* out: workgroups per CU the occupancy calculator allows */
     double ms_per_step;     /* out (rewl_batch_tune): measured ms per batched step   */
+    /* Mixed-slot form (mixed = 1): one workgroup per CU whose wavefronts own LDS
+     * slots sized per instance class (classes = instances of equal LDS need,
+     * largest first, at most 8); a wave serves its class, then the smaller ones.
+     * walkers_per_cu and tag_policy are then ignored.                          */
+    int32_t mixed;
+    int32_t tag_bytes;      /* mixed: conflict-tag table of a walker at most this    */
+                            /*    many bytes (power-of-two entries, >= 64)           */
+    int32_t slot_count[8];  /* mixed: slots per CU of each class (sum <= 16)         */
+    int32_t nclasses;       /* out: instance classes of the batch                    */
+    int32_t class_lds[8];   /* out: LDS bytes of a walker of each class              */
 } rewl_batch_plan;
 
 /* Device workspace for these instances (bytes), 0 if any is invalid.        */
@@ -301,8 +311,9 @@ int rewl_batch_set_plan(rewl_batch_t *b, rewl_batch_plan *plan);
 int rewl_batch_get_plan(rewl_batch_t *b, rewl_batch_plan *plan);
 
 /* Autotuner: time `steps_per_plan` batched steps under every feasible plan
- * (walkers per CU from 1 to the occupancy limit x both tag policies), keep the
- * fastest (with use_graph = 1).  The trial steps are ordinary steps of the
+ * (uniform: walkers per CU from 1 to the occupancy limit x both tag policies;
+ * mixed-slot: slot mixes proportional to each class's work for several slot
+ * totals and tag-table sizes), keep the fastest (with use_graph = 1).  The trial steps are ordinary steps of the
  * runs (results do not depend on the plan).  tried: host array of `cap`
  * plans (may be NULL) receiving every trial with its ms_per_step; *n_tried
  * the number of trials.                                                      */

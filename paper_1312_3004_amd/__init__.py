@@ -50,10 +50,15 @@ class Plan(ctypes.Structure):
     """Mirror of rewl_batch_plan in include/rewl.h."""
     _fields_ = [("walkers_per_cu", ctypes.c_int32), ("tag_policy", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("resident", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+                ("resident", ctypes.c_int32), ("ms_per_step", ctypes.c_double), ("mixed", ctypes.c_int32),
+                ("tag_bytes", ctypes.c_int32), ("slot_count", ctypes.c_int32 * 8), ("nclasses", ctypes.c_int32),
+                ("class_lds", ctypes.c_int32 * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["slot_count"] = list(self.slot_count)[: self.nclasses]
+        d["class_lds"] = list(self.class_lds)[: self.nclasses]
+        return d
 
 
 _lib = None
@@ -443,9 +448,15 @@ class Batch:
         _check(lib().rewl_batch_get_plan(self._h, ctypes.byref(p)))
         return p.as_dict()
 
-    def set_plan(self, walkers_per_cu=0, tag_policy=0, use_graph=1):
+    def set_plan(self, walkers_per_cu=0, tag_policy=0, use_graph=1, slot_count=None, tag_bytes=4096):
+        """Uniform plan, or with slot_count (slots per CU per class, largest class
+        first) the mixed-slot plan."""
         p = Plan()
         p.walkers_per_cu, p.tag_policy, p.use_graph = walkers_per_cu, tag_policy, use_graph
+        if slot_count is not None:
+            p.mixed, p.tag_bytes = 1, tag_bytes
+            for i, c in enumerate(slot_count):
+                p.slot_count[i] = c
         _check(lib().rewl_batch_set_plan(self._h, ctypes.byref(p)))
         return p.as_dict()
 

@@ -6,6 +6,7 @@
 // Workspace: [descriptor table | task lists | counters | status | queue]
 // followed by one single-run workspace per instance (rewl_create layout).
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -24,7 +25,7 @@ constexpr int64_t kWalkinChunk = int64_t(1) << 20;
 constexpr int kStatusEvery = 16;   // batched steps between convergence reads
 
 struct BatchLayout {
-    size_t descs, tasks, tasks_inst, wtasks, xtasks, ctl, status, queue, inst0, total;
+    size_t descs, tasks, tasks_inst, tasks_cls, wtasks, xtasks, ctl, status, queue, slots, inst0, total;
     std::vector<size_t> inst;      // offset of each instance's workspace
     std::vector<size_t> inst_bytes;
 };
@@ -55,11 +56,13 @@ BatchLayout batch_layout(int n, const rewl_instance *inst) {
     l.descs = take(sizeof(DevState) * n);
     l.tasks = take(sizeof(BatchTask) * walkers);
     l.tasks_inst = take(sizeof(BatchTask) * walkers);
+    l.tasks_cls = take(sizeof(BatchTask) * walkers);
     l.wtasks = take(sizeof(BatchTask) * windows);
     l.xtasks = take(sizeof(BatchTask) * pairs);
     l.ctl = take(sizeof(int64_t) * 2 * n);
     l.status = take(sizeof(BatchStatus) * n);
     l.queue = take(sizeof(int) * 64);
+    l.slots = take(sizeof(rewl_gpu::SlotPlan));
     l.inst0 = off;
     for (int i = 0; i < n; ++i) {
         const size_t bytes = rewl_workspace_bytes(inst[i].model, inst[i].L, inst[i].q, inst[i].windows,
@@ -81,7 +84,8 @@ struct rewl_batch {
     hipStream_t stream = nullptr;     // caller's stream
     hipStream_t capture = nullptr;    // library stream used only to capture the step graph
     DevState *d_descs = nullptr;
-    BatchTask *d_tasks = nullptr, *d_tasks_inst = nullptr, *d_wtasks = nullptr, *d_xtasks = nullptr;
+    BatchTask *d_tasks = nullptr, *d_tasks_inst = nullptr, *d_tasks_cls = nullptr, *d_wtasks = nullptr,
+              *d_xtasks = nullptr;
     int64_t *d_ctl = nullptr;
     BatchStatus *d_status = nullptr;
     int *d_queue = nullptr;
@@ -89,6 +93,13 @@ struct rewl_batch {
     int ntasks = 0, nwin = 0, npairs = 0;
     std::vector<int> ntag;                        // per-instance tag entries under the plan
     std::vector<size_t> lds_inst;                 // per-instance attempt-kernel LDS under the plan
+    // instance classes of the mixed-slot form: instances of equal LDS state and
+    // lattice size, largest LDS need first (at most kMaxClasses)
+    int nclasses = 0;
+    std::vector<int> cls_of;                      // class of each instance
+    std::vector<int> cls_task_lo, cls_task_n;     // class ranges of d_tasks_cls
+    rewl_gpu::SlotPlan slots{};
+    rewl_gpu::SlotPlan *d_slots = nullptr;
     rewl_batch_plan plan{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -182,10 +193,17 @@ int walkin_all(rewl_batch *b, int64_t budget) {
 
 // Enqueue one persistent batched step on `s`.
 hipError_t enqueue_step(rewl_batch *b, hipStream_t s) {
-    hipError_t e = rewl_gpu::launch_queue_reset(b->d_queue, s);
-    if (e == hipSuccess)
-        e = rewl_gpu::launch_sweep_batch(b->precision, b->d_descs, b->d_tasks, 0, b->ntasks, b->d_queue,
-                                         b->plan.grid, (size_t)b->plan.lds_bytes, s);
+    hipError_t e = hipSuccess;
+    if (b->plan.mixed) {
+        e = rewl_gpu::launch_sweep_batch_slots(b->precision, b->d_descs, b->d_tasks_cls, b->d_slots,
+                                               b->slots.nclasses, b->slots.nslots, b->d_queue, b->plan.grid,
+                                               (size_t)b->plan.lds_bytes, s);
+    } else {
+        e = rewl_gpu::launch_queue_reset(b->d_queue, s);
+        if (e == hipSuccess)
+            e = rewl_gpu::launch_sweep_batch(b->precision, b->d_descs, b->d_tasks, 0, b->ntasks, b->d_queue,
+                                             b->plan.grid, (size_t)b->plan.lds_bytes, s);
+    }
     if (e == hipSuccess) e = rewl_gpu::launch_sync_batch(b->precision, b->d_descs, b->d_wtasks, 0, b->nwin, s);
     if (e == hipSuccess) e = rewl_gpu::launch_exchange_batch(b->d_descs, b->d_xtasks, 0, b->npairs, s);
     if (e == hipSuccess) e = rewl_gpu::launch_advance_batch(b->d_descs, 0, b->n, s);
@@ -303,7 +321,72 @@ bool plan_layout(const rewl_batch *b, int wpc, int policy, std::vector<int> *nta
     return true;
 }
 
+// Tag entries of a walker with N sites when its table may take `tag_bytes`.
+int capped_tags(int N, int tag_bytes) {
+    int t = 64;
+    while (t < N && t < 4096 && 2 * t * 8 <= tag_bytes) t *= 2;
+    return t;
+}
+
+int apply_mixed(rewl_batch *b, rewl_batch_plan *p) {
+    if (p->tag_bytes < 512) return fail(REWL_EINVAL, "tag_bytes must be >= 512");
+    std::vector<int> ntag(b->n);
+    std::vector<size_t> lds(b->n);
+    std::vector<size_t> cls_lds(b->nclasses, 0);
+    for (int i = 0; i < b->n; ++i) {
+        const DevState &d = b->inst[i]->st;
+        ntag[i] = capped_tags(d.N, p->tag_bytes);
+        lds[i] = sweep_state_lds(d.Npad, d.Wpad) + (size_t)ntag[i] * 8;
+        size_t &cl = cls_lds[b->cls_of[i]];
+        cl = std::max(cl, round_up(lds[i], 256));
+    }
+    rewl_gpu::SlotPlan sp{};
+    sp.nclasses = b->nclasses;
+    int nslots = 0;
+    size_t total = 0;
+    for (int c = 0; c < b->nclasses; ++c) {
+        const int k = p->slot_count[c];
+        if (k < 0) return fail(REWL_EINVAL, "slot counts must be >= 0");
+        for (int j = 0; j < k; ++j) {
+            if (nslots >= rewl_gpu::kMaxSlots) return fail(REWL_EINVAL, "at most 16 slots per CU");
+            sp.cls[nslots] = c;
+            sp.off[nslots] = (int)total;
+            total += cls_lds[c];
+            ++nslots;
+        }
+        sp.task_lo[c] = b->cls_task_lo[c];
+        sp.task_n[c] = b->cls_task_n[c];
+    }
+    if (nslots < 1 || p->slot_count[0] < 1)
+        return fail(REWL_EINVAL, "the largest class needs at least one slot (it serves every class)");
+    if (total > (size_t)kMaxLds) return fail(REWL_EINVAL, "slots exceed the 160 KiB LDS of a CU");
+    sp.nslots = nslots;
+    int fits = 0;
+    HIP_TRY(rewl_gpu::sweep_batch_slots_fits(b->precision, total, nslots, &fits));
+    if (!fits) return fail(REWL_EINVAL, "a CU cannot hold this slot mix");
+    drop_graph(b);
+    b->ntag = ntag;
+    b->lds_inst = lds;
+    b->slots = sp;
+    HIP_TRY(hipMemcpyAsync(b->d_slots, &sp, sizeof(sp), hipMemcpyHostToDevice, b->stream));
+    rewl_batch_plan q = *p;
+    q.mixed = 1;
+    q.use_graph = p->use_graph ? 1 : 0;
+    q.lds_bytes = (int32_t)total;
+    q.grid = b->cus;
+    q.resident = nslots;
+    q.nclasses = b->nclasses;
+    for (int c = 0; c < 8; ++c) {
+        q.class_lds[c] = c < b->nclasses ? (int32_t)cls_lds[c] : 0;
+        if (c >= b->nclasses) q.slot_count[c] = 0;
+    }
+    b->plan = q;
+    *p = q;
+    return upload_descs(b);
+}
+
 int apply_plan(rewl_batch *b, rewl_batch_plan *p) {
+    if (p->mixed) return apply_mixed(b, p);
     if (p->tag_policy < 0 || p->tag_policy > 1) return fail(REWL_EINVAL, "tag_policy must be 0 or 1");
     if (p->walkers_per_cu < 0) return fail(REWL_EINVAL, "walkers_per_cu must be >= 0");
     std::vector<int> ntag;
@@ -327,6 +410,8 @@ int apply_plan(rewl_batch *b, rewl_batch_plan *p) {
     drop_graph(b);
     b->ntag = ntag;
     b->lds_inst = lds;
+    b->plan = rewl_batch_plan{};
+    b->plan.nclasses = b->nclasses;
     b->plan.walkers_per_cu = wpc;
     b->plan.tag_policy = p->tag_policy;
     b->plan.use_graph = p->use_graph ? 1 : 0;
@@ -396,6 +481,7 @@ int rewl_batch_create(rewl_batch_t **out, int n, const rewl_instance *inst, cons
     b->d_ctl = (int64_t *)(b->ws + lay.ctl);
     b->d_status = (BatchStatus *)(b->ws + lay.status);
     b->d_queue = (int *)(b->ws + lay.queue);
+    b->d_slots = (rewl_gpu::SlotPlan *)(b->ws + lay.slots);
 
     int dev = 0;
     hipDeviceProp_t prop;
@@ -439,6 +525,34 @@ int rewl_batch_create(rewl_batch_t **out, int n, const rewl_instance *inst, cons
     std::stable_sort(tasks.begin(), tasks.end(), [&](const BatchTask &x, const BatchTask &y) {
         return b->inst[x.inst]->opts.sync_attempts > b->inst[y.inst]->opts.sync_attempts;
     });
+    // classes: distinct (LDS state, sites), ordered by LDS need with exact tags
+    {
+        std::vector<std::pair<size_t, int>> keys;   // (need, sites) per instance
+        for (int i = 0; i < n; ++i) {
+            const DevState &d = b->inst[i]->st;
+            keys.push_back({sweep_state_lds(d.Npad, d.Wpad) + (size_t)std::min(d.N, 4096) * 8, d.N});
+        }
+        std::vector<std::pair<size_t, int>> uniq = keys;
+        std::sort(uniq.begin(), uniq.end(), [](const auto &x, const auto &y) { return x > y; });
+        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        b->cls_of.assign(n, 0);
+        for (int i = 0; i < n; ++i) {
+            const int pos = (int)(std::find(uniq.begin(), uniq.end(), keys[i]) - uniq.begin());
+            b->cls_of[i] = std::min(pos, rewl_gpu::kMaxClasses - 1);
+        }
+        b->nclasses = std::min((int)uniq.size(), rewl_gpu::kMaxClasses);
+        std::vector<BatchTask> tcls;
+        for (int c = 0; c < b->nclasses; ++c) {
+            b->cls_task_lo.push_back((int)tcls.size());
+            for (const BatchTask &t : tasks_inst)
+                if (b->cls_of[t.inst] == c) tcls.push_back(t);
+            b->cls_task_n.push_back((int)tcls.size() - b->cls_task_lo.back());
+        }
+        b->d_tasks_cls = (BatchTask *)(b->ws + lay.tasks_cls);
+        e = hipMemcpyAsync(b->d_tasks_cls, tcls.data(), sizeof(BatchTask) * tcls.size(), hipMemcpyHostToDevice,
+                           b->stream);
+        if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("rewl_batch_create: ") + hipGetErrorString(e)));
+    }
     b->ntasks = (int)tasks.size();
     b->nwin = (int)wtasks.size();
     b->npairs = (int)xtasks.size();
@@ -506,7 +620,7 @@ int rewl_batch_tune(rewl_batch_t *b, int steps_per_plan, rewl_batch_plan *tried,
     // both tag policies; a plan whose layout equals an earlier one is skipped
     std::vector<rewl_batch_plan> cands;
     std::vector<std::vector<int>> seen;
-    for (int policy = 0; policy <= 1; ++policy) {
+    for (int policy = 0; policy <= (b->nclasses > 1 ? 0 : 1); ++policy) {
         for (int c = 1; c <= 64; ++c) {
             std::vector<int> ntag;
             std::vector<size_t> lds;
@@ -524,6 +638,66 @@ int rewl_batch_tune(rewl_batch_t *b, int steps_per_plan, rewl_batch_plan *tried,
             p.tag_policy = policy;
             p.use_graph = 0;
             cands.push_back(p);
+        }
+    }
+    // mixed-slot plans.  Tasks of class c run on slots of classes 0..c, so with
+    // k_c slots of class c the step takes at least
+    //   max_c (work of classes 0..c) / (slots of classes 0..c);
+    // every slot mix within the LDS and the 16 waves of a CU is ranked by that
+    // bound and the best few (per tag-table cap) are timed.
+    if (b->nclasses > 1 && b->nclasses <= 6) {
+        std::vector<double> work(b->nclasses, 0.0);
+        for (int i = 0; i < b->n; ++i)
+            work[b->cls_of[i]] += (double)b->inst[i]->st.nw * (double)b->inst[i]->opts.sync_attempts;
+        for (int tag_bytes : {4096, 8192}) {
+            std::vector<size_t> cl(b->nclasses, 0);
+            for (int i = 0; i < b->n; ++i) {
+                const DevState &d = b->inst[i]->st;
+                const size_t need = sweep_state_lds(d.Npad, d.Wpad) + (size_t)capped_tags(d.N, tag_bytes) * 8;
+                cl[b->cls_of[i]] = std::max(cl[b->cls_of[i]], round_up(need, 256));
+            }
+            std::vector<std::pair<double, std::vector<int>>> ranked;
+            std::vector<int> k(b->nclasses, 0);
+            // depth-first over slot counts, class 0 first
+            std::vector<int> stack_pos;
+            std::function<void(int, int, size_t)> rec = [&](int c, int used, size_t lds) {
+                if (c == b->nclasses) {
+                    if (k[0] < 1) return;
+                    double bound = 0.0, wsum = 0.0;
+                    int ksum = 0;
+                    for (int x = 0; x < b->nclasses; ++x) {
+                        wsum += work[x];
+                        ksum += k[x];
+                        bound = std::max(bound, ksum > 0 ? wsum / ksum : 1e300);
+                    }
+                    ranked.push_back({bound, k});
+                    return;
+                }
+                for (int v = 0; used + v <= rewl_gpu::kMaxSlots && lds + (size_t)v * cl[c] <= (size_t)kMaxLds; ++v) {
+                    k[c] = v;
+                    rec(c + 1, used + v, lds + (size_t)v * cl[c]);
+                }
+                k[c] = 0;
+            };
+            rec(0, 0, 0);
+            std::sort(ranked.begin(), ranked.end(),
+                      [](const auto &x, const auto &y) { return x.first < y.first; });
+            int taken = 0;
+            for (const auto &rk : ranked) {
+                if (taken >= 4) break;
+                size_t lds = 0;
+                int ns = 0;
+                for (int c = 0; c < b->nclasses; ++c) { lds += (size_t)rk.second[c] * cl[c]; ns += rk.second[c]; }
+                int fits = 0;
+                HIP_TRY(rewl_gpu::sweep_batch_slots_fits(b->precision, lds, ns, &fits));
+                if (!fits) continue;
+                rewl_batch_plan p{};
+                p.mixed = 1;
+                p.tag_bytes = tag_bytes;
+                for (int c = 0; c < b->nclasses; ++c) p.slot_count[c] = rk.second[c];
+                cands.push_back(p);
+                ++taken;
+            }
         }
     }
     if (cands.empty()) return fail(REWL_EINVAL, "no feasible plan");

@@ -75,6 +75,20 @@ struct BatchTask {
     int32_t inst, idx;
 };
 
+// Mixed-slot plan of the batched attempt step: nslots wavefronts per
+// workgroup (one workgroup per CU); wavefront w owns the LDS slot at byte
+// offset off[w] and serves class cls[w] first, then the smaller classes.
+// Class c's tasks are tasks[task_lo[c] .. task_lo[c] + task_n[c]).
+constexpr int kMaxSlots = 16;
+constexpr int kMaxClasses = 8;
+struct SlotPlan {
+    int nslots, nclasses;
+    int cls[kMaxSlots];
+    int off[kMaxSlots];
+    int task_lo[kMaxClasses];
+    int task_n[kMaxClasses];
+};
+
 // Per-instance progress gathered after batched steps.
 struct BatchStatus {
     int64_t step, round;    // device-side counters (or the stop point once converged)
@@ -273,4 +287,10 @@ hipError_t launch_exchange_batch(const DevState *descs, const BatchTask *xtasks,
 hipError_t launch_advance_batch(const DevState *descs, int lo, int n, hipStream_t s);
 hipError_t launch_status_batch(const DevState *descs, int n, BatchStatus *out, hipStream_t s);
 hipError_t sweep_batch_occupancy(int precision, size_t lds_bytes, int *blocks_per_cu);
+// Mixed-slot attempt step (queue reset included); grid = workgroups (one per CU).
+// plan: device copy of the slot plan.
+hipError_t launch_sweep_batch_slots(int precision, const DevState *descs, const BatchTask *tasks,
+                                    const SlotPlan *plan, int nclasses, int nslots, int *queues, int grid,
+                                    size_t lds_bytes, hipStream_t s);
+hipError_t sweep_batch_slots_fits(int precision, size_t lds_bytes, int nslots, int *fits);
 }  // namespace rewl_gpu

@@ -250,12 +250,22 @@ __device__ __forceinline__ float f32_down(double x) {
     return f;
 }
 
-template <int PREC>
+// Orders this wavefront's LDS traffic at a phase boundary of a walker.  With
+// one walker per workgroup a workgroup barrier; with several independent
+// walkers (one per wavefront) in a workgroup a fence of the wave's own memory
+// operations (a wave's LDS operations execute in order).
+template <bool WAVE>
+__device__ __forceinline__ void walker_sync() {
+    if (WAVE) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    else __syncthreads();
+}
+
+template <int PREC, bool WAVE = false>
 __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t s0, int64_t n,
                                              unsigned char *smem) {
 #pragma clang fp contract(off)
     if (*st.converged) return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int k = w / st.m;
     const int W = st.W, Wpad = st.Wpad;
     int8_t *sp = (int8_t *)smem;
@@ -286,7 +296,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     }
     for (int i = lane; i < st.Ntag; i += 64) tag[i] = 0ull;
     cnt[lane] = 0u;
-    __syncthreads();
+    walker_sync<WAVE>();
 
     const int lo = st.start[k], hi = lo + W - 1;
     const int q = st.q;
@@ -733,7 +743,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     }
     cache_store();
     E = ebase + erel;
-    __syncthreads();
+    walker_sync<WAVE>();
     uint32_t *osp = (uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = lane; i < st.Npad / 4; i += 64) osp[i] = ((uint32_t *)sp)[i];
     for (int b = lane; b < W; b += 64) {
@@ -1301,6 +1311,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
+// Mixed-slot form of the attempt step: one workgroup per CU, one walker per
+// wavefront, and wavefront w owns an LDS slot sized for instance class
+// plan.cls[w] (classes ordered by LDS need, largest first).  A wave takes the
+// tasks of its own class from that class's queue, then those of the smaller
+// classes, which fit its slot as well.  Waves share nothing but the queues.
+template <int PREC>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch_slots(
+    const DevState *__restrict__ descs, const BatchTask *__restrict__ tasks, const SlotPlan *__restrict__ plan,
+    int *queues) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    unsigned char *mine = smem + plan->off[wave];
+    const int nclasses = plan->nclasses;
+    for (int c = plan->cls[wave]; c < nclasses; ++c) {
+        const int lo = plan->task_lo[c], nt = plan->task_n[c];
+        for (;;) {
+            int ti = 0;
+            if ((threadIdx.x & 63) == 0) ti = atomicAdd(&queues[c], 1);
+            ti = wave_broadcast(ti);
+            if (ti >= nt) break;
+            const BatchTask t = tasks[lo + ti];
+            const DevState &st = descs[t.inst];
+            sweep_walker<PREC, true>(st, t.idx, st.ctl[0], st.sync_attempts, mine);
+            walker_sync<true>();
+        }
+    }
+}
+
+__global__ void k_queue_reset_n(int *queue, int n) {
+    if ((int)threadIdx.x < n) queue[threadIdx.x] = 0;
+}
+
 // Sync point of window t.idx of instance t.inst, at the attempt count the
 // instance reaches with this step.
 template <int PREC>
@@ -1469,6 +1511,35 @@ hipError_t launch_sweep_batch(int precision, const DevState *descs, const BatchT
         hipLaunchKernelGGL((k_sweep_batch<1, false>), dim3(ntasks), dim3(64), lds_bytes, s, descs, tasks,
                            task_lo, ntasks, queue);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch_slots(int precision, const DevState *descs, const BatchTask *tasks,
+                                    const SlotPlan *plan, int nclasses, int nslots, int *queues, int grid,
+                                    size_t lds_bytes, hipStream_t s) {
+    const void *fn = precision == 0 ? (const void *)k_sweep_batch_slots<0> : (const void *)k_sweep_batch_slots<1>;
+    hipError_t e = allow_lds(fn, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_queue_reset_n, dim3(1), dim3(64), 0, s, queues, nclasses);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_sweep_batch_slots<0>, dim3(grid), dim3(64 * nslots), lds_bytes, s, descs, tasks,
+                           plan, queues);
+    else
+        hipLaunchKernelGGL(k_sweep_batch_slots<1>, dim3(grid), dim3(64 * nslots), lds_bytes, s, descs, tasks,
+                           plan, queues);
+    return hipGetLastError();
+}
+
+hipError_t sweep_batch_slots_fits(int precision, size_t lds_bytes, int nslots, int *fits) {
+    const void *fn = precision == 0 ? (const void *)k_sweep_batch_slots<0> : (const void *)k_sweep_batch_slots<1>;
+    hipError_t e = allow_lds(fn, lds_bytes);
+    if (e != hipSuccess) return e;
+    int blocks = 0;
+    if (precision == 0)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_batch_slots<0>, 64 * nslots, lds_bytes);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep_batch_slots<1>, 64 * nslots, lds_bytes);
+    *fits = blocks >= 1 ? 1 : 0;
+    return e;
 }
 
 hipError_t launch_sync_batch(int precision, const DevState *descs, const BatchTask *wtasks, int lo, int n,

@@ -97,7 +97,7 @@ def _instances(specs):
 
 
 def test_batch_structs_and_workspace(lib):
-    assert ctypes.sizeof(pk.Instance) == 104 and ctypes.sizeof(pk.Plan) == 32
+    assert ctypes.sizeof(pk.Instance) == 104 and ctypes.sizeof(pk.Plan) == 112
     specs = [(16, 2, 8, 4), (24, 4, 8, 4), (48, 10, 8, 4)]
     arr = _instances(specs)
     total = lib.rewl_batch_workspace_bytes(3, arr)

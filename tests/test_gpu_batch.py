@@ -69,7 +69,11 @@ def test_plans_give_identical_results():
     ref, insts, spins = make_batch(MIXED)
     ref.run(6)
     plans = [dict(walkers_per_cu=1, tag_policy=1, use_graph=0),
-             dict(walkers_per_cu=2, tag_policy=0, use_graph=1)]
+             dict(walkers_per_cu=2, tag_policy=0, use_graph=1),
+             # mixed-slot form: one slot per class (plus one more for the largest)
+             dict(slot_count=[2, 1, 1, 1, 1, 1], tag_bytes=4096, use_graph=1),
+             # only the largest class has slots: they serve every class
+             dict(slot_count=[3, 0, 0, 0, 0, 0], tag_bytes=2048, use_graph=0)]
     for p in plans:
         b, _, _ = make_batch(MIXED)
         b.set_plan(**p)
@@ -129,3 +133,20 @@ def test_batched_workload_instances_segment():
     b, insts, spins = make_batch(cases, seed=cfg["seed"])
     b.run(1)
     check_against_oracle(b, insts, spins, 1)
+
+
+def test_batched_workload_mixed_slots_match_uniform():
+    cfg = workloads.BATCHED
+    picks = [(L, cfg["q_choices"][-1]) for L in cfg["L_choices"]] * 2
+    cases = [(L, q, cfg["windows"], cfg["walkers"], cfg["sweeps_per_sync"] * L * L,
+              dict(lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"], flat=cfg["flat"],
+                   schedule=cfg["schedule"])) for L, q in picks]
+    a, _, _ = make_batch(cases, seed=cfg["seed"])
+    b, _, _ = make_batch(cases, seed=cfg["seed"])
+    pa = a.set_plan(walkers_per_cu=5)
+    pb = b.set_plan(slot_count=[3, 2, 1, 2], tag_bytes=4096)
+    assert pb["nclasses"] == 4 and pb["resident"] == 8 and pb["mixed"] == 1
+    a.run(2)
+    b.run(2)
+    for i in range(len(cases)):
+        assert_same_state(b.instance(i), a.instance(i))
