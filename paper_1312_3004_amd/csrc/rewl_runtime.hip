@@ -163,7 +163,9 @@ int check_trimer(const TrimerGeom &g, int h, double o, int m, const rewl_opts &o
     p->Wpad = (int)round_up((size_t)W, 64);
     p->Bpad = (int)round_up((size_t)p->B, 64);
     p->Ntag = 64;
-    if ((size_t)p->Npad + (size_t)p->Wpad * 12 > (size_t)kMaxLds)
+    // attempt kernel: coordinates, ln g and H, and up to two partner-term buffers
+    const size_t tbuf = (size_t)2 * ((3 * g.nmol + 63) / 64) * 64 * 8;
+    if ((size_t)p->Npad + (size_t)p->Wpad * 12 + tbuf > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "coordinates plus window state exceed the 160 KiB LDS of a CU");
     if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "walk-in counts over all bins exceed the 160 KiB LDS");

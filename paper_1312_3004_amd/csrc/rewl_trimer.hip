@@ -25,6 +25,8 @@ namespace rewl_gpu {
 
 namespace {
 
+constexpr double kTriMargin64 = 1e-10;   // log-domain slack of the acceptance test (binary64)
+constexpr double kTriMargin32 = 1e-5;    // log-domain slack of the acceptance test (binary32)
 constexpr double kBondK = 100.0;
 constexpr double kBondR0 = 1.0;
 constexpr double kTailCut2 = 6.25;                    // 2.5^2
@@ -76,6 +78,12 @@ __device__ __forceinline__ double shfl_down_d(double v, int d) {
     const int lo = __shfl_down((int)(uint32_t)b, d, 64);
     const int hi = __shfl_down((int)(uint32_t)((unsigned long long)b >> 32), d, 64);
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double readlane_d_tri(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((unsigned long long)b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 __device__ __forceinline__ double lane0_d(double v) {
     const long long b = __double_as_longlong(v);
@@ -278,6 +286,21 @@ __device__ __forceinline__ double halving_sum(double s) {
     return lane0_d(s);
 }
 
+// Layout of a trimer attempt workgroup: partner chunks of 64 beads; with
+// two roles the waves of role 0 evaluate the partners' energies with the bead
+// at its new position and those of role 1 at its old one, otherwise one wave
+// does both; P waves per role take chunks p, p+P, ... (at most 16 waves).
+struct TrimerWaves {
+    int chunks, roles, per_role;
+};
+__host__ __device__ inline TrimerWaves trimer_waves_of(int nb) {
+    TrimerWaves t;
+    t.chunks = (nb + 63) / 64;
+    t.roles = 2 * t.chunks <= 16 ? 2 : 1;
+    t.per_role = t.chunks < 16 / t.roles ? t.chunks : 16 / t.roles;
+    return t;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, int64_t n) {
 #pragma clang fp contract(off)
@@ -285,7 +308,8 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
     const int w = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
+    const TrimerWaves tw = trimer_waves_of(st.nb);
+    const int role = wave / tw.per_role, part = wave - role * tw.per_role;
     const int k = w / st.m;
     extern __shared__ __align__(16) unsigned char smem[];
     const int W = st.W, Wpad = st.Wpad;
@@ -294,7 +318,7 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
     float *gh = (float *)(smem + st.Npad);
     float *gl = gh + Wpad;
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
-    double *tbuf = (double *)(smem + st.Npad + (size_t)Wpad * 12);   // [nwaves][64]
+    double *tbuf = (double *)(smem + st.Npad + (size_t)Wpad * 12);   // [roles][chunks][64]
     const uint32_t *gx = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = threadIdx.x; i < st.Npad / 4; i += blockDim.x) ((uint32_t *)x)[i] = gx[i];
     const size_t row = (size_t)w * Wpad;
@@ -315,12 +339,16 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
     const double lnf = st.lnf[k];
     const float lnf32 = (float)lnf;
     const float box = st.box, half = 0.5f * st.box;
-    const int j = wave * 64 + lane;          // this lane's partner bead
-    const bool real = j < st.nb;
-    const float *xj = x + 3 * (real ? j : 0);
     for (int64_t base = 0; base < n; base += 64) {
         const int todo = (int)((n - base) < 64 ? (n - base) : 64);
         const Draw dr = draw(st, kDomMove, kDomMoveU, (uint64_t)(s0 + base + lane), (uint32_t)w);
+        // ln u of this lane's attempt: the serial step compares it with d and
+        // evaluates exp only inside a margin that covers the error of log/exp
+        double lnu = 0.0;
+        if (wave == 0) {
+            if (PREC == 0) lnu = dr.u == 0u ? -64.0 : log((double)dr.u * 0x1p-32);
+            else lnu = (dr.u >> 8) == 0u ? -64.0 : log((double)(dr.u >> 8) * 0x1p-24);
+        }
         for (int a = 0; a < todo; ++a) {
             const int b = __builtin_amdgcn_readlane(dr.bead, a);
             const float d0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(dr.d0), a));
@@ -330,25 +358,49 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
             const float n0 = wrap(o0 + d0, box);
             const float n1 = wrap(o1 + d1, box);
             const float n2 = wrap(o2 + d2, box);
-            double t = 0.0;
-            if (real && j != b) {
-                const float r0 = xj[0], r1 = xj[1], r2 = xj[2];
-                t = pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half) -
-                    pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half);
+            for (int c = part; c < tw.chunks; c += tw.per_role) {
+                const int j = c * 64 + lane;
+                double v = 0.0;
+                if (j < st.nb && j != b) {
+                    const float r0 = x[3 * j], r1 = x[3 * j + 1], r2 = x[3 * j + 2];
+                    if (tw.roles == 2) {
+                        v = role == 0 ? pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half)
+                                      : pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half);
+                    } else {
+                        v = pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half) -
+                            pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half);
+                    }
+                }
+                tbuf[(role * tw.chunks + c) * 64 + lane] = v;
             }
-            tbuf[wave * 64 + lane] = t;
             __syncthreads();
             if (wave == 0) {
-                double sl = tbuf[lane];
-                for (int c = 1; c < nwaves; ++c) sl = sl + tbuf[c * 64 + lane];
+                // t_j = V(new) - V(old) per partner, summed per lane in chunk order
+                double sl = 0.0;
+                for (int c = 0; c < tw.chunks; ++c) {
+                    const double t = tw.roles == 2 ? tbuf[c * 64 + lane] - tbuf[(tw.chunks + c) * 64 + lane]
+                                                   : tbuf[c * 64 + lane];
+                    sl = c == 0 ? t : sl + t;
+                }
                 const double e_new = Ed + halving_sum(sl);
                 const int bn = energy_bin(st, e_new);
-                const uint32_t u = __builtin_amdgcn_readlane(dr.u, a);
                 bool acc = false;
                 if (bn >= lo && bn <= hi) {
                     const int io = E - lo, in = bn - lo;
-                    if (PREC == 0) acc = accept64(g[io] - g[in], u);
-                    else acc = accept32((gh[io] - gh[in]) + (gl[io] - gl[in]), u);
+                    const double luj = readlane_d_tri(lnu, a);
+                    const uint32_t u = __builtin_amdgcn_readlane(dr.u, a);
+                    if (PREC == 0) {
+                        const double d = g[io] - g[in];
+                        const double t = d - luj;
+                        if (fabs(t) > kTriMargin64) acc = t > 0.0;
+                        else acc = accept64(d, u);
+                    } else {
+                        const float d = (gh[io] - gh[in]) + (gl[io] - gl[in]);
+                        const double t = (double)d - luj;
+                        if (fabs(t) > kTriMargin32) acc = t > 0.0;
+                        else acc = accept32(d, u);
+                    }
+                    acc = __ballot(acc) != 0ull;
                 }
                 if (acc) {
                     if (lane == 0) {
@@ -399,9 +451,13 @@ hipError_t allow(const void *fn, size_t bytes) {
 
 }  // namespace
 
-static int trimer_waves(const DevState &st) { return (st.nb + 63) / 64; }
+static int trimer_threads(const DevState &st) {
+    const TrimerWaves t = trimer_waves_of(st.nb);
+    return 64 * t.roles * t.per_role;
+}
 size_t trimer_sweep_lds_bytes(const DevState &st) {
-    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)trimer_waves(st) * 64 * 8;
+    const TrimerWaves t = trimer_waves_of(st.nb);
+    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)t.roles * t.chunks * 64 * 8;
 }
 size_t trimer_walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
 
@@ -423,11 +479,11 @@ hipError_t launch_trimer_sweep(const DevState &st, int64_t s0, int64_t n, hipStr
     if (st.precision == 0) {
         hipError_t e = allow((const void *)k_trimer_sweep<0>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_trimer_sweep<0>, dim3(st.nw), dim3(64 * trimer_waves(st)), lds, s, st, s0, n);
+        hipLaunchKernelGGL(k_trimer_sweep<0>, dim3(st.nw), dim3(trimer_threads(st)), lds, s, st, s0, n);
     } else {
         hipError_t e = allow((const void *)k_trimer_sweep<1>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_trimer_sweep<1>, dim3(st.nw), dim3(64 * trimer_waves(st)), lds, s, st, s0, n);
+        hipLaunchKernelGGL(k_trimer_sweep<1>, dim3(st.nw), dim3(trimer_threads(st)), lds, s, st, s0, n);
     }
     return hipGetLastError();
 }

@@ -83,3 +83,14 @@ def test_trimer_walkin_from_above_bitexact():
     assert_same_state(g, o)
     assert_same_energies(g, o)
     assert max(g.walker(w)["walkin_attempts"] for w in range(4)) > 0
+
+
+def test_trimer_many_molecules_bitexact():
+    # 400 molecules (1,200 beads, 19 chunks of 64 partners): one role per wave,
+    # 16 waves taking several chunks each
+    g, o = make_pair(400, 20.0, -30.0, 0.5, 200, 1, 2, lnf_init=0.05, fixed_lnf=1, sync_attempts=400,
+                     seed=6, threads=8)
+    g.run(800)
+    o.run(800)
+    assert_same_state(g, o)
+    assert_same_energies(g, o)
