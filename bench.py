@@ -30,6 +30,11 @@ LDS_PEAK_GBS = 256 * 128 * 2.4
 # FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg copy of known size
 # (profiles/k_sweep_potts_q10_L32_pmc.md).  Valid for the kernel as profiled.
 K_SWEEP_L32_HBM_BYTES = 975_000
+# VALU instructions (wave64) per attempt of the same kernel, rocprofv3 SQ_INSTS_VALU
+# over the same workload (same profile); the VALU lane-op peak is the binary32
+# vector rate, 157.3 TFLOP/s / 2 (an FMA counts two flops).
+K_SWEEP_L32_VALU_PER_ATTEMPT = 22.8
+VALU_LANE_OPS_PEAK = 157.3e12 / 2
 # 1/t phase ends once W/t < 1e-8, i.e. after W/1e-8 attempts per walker.
 
 
@@ -485,6 +490,12 @@ def main():
                      "traffic": K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" else None,
                      "kernel": "k_sweep", "kernel_avg_ms": avg_ms, "kernel_launches": launches,
                      "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT},
+        "valu": ({"instructions_per_attempt": K_SWEEP_L32_VALU_PER_ATTEMPT,
+                  "achieved_lane_ops_per_s": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch /
+                  (avg_ms * 1e-3),
+                  "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK,
+                  "frac": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch / (avg_ms * 1e-3) /
+                  VALU_LANE_OPS_PEAK} if args.config == "potts_q10_L32" else None),
         "per_walker_attempts_per_s": per_walker,
         "sync_point_avg_ms": sync_ms / max(syncs, 1),
         "walkin_s": walkin_s,
