@@ -378,6 +378,48 @@ def trajectory(g, S, seconds, converge_attempts, walkin_s, early_rate):
     return out
 
 
+def to_convergence(args):
+    """Wall time from creation to every window finished (the full protocol of
+    the named workload), on the GPU and for the CPU oracle on the same inputs."""
+    import torch
+
+    import oracle
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    cfg = dict(workloads.CONFIGS[args.config])
+    L, q, h, m = cfg["L"], cfg["q"], cfg["windows"], cfg["walkers"]
+    spins = workloads.init_spins(L, q, h * m, cfg["seed"])
+    kw = dict(seed=cfg["seed"], flat=cfg["flat"], lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"],
+              schedule=cfg["schedule"], sync_attempts=cfg["sync_attempts"], exchange=cfg["exchange"],
+              precision=cfg["precision"])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = pk.Rewl(L, q, h, cfg["overlap"], m, spins, device=dev, **kw)
+    st = pk.OK
+    while st != pk.CONVERGED and time.perf_counter() - t0 < args.to_convergence:
+        st = g.run(1000 * cfg["sync_attempts"])
+        log(f"[bench] GPU step {g.step} after {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    out = {"metric": f"time to ln f < {cfg['lnf_final']:g}, {args.config}", "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": args.config, "L": L, "q": q, "windows": h, "walkers_per_window": m},
+           "gpu": {"converged": st == pk.CONVERGED, "seconds": gpu_s, "attempts_per_walker": g.step}}
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, os.cpu_count() or 1, h * m))
+        t0 = time.perf_counter()
+        o = oracle.Rewl(L, q, h, cfg["overlap"], m, spins, threads=threads, **kw)
+        ost = o.run(10**13)
+        out["cpu_oracle"] = {"converged": ost == oracle.CONVERGED, "seconds": time.perf_counter() - t0,
+                             "attempts_per_walker": o.step, "cores": threads,
+                             "same_state": o.step == g.step and o.round == g.round}
+    out["value"] = gpu_s
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +428,9 @@ def main():
     ap.add_argument("--config", default="potts_q10_L32")
     ap.add_argument("--cpu-attempts", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--to-convergence", type=float, default=0.0,
+                    help="run the named workload from creation to convergence (at most this many seconds) "
+                         "on the GPU and, unless --no-cpu-baseline, on the CPU oracle")
     ap.add_argument("--trajectory", type=float, default=0.0,
                     help="after the measurement, continue the run for this many seconds and report "
                          "when every window reached the 1/t regime and the time to ln f_final")
@@ -413,6 +458,8 @@ def main():
         log(f"[bench] copy calibration: 3 x torch.neg over {args.copy_calibration_mib} MiB "
             f"(reads and writes {4 * n} bytes per launch)")
         del src, dst
+    if args.to_convergence > 0:
+        return to_convergence(args)
     if args.workload == "batched":
         return batched(args)
     if args.workload == "precision":
