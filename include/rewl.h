@@ -159,6 +159,24 @@ int rewl_run_attempts(rewl_t *r, int64_t attempts);
  * with k = r mod 2, r mod 2 + 2, ...                                          */
 int rewl_exchange(rewl_t *r);
 
+/* Replica paths under exchange (Sec. 2; Sec. 3.2, Fig. 7): replica r starts
+ * in walker slot r (window r / m) and moves with every accepted exchange.
+ * Positions are looked up at creation, at every sync point (after its
+ * exchange round) and after every rewl_exchange call.  window_of[r] receives
+ * the window replica r is in now and trips[r] the round trips it completed:
+ * paths window 0 -> window h-1 -> window 0, counted on the return, which also
+ * starts the next (a run with one window has none).  Host buffers of h*m
+ * entries, indexed by replica id; either may be NULL.
+ * Errors: REWL_EINVAL on a null handle.                                       */
+int rewl_get_replicas(rewl_t *r, uint32_t *window_of, uint32_t *trips);
+
+/* Replicas seen by walker slot w (Fig. 7c): counts[r] = lookups (as above)
+ * that found replica r in slot w; a host buffer of h*m entries.  Kept for
+ * runs of at most 4096 walkers (h*m*h*m counters in the workspace).
+ * Errors: REWL_EINVAL on a null handle or buffer, w out of range, or a run
+ * with more than 4096 walkers.                                                */
+int rewl_get_replica_visits(rewl_t *r, int walker, uint32_t *counts);
+
 /* Progress counters: main-phase attempts per walker, exchange rounds done,
  * and whether the run converged.  Any pointer may be NULL.                   */
 int rewl_get_progress(rewl_t *r, int64_t *step, int64_t *round, int32_t *converged);

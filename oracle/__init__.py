@@ -31,6 +31,9 @@ def lib():
         L.orc_create.argtypes = [i32, i32, i32, dbl, i32, u64, u32, u32, u32, dbl, dbl, i32, i64,
                                  i32, i32, i32, i32, i32, P]
         L.orc_get_shadow.argtypes = [P, i32, P, P]
+        L.orc_get_replicas.argtypes = [P, P, P]
+        L.orc_get_replicas.restype = None
+        L.orc_get_replica_visits.argtypes = [P, i32, P]
         L.orc_create_trimer.restype = P
         L.orc_create_trimer.argtypes = [i32, ctypes.c_float, dbl, dbl, i32, i32, dbl, i32, u64, u32, u32,
                                         u32, dbl, dbl, i32, i64, i32, i32, i32, i32, i32, P]
@@ -289,6 +292,20 @@ class Rewl:
                              ctypes.byref(xc))
         return dict(lnf=lnf.value, lnf_last=lnf_last.value, regime=regime.value, finished=fin.value,
                     iterations=it.value, visited=vis, x_att=xa.value, x_acc=xc.value)
+
+    def replicas(self):
+        """(window_of, trips), uint32 [h*m] by replica id: current window and completed round trips."""
+        win = np.zeros(self.nw, dtype=np.uint32)
+        trips = np.zeros(self.nw, dtype=np.uint32)
+        lib().orc_get_replicas(self.h_, _ptr(win), _ptr(trips))
+        return win, trips
+
+    def replica_visits(self, w):
+        """uint32 [h*m]: lookups that found each replica id in walker slot w."""
+        out = np.zeros(self.nw, dtype=np.uint32)
+        if lib().orc_get_replica_visits(self.h_, w, _ptr(out)) != 0:
+            raise ValueError("visit matrix not kept")
+        return out
 
     def shadow(self, w):
         """(hi, lo): double-double exact reference of walker w's ln g."""

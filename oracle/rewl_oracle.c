@@ -219,7 +219,11 @@ typedef struct {
     double *sh_hi, *sh_lo; /* [nw][W] shadow: ln g in double-double          */
     uint32_t *hprev;       /* [nw][W] H at the previous sync point           */
     uint8_t *vis;          /* [nw][W] bins this walker reached since creation */
-    uint32_t *replica;     /* [nw] */
+    uint32_t *replica;     /* [nw] replica id held by walker slot w */
+    int32_t *rep_end;      /* [nw] by replica id: 0 lowest window not reached yet,
+                              1 lowest reached (highest not since), 2 highest since */
+    uint32_t *rep_trips;   /* [nw] by replica id: completed round trips lowest-highest-lowest */
+    uint32_t *rep_visits;  /* [nw][nw] lookups that found replica r in slot w (nw <= 4096) */
     int64_t *walkin_att;   /* [nw] */
     /* window state */
     double *lnf;           /* [h] current ln f (0 once finished)             */
@@ -242,11 +246,51 @@ static void orc_free(orc_t *o)
     free(o->lng_lo); free(o->H); free(o->sh_hi); free(o->sh_lo); free(o->hprev); free(o->vis); free(o->replica); free(o->walkin_att);
     free(o->lnf); free(o->lnf_last); free(o->regime); free(o->finished);
     free(o->iterations); free(o->visited); free(o->x_att); free(o->x_acc);
-    free(o->Ed);
+    free(o->Ed); free(o->rep_end); free(o->rep_trips); free(o->rep_visits);
     free(o);
 }
 
 void orc_destroy(orc_t *o) { orc_free(o); }
+
+/* Replica-path diagnostics (Sec. 3.2, Fig. 7): the position of every replica
+ * is looked up at creation, at every sync point (after its exchange round)
+ * and after every exchange round called on its own.  Each lookup adds one to
+ * visits[w][r] for the replica r held by walker slot w.  A round trip is a
+ * path from the lowest window to the highest and back to the lowest; the
+ * return to the lowest window completes one and starts the next.           */
+static void replica_track(orc_t *o)
+{
+    if (o->rep_visits)
+        for (int w = 0; w < o->nw; ++w) o->rep_visits[(size_t)w * o->nw + o->replica[w]] += 1;
+    if (o->h < 2) return;
+    for (int w = 0; w < o->nw; ++w) {
+        int k = w / o->m;
+        uint32_t r = o->replica[w];
+        if (k == 0) {
+            if (o->rep_end[r] == 2) o->rep_trips[r] += 1;
+            o->rep_end[r] = 1;
+        } else if (k == o->h - 1 && o->rep_end[r] == 1) {
+            o->rep_end[r] = 2;
+        }
+    }
+}
+
+void orc_get_replicas(const orc_t *o, uint32_t *window_of, uint32_t *trips)
+{
+    for (int w = 0; w < o->nw; ++w) {
+        if (window_of) window_of[o->replica[w]] = (uint32_t)(w / o->m);
+    }
+    if (trips) for (int r = 0; r < o->nw; ++r) trips[r] = o->rep_trips[r];
+}
+
+/* counts[r] = lookups that found replica r in walker slot w; -1 if the
+ * matrix is not kept (more than 4096 walkers).                              */
+int orc_get_replica_visits(const orc_t *o, int w, uint32_t *counts)
+{
+    if (!o->rep_visits || w < 0 || w >= o->nw) return ORC_EINVAL;
+    memcpy(counts, o->rep_visits + (size_t)w * o->nw, (size_t)o->nw * sizeof(uint32_t));
+    return ORC_OK;
+}
 
 /* Exposed for the tests. */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox4x32_10(ctr, key, out); }
@@ -302,6 +346,12 @@ static orc_t *orc_new(int B, int e_lo, int N, int h, double overlap, int m, uint
     }
     o->vis = (uint8_t *)calloc(nw * W, 1);
     o->replica = (uint32_t *)calloc(nw, sizeof(uint32_t));
+    o->rep_end = (int32_t *)calloc(nw, sizeof(int32_t));
+    o->rep_trips = (uint32_t *)calloc(nw, sizeof(uint32_t));
+    if (nw <= 4096) {
+        o->rep_visits = (uint32_t *)calloc((size_t)nw * nw, sizeof(uint32_t));
+        if (!o->rep_visits) { orc_free(o); return NULL; }
+    }
     o->walkin_att = (int64_t *)calloc(nw, sizeof(int64_t));
     o->lnf = (double *)calloc((size_t)h, sizeof(double));
     o->lnf_last = (double *)calloc((size_t)h, sizeof(double));
@@ -312,12 +362,13 @@ static orc_t *orc_new(int B, int e_lo, int N, int h, double overlap, int m, uint
     o->x_att = (uint64_t *)calloc((size_t)h, sizeof(uint64_t));
     o->x_acc = (uint64_t *)calloc((size_t)h, sizeof(uint64_t));
     if (!o->spin || !o->E || !(o->lng || (o->lng_hi && o->lng_lo)) || !o->H || !o->vis ||
-        !o->replica || !o->walkin_att || !o->lnf || !o->lnf_last || !o->regime ||
+        !o->replica || !o->rep_end || !o->rep_trips || !o->walkin_att || !o->lnf || !o->lnf_last || !o->regime ||
         !o->finished || !o->iterations || !o->visited || !o->x_att || !o->x_acc) {
         orc_free(o);
         return NULL;
     }
     for (int w = 0; w < o->nw; ++w) o->replica[w] = (uint32_t)w;
+    replica_track(o);
     for (int k = 0; k < h; ++k) o->lnf[k] = lnf_init;
     return o;
 }
@@ -940,7 +991,7 @@ static uint32_t next_word(word_stream *ws)
     return ws->buf[ws->pos++];
 }
 
-int orc_exchange(orc_t *o)
+static int exchange_round(orc_t *o)
 {
     int h = o->h, m = o->m, W = o->W, N = o->N;
     uint32_t r = (uint32_t)o->round;
@@ -986,6 +1037,15 @@ int orc_exchange(orc_t *o)
     return ORC_OK;
 }
 
+/* One exchange round on its own (no sync point); nothing once converged.   */
+int orc_exchange(orc_t *o)
+{
+    if (o->converged) return ORC_CONVERGED;
+    int st = exchange_round(o);
+    if (st == ORC_OK) replica_track(o);
+    return st;
+}
+
 /* Run `attempts` more Wang-Landau attempts per walker.  Sync points (flatness,
  * averaging, ln f update, then an exchange round) fall at every multiple of S
  * attempts counted from the start of the main phase, so splitting a run into
@@ -1018,7 +1078,11 @@ int orc_run(orc_t *o, int64_t attempts, int64_t walkin_budget)
         attempts -= seg;
         if (o->step % o->S == 0) {
             for (int k = 0; k < o->h; ++k) window_sync(o, k);
-            if (o->exchange) orc_exchange(o);
+            if (o->exchange) {
+                int st = exchange_round(o);
+                if (st != ORC_OK) return st;
+            }
+            replica_track(o);
             int all = 1;
             for (int k = 0; k < o->h; ++k) all = all && o->finished[k];
             if (all) { o->converged = 1; return ORC_CONVERGED; }

@@ -90,6 +90,8 @@ def lib():
         L.rewl_get_window.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.rewl_set_lng.argtypes = [P, i32, P]
         L.rewl_get_shadow.argtypes = [P, i32, P, P]
+        L.rewl_get_replicas.argtypes = [P, P, P]
+        L.rewl_get_replica_visits.argtypes = [P, i32, P]
         flt = ctypes.c_float
         L.rewl_trimer_workspace_bytes.argtypes = [i32, flt, dbl, dbl, i32, i32, dbl, i32, ctypes.POINTER(Opts)]
         L.rewl_trimer_workspace_bytes.restype = ctypes.c_size_t
@@ -329,6 +331,19 @@ class Rewl:
                                      ctypes.byref(xa), ctypes.byref(xc)))
         return dict(lnf=lnf.value, lnf_last=lnf_last.value, regime=regime.value, finished=fin.value,
                     iterations=it.value, visited=vis, x_att=xa.value, x_acc=xc.value)
+
+    def replicas(self):
+        """(window_of, trips), uint32 [h*m] by replica id: current window and completed round trips."""
+        win = np.zeros(self.nw, dtype=np.uint32)
+        trips = np.zeros(self.nw, dtype=np.uint32)
+        _check(lib().rewl_get_replicas(self._h, _ptr(win), _ptr(trips)))
+        return win, trips
+
+    def replica_visits(self, w):
+        """uint32 [h*m]: lookups that found each replica id in walker slot w."""
+        out = np.zeros(self.nw, dtype=np.uint32)
+        _check(lib().rewl_get_replica_visits(self._h, w, _ptr(out)))
+        return out
 
     def shadow(self, w):
         """(hi, lo): double-double exact reference of walker w's ln g (opts shadow=1)."""

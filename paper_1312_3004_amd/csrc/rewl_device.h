@@ -21,6 +21,10 @@ constexpr int kModelTrimer3D = 1;
 
 // Everything a kernel needs to find one run's state in the device workspace.
 // Per-walker rows are padded so every row starts on a 256-byte boundary.
+// Largest walker count for which the walker-by-replica visit matrix is kept
+// (4096^2 counters = 64 MiB).
+constexpr int kMaxVisitWalkers = 4096;
+
 struct DevState {
     int model;                   // kModelPotts2D or kModelTrimer3D
     // Potts: L x L lattice, q states, N = L*L sites, energies e_lo .. e_lo+B-1.
@@ -51,7 +55,12 @@ struct DevState {
     uint32_t *H;                 // [nw][Wpad]
     double *sh_hi, *sh_lo;       // [nw][Wpad] exact reference of ln g (double-double), if kept
     uint32_t *hprev;             // [nw][Wpad] H at the previous sync point (shadow only)
-    uint32_t *replica;           // [nw]
+    uint32_t *replica;           // [nw] replica id held by each walker slot
+    int32_t *rep_end;            // [nw] per replica id: 0 lowest window not reached yet, 1 reached
+                                 // (highest not since), 2 highest reached since
+    uint32_t *rep_trips;         // [nw] per replica id: completed lowest-highest-lowest round trips
+    uint32_t *rep_visits;        // [nw][nw] lookups that found replica r in slot w (null above
+                                 // kMaxVisitWalkers walkers)
     int64_t *walkin_att;         // [nw]
     int32_t *walkin_done;        // [nw]
     int32_t *walkin_bound;       // [nw] walk-in lid (walker above its window) or floor
@@ -257,6 +266,7 @@ hipError_t launch_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s
 hipError_t launch_sync(const DevState &st, int64_t attempts, hipStream_t s);
 hipError_t launch_exchange(const DevState &st, uint32_t round, hipStream_t s);
 hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, hipStream_t s);
+hipError_t launch_track(const DevState &st, hipStream_t s);
 hipError_t launch_join(const DevState &st, double log_total, hipStream_t s);
 hipError_t launch_thermo(const DevState &st, const double *T, int nT, double *out, hipStream_t s);
 size_t sweep_lds_bytes(const DevState &st);

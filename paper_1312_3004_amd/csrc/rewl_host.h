@@ -42,7 +42,7 @@ struct Timer {
 
 // Byte offsets of the state arrays of one run inside its device workspace.
 struct Layout {
-    size_t start, spins, E, Ed, lng, lng_hi, lng_lo, H, sh_hi, sh_lo, hprev, replica, walkin_att, walkin_done,
+    size_t start, spins, E, Ed, lng, lng_hi, lng_lo, H, sh_hi, sh_lo, hprev, replica, rep_end, rep_trips, rep_visits, walkin_att, walkin_done,
         walkin_bound, walkin_cnt,
         lnf, lnf_last, regime, finished, iterations, visited, x_att, x_acc, converged, stop, joined,
         cuts, join_status, scratch, T, thermo_out, total;

@@ -1006,6 +1006,32 @@ __global__ __launch_bounds__(64) void k_exchange(DevState st, uint32_t r) {
     exchange_pair(st, r, blockIdx.x);
 }
 
+// Replica paths (Sec. 3.2, Fig. 7).  Positions are looked up at creation, at
+// every sync point (after its exchange round) and after an exchange round
+// called on its own.  Each lookup adds one to visits[w][r] for the replica r
+// in slot w.  A round trip takes a replica from the lowest window to the
+// highest and back (the usual measure of how fast replica exchange carries
+// configurations across the energy range); the return completes one and
+// starts the next.  Every slot has its own row of the visit matrix and each
+// replica id sits in exactly one slot, so lanes never share a counter.
+__device__ __forceinline__ void track_replicas(const DevState &st, int lane, int nlanes) {
+    if (st.rep_visits)
+        for (int w = lane; w < st.nw; w += nlanes) st.rep_visits[(size_t)w * st.nw + st.replica[w]] += 1u;
+    if (st.h < 2) return;
+    const int m = st.m;
+    for (int i = lane; i < 2 * m; i += nlanes) {
+        const bool low = i < m;
+        const int w = low ? i : (st.h - 1) * m + (i - m);
+        const uint32_t r = st.replica[w];
+        if (low) {
+            if (st.rep_end[r] == 2) st.rep_trips[r] += 1u;
+            st.rep_end[r] = 1;
+        } else if (st.rep_end[r] == 1) {
+            st.rep_end[r] = 2;
+        }
+    }
+}
+
 // Termination (Sec. 2): the run ends once every window reached ln f_final.
 __device__ __forceinline__ void check_instance(const DevState &st, int64_t step, int64_t round_after) {
     if (*st.converged) return;
@@ -1017,7 +1043,12 @@ __device__ __forceinline__ void check_instance(const DevState &st, int64_t step,
 }
 
 __global__ void k_check(DevState st, int64_t step, int64_t round_after) {
+    if (!*st.converged) track_replicas(st, (int)threadIdx.x, (int)blockDim.x);
     if (threadIdx.x == 0) check_instance(st, step, round_after);
+}
+
+__global__ void k_track(DevState st) {
+    if (!*st.converged) track_replicas(st, (int)threadIdx.x, (int)blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1368,6 +1399,7 @@ __global__ void k_advance_batch(const DevState *__restrict__ descs, int lo, int 
     if (i >= n) return;
     const DevState &st = descs[lo + i];
     if (*st.converged) return;
+    track_replicas(st, 0, 1);
     const int64_t step = st.ctl[0] + st.sync_attempts;
     const int64_t round = st.ctl[1] + (st.exchange ? 1 : 0);
     st.ctl[0] = step;
@@ -1448,6 +1480,11 @@ hipError_t launch_exchange(const DevState &st, uint32_t round, hipStream_t s) {
 
 hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, hipStream_t s) {
     hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, s, st, step, round_after);
+    return hipGetLastError();
+}
+
+hipError_t launch_track(const DevState &st, hipStream_t s) {
+    hipLaunchKernelGGL(k_track, dim3(1), dim3(64), 0, s, st);
     return hipGetLastError();
 }
 

@@ -72,6 +72,9 @@ Layout make_layout(const Params &p, int precision, int shadow, bool trimer) {
     l.sh_lo = shadow ? take(sizeof(double) * p.nw * p.Wpad) : 0;
     l.hprev = shadow ? take(sizeof(uint32_t) * p.nw * p.Wpad) : 0;
     l.replica = take(sizeof(uint32_t) * p.nw);
+    l.rep_end = take(sizeof(int32_t) * p.nw);
+    l.rep_trips = take(sizeof(uint32_t) * p.nw);
+    l.rep_visits = p.nw <= rewl_gpu::kMaxVisitWalkers ? take(sizeof(uint32_t) * (size_t)p.nw * p.nw) : 0;
     l.walkin_att = take(sizeof(int64_t) * p.nw);
     l.walkin_done = take(sizeof(int32_t) * p.nw);
     l.walkin_bound = take(sizeof(int32_t) * p.nw);
@@ -354,6 +357,9 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     d.sh_lo = op.shadow ? (double *)(b + lay.sh_lo) : nullptr;
     d.hprev = op.shadow ? (uint32_t *)(b + lay.hprev) : nullptr;
     d.replica = (uint32_t *)(b + lay.replica);
+    d.rep_end = (int32_t *)(b + lay.rep_end);
+    d.rep_trips = (uint32_t *)(b + lay.rep_trips);
+    d.rep_visits = p.nw <= rewl_gpu::kMaxVisitWalkers ? (uint32_t *)(b + lay.rep_visits) : nullptr;
     d.walkin_att = (int64_t *)(b + lay.walkin_att);
     d.walkin_done = (int32_t *)(b + lay.walkin_done);
     d.walkin_bound = (int32_t *)(b + lay.walkin_bound);
@@ -400,6 +406,8 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     if (e == hipSuccess) e = hipMemcpyAsync(d.replica, rep.data(), sizeof(uint32_t) * p.nw, hipMemcpyHostToDevice, r->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.lnf, lnf.data(), sizeof(double) * p.h, hipMemcpyHostToDevice, r->stream);
     if (e == hipSuccess) e = rewl_gpu::launch_init_energy(d, r->stream);
+    // replica paths start from the initial placement (replica w in slot w)
+    if (e == hipSuccess) e = rewl_gpu::launch_track(d, r->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("rewl_create: ") + hipGetErrorString(e)));
     *out = r;
@@ -601,6 +609,7 @@ int rewl_exchange(rewl_t *r) {
     if (!r) return fail(REWL_EINVAL, "null handle");
     if (r->converged) return REWL_CONVERGED;
     HIP_TRY(rewl_gpu::launch_exchange(r->st, (uint32_t)r->round, r->stream));
+    HIP_TRY(rewl_gpu::launch_track(r->st, r->stream));
     r->round += 1;
     r->joined = false;
     HIP_TRY(hipStreamSynchronize(r->stream));
@@ -612,6 +621,31 @@ int rewl_get_progress(rewl_t *r, int64_t *step, int64_t *round, int32_t *converg
     if (step) *step = r->step;
     if (round) *round = r->round;
     if (converged) *converged = r->converged ? 1 : 0;
+    return REWL_OK;
+}
+
+int rewl_get_replicas(rewl_t *r, uint32_t *window_of, uint32_t *trips) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    const DevState &d = r->st;
+    std::vector<uint32_t> rep(d.nw);
+    if (window_of)
+        HIP_TRY(hipMemcpyAsync(rep.data(), d.replica, sizeof(uint32_t) * d.nw, hipMemcpyDeviceToHost, r->stream));
+    if (trips) HIP_TRY(hipMemcpyAsync(trips, d.rep_trips, sizeof(uint32_t) * d.nw, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    if (window_of)
+        for (int w = 0; w < d.nw; ++w) window_of[rep[w]] = (uint32_t)(w / d.m);
+    return REWL_OK;
+}
+
+int rewl_get_replica_visits(rewl_t *r, int w, uint32_t *counts) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    const DevState &d = r->st;
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    if (!d.rep_visits) return fail(REWL_EINVAL, "visit matrix not kept for more than 4096 walkers");
+    if (!counts) return fail(REWL_EINVAL, "null buffer");
+    HIP_TRY(hipMemcpyAsync(counts, d.rep_visits + (size_t)w * d.nw, sizeof(uint32_t) * d.nw,
+                           hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
     return REWL_OK;
 }
 

@@ -18,3 +18,10 @@ def assert_same_state(g, o):
         for key in ("lnf", "lnf_last", "regime", "finished", "iterations", "x_att", "x_acc"):
             assert a[key] == b[key], (k, key, a[key], b[key])
         assert np.array_equal(a["visited"], b["visited"]), f"visited of window {k}"
+    wa, ta = g.replicas()
+    wb, tb = o.replicas()
+    assert np.array_equal(wa, wb), "replica windows"
+    assert np.array_equal(ta, tb), "replica round trips"
+    if g.nw <= 4096:
+        for w in range(g.nw):
+            assert np.array_equal(g.replica_visits(w), o.replica_visits(w)), f"replica visits of slot {w}"

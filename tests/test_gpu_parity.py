@@ -155,6 +155,46 @@ def test_fixed_exact_weights_and_set_lng():
     assert np.max(np.abs(H[reach] / H[reach].mean() - 1)) < 0.1
 
 
+def test_replica_round_trips_bitexact():
+    # Exact weights make most exchanges acceptable (Eq. (1)), so replicas
+    # cross the whole range many times; sync points with an exchange round
+    # every 31 attempts, then manual rounds.
+    L, q, h, m = 4, 2, 3, 2
+    gex = bruteforce.potts_dos(L, q)
+    ex = np.where(gex > 0, np.log(np.maximum(gex, 1).astype(float)), 0.0)
+    g, o = make_pair(L, q, h, m, lnf_init=0.0, fixed_lnf=1, sync_attempts=31, exchange=1, seed=5,
+                     spins_seed=13)
+    for w in range(h * m):
+        k = w // m
+        seg = ex[o.starts[k] - o.e_lo: o.starts[k] - o.e_lo + o.W]
+        g.set_lng(w, seg)
+        o.set_lng(w, seg)
+    g.run(31 * 400)
+    o.run(31 * 400)
+    assert_same_state(g, o)
+    for _ in range(9):
+        g.exchange()
+        o.exchange()
+    assert_same_state(g, o)
+    win, trips = g.replicas()
+    assert trips.sum() >= 10 and sorted(win) == sorted(w // m for w in range(h * m))
+
+
+def test_replica_visits_kept_up_to_4096_walkers():
+    pk = _pk()
+    spins = workloads.init_spins(64, 2, 65 * 64, 3)
+    print("[case] L=64 q=2 h=65 m=64 replica visits limit", flush=True)
+    g = pk.Rewl(64, 2, 65, 0.75, 64, spins, seed=1)
+    win, trips = g.replicas()
+    assert np.array_equal(win, np.arange(65 * 64) // 64) and not trips.any()
+    with pytest.raises(pk.RewlError):
+        g.replica_visits(0)
+    del g
+    g = pk.Rewl(64, 2, 64, 0.75, 64, spins[:4096], seed=1)
+    v = g.replica_visits(4095)
+    assert v[4095] == 1 and v.sum() == 1
+
+
 def test_walkin_budget_error_on_gpu():
     spins = np.zeros((4, 64), np.int8)
     g = _pk().Rewl(8, 10, 4, 0.75, 1, spins, seed=1)

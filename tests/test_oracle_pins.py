@@ -303,6 +303,72 @@ def test_exchange_accepts_everything_under_exact_weights():
     assert eligible_total > 5
 
 
+def _trips_from_history(windows, h):
+    # Round trips of one replica from the sequence of windows it was seen in:
+    # keep only the visits to the end windows ('L' lowest, 'H' highest), drop
+    # everything before the first 'L', merge repeats; every "HL" that remains
+    # closes one lowest -> highest -> lowest path.
+    ends = "".join("L" if k == 0 else "H" for k in windows if k in (0, h - 1))
+    ends = ends[ends.find("L"):] if "L" in ends else ""
+    merged = "".join(c for i, c in enumerate(ends) if i == 0 or c != ends[i - 1])
+    return merged.count("HL")
+
+
+@pytest.mark.parametrize("h,m", [(3, 2), (4, 1), (2, 3), (1, 2)])
+def test_replica_round_trips_replayed(h, m):
+    # Replica ids move only with accepted exchanges (Eq. (1)); the round-trip
+    # counts and the walker-by-replica visit counts (Fig. 7) must equal those
+    # replayed from the positions seen at every lookup: creation, each sync
+    # point (here every 500 attempts, no exchange there) and each exchange
+    # round called on its own.  Exact weights make most exchanges acceptable,
+    # so replicas cross the whole range many times.
+    L, q = 4, 2
+    ex = exact_lng(L, q)
+    nw = h * m
+    spins = workloads.init_spins(L, q, nw, 13)
+    o = oracle.Rewl(L, q, h, 0.75, m, spins, seed=5, lnf_init=0.0, fixed_lnf=1, exchange=0,
+                    sync_attempts=500)
+    for w in range(nw):
+        k = w // m
+        seg = ex[o.starts[k] - o.e_lo: o.starts[k] - o.e_lo + o.W]
+        o.set_lng(w, np.where(np.isfinite(seg), seg, 0.0))
+    o.walkin()
+    hist = [[r // m] for r in range(nw)]
+    visits = np.eye(nw, dtype=np.int64)
+    lookups = 1
+
+    def look():
+        reps = [o.walker(w)["replica"] for w in range(nw)]
+        for w, r in enumerate(reps):
+            visits[w, r] += 1
+        return reps
+
+    for rnd in range(300):
+        before = o.step // 500
+        o.run(31)
+        for _ in range(o.step // 500 - before):      # sync points: positions unchanged
+            look()
+            lookups += 1
+        o.exchange()
+        for w, r in enumerate(look()):
+            hist[r].append(w // m)
+        lookups += 1
+        if rnd % 50 == 49 or rnd == 299:
+            win, trips = o.replicas()
+            assert list(win) == [hst[-1] for hst in hist]
+            assert list(trips) == [_trips_from_history(hst, h) if h > 1 else 0 for hst in hist]
+            got = np.stack([o.replica_visits(w) for w in range(nw)])
+            assert np.array_equal(got, visits)
+    assert np.all(got.sum(axis=0) == lookups) and np.all(got.sum(axis=1) == lookups)
+    assert o.step // 500 >= 18
+    if h > 1:
+        assert sum(trips) >= 3
+        assert sorted(win) == sorted(w // m for w in range(nw))
+        assert np.count_nonzero(got[0]) == nw          # every replica reached slot 0
+    else:
+        assert not trips.any()
+
+
 @pytest.mark.parametrize("bias,accepted", [(-100.0, 0), (100.0, 1), (-1e-12, 1)])
 def test_exchange_planted_weights(bias, accepted):
     # Walker a carries X at E_X = -24 and walker b carries Y at E_Y = -20 (4x4
