@@ -29,7 +29,15 @@ def lib():
         i32, i64, u32, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
         L.orc_create.restype = P
         L.orc_create.argtypes = [i32, i32, i32, dbl, i32, u64, u32, u32, u32, dbl, dbl, i32, i64,
-                                 i32, i32, i32, i32, i32, P]
+                                 i32, i32, i32, i32, i32, i32, P]
+        L.orc_begin_production.argtypes = [P]
+        L.orc_begin_production.restype = i32
+        L.orc_get_obs.argtypes = [P, i32, P, P, P]
+        L.orc_get_obs.restype = i32
+        L.orc_obs_micro.argtypes = [P, P, P]
+        L.orc_obs_micro.restype = i32
+        L.orc_obs_thermo.argtypes = [P, P, i32, dbl, dbl, P, i32, P]
+        L.orc_obs_thermo.restype = None
         L.orc_get_shadow.argtypes = [P, i32, P, P]
         L.orc_get_replicas.argtypes = [P, P, P]
         L.orc_get_replicas.restype = None
@@ -164,6 +172,16 @@ def thermo(lng, e_first, T, de=1.0):
     return lnZ, U, C
 
 
+def obs_thermo(lng, mu, e_first, T, de=1.0):
+    """Canonical average of an observable from ln g(E) and its microcanonical mean mu(E)."""
+    g = np.ascontiguousarray(lng, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    out = np.zeros_like(T)
+    lib().orc_obs_thermo(_ptr(g), _ptr(mu), len(g), float(e_first), float(de), _ptr(T), len(T), _ptr(out))
+    return out
+
+
 def join_pieces(pieces, visited, starts, e_lo, B, log_total):
     pieces = np.ascontiguousarray(pieces, dtype=np.float64)
     vis = np.ascontiguousarray(visited, dtype=np.uint8)
@@ -181,16 +199,16 @@ class Rewl:
 
     def __init__(self, L, q, windows, overlap, walkers, init_spins, seed=1, instance=0,
                  flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0, sync_attempts=1000,
-                 exchange=1, precision=0, fixed_lnf=0, shadow=0, walkin_slack=16, threads=1):
+                 exchange=1, precision=0, fixed_lnf=0, shadow=0, walkin_slack=16, obs_bins=0, threads=1):
         self.L, self.q, self.h, self.m = L, q, windows, walkers
-        self.precision = precision
+        self.precision, self.obs_bins = precision, obs_bins
         spins = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(-1)
         if spins.size != windows * walkers * L * L:
             raise ValueError("init_spins must hold one L*L lattice per walker")
         self._keep = spins
         self.h_ = lib().orc_create(L, q, windows, overlap, walkers, seed, instance, flat[0], flat[1],
                                    lnf_init, lnf_final, schedule, sync_attempts, exchange, precision,
-                                   fixed_lnf, shadow, walkin_slack, _ptr(spins))
+                                   fixed_lnf, shadow, walkin_slack, obs_bins, _ptr(spins))
         if not self.h_:
             raise ValueError("oracle rejected the parameters")
         lib().orc_set_threads(self.h_, threads)
@@ -206,6 +224,7 @@ class Rewl:
         """REWL run of the trimer model; init_coords: float32 [walkers, 3 nmol, 3]."""
         self = cls.__new__(cls)
         self.h, self.m, self.precision, self.nmol = windows, walkers, precision, nmol
+        self.obs_bins = 0
         x = np.ascontiguousarray(init_coords, dtype=np.float32).reshape(-1)
         if x.size != windows * walkers * nmol * 9:
             raise ValueError("init_coords must hold 3 nmol beads x 3 coordinates per walker")
@@ -299,6 +318,27 @@ class Rewl:
         trips = np.zeros(self.nw, dtype=np.uint32)
         lib().orc_get_replicas(self.h_, _ptr(win), _ptr(trips))
         return win, trips
+
+    def begin_production(self):
+        """Freeze the current ln g as weights (ln f = 0 everywhere), no termination, restart H."""
+        return lib().orc_begin_production(self.h_)
+
+    def obs(self, w):
+        """Walker w's H(E, O) [W, obs_bins], sum of O [W] and samples [W]."""
+        hist = np.zeros((self.W, self.obs_bins), dtype=np.uint32)
+        s = np.zeros(self.W, dtype=np.uint64)
+        c = np.zeros(self.W, dtype=np.uint32)
+        if lib().orc_get_obs(self.h_, w, _ptr(hist), _ptr(s), _ptr(c)) != 0:
+            raise ValueError("observable not sampled")
+        return hist, s, c
+
+    def obs_micro(self):
+        """(mean O [B], samples [B]) pooled over the walkers of every window holding the bin."""
+        mean = np.zeros(self.B)
+        cnt = np.zeros(self.B, dtype=np.uint64)
+        if lib().orc_obs_micro(self.h_, _ptr(mean), _ptr(cnt)) != 0:
+            raise ValueError("observable not sampled")
+        return mean, cnt
 
     def replica_visits(self, w):
         """uint32 [h*m]: lookups that found each replica id in walker slot w."""

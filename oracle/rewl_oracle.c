@@ -224,6 +224,12 @@ typedef struct {
                               1 lowest reached (highest not since), 2 highest since */
     uint32_t *rep_trips;   /* [nw] by replica id: completed round trips lowest-highest-lowest */
     uint32_t *rep_visits;  /* [nw][nw] lookups that found replica r in slot w (nw <= 4096) */
+    /* observable O = max_s n_s (Potts), sampled at sync points              */
+    int obs_bins;          /* 0: not sampled; else O bins of H(E, O)         */
+    uint32_t *obs_hist;    /* [nw][W][obs_bins] H(E, O) per walker           */
+    uint64_t *obs_sum;     /* [nw][W] sum of O per energy bin                */
+    uint32_t *obs_cnt;     /* [nw][W] samples per energy bin                 */
+    int production;        /* 1: weights frozen, no termination              */
     int64_t *walkin_att;   /* [nw] */
     /* window state */
     double *lnf;           /* [h] current ln f (0 once finished)             */
@@ -247,6 +253,7 @@ static void orc_free(orc_t *o)
     free(o->lnf); free(o->lnf_last); free(o->regime); free(o->finished);
     free(o->iterations); free(o->visited); free(o->x_att); free(o->x_acc);
     free(o->Ed); free(o->rep_end); free(o->rep_trips); free(o->rep_visits);
+    free(o->obs_hist); free(o->obs_sum); free(o->obs_cnt);
     free(o);
 }
 
@@ -379,11 +386,12 @@ static orc_t *orc_new(int B, int e_lo, int N, int h, double overlap, int m, uint
 orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uint32_t instance,
                   uint32_t flat_num, uint32_t flat_den, double lnf_init, double lnf_final,
                   int schedule, int64_t sync_attempts, int exchange, int precision, int fixed_lnf,
-                  int shadow, int walkin_slack, const int8_t *init_spins)
+                  int shadow, int walkin_slack, int obs_bins, const int8_t *init_spins)
 {
     if (L < 3 || L > 724 || q < 2 || q > 127) return NULL;
     if (!init_spins) return NULL;
     int N = L * L;
+    if (obs_bins < 0 || obs_bins > N + 1) return NULL;
     orc_t *o = orc_new(2 * N + 1, -2 * N, N, h, overlap, m, seed, instance, flat_num, flat_den,
                        lnf_init, lnf_final, schedule, sync_attempts, exchange, precision, fixed_lnf,
                        shadow, walkin_slack);
@@ -396,6 +404,14 @@ orc_t *orc_create(int L, int q, int h, double overlap, int m, uint64_t seed, uin
         o->spin[i] = init_spins[i];
     }
     for (int w = 0; w < o->nw; ++w) o->E[w] = potts_energy(o->spin + (size_t)w * N, L);
+    o->obs_bins = obs_bins;
+    if (obs_bins > 0) {
+        size_t cells = nw * (size_t)o->W;
+        o->obs_hist = (uint32_t *)calloc(cells * (size_t)obs_bins, sizeof(uint32_t));
+        o->obs_sum = (uint64_t *)calloc(cells, sizeof(uint64_t));
+        o->obs_cnt = (uint32_t *)calloc(cells, sizeof(uint32_t));
+        if (!o->obs_hist || !o->obs_sum || !o->obs_cnt) { orc_free(o); return NULL; }
+    }
     return o;
 }
 
@@ -1046,6 +1062,64 @@ int orc_exchange(orc_t *o)
     return st;
 }
 
+/* Observable sampling (Sec. 3.2: after the density of states is known, the
+ * paper keeps sampling with fixed weights 1/g(E) and records distributions
+ * H(E, O) of observables O).  For the Potts model O is the population of the
+ * most occupied state, O = max_s n_s, from which the usual order parameter
+ * (q O / N - 1) / (q - 1) follows.  At every sync point (after its exchange
+ * round) each walker adds its current configuration: H(E, O) gains one count
+ * in O bin floor(O * obs_bins / (N + 1)), and the exact sum of O and the
+ * sample count of bin E grow.                                               */
+static void obs_measure(orc_t *o)
+{
+    if (o->obs_bins <= 0) return;
+    int N = o->N, W = o->W, nb = o->obs_bins;
+    int *cnt = (int *)calloc((size_t)o->q, sizeof(int));
+    if (!cnt) return;
+    for (int w = 0; w < o->nw; ++w) {
+        const int8_t *s = o->spin + (size_t)w * N;
+        for (int v = 0; v < o->q; ++v) cnt[v] = 0;
+        for (int i = 0; i < N; ++i) cnt[s[i]] += 1;
+        int O = 0;
+        for (int v = 0; v < o->q; ++v) if (cnt[v] > O) O = cnt[v];
+        int b = o->E[w] - o->start[w / o->m];
+        if (b < 0 || b >= W) continue;
+        size_t cell = (size_t)w * W + (size_t)b;
+        int ob = (int)(((int64_t)O * nb) / (N + 1));
+        o->obs_hist[cell * nb + ob] += 1;
+        o->obs_sum[cell] += (uint64_t)O;
+        o->obs_cnt[cell] += 1;
+    }
+    free(cnt);
+}
+
+/* Production phase: from now on every window keeps its current ln g as
+ * fixed weights (ln f = 0, window marked finished; a window that had not
+ * finished records its current ln f as the last one), the run no longer
+ * terminates, and H and the observable histograms restart from zero.
+ * Needs a walked-in run.                                                    */
+int orc_begin_production(orc_t *o)
+{
+    if (!o->walked_in) return ORC_EINVAL;
+    for (int k = 0; k < o->h; ++k) {
+        if (!o->finished[k]) {
+            o->finished[k] = 1;
+            o->lnf_last[k] = o->lnf[k];
+        }
+        o->lnf[k] = 0.0;
+    }
+    memset(o->H, 0, (size_t)o->nw * o->W * sizeof(uint32_t));
+    if (o->obs_bins > 0) {
+        size_t cells = (size_t)o->nw * o->W;
+        memset(o->obs_hist, 0, cells * (size_t)o->obs_bins * sizeof(uint32_t));
+        memset(o->obs_sum, 0, cells * sizeof(uint64_t));
+        memset(o->obs_cnt, 0, cells * sizeof(uint32_t));
+    }
+    o->converged = 0;
+    o->production = 1;
+    return ORC_OK;
+}
+
 /* Run `attempts` more Wang-Landau attempts per walker.  Sync points (flatness,
  * averaging, ln f update, then an exchange round) fall at every multiple of S
  * attempts counted from the start of the main phase, so splitting a run into
@@ -1083,7 +1157,8 @@ int orc_run(orc_t *o, int64_t attempts, int64_t walkin_budget)
                 if (st != ORC_OK) return st;
             }
             replica_track(o);
-            int all = 1;
+            obs_measure(o);
+            int all = !o->production;
             for (int k = 0; k < o->h; ++k) all = all && o->finished[k];
             if (all) { o->converged = 1; return ORC_CONVERGED; }
         }
@@ -1301,5 +1376,66 @@ void orc_thermo(const double *lng, int B, double e_first, double de, const doubl
         lnZ[t] = lz;
         U[t] = u;
         C[t] = var / (T[t] * T[t]);
+    }
+}
+
+/* Walker w's observable record: H(E, O) [W][obs_bins], sum of O [W] and
+ * samples [W] per energy bin of its window; -1 if O is not sampled.         */
+int orc_get_obs(const orc_t *o, int w, uint32_t *hist, uint64_t *sum, uint32_t *count)
+{
+    if (o->obs_bins <= 0 || w < 0 || w >= o->nw) return ORC_EINVAL;
+    size_t W = (size_t)o->W, nb = (size_t)o->obs_bins;
+    if (hist) memcpy(hist, o->obs_hist + (size_t)w * W * nb, W * nb * sizeof(uint32_t));
+    if (sum) memcpy(sum, o->obs_sum + (size_t)w * W, W * sizeof(uint64_t));
+    if (count) memcpy(count, o->obs_cnt + (size_t)w * W, W * sizeof(uint32_t));
+    return ORC_OK;
+}
+
+/* Microcanonical mean of O per energy bin of the whole range: the samples of
+ * every walker whose window holds the bin, pooled (with weights that depend
+ * on E only, the distribution of O at fixed E does not depend on them).
+ * mean[b] = NaN where no sample fell.                                       */
+int orc_obs_micro(const orc_t *o, double *mean, uint64_t *count)
+{
+    if (o->obs_bins <= 0) return ORC_EINVAL;
+    for (int b = 0; b < o->B; ++b) {
+        uint64_t s = 0, c = 0;
+        for (int k = 0; k < o->h; ++k) {
+            int lb = b - (o->start[k] - o->e_lo);
+            if (lb < 0 || lb >= o->W) continue;
+            for (int j = 0; j < o->m; ++j) {
+                size_t cell = (size_t)(k * o->m + j) * o->W + (size_t)lb;
+                s += o->obs_sum[cell];
+                c += o->obs_cnt[cell];
+            }
+        }
+        mean[b] = c ? (double)s / (double)c : NAN;
+        if (count) count[b] = c;
+    }
+    return ORC_OK;
+}
+
+/* Canonical average of O at temperature T (Sec. 3.2 with Sec. 3.1's
+ * canonical weights): <O>_T = sum_E g(E) e^{-E/T} mu(E) / sum_E g(E) e^{-E/T}
+ * over the bins where ln g is finite and mu(E) was sampled, with the
+ * largest exponent factored out.                                            */
+void orc_obs_thermo(const double *lng, const double *mu, int B, double e_first, double de,
+                    const double *T, int nT, double *out)
+{
+    for (int t = 0; t < nT; ++t) {
+        double mx = -INFINITY;
+        for (int b = 0; b < B; ++b) {
+            if (lng[b] == -INFINITY || isnan(mu[b])) continue;
+            double x = lng[b] - (e_first + (double)b * de) / T[t];
+            if (x > mx) mx = x;
+        }
+        double z = 0.0, num = 0.0;
+        for (int b = 0; b < B; ++b) {
+            if (lng[b] == -INFINITY || isnan(mu[b])) continue;
+            double p = exp((lng[b] - (e_first + (double)b * de) / T[t]) - mx);
+            z += p;
+            num += p * mu[b];
+        }
+        out[t] = num / z;
     }
 }

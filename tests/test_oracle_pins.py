@@ -674,3 +674,119 @@ def test_trimer_rewl_walks_in_and_converges():
     assert abs(np.log(np.exp(lng[fin]).sum())) < 1e-9          # sum over bins of g = 1
     for w in range(4):
         assert o.starts[w // 2] <= o.walker(w)["E"] <= o.starts[w // 2] + o.W - 1
+
+
+# --------------------------------------------------------------------------
+# Production sampling with fixed weights and observable histograms H(E, O)
+# (Sec. 3.2).  O = max_s n_s, the population of the most occupied state.
+
+def enumerate_potts(L, q):
+    """Energy and O of every configuration of the L x L lattice (periodic, each bond once)."""
+    N = L * L
+    idx = np.arange(q ** N, dtype=np.int64)
+    s = np.stack([(idx // q ** i) % q for i in range(N)], axis=1).reshape(-1, L, L)
+    E = -((s == np.roll(s, 1, axis=1)).sum(axis=(1, 2)) + (s == np.roll(s, 1, axis=2)).sum(axis=(1, 2)))
+    O = np.max(np.stack([(s == v).sum(axis=(1, 2)) for v in range(q)]), axis=0)
+    return E, O
+
+
+@pytest.mark.parametrize("h,m,nb", [(1, 2, 7), (2, 1, 26), (3, 2, 1)])
+def test_obs_sampled_at_sync_points_from_the_current_lattice(h, m, nb):
+    # Each sync point adds the configuration each walker holds then: one count
+    # in H(E, O) at O bin floor(O nb / (N + 1)), O added to the bin's sum.
+    L, q, S = 5, 4, 50
+    N = L * L
+    spins = workloads.init_spins(L, q, h * m, 21)
+    o = oracle.Rewl(L, q, h, 0.75, m, spins, seed=6, lnf_init=0.05, fixed_lnf=1, exchange=0,
+                    sync_attempts=S, obs_bins=nb)
+    hist = np.zeros((h * m, o.W, nb), dtype=np.int64)
+    tot = np.zeros((h * m, o.W), dtype=np.int64)
+    cnt = np.zeros((h * m, o.W), dtype=np.int64)
+    for _ in range(6):
+        o.run(S)
+        for w in range(h * m):
+            d = o.walker(w)
+            O = int(np.bincount(d["spins"], minlength=q).max())
+            b = d["E"] - o.starts[w // m]
+            assert 0 <= b < o.W
+            hist[w, b, O * nb // (N + 1)] += 1
+            tot[w, b] += O
+            cnt[w, b] += 1
+    for w in range(h * m):
+        gh, gs, gc = o.obs(w)
+        assert np.array_equal(gh, hist[w]) and np.array_equal(gs, tot[w]) and np.array_equal(gc, cnt[w])
+
+
+def test_obs_distribution_under_exact_weights_matches_enumeration():
+    # With weights 1/g(E) the walk samples, at each energy, configurations
+    # uniformly; the pooled H(E, O) must approach the exact conditional
+    # distribution of O at E, and the pooled mean of O the exact one.
+    L, q = 3, 3
+    E, O = enumerate_potts(L, q)
+    N = L * L
+    ex = exact_lng(L, q)
+    e_lo = -2 * N
+    spins = workloads.init_spins(L, q, 4, 23)
+    o = oracle.Rewl(L, q, 2, 0.75, 2, spins, seed=3, lnf_init=0.0, fixed_lnf=1, exchange=1,
+                    sync_attempts=9, obs_bins=N + 1)
+    for w in range(4):
+        k = w // 2
+        seg = ex[o.starts[k] - e_lo: o.starts[k] - e_lo + o.W]
+        o.set_lng(w, np.where(np.isfinite(seg), seg, 0.0))
+    o.run(9 * 60_000)
+    mean, cnt = o.obs_micro()
+    reach = np.isfinite(ex)
+    assert np.all(cnt[reach] > 0) and np.all(cnt[~reach] == 0)
+    pooled = np.zeros((o.B, N + 1))
+    for w in range(4):
+        off = o.starts[w // 2] - e_lo
+        pooled[off: off + o.W] += o.obs(w)[0]
+    for b in np.flatnonzero(reach):
+        at = E == b + e_lo
+        exact_mean = O[at].mean()
+        exact_p = np.bincount(O[at], minlength=N + 1) / at.sum()
+        assert abs(mean[b] - exact_mean) < 0.08, (b, mean[b], exact_mean)
+        assert np.max(np.abs(pooled[b] / pooled[b].sum() - exact_p)) < 0.05, b
+
+
+def test_obs_thermo_matches_canonical_enumeration():
+    L, q = 3, 3
+    E, O = enumerate_potts(L, q)
+    N = L * L
+    B = 2 * N + 1
+    n_at = np.bincount(E + 2 * N, minlength=B)
+    lng = np.full(B, -np.inf)
+    lng[n_at > 0] = np.log(n_at[n_at > 0])
+    mu = np.full(B, np.nan)
+    for b in np.flatnonzero(n_at):
+        mu[b] = O[E + 2 * N == b].mean()
+    T = np.array([0.2, 0.5, 0.9, 1.5, 4.0, 50.0])
+    got = oracle.obs_thermo(lng, mu, -2 * N, T)
+    for t, g in zip(T, got):
+        x = -E / t
+        p = np.exp(x - x.max())
+        assert g == pytest.approx(float((p * O).sum() / p.sum()), rel=1e-12)
+
+
+def test_production_after_convergence_keeps_weights_and_samples_o():
+    L, q = 3, 3
+    E, O = enumerate_potts(L, q)
+    N = L * L
+    spins = workloads.init_spins(L, q, 4, 29)
+    o = oracle.Rewl(L, q, 2, 0.75, 2, spins, seed=8, lnf_final=1e-3, sync_attempts=90, obs_bins=5)
+    assert o.begin_production() != 0          # not walked in yet
+    assert o.run(10**9) == oracle.CONVERGED
+    step = o.step
+    lng0 = [o.walker(w)["lng"].copy() for w in range(4)]
+    assert o.begin_production() == 0
+    assert all(o.window(k)["lnf"] == 0.0 and o.window(k)["finished"] == 1 for k in range(2))
+    assert all(o.walker(w)["H"].sum() == 0 for w in range(4))
+    assert o.run(90 * 10_000) == oracle.OK
+    assert o.step == step + 90 * 10_000
+    for w in range(4):
+        d = o.walker(w)
+        assert np.array_equal(d["lng"], lng0[w]) and d["H"].sum() == 90 * 10_000
+        assert o.obs(w)[2].sum() == 10_000
+    mean, cnt = o.obs_micro()
+    for b in np.flatnonzero(cnt > 500):
+        assert abs(mean[b] - O[E == b - 2 * N].mean()) < 0.15, b
