@@ -420,6 +420,63 @@ def to_convergence(args):
     print(json.dumps(out), flush=True)
 
 
+def production(args):
+    """The potts_q10_L32 workload in the production phase (frozen weights, Sec. 3.2):
+    after a WL segment, begin_production, then sample H(E, O) of O = max_s n_s at
+    every sync point with full O resolution (L*L + 1 bins).  Reported beside the
+    same run's WL-phase rate: the attempt kernel is the same, the sync point
+    gains the observable pass."""
+    import torch
+
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    cfg = dict(workloads.CONFIGS[args.config])
+    L, q, h, m = cfg["L"], cfg["q"], cfg["windows"], cfg["walkers"]
+    nw, S = h * m, cfg["sync_attempts"]
+    spins = workloads.init_spins(L, q, nw, cfg["seed"])
+    torch.cuda.set_device(0)
+    g = pk.Rewl(L, q, h, cfg["overlap"], m, spins, seed=cfg["seed"], flat=cfg["flat"],
+                lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"], schedule=cfg["schedule"],
+                sync_attempts=S, exchange=cfg["exchange"], precision=cfg["precision"], obs_bins=L * L + 1)
+    g.walkin()
+    g.run(args.warmup * S)
+    torch.cuda.synchronize()
+    rates = {}
+    for phase in ("wl", "production"):
+        if phase == "production":
+            g.begin_production()
+            g.run(args.warmup * S)
+        g.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = g.run(args.steps * S)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        sweep_ms, launches, sync_ms, syncs = g.timing()
+        g.set_timing(False)
+        if st == pk.CONVERGED:
+            raise RuntimeError("run converged inside the timed region")
+        rates[phase] = dict(attempts_per_s=nw * S * args.steps / elapsed, ms_per_step=elapsed * 1e3 / args.steps,
+                            k_sweep_avg_ms=sweep_ms / max(launches, 1), sync_point_avg_ms=sync_ms / max(syncs, 1))
+        log(f"[bench] {phase}: {rates[phase]}")
+    mean, cnt = g.obs_micro()
+    p = rates["production"]
+    out = {
+        "metric": "spin-flip attempts/s (1 GPU), production phase with H(E, O) sampling, q=10 Potts L=32",
+        "value": p["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": p["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config} after {args.warmup} WL steps, weights frozen, "
+                               f"O = max_s n_s in {L * L + 1} bins sampled every {S} attempts per walker",
+                   "walkers": nw, "obs_bins": L * L + 1},
+        "phases": rates,
+        "production_over_wl": p["attempts_per_s"] / rates["wl"]["attempts_per_s"],
+        "samples": int(cnt.sum()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,10 +494,12 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
                          "times first: the reference for the HBM byte counters of a profiler run")
-    ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer"), default="potts",
+    ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer", "production"),
+                    default="potts",
                     help="potts: the single-run workload (--config); batched: 256 instances; "
                          "precision: the L=80 workload in binary64 and in the binary32 pair form; "
-                         "trimer: the continuous-move workload")
+                         "trimer: the continuous-move workload; production: the single-run workload "
+                         "with frozen weights and H(E, O) sampling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
@@ -466,6 +525,8 @@ def main():
         return precision_study(args)
     if args.workload == "trimer":
         return trimer(args)
+    if args.workload == "production":
+        return production(args)
 
     import torch
 

@@ -74,6 +74,11 @@ typedef struct {
     int32_t shadow;         /* [0] 1: keep an exact reference of ln g (see           */
                             /*     rewl_get_shadow); costs 20 bytes per bin and walker */
     int32_t walkin_slack;   /* [16] walk-in lid width (energy units), 0 = no lid    */
+    int32_t obs_bins;       /* [0] Potts only: > 0 samples O = max_s n_s at every    */
+                            /*     sync point into H(E, O) with this many O bins   */
+                            /*     (at most L*L+1; see rewl_get_obs); costs        */
+                            /*     4*obs_bins + 12 bytes per bin and walker        */
+    int32_t reserved;       /* [0] must be 0                                        */
 } rewl_opts;
 
 void rewl_default_opts(rewl_opts *o);
@@ -176,6 +181,43 @@ int rewl_get_replicas(rewl_t *r, uint32_t *window_of, uint32_t *trips);
  * Errors: REWL_EINVAL on a null handle or buffer, w out of range, or a run
  * with more than 4096 walkers.                                                */
 int rewl_get_replica_visits(rewl_t *r, int walker, uint32_t *counts);
+
+/* Production phase (Sec. 3.2: after g(E) is estimated, sampling goes on
+ * with fixed weights 1/g(E) while observables are recorded).  From this call
+ * on every walker keeps its current ln g as fixed weights: each window gets
+ * ln f = 0 and is marked finished (a window not finished before records its
+ * current ln f as lnf_last), the run no longer terminates, and H and the
+ * observable record restart from zero; step and round counters continue.
+ * Usually called once rewl_run has returned REWL_CONVERGED; rewl_run then
+ * keeps sampling.  Errors: REWL_EINVAL on a null handle, REWL_ESTATE before
+ * the walk-in or on an instance of a batch.                                   */
+int rewl_begin_production(rewl_t *r);
+
+/* Observable record of walker w (runs with opts.obs_bins > 0).  At every
+ * sync point, after its exchange round, each walker adds the configuration it
+ * holds: with O = max_s n_s (the population of the most occupied state; the
+ * order parameter is (q O / N - 1) / (q - 1)) and b its energy bin in the
+ * window, hist[b][floor(O * obs_bins / (N + 1))] += 1, sum[b] += O,
+ * count[b] += 1.  Host buffers hist uint32[W][obs_bins], sum uint64[W],
+ * count uint32[W]; any may be NULL.  Errors: REWL_EINVAL on a null handle,
+ * w out of range, or a run without observable sampling.                      */
+int rewl_get_obs(rewl_t *r, int walker, uint32_t *hist, uint64_t *sum, uint32_t *count);
+
+/* Microcanonical mean of O per energy bin of the whole range (B bins, bin b
+ * at energy e_lo + b): the samples of all walkers whose window holds the bin,
+ * pooled (weights that depend only on E leave the distribution of O at fixed
+ * E unchanged).  mean double[B] (NaN where no sample fell), count uint64[B]
+ * (may be NULL).  Errors: REWL_EINVAL on a null handle or mean, or a run
+ * without observable sampling.                                               */
+int rewl_obs_micro(rewl_t *r, double *mean, uint64_t *count);
+
+/* Canonical average of O at nT temperatures (Sec. 3.2 with the canonical
+ * weights of Sec. 3.1): <O>_T = sum_E g(E) e^{-E/T} mu(E) / sum_E g(E)
+ * e^{-E/T} over the bins with a finite joined ln g and samples of O, mu the
+ * pooled mean of rewl_obs_micro.  Needs a current rewl_join.  out double[nT].
+ * Errors: REWL_EINVAL (null argument, nT outside [1, 4096], T <= 0, no
+ * observable sampling), REWL_ESTATE without a current join.                  */
+int rewl_obs_thermo(rewl_t *r, const double *T, int nT, double *out);
 
 /* Progress counters: main-phase attempts per walker, exchange rounds done,
  * and whether the run converged.  Any pointer may be NULL.                   */

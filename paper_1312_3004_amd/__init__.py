@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("exchange", ctypes.c_int32),
                 ("sync_attempts", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("fixed_lnf", ctypes.c_int32), ("shadow", ctypes.c_int32),
-                ("walkin_slack", ctypes.c_int32)]
+                ("walkin_slack", ctypes.c_int32), ("obs_bins", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -92,6 +92,10 @@ def lib():
         L.rewl_get_shadow.argtypes = [P, i32, P, P]
         L.rewl_get_replicas.argtypes = [P, P, P]
         L.rewl_get_replica_visits.argtypes = [P, i32, P]
+        L.rewl_begin_production.argtypes = [P]
+        L.rewl_get_obs.argtypes = [P, i32, P, P, P]
+        L.rewl_obs_micro.argtypes = [P, P, P]
+        L.rewl_obs_thermo.argtypes = [P, P, i32, P]
         flt = ctypes.c_float
         L.rewl_trimer_workspace_bytes.argtypes = [i32, flt, dbl, dbl, i32, i32, dbl, i32, ctypes.POINTER(Opts)]
         L.rewl_trimer_workspace_bytes.restype = ctypes.c_size_t
@@ -153,7 +157,7 @@ def window_layout(L, windows, overlap):
 
 
 def make_opts(seed=1, instance=0, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
-              sync_attempts=1000, exchange=1, precision=0, fixed_lnf=0, shadow=0, walkin_slack=16):
+              sync_attempts=1000, exchange=1, precision=0, fixed_lnf=0, shadow=0, walkin_slack=16, obs_bins=0):
     o = default_opts()
     o.seed, o.instance = seed, instance
     o.flat_num, o.flat_den = flat
@@ -161,6 +165,7 @@ def make_opts(seed=1, instance=0, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, sch
     o.schedule, o.sync_attempts, o.exchange = schedule, sync_attempts, exchange
     o.precision, o.fixed_lnf, o.shadow = precision, fixed_lnf, shadow
     o.walkin_slack = walkin_slack
+    o.obs_bins = obs_bins
     return o
 
 
@@ -204,7 +209,7 @@ class Rewl:
         self.N = L * L
         self.nw = windows * walkers
         self.opts = opts
-        self.precision = self.opts.precision
+        self.precision, self.obs_bins = self.opts.precision, self.opts.obs_bins
         self.W, self.starts = window_layout(L, windows, overlap)
         self.B = 2 * self.N + 1
         self.e_lo = -2 * self.N
@@ -218,7 +223,7 @@ class Rewl:
         self = cls.__new__(cls)
         o = make_opts(**opts)
         self.h, self.m, self.nw = windows, walkers, windows * walkers
-        self.opts, self.precision = o, o.precision
+        self.opts, self.precision, self.obs_bins = o, o.precision, o.obs_bins
         self.nmol, self.box, self.e_min, self.bin_w = nmol, box, e_min, bin_w
         self.L = self.q = 0
         self.N = 9 * nmol * 4
@@ -338,6 +343,32 @@ class Rewl:
         trips = np.zeros(self.nw, dtype=np.uint32)
         _check(lib().rewl_get_replicas(self._h, _ptr(win), _ptr(trips)))
         return win, trips
+
+    def begin_production(self):
+        """Freeze the current ln g as weights (ln f = 0 everywhere), no termination, restart H."""
+        _check(lib().rewl_begin_production(self._h))
+
+    def obs(self, w):
+        """Walker w's H(E, O) [W, obs_bins], sum of O [W] and samples [W]."""
+        hist = np.zeros((self.W, self.obs_bins), dtype=np.uint32)
+        s = np.zeros(self.W, dtype=np.uint64)
+        c = np.zeros(self.W, dtype=np.uint32)
+        _check(lib().rewl_get_obs(self._h, w, _ptr(hist), _ptr(s), _ptr(c)))
+        return hist, s, c
+
+    def obs_micro(self):
+        """(mean O [B], samples [B]) pooled over the walkers of every window holding the bin."""
+        mean = np.zeros(self.B)
+        cnt = np.zeros(self.B, dtype=np.uint64)
+        _check(lib().rewl_obs_micro(self._h, _ptr(mean), _ptr(cnt)))
+        return mean, cnt
+
+    def obs_thermo(self, T):
+        """Canonical average of O on the temperature grid T (needs a current join)."""
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        out = np.zeros_like(T)
+        _check(lib().rewl_obs_thermo(self._h, _ptr(T), len(T), _ptr(out)))
+        return out
 
     def replica_visits(self, w):
         """uint32 [h*m]: lookups that found each replica id in walker slot w."""

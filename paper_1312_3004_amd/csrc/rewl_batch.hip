@@ -105,6 +105,7 @@ struct rewl_batch {
     hipGraphExec_t exec = nullptr;
     int64_t steps = 0;
     int32_t n_converged = 0;
+    bool any_obs = false;                         // some instance samples an observable
     Timer timer;
 };
 
@@ -206,6 +207,7 @@ hipError_t enqueue_step(rewl_batch *b, hipStream_t s) {
     }
     if (e == hipSuccess) e = rewl_gpu::launch_sync_batch(b->precision, b->d_descs, b->d_wtasks, 0, b->nwin, s);
     if (e == hipSuccess) e = rewl_gpu::launch_exchange_batch(b->d_descs, b->d_xtasks, 0, b->npairs, s);
+    if (e == hipSuccess && b->any_obs) e = rewl_gpu::launch_measure_batch(b->d_descs, b->d_tasks_inst, 0, b->ntasks, s);
     if (e == hipSuccess) e = rewl_gpu::launch_advance_batch(b->d_descs, 0, b->n, s);
     return e;
 }
@@ -282,6 +284,8 @@ int run_steps(rewl_batch *b, int64_t steps, bool per_instance) {
                 HIP_TRY(rewl_gpu::launch_sync_batch(b->precision, b->d_descs, b->d_wtasks, b->win_lo[i], h,
                                                     b->stream));
                 HIP_TRY(rewl_gpu::launch_exchange_batch(b->d_descs, b->d_xtasks, b->pair_lo[i], h / 2, b->stream));
+                if (r->st.obs_bins > 0)
+                    HIP_TRY(rewl_gpu::launch_measure_batch(b->d_descs, b->d_tasks_inst, b->task_lo[i], nw, b->stream));
                 HIP_TRY(rewl_gpu::launch_advance_batch(b->d_descs, i, 1, b->stream));
             }
         } else if (b->plan.use_graph) {
@@ -505,6 +509,7 @@ int rewl_batch_create(rewl_batch_t **out, int n, const rewl_instance *inst, cons
             return bail(fail(st, "instance " + std::to_string(i) + ": " + msg));
         }
         r->in_batch = true;
+        b->any_obs = b->any_obs || r->st.obs_bins > 0;
         b->inst.push_back(r);
         spin_off += (size_t)inst[i].windows * inst[i].walkers * inst[i].L * inst[i].L;
     }

@@ -61,6 +61,11 @@ struct DevState {
     uint32_t *rep_trips;         // [nw] per replica id: completed lowest-highest-lowest round trips
     uint32_t *rep_visits;        // [nw][nw] lookups that found replica r in slot w (null above
                                  // kMaxVisitWalkers walkers)
+    int obs_bins;                // O bins of H(E, O); 0: observables not sampled
+    uint32_t *obs_hist;          // [nw][Wpad][obs_bins] H(E, O) per walker
+    unsigned long long *obs_sum; // [nw][Wpad] sum of O per energy bin
+    uint32_t *obs_cnt;           // [nw][Wpad] samples per energy bin
+    int32_t *production;         // [1] 1: weights frozen, no termination
     int64_t *walkin_att;         // [nw]
     int32_t *walkin_done;        // [nw]
     int32_t *walkin_bound;       // [nw] walk-in lid (walker above its window) or floor
@@ -267,6 +272,11 @@ hipError_t launch_sync(const DevState &st, int64_t attempts, hipStream_t s);
 hipError_t launch_exchange(const DevState &st, uint32_t round, hipStream_t s);
 hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, hipStream_t s);
 hipError_t launch_track(const DevState &st, hipStream_t s);
+hipError_t launch_measure(const DevState &st, hipStream_t s);
+hipError_t launch_begin_production(const DevState &st, hipStream_t s);
+hipError_t launch_obs_micro(const DevState &st, double *mean, unsigned long long *count, hipStream_t s);
+hipError_t launch_obs_thermo(const DevState &st, const double *T, int nT, const double *mean, double *out,
+                             hipStream_t s);
 hipError_t launch_join(const DevState &st, double log_total, hipStream_t s);
 hipError_t launch_thermo(const DevState &st, const double *T, int nT, double *out, hipStream_t s);
 size_t sweep_lds_bytes(const DevState &st);
@@ -292,6 +302,7 @@ hipError_t launch_sweep_batch(int precision, const DevState *descs, const BatchT
                               int ntasks, int *queue, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_sync_batch(int precision, const DevState *descs, const BatchTask *wtasks, int lo, int n,
                              hipStream_t s);
+hipError_t launch_measure_batch(const DevState *descs, const BatchTask *tasks, int lo, int n, hipStream_t s);
 hipError_t launch_exchange_batch(const DevState *descs, const BatchTask *xtasks, int lo, int n,
                                  hipStream_t s);
 hipError_t launch_advance_batch(const DevState *descs, int lo, int n, hipStream_t s);

@@ -191,27 +191,13 @@ __global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64
 //  * ln g of 64 consecutive energies around the walker sit in VGPRs (lane b
 //    holds energy ebase + b; energies outside the window hold +inf, which
 //    makes any move there a certain reject).
-// Two serial modes:
-//  * exact mode (large ln f): the current ln g is carried through every
-//    attempt and compared with the cached ln g of the proposed energy;
-//  * table mode (ln f <= kTableMaxLnf, i.e. nearly all of a run): ln g is
-//    frozen at its block-start values during the block.  For every attempt
-//    the lanes (one per candidate energy e) compare d(e) = ln g(e) -
-//    ln g(e + dE) with ln u; one compare yields a 64-bit accept mask and a
-//    "decided" mask, and the serial step is a bit test on the walker's
-//    energy.  The margin also covers the drift of ln g within a block (at
-//    most 64 ln f) and the binary32 rounding of d, so every decided bit
-//    equals the sequential decision; undecided attempts rebuild the exact
-//    current ln g (block-start value plus the same sequence of ln f
-//    additions) and apply the exact rule.  At block end every bin receives
-//    its ln f additions in sequence, the result the sequential walk leaves.
+// The serial phase carries the walker's current ln g through every attempt
+// and compares it with the cached ln g of the proposed energy.
 // H(E) increments and accepted spins are applied to LDS once per block (no
 // two pending spin writes share a site: a repeat hit is a conflict and is
 // written at once).
 constexpr double kMargin64 = 1e-10;   // log-domain slack of the exact-mode test (binary64)
 constexpr double kMargin32 = 1e-5;    // log-domain slack of the exact-mode test (binary32)
-constexpr double kTableMaxLnf = 2e-4; // table mode when ln f is at most this
-constexpr double kTableDmax = 64.0;   // |d| in (64, 65]: undecided; beyond: decided by its sign
 
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
@@ -225,31 +211,6 @@ __device__ __forceinline__ double readlane_d(double v, int j) {
 __device__ __forceinline__ float readlane_f(float v, int j) {
     return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), j));
 }
-// binary32 rounding of a finite x towards +inf / -inf (one ulp step when
-// round-to-nearest went the wrong way)
-__device__ __forceinline__ float f32_up(double x) {
-    float f = (float)x;
-    if ((double)f < x) {
-        uint32_t b = __float_as_uint(f);
-        if (f == 0.0f) b = 1u;
-        else if (f > 0.0f) b += 1u;
-        else b -= 1u;
-        f = __uint_as_float(b);
-    }
-    return f;
-}
-__device__ __forceinline__ float f32_down(double x) {
-    float f = (float)x;
-    if ((double)f > x) {
-        uint32_t b = __float_as_uint(f);
-        if (f == 0.0f) b = 0x80000001u;
-        else if (f > 0.0f) b -= 1u;
-        else b += 1u;
-        f = __uint_as_float(b);
-    }
-    return f;
-}
-
 // Orders this wavefront's LDS traffic at a phase boundary of a walker.  With
 // one walker per workgroup a workgroup barrier; with several independent
 // walkers (one per wavefront) in a workgroup a fence of the wave's own memory
@@ -274,28 +235,21 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     float *gl = gh + Wpad;
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
     unsigned long long *tag = (unsigned long long *)(smem + st.Npad + (size_t)Wpad * 12);
-    uint32_t *cnt = (uint32_t *)(tag + st.Ntag);
-    float *dtab = (float *)(cnt + 64);   // [9][64] table-mode differences
-    uint4 *apar = (uint4 *)(dtab + 9 * 64);  // [64] per-attempt table offset, dE + 64, thresholds
     const uint32_t tag_mask = (uint32_t)st.Ntag - 1u;
 
     const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)sp)[i] = gsp[i];
     const size_t row = (size_t)w * Wpad;
-    double gmax = 0.0;
     for (int b = lane; b < W; b += 64) {
         if (PREC == 0) {
             g[b] = st.lng[row + b];
-            gmax = fmax(gmax, fabs(g[b]));
         } else {
             gh[b] = st.lng_hi[row + b];
             gl[b] = st.lng_lo[row + b];
-            gmax = fmax(gmax, fabs((double)gh[b]) + fabs((double)gl[b]));
         }
         H[b] = st.H[row + b];
     }
     for (int i = lane; i < st.Ntag; i += 64) tag[i] = 0ull;
-    cnt[lane] = 0u;
     walker_sync<WAVE>();
 
     const int lo = st.start[k], hi = lo + W - 1;
@@ -304,13 +258,6 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     const float lnf32 = (float)lnf;
     int E = st.E[w];
     if (E < lo || E > hi) return;  // not walked in: leave the walker untouched
-
-    // Table-mode margin: exp/log error and binary32 rounding of d (2e-5),
-    // drift of ln g within a block (64 ln f), and the rounding of up to 64
-    // additions on values bounded by gmax + n ln f.
-    for (int o = 32; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o));
-    const bool tbl = lnf <= kTableMaxLnf;
-    const double margin = 2e-5 + 64.5 * lnf + 0x1p-44 * (gmax + (double)n * lnf + 1.0);
 
     // ln g cache: lane b holds energy ebase + b (+inf outside the window)
     int ebase = E - 32;
@@ -346,10 +293,9 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             erel = 32;
             cache_load();
         }
-        if (!tbl) {   // exact mode carries the current ln g in registers
-            if (PREC == 0) { gEs = readlane_d(c64, erel); gEv = gEs; }
-            else { gEh = readlane_f(ch, erel); gEl = readlane_f(cl, erel); }
-        }
+        // the current ln g rides in registers through the block
+        if (PREC == 0) { gEs = readlane_d(c64, erel); gEv = gEs; }
+        else { gEh = readlane_f(ch, erel); gEl = readlane_f(cl, erel); }
         // ---- lane-parallel phase: proposal, energy change, conflicts, ln u
         const Proposal p = propose(st, kDomMove, (uint64_t)(s0 + base + lane), (uint32_t)w);
         const int sc = sp[p.site];
@@ -391,16 +337,14 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                        (int)(v == a0) - (int)(v == a1) - (int)(v == a2) - (int)(v == a3));
         };
 
-        // Exact decision of attempt j from the exact current ln g of the walker's
-        // energy and of the proposed one (table mode: rebuilt by replaying this
-        // block's ln f additions).  Also handles conflicts.  Returns acceptance
-        // and writes dE actually used.
-        auto slow_attempt = [&](int j, bool table_values, int dEj_in = 0, bool now_in = false,
-                                int nvj_in = 0, bool resolve = true) -> void {
-            int dEj = resolve ? __builtin_amdgcn_readlane(dE, j) : dEj_in;
-            bool now = resolve ? false : now_in;
-            int nvj = resolve ? 0 : nvj_in;
-            if (resolve && ((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
+        // Decision of attempt j through the general path: settles its conflict
+        // first (recomputing dE from the live lattice), then applies the rule
+        // with the carried current ln g and the cached ln g of the new energy.
+        auto slow_attempt = [&](int j) -> void {
+            int dEj = __builtin_amdgcn_readlane(dE, j);
+            bool now = false;
+            int nvj = 0;
+            if (((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
                 dEj = settle(j, nvj);
                 now = true;
             }
@@ -408,57 +352,31 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             bool acc = false;
             if (En >= lo && En <= hi) {
                 const uint32_t u = __builtin_amdgcn_readlane(p.u, j);
-                if (table_values) {
-                    // exact current values: block-start value + this block's additions
-                    const unsigned long long before = (1ull << j) - 1ull;
-                    const int n_cur = __builtin_popcountll(__ballot(hist == Ecur - ebase) & before);
-                    const int n_new = __builtin_popcountll(__ballot(hist == En - ebase) & before);
-                    const int rc = Ecur - ebase, rn = En - ebase;
-                    if (PREC == 0) {
-                        double vc = (unsigned)rc < 64u ? readlane_d(c64, rc) : g[Ecur - lo];
-                        double vn = (unsigned)rn < 64u ? readlane_d(c64, rn) : g[En - lo];
-                        vc = rfl(vc);
-                        vn = rfl(vn);
-                        for (int i = 0; i < n_cur; ++i) vc = vc + lnf;
-                        for (int i = 0; i < n_new; ++i) vn = vn + lnf;
-                        acc = __ballot(accept64(vc - vn, u)) != 0ull;
-                    } else {
-                        float hc = (unsigned)rc < 64u ? readlane_f(ch, rc) : gh[Ecur - lo];
-                        float lc = (unsigned)rc < 64u ? readlane_f(cl, rc) : gl[Ecur - lo];
-                        float hn = (unsigned)rn < 64u ? readlane_f(ch, rn) : gh[En - lo];
-                        float ln_ = (unsigned)rn < 64u ? readlane_f(cl, rn) : gl[En - lo];
-                        hc = rfl(hc); lc = rfl(lc); hn = rfl(hn); ln_ = rfl(ln_);
-                        for (int i = 0; i < n_cur; ++i) two_sum_add(hc, lc, lnf32);
-                        for (int i = 0; i < n_new; ++i) two_sum_add(hn, ln_, lnf32);
-                        acc = __ballot(accept32((hc - hn) + (lc - ln_), u)) != 0ull;
-                    }
+                int idx = erel + dEj;
+                if ((unsigned)idx >= 64u) {
+                    cache_store();
+                    ebase += idx - 32;
+                    cache_load();
+                    erel = erel - idx + 32;
+                    idx = 32;
+                }
+                const double luj = readlane_d(lnu, j);
+                if (PREC == 0) {
+                    const double gN = readlane_d(c64, idx);
+                    const double d = gEv - gN;
+                    const double t = d - luj;
+                    if (__ballot(fabs(t) > kMargin64) != 0ull) acc = __ballot(t > 0.0) != 0ull;
+                    else acc = __ballot(accept64(d, u)) != 0ull;
+                    gEs = acc ? gN : gEs;
                 } else {
-                    int idx = erel + dEj;
-                    if ((unsigned)idx >= 64u) {
-                        cache_store();
-                        ebase += idx - 32;
-                        cache_load();
-                        erel = erel - idx + 32;
-                        idx = 32;
-                    }
-                    const double luj = readlane_d(lnu, j);
-                    if (PREC == 0) {
-                        const double gN = readlane_d(c64, idx);
-                        const double d = gEv - gN;
-                        const double t = d - luj;
-                        if (__ballot(fabs(t) > kMargin64) != 0ull) acc = __ballot(t > 0.0) != 0ull;
-                        else acc = __ballot(accept64(d, u)) != 0ull;
-                        gEs = acc ? gN : gEs;
-                    } else {
-                        const float gNh = readlane_f(ch, idx);
-                        const float gNl = readlane_f(cl, idx);
-                        const float d = (gEh - gNh) + (gEl - gNl);
-                        const double t = (double)d - luj;
-                        if (__ballot(fabs(t) > kMargin32) != 0ull) acc = __ballot(t > 0.0) != 0ull;
-                        else acc = __ballot(accept32(d, u)) != 0ull;
-                        gEh = acc ? gNh : gEh;
-                        gEl = acc ? gNl : gEl;
-                    }
+                    const float gNh = readlane_f(ch, idx);
+                    const float gNl = readlane_f(cl, idx);
+                    const float d = (gEh - gNh) + (gEl - gNl);
+                    const double t = (double)d - luj;
+                    if (__ballot(fabs(t) > kMargin32) != 0ull) acc = __ballot(t > 0.0) != 0ull;
+                    else acc = __ballot(accept32(d, u)) != 0ull;
+                    gEh = acc ? gNh : gEh;
+                    gEl = acc ? gNl : gEl;
                 }
             }
             erel = acc ? En - ebase : erel;
@@ -467,163 +385,22 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 if (lane == 0) sp[__builtin_amdgcn_readlane(p.site, j)] = (int8_t)nvj;
                 flushed |= 1ull << j;
             }
-            if (!table_values) {
-                if (PREC == 0) {
-                    gEv = gEs + lnf_v;
-                    gEs = rfl(gEv);
-                    c64 = (lane == erel) ? gEv : c64;
-                } else {
-                    two_sum_add(gEh, gEl, lnf32);
-                    gEh = rfl(gEh);
-                    gEl = rfl(gEl);
-                    ch = (lane == erel) ? gEh : ch;
-                    cl = (lane == erel) ? gEl : cl;
-                }
+            if (PREC == 0) {
+                gEv = gEs + lnf_v;
+                gEs = rfl(gEv);
+                c64 = (lane == erel) ? gEv : c64;
+            } else {
+                two_sum_add(gEh, gEl, lnf32);
+                gEh = rfl(gEh);
+                gEl = rfl(gEl);
+                ch = (lane == erel) ? gEh : ch;
+                cl = (lane == erel) ? gEl : cl;
             }
-            hist = writelane_i32(table_values ? erel : ebase + erel, j, hist);
+            hist = writelane_i32(ebase + erel, j, hist);
         };
 
-        if (tbl) {
-            // ---- table mode.  Lane e: d_k(e) = ln g(ebase+e) - ln g(ebase+e+k-4)
-            // at block start (binary32; NaN = undecided), and per attempt lane j
-            // the thresholds ln u -+ margin rounded outwards.
-            double cself;
-            if (PREC == 0) cself = c64;
-            else cself = (double)ch + (double)cl;
-#pragma unroll
-            for (int kk = 0; kk < 9; ++kk) {
-                const int src = lane + kk - 4;
-                const double other = __shfl(cself, src & 63);
-                const double d = cself - other;
-                float v = __builtin_nanf("");
-                if (src >= 0 && src < 64) {
-                    if (fabs(d) <= kTableDmax) v = (float)d;
-                    // beyond 65 the block's drift (<= 64 ln f) cannot cross the
-                    // cut-off of exp at -64: d > 0 always accepts, d < 0 never
-                    else if (d > kTableDmax + 1.0) v = __builtin_inff();
-                    else if (d < -(kTableDmax + 1.0)) v = -__builtin_inff();
-                }
-                dtab[kk * 64 + lane] = v;
-            }
-            const float th_hi = f32_up(lnu + margin);
-            const float th_lo = f32_down(lnu - margin);
-            apar[lane] = make_uint4((uint32_t)((dE + 4) * 256), (uint32_t)(dE + 64),
-                                    __float_as_uint(th_hi), __float_as_uint(th_lo));
-            const unsigned char *dtab_b = (const unsigned char *)dtab + lane * 4;
-            // Next-state table of one attempt: lane e holds the walker's cache
-            // offset after the attempt if it is at offset e before it, plus 64
-            // when the move is accepted, or e + 128 when the table cannot decide.
-            auto next_table = [&](uint4 P, float ds) -> int {
-                const int ma = (ds > __uint_as_float(P.z)) ? -1 : 0;
-                const int ml = (ds < __uint_as_float(P.w)) ? -1 : 0;
-                return lane + ((int)P.y & ma) + (128 & ~(ma | ml));
-            };
-            bool outside = false;   // walker left the cached range in this block
-            int j = 0;
-            while (j < todo) {
-                if (outside) {   // rest of the block after leaving the cache range
-                    slow_attempt(j, true, 0, false, 0, true);
-                    ++j;
-                    continue;
-                }
-                // Attempt j's conflict is settled by the acceptances so far.
-                bool now = false;
-                int nvj = 0;
-                if (((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
-                    const int dEj = settle(j, nvj);
-                    if (lane == 0) {
-                        apar[j].x = (uint32_t)((dEj + 4) * 256);
-                        apar[j].y = (uint32_t)(dEj + 64);
-                    }
-                    now = true;
-                }
-                // Group of up to 8 attempts: tables (vector work), then the chain
-                // of lane lookups, one per attempt.
-                const int len = min(8, todo - j);
-                uint4 P8[8];
-                float ds8[8];
-                int lut[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) P8[i] = apar[(j + i) & 63];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) ds8[i] = *(const float *)(dtab_b + P8[i].x);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) lut[i] = next_table(P8[i], ds8[i]);
-                int chain[8];
-                int sc = erel;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    sc = __builtin_amdgcn_readlane(lut[i], sc);
-                    chain[i] = sc;
-                }
-                int rec = 0;   // lane i <- chain value of step i
-#pragma unroll
-                for (int i = 0; i < 8; ++i) rec = writelane_i32(chain[i], i, rec);
-                const unsigned long long gmask = (len >= 64) ? ~0ull : ((1ull << len) - 1ull);
-                const unsigned long long und = __ballot((rec & 128) != 0) & gmask;
-                const unsigned long long accl = __ballot((rec & 64) != 0) & gmask;
-                // first step whose speculation fails: undecided, or a later step of
-                // the group hit by an accepted flip earlier in the group
-                int bad = und ? (int)__builtin_ctzll(und) : len;
-                unsigned long long fl = (anyconf >> j) & gmask & ~1ull;
-                while (fl) {
-                    const int i = (int)__builtin_ctzll(fl);
-                    if (i >= bad) break;
-                    fl &= fl - 1ull;
-                    const unsigned long long acc_before = accepted | ((accl & ((1ull << i) - 1ull)) << j);
-                    if (readlane64(conf, j + i) & acc_before) { bad = i; break; }
-                }
-                if (bad == 0 && now) bad = -1;   // resolved conflict attempt: decide it singly
-                const int ncommit = bad < 0 ? 0 : bad;
-                if (ncommit > 0) {
-                    // commit steps 0 .. ncommit-1
-                    const int src = lane - j;
-                    const int moved = __shfl(rec, src & 63);
-                    const bool mine = src >= 0 && src < ncommit;
-                    hist = mine ? (moved & 63) : hist;
-                    accepted |= (accl & ((ncommit >= 64) ? ~0ull : ((1ull << ncommit) - 1ull))) << j;
-                    erel = __builtin_amdgcn_readlane(rec, ncommit - 1) & 63;
-                    if (now && (accl & 1ull)) {   // recomputed attempt accepted: write at once
-                        if (lane == 0) sp[__builtin_amdgcn_readlane(p.site, j)] = (int8_t)nvj;
-                        flushed |= 1ull << j;
-                    }
-                }
-                j += ncommit;
-                if (ncommit == len) continue;
-                // step j could not be taken with the group: settle its conflict
-                // (if the group did not already), then decide it from its table
-                // unless the table is undecided there
-                const bool was_now = (ncommit == 0) && now;
-                bool now2 = was_now;
-                int nvj2 = was_now ? nvj : 0;
-                if (!was_now && ((anyconf >> j) & 1ull) && (readlane64(conf, j) & accepted)) {
-                    const int dEr = settle(j, nvj2);
-                    if (lane == 0) {
-                        apar[j].x = (uint32_t)((dEr + 4) * 256);
-                        apar[j].y = (uint32_t)(dEr + 64);
-                    }
-                    now2 = true;
-                }
-                const uint4 Pj = apar[j];
-                const int dEj = (int)Pj.y - 64;
-                const int v = __builtin_amdgcn_readlane(next_table(Pj, *(const float *)(dtab_b + Pj.x)), erel);
-                if (v & 128) {
-                    slow_attempt(j, true, dEj, now2, nvj2, false);
-                    outside = outside || (unsigned)erel >= 64u;
-                } else {
-                    const bool acc = (v & 64) != 0;
-                    erel = v & 63;
-                    accepted |= acc ? (1ull << j) : 0ull;
-                    if (acc && now2) {
-                        if (lane == 0) sp[__builtin_amdgcn_readlane(p.site, j)] = (int8_t)nvj2;
-                        flushed |= 1ull << j;
-                    }
-                    hist = writelane_i32(erel, j, hist);
-                }
-                ++j;
-            }
-        } else {
-            // ---- exact mode: runs of attempts with no possible conflict take the
+        {
+            // ---- serial phase: runs of attempts with no possible conflict take the
             // inline path; the others go through slow_attempt (which settles the
             // conflict first)
             int j = 0;
@@ -677,69 +454,13 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     hist = writelane_i32(ebase + erel, j, hist);
                 }
                 if (j >= todo) break;
-                slow_attempt(j, false);
+                slow_attempt(j);
                 ++j;
             }
         }
 
         if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
-        if (!tbl) {
-            if (live) atomicAdd(&H[hist - lo], 1u);
-        } else {
-            // this block's visits per cached energy; H and ln g of the bin take
-            // them in sequence (visits outside the cached range, rare, go
-            // straight to LDS one by one)
-            hist += ebase;   // table mode records energies relative to ebase
-            const int rb = hist - ebase;
-            const bool incache = (unsigned)rb < 64u;
-            if (live && incache) atomicAdd(&cnt[rb], 1u);
-            unsigned long long far = __ballot(live && !incache);
-            while (far) {
-                const int jj = (int)__builtin_ctzll(far);
-                far &= far - 1ull;
-                const int b = __builtin_amdgcn_readlane(hist, jj) - lo;
-                if (lane == 0) {
-                    H[b] += 1u;
-                    if (PREC == 0) g[b] = g[b] + lnf;
-                    else { float a = gh[b], c = gl[b]; two_sum_add(a, c, lnf32); gh[b] = a; gl[b] = c; }
-                }
-            }
-            int nvis = (int)cnt[lane];
-            cnt[lane] = 0u;
-            const int hb = ebase + lane - lo;
-            if (nvis > 0) H[hb] += (uint32_t)nvis;
-            if (PREC == 0) {
-                // n additions of ln f in sequence.  Inside one binade every
-                // addition adds the same exact step d = RN(x + ln f) - x, so the
-                // result is x + n d, unless ln f sits exactly halfway between two
-                // multiples of ulp(x) (ties round to even) or the sum leaves the
-                // binade; those lanes (and x = 0) add one by one.
-                if (nvis > 0 && c64 > 0.0) {
-                    const double x1 = c64 + lnf;
-                    const double d = x1 - c64;
-                    const int ex = ilogb(c64);
-                    const double u = __builtin_ldexp(1.0, ex - 52);
-                    const double xn = c64 + (double)nvis * d;
-                    if (fabs(lnf - d) != 0.5 * u && ilogb(xn) == ex) {
-                        c64 = xn;
-                        nvis = 0;
-                    }
-                }
-            }
-            while (__ballot(nvis > 0) != 0ull) {
-                if (nvis > 0) {
-                    if (PREC == 0) c64 = c64 + lnf;
-                    else two_sum_add(ch, cl, lnf32);
-                    --nvis;
-                }
-            }
-            if ((unsigned)erel >= 64u) {   // walker left the cached range: recentre
-                cache_store();
-                ebase += erel - 32;
-                erel = 32;
-                cache_load();
-            }
-        }
+        if (live) atomicAdd(&H[hist - lo], 1u);
     }
     cache_store();
     E = ebase + erel;
@@ -1032,9 +753,143 @@ __device__ __forceinline__ void track_replicas(const DevState &st, int lane, int
     }
 }
 
-// Termination (Sec. 2): the run ends once every window reached ln f_final.
-__device__ __forceinline__ void check_instance(const DevState &st, int64_t step, int64_t round_after) {
+// Observable sampling (Sec. 3.2: distributions H(E, O) recorded while the
+// walk goes on).  O = max_s n_s of walker w's current lattice, counted with
+// LDS atomics over the N sites by the whole workgroup, the maximum over the
+// q states taken by one wavefront; lane 0 then adds the sample to energy bin
+// E - start_k of the walker's window.  Integer arithmetic throughout.
+__device__ __forceinline__ void measure_walker(const DevState &st, int w) {
+    __shared__ int s_cnt[128];
+    __shared__ int s_max;
+    const int tid = threadIdx.x;
+    for (int v = tid; v < 128; v += blockDim.x) s_cnt[v] = 0;
+    __syncthreads();
+    const int8_t *sp = st.spins + (size_t)w * st.Npad;
+    for (int i = tid; i < st.N; i += blockDim.x) atomicAdd(&s_cnt[(int)sp[i]], 1);
+    __syncthreads();
+    if (tid < 64) {
+        int mx = 0;
+        for (int v = tid; v < st.q; v += 64) mx = s_cnt[v] > mx ? s_cnt[v] : mx;
+        for (int off = 32; off > 0; off >>= 1) {
+            const int o = __shfl_xor(mx, off, 64);
+            mx = o > mx ? o : mx;
+        }
+        if (tid == 0) s_max = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int O = s_max;
+        const int b = st.E[w] - st.start[w / st.m];
+        if (b >= 0 && b < st.W) {
+            const size_t cell = (size_t)w * st.Wpad + b;
+            const int ob = (int)(((long long)O * st.obs_bins) / (st.N + 1));
+            st.obs_hist[cell * st.obs_bins + ob] += 1u;
+            st.obs_sum[cell] += (unsigned long long)O;
+            st.obs_cnt[cell] += 1u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_measure(DevState st) {
     if (*st.converged) return;
+    measure_walker(st, blockIdx.x);
+}
+
+// Production phase: every window keeps its walkers' current ln g as fixed
+// weights (ln f = 0, marked finished; lnf_last records the ln f a window
+// still had), termination off, H and the observable record cleared.
+__global__ __launch_bounds__(256) void k_begin_production(DevState st) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t cells = (size_t)st.nw * st.Wpad;
+    for (size_t c = i; c < cells; c += stride) {
+        st.H[c] = 0u;
+        if (st.obs_bins > 0) {
+            st.obs_sum[c] = 0ull;
+            st.obs_cnt[c] = 0u;
+        }
+    }
+    if (st.obs_bins > 0)
+        for (size_t c = i; c < cells * st.obs_bins; c += stride) st.obs_hist[c] = 0u;
+    if (i == 0) {
+        for (int k = 0; k < st.h; ++k) {
+            if (!st.finished[k]) {
+                st.finished[k] = 1;
+                st.lnf_last[k] = st.lnf[k];
+            }
+            st.lnf[k] = 0.0;
+        }
+        *st.converged = 0;
+        *st.production = 1;
+    }
+}
+
+// Pooled microcanonical mean of O per energy bin (one thread per bin): the
+// integer sums and counts of every walker whose window holds the bin.
+__global__ __launch_bounds__(256) void k_obs_micro(DevState st, double *mean, unsigned long long *count) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= st.B) return;
+    unsigned long long s = 0, c = 0;
+    for (int k = 0; k < st.h; ++k) {
+        const int lb = b - (st.start[k] - st.e_lo);
+        if (lb < 0 || lb >= st.W) continue;
+        for (int j = 0; j < st.m; ++j) {
+            const size_t cell = (size_t)(k * st.m + j) * st.Wpad + lb;
+            s += st.obs_sum[cell];
+            c += st.obs_cnt[cell];
+        }
+    }
+    mean[b] = c ? (double)s / (double)c : __builtin_nan("");
+    count[b] = c;
+}
+
+// Canonical average of O, one workgroup per temperature: weights
+// exp(ln g(E) - E/T - max) over the bins with a finite joined ln g and
+// samples of O; <O>_T = sum w mu / sum w.
+__global__ __launch_bounds__(256) void k_obs_thermo(DevState st, const double *T, const double *mean,
+                                                    double *out) {
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const double temp = T[t];
+    __shared__ double s[256], s2[256];
+    double mx = -__builtin_inf();
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v == -__builtin_inf() || __builtin_isnan(mean[b])) continue;
+        mx = fmax(mx, v - (st.th_e0 + (double)b * st.th_de) / temp);
+    }
+    s[tid] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] = fmax(s[tid], s[tid + o]);
+        __syncthreads();
+    }
+    mx = s[0];
+    __syncthreads();
+    double z = 0.0, num = 0.0;
+    for (int b = tid; b < st.B; b += 256) {
+        const double v = st.joined[b];
+        if (v == -__builtin_inf() || __builtin_isnan(mean[b])) continue;
+        const double p = exp((v - (st.th_e0 + (double)b * st.th_de) / temp) - mx);
+        z += p;
+        num += p * mean[b];
+    }
+    s[tid] = z;
+    s2[tid] = num;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            s[tid] += s[tid + o];
+            s2[tid] += s2[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) out[t] = s2[0] / s[0];
+}
+
+// Termination (Sec. 2): the run ends once every window reached ln f_final
+// (never in the production phase).
+__device__ __forceinline__ void check_instance(const DevState &st, int64_t step, int64_t round_after) {
+    if (*st.converged || *st.production) return;
     for (int k = 0; k < st.h; ++k)
         if (!st.finished[k]) return;
     *st.converged = 1;
@@ -1384,6 +1239,15 @@ __global__ __launch_bounds__(256) void k_sync_batch(const DevState *__restrict__
     sync_window<PREC>(st, t.idx, st.ctl[0] + st.sync_attempts);
 }
 
+// Observable sample of walker t.idx of instance t.inst (instances that sample one).
+__global__ __launch_bounds__(256) void k_measure_batch(const DevState *__restrict__ descs,
+                                                       const BatchTask *__restrict__ tasks, int lo) {
+    const BatchTask t = tasks[lo + (int)blockIdx.x];
+    const DevState &st = descs[t.inst];
+    if (st.obs_bins <= 0 || *st.converged) return;
+    measure_walker(st, t.idx);
+}
+
 // Exchange round of instance t.inst (at its own round counter), pair slot t.idx.
 __global__ __launch_bounds__(64) void k_exchange_batch(const DevState *__restrict__ descs,
                                                        const BatchTask *__restrict__ xtasks, int lo) {
@@ -1423,7 +1287,7 @@ __global__ void k_status_batch(const DevState *__restrict__ descs, int n, BatchS
 // Launchers.
 
 size_t sweep_lds_bytes(const DevState &st) {
-    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)st.Ntag * 8 + 64 * 4 + 9 * 64 * 4 + 64 * 16;
+    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)st.Ntag * 8;
 }
 
 size_t walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
@@ -1485,6 +1349,29 @@ hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, h
 
 hipError_t launch_track(const DevState &st, hipStream_t s) {
     hipLaunchKernelGGL(k_track, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const DevState &st, hipStream_t s) {
+    hipLaunchKernelGGL(k_measure, dim3(st.nw), dim3(256), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_begin_production(const DevState &st, hipStream_t s) {
+    const size_t cells = (size_t)st.nw * st.Wpad * (st.obs_bins > 0 ? st.obs_bins : 1);
+    const size_t blocks = std::min<size_t>((cells + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_begin_production, dim3((unsigned)blocks), dim3(256), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_micro(const DevState &st, double *mean, unsigned long long *count, hipStream_t s) {
+    hipLaunchKernelGGL(k_obs_micro, dim3((st.B + 255) / 256), dim3(256), 0, s, st, mean, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_thermo(const DevState &st, const double *T, int nT, const double *mean, double *out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_obs_thermo, dim3(nT), dim3(256), 0, s, st, T, mean, out);
     return hipGetLastError();
 }
 
@@ -1586,6 +1473,12 @@ hipError_t launch_sync_batch(int precision, const DevState *descs, const BatchTa
         hipLaunchKernelGGL(k_sync_batch<0>, dim3(n), dim3(256), 0, s, descs, wtasks, lo);
     else
         hipLaunchKernelGGL(k_sync_batch<1>, dim3(n), dim3(256), 0, s, descs, wtasks, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure_batch(const DevState *descs, const BatchTask *tasks, int lo, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_measure_batch, dim3(n), dim3(256), 0, s, descs, tasks, lo);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ int tag_entries(int N, size_t lds_free) {
 }
 
 size_t sweep_state_lds(int Npad, int Wpad) {
-    return (size_t)Npad + (size_t)Wpad * 12 + 64 * 4 + 9 * 64 * 4 + 64 * 16;
+    return (size_t)Npad + (size_t)Wpad * 12;
 }
 
 }  // namespace rewl_host
@@ -52,7 +52,7 @@ struct Params {
     int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad, Ntag;
 };
 
-Layout make_layout(const Params &p, int precision, int shadow, bool trimer) {
+Layout make_layout(const Params &p, int precision, int shadow, bool trimer, int obs_bins) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -95,6 +95,14 @@ Layout make_layout(const Params &p, int precision, int shadow, bool trimer) {
     l.scratch = take(sizeof(double) * ((size_t)p.h * p.Wpad + p.h + 16));
     l.T = take(sizeof(double) * kMaxThermo);
     l.thermo_out = take(sizeof(double) * 3 * kMaxThermo);
+    l.production = take(sizeof(int32_t));
+    if (obs_bins > 0) {
+        l.obs_hist = take(sizeof(uint32_t) * (size_t)p.nw * p.Wpad * obs_bins);
+        l.obs_sum = take(sizeof(unsigned long long) * (size_t)p.nw * p.Wpad);
+        l.obs_cnt = take(sizeof(uint32_t) * (size_t)p.nw * p.Wpad);
+        l.obs_mean = take(sizeof(double) * p.Bpad);
+        l.obs_count = take(sizeof(unsigned long long) * p.Bpad);
+    }
     l.total = off;
     return l;
 }
@@ -136,6 +144,8 @@ int check_opts(int h, int m, const rewl_opts &op) {
     if (op.schedule < 0 || op.schedule > 1) return fail(REWL_EINVAL, "schedule must be 0 or 1");
     if (op.shadow < 0 || op.shadow > 1) return fail(REWL_EINVAL, "shadow must be 0 or 1");
     if (op.walkin_slack < 0) return fail(REWL_EINVAL, "walkin_slack must be >= 0");
+    if (op.obs_bins < 0) return fail(REWL_EINVAL, "obs_bins must be >= 0");
+    if (op.reserved != 0) return fail(REWL_EINVAL, "opts.reserved must be 0");
     if (!(op.lnf_init >= 0.0) || !(op.lnf_final >= 0.0)) return fail(REWL_EINVAL, "ln f must be >= 0");
     return REWL_OK;
 }
@@ -156,6 +166,7 @@ int check_trimer(const TrimerGeom &g, int h, double o, int m, const rewl_opts &o
     if (g.bins < 8) return fail(REWL_EINVAL, "at least 8 energy bins");
     int st = check_opts(h, m, op);
     if (st != REWL_OK) return st;
+    if (op.obs_bins != 0) return fail(REWL_EINVAL, "observable sampling (obs_bins) is defined for the Potts model only");
     starts->assign((size_t)std::max(h, 1), 0);
     int W = 0;
     st = layout_bins(g.bins, 0, h, o, &W, starts->data());
@@ -181,6 +192,7 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     if (q < 2 || q > 127) return fail(REWL_EINVAL, "q must be in [2, 127]");
     int st = check_opts(h, m, op);
     if (st != REWL_OK) return st;
+    if (L >= 3 && L <= 724 && op.obs_bins > L * L + 1) return fail(REWL_EINVAL, "obs_bins must be at most L*L+1");
     starts->assign((size_t)std::max(h, 1), 0);
     int W = 0;
     st = layout_windows(L, h, o, &W, starts->data());
@@ -299,7 +311,7 @@ size_t rewl_workspace_bytes(int model, int L, int q, int windows, double overlap
     Params p;
     std::vector<int32_t> starts;
     if (check_params(model, L, q, windows, overlap, walkers, op, &p, &starts) != REWL_OK) return 0;
-    return make_layout(p, op.precision, op.shadow, false).total;
+    return make_layout(p, op.precision, op.shadow, false, op.obs_bins).total;
 }
 
 namespace {
@@ -310,7 +322,7 @@ namespace {
 int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts, const rewl_opts &op,
                const TrimerGeom *geom, const unsigned char *init, void *dev_workspace, size_t ws_bytes,
                void *hip_stream) {
-    const Layout lay = make_layout(p, op.precision, op.shadow, geom != nullptr);
+    const Layout lay = make_layout(p, op.precision, op.shadow, geom != nullptr, op.obs_bins);
     if (!dev_workspace) return fail(REWL_EINVAL, "null device workspace");
     if (ws_bytes < lay.total) return fail(REWL_ENOMEM, "device workspace smaller than rewl_workspace_bytes");
     if (((uintptr_t)dev_workspace) % kAlign != 0) return fail(REWL_EINVAL, "workspace must be 256-byte aligned");
@@ -360,6 +372,11 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     d.rep_end = (int32_t *)(b + lay.rep_end);
     d.rep_trips = (uint32_t *)(b + lay.rep_trips);
     d.rep_visits = p.nw <= rewl_gpu::kMaxVisitWalkers ? (uint32_t *)(b + lay.rep_visits) : nullptr;
+    d.obs_bins = op.obs_bins;
+    d.obs_hist = op.obs_bins > 0 ? (uint32_t *)(b + lay.obs_hist) : nullptr;
+    d.obs_sum = op.obs_bins > 0 ? (unsigned long long *)(b + lay.obs_sum) : nullptr;
+    d.obs_cnt = op.obs_bins > 0 ? (uint32_t *)(b + lay.obs_cnt) : nullptr;
+    d.production = (int32_t *)(b + lay.production);
     d.walkin_att = (int64_t *)(b + lay.walkin_att);
     d.walkin_done = (int32_t *)(b + lay.walkin_done);
     d.walkin_bound = (int32_t *)(b + lay.walkin_bound);
@@ -443,7 +460,7 @@ size_t rewl_trimer_workspace_bytes(int nmol, float box, double e_min, double bin
     std::vector<int32_t> starts;
     const TrimerGeom g{nmol, box, e_min, bin_w, bins};
     if (check_trimer(g, windows, overlap, walkers, op, &p, &starts) != REWL_OK) return 0;
-    return make_layout(p, op.precision, op.shadow, true).total;
+    return make_layout(p, op.precision, op.shadow, true, op.obs_bins).total;
 }
 
 int rewl_create_trimer(rewl_t **out, int nmol, float box, double e_min, double bin_w, int bins, int windows,
@@ -584,6 +601,7 @@ int rewl_run_attempts(rewl_t *r, int64_t attempts) {
                 HIP_TRY(rewl_gpu::launch_exchange(r->st, (uint32_t)r->round, r->stream));
                 r->round += 1;
             }
+            if (r->st.obs_bins > 0) HIP_TRY(rewl_gpu::launch_measure(r->st, r->stream));
             HIP_TRY(rewl_gpu::launch_check(r->st, r->step, r->round, r->stream));
             HIP_TRY(timer_end(r, 1, ev));
             if (!r->opts.fixed_lnf && ++syncs_since_read >= 64) {
@@ -621,6 +639,65 @@ int rewl_get_progress(rewl_t *r, int64_t *step, int64_t *round, int32_t *converg
     if (step) *step = r->step;
     if (round) *round = r->round;
     if (converged) *converged = r->converged ? 1 : 0;
+    return REWL_OK;
+}
+
+int rewl_begin_production(rewl_t *r) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    if (r->in_batch) return fail(REWL_ESTATE, "production runs are standalone, not instances of a batch");
+    if (!r->walked_in) return fail(REWL_ESTATE, "rewl_begin_production needs a walked-in run");
+    HIP_TRY(rewl_gpu::launch_begin_production(r->st, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    r->converged = false;
+    r->joined = false;
+    return REWL_OK;
+}
+
+int rewl_get_obs(rewl_t *r, int w, uint32_t *hist, uint64_t *sum, uint32_t *count) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    const DevState &d = r->st;
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    if (d.obs_bins <= 0) return fail(REWL_EINVAL, "the run samples no observable (opts.obs_bins = 0)");
+    const size_t row = (size_t)w * d.Wpad;
+    if (hist)
+        HIP_TRY(hipMemcpyAsync(hist, d.obs_hist + row * d.obs_bins, sizeof(uint32_t) * d.W * d.obs_bins,
+                               hipMemcpyDeviceToHost, r->stream));
+    if (sum) HIP_TRY(hipMemcpyAsync(sum, d.obs_sum + row, sizeof(uint64_t) * d.W, hipMemcpyDeviceToHost, r->stream));
+    if (count) HIP_TRY(hipMemcpyAsync(count, d.obs_cnt + row, sizeof(uint32_t) * d.W, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return REWL_OK;
+}
+
+int rewl_obs_micro(rewl_t *r, double *mean, uint64_t *count) {
+    if (!r || !mean) return fail(REWL_EINVAL, "null argument");
+    const DevState &d = r->st;
+    if (d.obs_bins <= 0) return fail(REWL_EINVAL, "the run samples no observable (opts.obs_bins = 0)");
+    double *dmean = (double *)(r->ws + r->lay.obs_mean);
+    unsigned long long *dcount = (unsigned long long *)(r->ws + r->lay.obs_count);
+    HIP_TRY(rewl_gpu::launch_obs_micro(d, dmean, dcount, r->stream));
+    HIP_TRY(hipMemcpyAsync(mean, dmean, sizeof(double) * d.B, hipMemcpyDeviceToHost, r->stream));
+    if (count) HIP_TRY(hipMemcpyAsync(count, dcount, sizeof(uint64_t) * d.B, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return REWL_OK;
+}
+
+int rewl_obs_thermo(rewl_t *r, const double *T, int nT, double *out) {
+    if (!r || !T || !out) return fail(REWL_EINVAL, "null argument");
+    if (nT < 1 || nT > kMaxThermo) return fail(REWL_EINVAL, "nT must be in [1, 4096]");
+    const DevState &d = r->st;
+    if (d.obs_bins <= 0) return fail(REWL_EINVAL, "the run samples no observable (opts.obs_bins = 0)");
+    if (!r->joined) return fail(REWL_ESTATE, "rewl_obs_thermo needs a current rewl_join");
+    for (int i = 0; i < nT; ++i)
+        if (!(T[i] > 0.0)) return fail(REWL_EINVAL, "temperatures must be positive");
+    double *dT = (double *)(r->ws + r->lay.T);
+    double *dout = (double *)(r->ws + r->lay.thermo_out);
+    double *dmean = (double *)(r->ws + r->lay.obs_mean);
+    unsigned long long *dcount = (unsigned long long *)(r->ws + r->lay.obs_count);
+    HIP_TRY(hipMemcpyAsync(dT, T, sizeof(double) * nT, hipMemcpyHostToDevice, r->stream));
+    HIP_TRY(rewl_gpu::launch_obs_micro(d, dmean, dcount, r->stream));
+    HIP_TRY(rewl_gpu::launch_obs_thermo(d, dT, nT, dmean, dout, r->stream));
+    HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double) * nT, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
     return REWL_OK;
 }
 
@@ -734,6 +811,7 @@ SaveHeader make_header(const rewl *r) {
     h.lnf_init = r->opts.lnf_init; h.lnf_final = r->opts.lnf_final;
     h.seed = r->opts.seed; h.instance = r->opts.instance;
     h.flat_num = r->opts.flat_num; h.flat_den = r->opts.flat_den;
+    h.reserved = (uint32_t)r->opts.obs_bins;
     h.sync_attempts = r->opts.sync_attempts;
     h.step = r->step; h.round = r->round;
     h.walked_in = r->walked_in ? 1 : 0;

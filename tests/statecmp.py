@@ -25,3 +25,8 @@ def assert_same_state(g, o):
     if g.nw <= 4096:
         for w in range(g.nw):
             assert np.array_equal(g.replica_visits(w), o.replica_visits(w)), f"replica visits of slot {w}"
+    if getattr(g, "obs_bins", 0) > 0:
+        assert o.obs_bins == g.obs_bins
+        for w in range(g.nw):
+            for a, b, name in zip(g.obs(w), o.obs(w), ("H(E, O)", "sum of O", "samples")):
+                assert np.array_equal(a, b), f"{name} of walker {w}"

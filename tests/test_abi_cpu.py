@@ -46,7 +46,7 @@ def test_default_opts(lib):
     o = pk.default_opts()
     assert (o.seed, o.flat_num, o.flat_den, o.lnf_init, o.lnf_final) == (1, 4, 5, 1.0, 1e-6)
     assert (o.schedule, o.exchange, o.sync_attempts, o.precision, o.fixed_lnf) == (0, 1, 1000, 0, 0)
-    assert ctypes.sizeof(pk.Opts) == 72 and o.shadow == 0
+    assert ctypes.sizeof(pk.Opts) == 80 and o.shadow == 0 and o.obs_bins == 0 and o.reserved == 0
 
 
 @pytest.mark.parametrize("L,h,o", [(3, 1, 0.5), (4, 2, 0.75), (8, 4, 0.75), (32, 16, 0.75), (80, 64, 0.75),
@@ -97,7 +97,7 @@ def _instances(specs):
 
 
 def test_batch_structs_and_workspace(lib):
-    assert ctypes.sizeof(pk.Instance) == 104 and ctypes.sizeof(pk.Plan) == 112
+    assert ctypes.sizeof(pk.Instance) == 112 and ctypes.sizeof(pk.Plan) == 112
     specs = [(16, 2, 8, 4), (24, 4, 8, 4), (48, 10, 8, 4)]
     arr = _instances(specs)
     total = lib.rewl_batch_workspace_bytes(3, arr)
