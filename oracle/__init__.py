@@ -38,6 +38,9 @@ def lib():
         L.orc_obs_micro.restype = i32
         L.orc_obs_thermo.argtypes = [P, P, i32, dbl, dbl, P, i32, P]
         L.orc_obs_thermo.restype = None
+        L.orc_bootstrap.argtypes = [i32, i32, i32, P, i32, i32, P, P, dbl, i32, u64, P, i32, dbl, dbl,
+                                    P, P, P, P, P, P]
+        L.orc_bootstrap.restype = i32
         L.orc_get_shadow.argtypes = [P, i32, P, P]
         L.orc_get_replicas.argtypes = [P, P, P]
         L.orc_get_replicas.restype = None
@@ -170,6 +173,31 @@ def thermo(lng, e_first, T, de=1.0):
     lib().orc_thermo(_ptr(g), len(g), float(e_first), float(de), _ptr(T), len(T), _ptr(lnZ), _ptr(U),
                      _ptr(C))
     return lnZ, U, C
+
+
+def bootstrap(pieces, visited, starts, e_lo, B, log_total, nboot, seed, T, e_first=None, de=1.0):
+    """Bootstrap over R runs: pieces float64 [R, h, W], visited uint8 [R, h, W].
+
+    Returns (status, dict of lng_mean, lng_std [B], U_mean, U_std, C_mean, C_std [nT])."""
+    p = np.ascontiguousarray(pieces, dtype=np.float64)
+    v = np.ascontiguousarray(visited, dtype=np.uint8)
+    R, h, W = p.shape
+    starts = np.ascontiguousarray(starts, dtype=np.int32)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    out = {k: np.zeros(B) for k in ("lng_mean", "lng_std")}
+    out.update({k: np.zeros(len(T)) for k in ("U_mean", "U_std", "C_mean", "C_std")})
+    st = lib().orc_bootstrap(R, h, W, _ptr(starts), int(e_lo), int(B), _ptr(p), _ptr(v), float(log_total),
+                             int(nboot), int(seed), _ptr(T), len(T), float(e_lo if e_first is None else e_first),
+                             float(de), _ptr(out["lng_mean"]), _ptr(out["lng_std"]), _ptr(out["U_mean"]),
+                             _ptr(out["U_std"]), _ptr(out["C_mean"]), _ptr(out["C_std"]))
+    return st, out
+
+
+def run_pieces(o):
+    """(pieces [h, W], visited [h, W]) of a run: walker 0 of every window and the window's flags."""
+    pieces = np.stack([o.walker(k * o.m)["lng"] for k in range(o.h)])
+    vis = np.stack([o.window(k)["visited"] for k in range(o.h)])
+    return pieces, vis
 
 
 def obs_thermo(lng, mu, e_first, T, de=1.0):

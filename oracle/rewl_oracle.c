@@ -35,7 +35,7 @@ enum { ORC_OK = 0, ORC_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENOMEM = -2,
        ORC_ESTATE = -4, ORC_EBUDGET = -5 };
 
 /* Philox counter domains: the fourth counter word carries domain << 24 | instance. */
-enum { DOM_MOVE = 0, DOM_WALKIN = 2, DOM_EXCH = 3, DOM_MOVE_U = 5, DOM_WALKIN_U = 6 };
+enum { DOM_MOVE = 0, DOM_WALKIN = 2, DOM_EXCH = 3, DOM_MOVE_U = 5, DOM_WALKIN_U = 6, DOM_BOOT = 7 };
 
 /* Models. */
 enum { MODEL_POTTS2D = 0, MODEL_TRIMER3D = 1 };
@@ -1377,6 +1377,91 @@ void orc_thermo(const double *lng, int B, double e_first, double de, const doubl
         U[t] = u;
         C[t] = var / (T[t] * T[t]);
     }
+}
+
+/* Mean and sample standard deviation of x[0], x[stride], ... (n values, in
+ * order) over the finite ones; mean -inf and std 0 when none is finite.     */
+static void finite_stats(const double *x, int n, size_t stride, double *mean, double *sd)
+{
+    double s = 0.0;
+    int c = 0;
+    for (int j = 0; j < n; ++j) {
+        double v = x[(size_t)j * stride];
+        if (isfinite(v)) { s += v; ++c; }
+    }
+    if (c == 0) { *mean = -INFINITY; *sd = 0.0; return; }
+    double m = s / (double)c, q = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double v = x[(size_t)j * stride];
+        if (isfinite(v)) { double d = v - m; q += d * d; }
+    }
+    *mean = m;
+    *sd = c > 1 ? sqrt(q / (double)(c - 1)) : 0.0;
+}
+
+/* Bootstrap error analysis (Sec. 2: the simulation is repeated and the
+ * results resampled; every resampled global g(E) is joined anew, so its
+ * joining points move).  Inputs: R independent runs of one system, each
+ * window's final ln g as pieces[R][h][W] and its visited flags vis[R][h][W].
+ * Replicate j draws R run indices with replacement: r_i = floor(w_i R / 2^32)
+ * for the Philox words w_i, four per block (j, i / 4, 0, BOOT << 24), keyed
+ * by seed.  Its piece k is the mean over i, summed in order, of the drawn
+ * runs' piece k; the pieces are joined (orc_join_pieces) over the union of
+ * all runs' visited flags and normalised to log_total, and U and C_v follow
+ * at the nT temperatures (orc_thermo, bin b at energy e_first + b de).
+ * Outputs: over the nboot replicates, mean and sample standard deviation of
+ * the joined ln g per bin (over the replicates where it is finite) and of U
+ * and C_v per temperature.  Returns ORC_ESTATE if a replicate cannot be
+ * joined.                                                                   */
+int orc_bootstrap(int R, int h, int W, const int32_t *start, int e_lo, int B, const double *pieces,
+                  const uint8_t *vis, double log_total, int nboot, uint64_t seed, const double *T,
+                  int nT, double e_first, double de, double *lng_mean, double *lng_std,
+                  double *U_mean, double *U_std, double *C_mean, double *C_std)
+{
+    if (R < 1 || h < 1 || W < 1 || nboot < 1 || nT < 0) return ORC_EINVAL;
+    size_t HW = (size_t)h * W;
+    int *draw = (int *)malloc((size_t)R * sizeof(int));
+    uint8_t *vu = (uint8_t *)calloc(HW, 1);
+    double *mp = (double *)malloc(HW * sizeof(double));
+    double *reps = (double *)malloc((size_t)nboot * B * sizeof(double));
+    double *ru = (double *)malloc(((size_t)nboot * nT + 1) * sizeof(double));
+    double *rc = (double *)malloc(((size_t)nboot * nT + 1) * sizeof(double));
+    double *lz = (double *)malloc(((size_t)nT + 1) * sizeof(double));
+    int32_t *cuts = (int32_t *)malloc((size_t)(h > 1 ? h - 1 : 1) * sizeof(int32_t));
+    int st = ORC_OK;
+    if (!draw || !vu || !mp || !reps || !ru || !rc || !lz || !cuts) { st = ORC_ENOMEM; goto done; }
+    for (int r = 0; r < R; ++r)
+        for (size_t i = 0; i < HW; ++i) vu[i] |= vis[(size_t)r * HW + i] ? 1 : 0;
+    {
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        for (int j = 0; j < nboot && st == ORC_OK; ++j) {
+            for (int i = 0; i < R; i += 4) {
+                uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(i / 4), 0u, (uint32_t)DOM_BOOT << 24};
+                uint32_t w[4];
+                philox4x32_10(ctr, key, w);
+                for (int t = 0; t < 4 && i + t < R; ++t)
+                    draw[i + t] = (int)(((uint64_t)w[t] * (uint64_t)R) >> 32);
+            }
+            for (size_t c = 0; c < HW; ++c) {
+                double sum = 0.0;
+                for (int i = 0; i < R; ++i) sum = sum + pieces[(size_t)draw[i] * HW + c];
+                mp[c] = sum / (double)R;
+            }
+            st = orc_join_pieces(h, W, start, e_lo, B, mp, vu, log_total, reps + (size_t)j * B, cuts);
+            if (st == ORC_OK && nT > 0)
+                orc_thermo(reps + (size_t)j * B, B, e_first, de, T, nT, lz, ru + (size_t)j * nT,
+                           rc + (size_t)j * nT);
+        }
+    }
+    if (st != ORC_OK) goto done;
+    for (int b = 0; b < B; ++b) finite_stats(reps + b, nboot, (size_t)B, lng_mean + b, lng_std + b);
+    for (int t = 0; t < nT; ++t) {
+        finite_stats(ru + t, nboot, (size_t)nT, U_mean + t, U_std + t);
+        finite_stats(rc + t, nboot, (size_t)nT, C_mean + t, C_std + t);
+    }
+done:
+    free(draw); free(vu); free(mp); free(reps); free(ru); free(rc); free(lz); free(cuts);
+    return st;
 }
 
 /* Walker w's observable record: H(E, O) [W][obs_bins], sum of O [W] and

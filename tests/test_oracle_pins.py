@@ -790,3 +790,104 @@ def test_production_after_convergence_keeps_weights_and_samples_o():
     mean, cnt = o.obs_micro()
     for b in np.flatnonzero(cnt > 500):
         assert abs(mean[b] - O[E == b - 2 * N].mean()) < 0.15, b
+
+
+# --------------------------------------------------------------------------
+# Error analysis (Sec. 2): independent runs, bootstrap resampling with the
+# joining points found anew for every resample; the error claims of Sec. 2.
+
+def _converged_runs(L, q, h, m, lnf_final, R, seed0=1000):
+    runs = []
+    for r in range(R):
+        spins = workloads.init_spins(L, q, h * m, seed0 + r)
+        o = oracle.Rewl(L, q, h, 0.75, m, spins, seed=77, instance=r, lnf_final=lnf_final, sync_attempts=500,
+                        threads=4)
+        assert o.run(10**12) == oracle.CONVERGED
+        runs.append(o)
+    return runs
+
+
+def test_bootstrap_of_identical_runs_has_no_spread():
+    o = _converged_runs(4, 2, 3, 2, 1e-3, 1)[0]
+    p, v = oracle.run_pieces(o)
+    T = np.array([0.5, 1.0, 2.0, 4.0])
+    st, out = oracle.bootstrap(np.stack([p] * 5), np.stack([v] * 5), o.starts, o.e_lo, o.B,
+                               16 * math.log(2), 50, 9, T)
+    assert st == 0
+    s, lng, _ = o.join()
+    fin = np.isfinite(lng)
+    assert np.array_equal(np.isfinite(out["lng_mean"]), fin)
+    np.testing.assert_allclose(out["lng_mean"][fin], lng[fin], rtol=0, atol=1e-12)
+    # every replicate is the same curve; only the rounding of the means is left
+    assert out["lng_std"].max() < 1e-12 and out["U_std"].max() < 1e-12 and out["C_std"].max() < 1e-12
+    _, U, C = oracle.thermo(lng, o.e_lo, T)
+    np.testing.assert_allclose(out["U_mean"], U, rtol=1e-12)
+    np.testing.assert_allclose(out["C_mean"], C, rtol=1e-12)
+
+
+def test_bootstrap_resamples_runs_with_replacement():
+    # Two runs a, b: a replicate joins the mean of the two drawn runs' pieces,
+    # i.e. a, (a + b) / 2 or b, with probabilities 1/4, 1/2, 1/4.
+    runs = _converged_runs(4, 2, 3, 2, 1e-2, 2)
+    (pa, va), (pb, vb) = (oracle.run_pieces(o) for o in runs)
+    o = runs[0]
+    vis = np.stack([va, vb])
+    union = vis.max(axis=0)
+    lt = 16 * math.log(2)
+    outcomes = []
+    for pieces in (pa, (pa + pb) / 2.0, pb):
+        st, lng, _ = oracle.join_pieces(pieces, union, o.starts, o.e_lo, o.B, lt)
+        assert st == 0
+        outcomes.append(lng)
+    assert not np.array_equal(outcomes[0], outcomes[2])
+    counts = [0, 0, 0]
+    for seed in range(400):
+        st, out = oracle.bootstrap(np.stack([pa, pb]), vis, o.starts, o.e_lo, o.B, lt, 1, seed, [1.0])
+        assert st == 0
+        hit = [i for i, x in enumerate(outcomes) if np.array_equal(x, out["lng_mean"])]
+        assert len(hit) == 1
+        counts[hit[0]] += 1
+    freq = np.array(counts) / 400
+    assert np.all(np.abs(freq - [0.25, 0.5, 0.25]) < 0.07), freq
+
+
+def test_error_falls_with_walkers_per_window_and_with_final_lnf():
+    # Sec. 2: averaging the m walkers of a window cuts the statistical error as
+    # 1/sqrt(m) (squared error / m); the error also falls with ln f_final.
+    # 4x4 Ising-like q=2 lattice, exact ln g by enumeration, 32 runs each.
+    L, q = 4, 2
+    ex = exact_lng(L, q)
+    reach = np.isfinite(ex)
+    mse = {}
+    for m in (1, 4):
+        for lf in (1e-3, 1e-4):
+            e = []
+            for o in _converged_runs(L, q, 2, m, lf, 32):
+                st, lng, _ = o.join()
+                e.append(np.mean((lng[reach] - ex[reach]) ** 2))
+            mse[m, lf] = np.mean(e)
+    for lf in (1e-3, 1e-4):
+        assert 2.0 < mse[1, lf] / mse[4, lf] < 8.0, mse
+    for m in (1, 4):
+        assert mse[m, 1e-3] / mse[m, 1e-4] > 2.0, mse
+
+
+def test_bootstrap_spread_matches_the_spread_of_independent_runs():
+    # The bootstrap standard deviation of ln g (mean of R runs) must agree with
+    # the sample standard deviation of the runs' joined ln g over sqrt(R).
+    L, q, R = 4, 2, 32
+    runs = _converged_runs(L, q, 2, 4, 1e-4, R)
+    o = runs[0]
+    pv = [oracle.run_pieces(r) for r in runs]
+    st, out = oracle.bootstrap(np.stack([p for p, _ in pv]), np.stack([v for _, v in pv]), o.starts, o.e_lo,
+                               o.B, 16 * math.log(2), 400, 3, [1.0, 2.5])
+    assert st == 0
+    joined = np.stack([r.join()[1] for r in runs])
+    fin = np.all(np.isfinite(joined), axis=0)
+    sd = np.full(o.B, np.inf)
+    sd[fin] = joined[:, fin].std(axis=0)
+    fin[np.argmin(sd)] = False   # the bin the normalisation nearly pins
+    direct = joined[:, fin].std(axis=0, ddof=1) / math.sqrt(R)
+    ratio = np.median(out["lng_std"][fin] / direct)
+    assert 0.8 < ratio < 1.25, ratio
+    assert np.all(out["U_std"] > 0) and np.all(out["C_std"] > 0)
