@@ -389,6 +389,28 @@ int rewl_batch_run(rewl_batch_t *b, int64_t steps);
  * form.  Results are identical to rewl_batch_run.                           */
 int rewl_batch_run_per_instance(rewl_batch_t *b, int64_t steps);
 
+/* Bootstrap error analysis over the instances of a batch (Sec. 2: repeat the
+ * simulation, resample, and join every resampled g(E) anew, so the joining
+ * points move).  The R instances must be independent converged runs of one
+ * Potts system (same L, q, windows, overlap and walkers; different seeds or
+ * instance ids).  Replicate j draws R instances with replacement (Philox4x32-10
+ * keyed by `seed`, block (j, i/4, 0, 7 << 24), index floor(w R / 2^32) for
+ * its four words w), averages their final ln g window by window (summed in
+ * draw order, divided by R), joins the pieces over the union of the runs'
+ * visited flags, normalises to q^N and evaluates U and C_v at the nT
+ * temperatures T.  Outputs, host double buffers: lng_mean/lng_std[B] (mean
+ * and sample standard deviation over the replicates where ln g is finite;
+ * -inf and 0 where it never is), U_mean/U_std/C_mean/C_std[nT] (may be NULL
+ * when nT = 0).  dev_scratch: device memory of rewl_batch_bootstrap_bytes
+ * bytes, owned by the caller.  Errors: REWL_EINVAL (null argument, nboot
+ * outside [1, 65535], nT outside [0, 4096], T <= 0, instances of different
+ * systems, scratch too small), REWL_ESTATE (an instance not converged, or a
+ * resample without a common visited bin for a pair of windows).              */
+size_t rewl_batch_bootstrap_bytes(rewl_batch_t *b, int nboot, int nT);
+int rewl_batch_bootstrap(rewl_batch_t *b, int nboot, uint64_t seed, const double *T, int nT, void *dev_scratch,
+                         size_t scratch_bytes, double *lng_mean, double *lng_std, double *U_mean, double *U_std,
+                         double *C_mean, double *C_std);
+
 /* Batched steps done by the batch, and how many instances have converged.   */
 int rewl_batch_progress(rewl_batch_t *b, int64_t *steps, int32_t *converged);
 

@@ -126,6 +126,9 @@ def lib():
         L.rewl_batch_run.argtypes = [P, i64]
         L.rewl_batch_run_per_instance.argtypes = [P, i64]
         L.rewl_batch_progress.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+        L.rewl_batch_bootstrap_bytes.argtypes = [P, i32, i32]
+        L.rewl_batch_bootstrap_bytes.restype = ctypes.c_size_t
+        L.rewl_batch_bootstrap.argtypes = [P, i32, ctypes.c_uint64, P, i32, P, ctypes.c_size_t, P, P, P, P, P, P]
         L.rewl_batch_set_timing.argtypes = [P, i32]
         L.rewl_batch_get_timing.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         _lib = L
@@ -468,6 +471,29 @@ class Batch:
         if h is not None and h.value and _lib is not None:
             _lib.rewl_batch_destroy(h)
             self._h = None
+
+    def bootstrap(self, nboot, seed, T=()):
+        """Bootstrap over the instances (independent converged runs of one system).
+
+        Returns a dict: lng_mean, lng_std [B]; U_mean, U_std, C_mean, C_std [len(T)]."""
+        import torch
+
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        nT = len(T)
+        nbytes = lib().rewl_batch_bootstrap_bytes(self._h, int(nboot), nT)
+        if nbytes == 0:
+            raise RewlError("invalid bootstrap arguments")
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        B = 2 * self._desc[0][0]["L"] ** 2 + 1
+        out = {k: np.zeros(B) for k in ("lng_mean", "lng_std")}
+        out.update({k: np.zeros(nT) for k in ("U_mean", "U_std", "C_mean", "C_std")})
+        with torch.cuda.device(self.device):
+            _check(lib().rewl_batch_bootstrap(self._h, int(nboot), int(seed), _ptr(T), nT,
+                                              ctypes.c_void_p(scratch.data_ptr()), nbytes, _ptr(out["lng_mean"]),
+                                              _ptr(out["lng_std"]), _ptr(out["U_mean"]), _ptr(out["U_std"]),
+                                              _ptr(out["C_mean"]), _ptr(out["C_std"])))
+        self._stream.synchronize()
+        return out
 
     def instance(self, i):
         """Rewl view of instance i (walker/window/join/thermo queries)."""

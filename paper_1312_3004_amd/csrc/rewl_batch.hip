@@ -6,6 +6,7 @@
 // Workspace: [descriptor table | task lists | counters | status | queue]
 // followed by one single-run workspace per instance (rewl_create layout).
 #include <algorithm>
+#include <cmath>
 #include <functional>
 #include <cstring>
 #include <numeric>
@@ -738,6 +739,114 @@ int rewl_batch_tune(rewl_batch_t *b, int steps_per_plan, rewl_batch_plan *tried,
     st = apply_plan(b, &p);
     if (st != REWL_OK) return st;
     return b->n_converged == b->n ? REWL_CONVERGED : REWL_OK;
+}
+
+namespace {
+
+// Device scratch of a bootstrap: offsets of its buffers (256-byte aligned).
+struct BootLayout {
+    size_t draws, pieces, vis, beta, shift, cuts, status, joined, T, th, out, total;
+};
+
+BootLayout boot_layout(const DevState &d, int R, int nboot, int nT) {
+    BootLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = round_up(off + bytes, 256);
+        return at;
+    };
+    const size_t hw = (size_t)d.h * d.Wpad;
+    l.draws = take(sizeof(int32_t) * (size_t)nboot * R);
+    l.pieces = take(sizeof(double) * (size_t)nboot * hw);
+    l.vis = take(hw);
+    l.beta = take(sizeof(double) * (size_t)nboot * hw);
+    l.shift = take(sizeof(double) * (size_t)nboot * d.h);
+    l.cuts = take(sizeof(int32_t) * (size_t)nboot * d.h);
+    l.status = take(sizeof(int32_t) * (size_t)nboot);
+    l.joined = take(sizeof(double) * (size_t)nboot * d.Bpad);
+    l.T = take(sizeof(double) * (size_t)(nT > 0 ? nT : 1));
+    l.th = take(sizeof(double) * 3 * (size_t)nboot * (nT > 0 ? nT : 1));
+    l.out = take(sizeof(double) * (2 * (size_t)d.B + 4 * (size_t)nT));
+    l.total = off;
+    return l;
+}
+
+// Every instance a run of the same Potts system (lattice, q, windows, walkers).
+int check_same_system(const rewl_batch *b) {
+    const rewl *a = b->inst[0];
+    if (a->st.model != rewl_gpu::kModelPotts2D) return fail(REWL_EINVAL, "bootstrap needs Potts instances");
+    for (const rewl *r : b->inst) {
+        const DevState &d = r->st;
+        if (d.model != a->st.model || d.L != a->st.L || d.q != a->st.q || d.h != a->st.h || d.m != a->st.m ||
+            d.W != a->st.W || r->starts != a->starts)
+            return fail(REWL_EINVAL, "bootstrap needs instances of one system (same L, q, windows, walkers, overlap)");
+    }
+    return REWL_OK;
+}
+
+}  // namespace
+
+size_t rewl_batch_bootstrap_bytes(rewl_batch_t *b, int nboot, int nT) {
+    if (!b || b->n < 1 || nboot < 1 || nT < 0) return 0;
+    return boot_layout(b->inst[0]->st, b->n, nboot, nT).total;
+}
+
+int rewl_batch_bootstrap(rewl_batch_t *b, int nboot, uint64_t seed, const double *T, int nT, void *dev_scratch,
+                         size_t scratch_bytes, double *lng_mean, double *lng_std, double *U_mean, double *U_std,
+                         double *C_mean, double *C_std) {
+    if (!b || !dev_scratch || !lng_mean || !lng_std) return fail(REWL_EINVAL, "null argument");
+    if (nboot < 1 || nboot > 65535) return fail(REWL_EINVAL, "nboot must be in [1, 65535]");
+    if (nT < 0 || nT > 4096) return fail(REWL_EINVAL, "nT must be in [0, 4096]");
+    if (nT > 0 && (!T || !U_mean || !U_std || !C_mean || !C_std)) return fail(REWL_EINVAL, "null argument");
+    for (int i = 0; i < nT; ++i)
+        if (!(T[i] > 0.0)) return fail(REWL_EINVAL, "temperatures must be positive");
+    int st = check_same_system(b);
+    if (st != REWL_OK) return st;
+    st = download_status(b);
+    if (st != REWL_OK) return st;
+    if (b->n_converged != b->n) return fail(REWL_ESTATE, "bootstrap needs every instance converged");
+    const DevState &d = b->inst[0]->st;
+    const BootLayout l = boot_layout(d, b->n, nboot, nT);
+    if (scratch_bytes < l.total) return fail(REWL_EINVAL, "scratch smaller than rewl_batch_bootstrap_bytes");
+    unsigned char *w = (unsigned char *)dev_scratch;
+    rewl_gpu::BootArgs a{};
+    a.R = b->n; a.h = d.h; a.W = d.W; a.Wpad = d.Wpad; a.B = d.B; a.Bpad = d.Bpad; a.e_lo = d.e_lo; a.m = d.m;
+    a.nboot = nboot; a.nT = nT;
+    a.key0 = (uint32_t)seed; a.key1 = (uint32_t)(seed >> 32);
+    a.log_total = (double)d.N * std::log((double)d.q);
+    a.e0 = (double)d.e_lo; a.de = 1.0;
+    a.start = d.start;
+    a.draws = (int32_t *)(w + l.draws);
+    a.pieces = (double *)(w + l.pieces);
+    a.vis = (uint8_t *)(w + l.vis);
+    a.beta = (double *)(w + l.beta);
+    a.shift = (double *)(w + l.shift);
+    a.cuts = (int32_t *)(w + l.cuts);
+    a.status = (int32_t *)(w + l.status);
+    a.joined = (double *)(w + l.joined);
+    a.T = (const double *)(w + l.T);
+    a.th = (double *)(w + l.th);
+    a.out = (double *)(w + l.out);
+    if (nT > 0) HIP_TRY(hipMemcpyAsync((void *)a.T, T, sizeof(double) * nT, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(rewl_gpu::launch_bootstrap(a, b->d_descs, b->stream));
+    std::vector<double> out(2 * (size_t)d.B + 4 * (size_t)nT);
+    std::vector<int32_t> status(nboot);
+    HIP_TRY(hipMemcpyAsync(out.data(), a.out, sizeof(double) * out.size(), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipMemcpyAsync(status.data(), a.status, sizeof(int32_t) * nboot, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int j = 0; j < nboot; ++j)
+        if (status[j] != 0) return fail(REWL_ESTATE, "a resample could not be joined (no common visited bin)");
+    std::memcpy(lng_mean, out.data(), sizeof(double) * d.B);
+    std::memcpy(lng_std, out.data() + d.B, sizeof(double) * d.B);
+    const double *o = out.data() + 2 * (size_t)d.B;
+    if (nT > 0) {
+        std::memcpy(U_mean, o, sizeof(double) * nT);
+        std::memcpy(U_std, o + nT, sizeof(double) * nT);
+        std::memcpy(C_mean, o + 2 * nT, sizeof(double) * nT);
+        std::memcpy(C_std, o + 3 * nT, sizeof(double) * nT);
+    }
+    return REWL_OK;
 }
 
 int rewl_batch_progress(rewl_batch_t *b, int64_t *steps, int32_t *converged) {

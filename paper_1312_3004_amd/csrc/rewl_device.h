@@ -15,6 +15,7 @@ constexpr uint32_t kDomWalkin = 2;  // walk-in attempts
 constexpr uint32_t kDomExch = 3;    // exchange permutation and acceptance words
 constexpr uint32_t kDomMoveU = 5;   // trimer model: uniform word of a main-phase attempt
 constexpr uint32_t kDomWalkinU = 6; // trimer model: uniform word of a walk-in attempt
+constexpr uint32_t kDomBoot = 7;    // bootstrap: run indices drawn for the resamples
 
 constexpr int kModelPotts2D = 0;
 constexpr int kModelTrimer3D = 1;
@@ -302,6 +303,25 @@ hipError_t launch_sweep_batch(int precision, const DevState *descs, const BatchT
                               int ntasks, int *queue, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_sync_batch(int precision, const DevState *descs, const BatchTask *wtasks, int lo, int n,
                              hipStream_t s);
+// Bootstrap over the R instances of a batch (device buffers carved by the host).
+struct BootArgs {
+    int R, h, W, Wpad, B, Bpad, e_lo, m, nboot, nT;
+    uint32_t key0, key1;
+    double log_total, e0, de;
+    const int32_t *start;
+    int32_t *draws;     // [nboot][R]
+    double *pieces;     // [nboot][h][Wpad]
+    uint8_t *vis;       // [h][Wpad]
+    double *beta;       // [nboot][h][Wpad]
+    double *shift;      // [nboot][h]
+    int32_t *cuts;      // [nboot][h]
+    int32_t *status;    // [nboot]
+    double *joined;     // [nboot][Bpad]
+    const double *T;    // [nT]
+    double *th;         // [nboot][nT][3]
+    double *out;        // [2B + 4 nT]: ln g mean, std; U mean, std; C mean, std
+};
+hipError_t launch_bootstrap(const BootArgs &a, const DevState *descs, hipStream_t s);
 hipError_t launch_measure_batch(const DevState *descs, const BatchTask *tasks, int lo, int n, hipStream_t s);
 hipError_t launch_exchange_batch(const DevState *descs, const BatchTask *xtasks, int lo, int n,
                                  hipStream_t s);

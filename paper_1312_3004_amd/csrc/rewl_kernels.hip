@@ -929,46 +929,72 @@ __global__ __launch_bounds__(256) void k_fold_visited(DevState st) {
     }
 }
 
-__device__ __forceinline__ double piece_at(const DevState &st, int k, int b) {
-    return lng_at(st, k * st.m, b, st.precision);
+// A set of h pieces of ln g to join: piece k, bin b at p64[k * kstride + b]
+// in binary64, or as the (hi, lo) pair phi/plo at the same index.
+struct JoinView {
+    int h, W, Wpad, B, e_lo;
+    const int32_t *start;   // [h] lowest energy of each window
+    const uint8_t *vis;     // [h][Wpad] visited flags
+    const double *p64;
+    const float *phi, *plo;
+    size_t kstride;
+    __device__ double piece(int k, int b) const {
+        const size_t i = (size_t)k * kstride + b;
+        if (p64) return p64[i];
+        return (double)phi[i] + (double)plo[i];
+    }
+};
+
+// The pieces of a run: walker k*m of every window (all walkers of a finished
+// window hold the same averaged ln g).
+__device__ __forceinline__ JoinView view_of(const DevState &st) {
+    JoinView v;
+    v.h = st.h; v.W = st.W; v.Wpad = st.Wpad; v.B = st.B; v.e_lo = st.e_lo;
+    v.start = st.start;
+    v.vis = st.visited;
+    v.p64 = st.precision == 0 ? st.lng : nullptr;
+    v.phi = st.lng_hi;
+    v.plo = st.lng_lo;
+    v.kstride = (size_t)st.m * st.Wpad;
+    return v;
 }
 
-__global__ __launch_bounds__(256) void k_beta(DevState st, double *beta) {
+// (b) beta of piece k at bin b.
+__device__ __forceinline__ void join_beta(const JoinView &v, int k, int b, double *beta) {
 #pragma clang fp contract(off)
-    const int k = blockIdx.y;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= st.W) return;
-    const uint8_t *vis = st.visited + (size_t)k * st.Wpad;
+    const uint8_t *vis = v.vis + (size_t)k * v.Wpad;
     double out = __builtin_nan("");
     if (vis[b]) {
         int bp = -1, bm = -1;
-        for (int t = b + 1; t < st.W; ++t) if (vis[t]) { bp = t; break; }
+        for (int t = b + 1; t < v.W; ++t) if (vis[t]) { bp = t; break; }
         for (int t = b - 1; t >= 0; --t) if (vis[t]) { bm = t; break; }
         if (bp >= 0 && bm >= 0)
-            out = (piece_at(st, k, bp) - piece_at(st, k, bm)) / (double)(bp - bm);
+            out = (v.piece(k, bp) - v.piece(k, bm)) / (double)(bp - bm);
     }
-    beta[(size_t)k * st.Wpad + b] = out;
+    beta[(size_t)k * v.Wpad + b] = out;
 }
 
-__global__ __launch_bounds__(256) void k_join_cuts(DevState st, const double *beta, double *shift) {
+// (c) joining energies and shifts, one workgroup of 256 threads.
+__device__ __forceinline__ void join_cuts(const JoinView &v, const double *beta, double *shift, int32_t *cuts,
+                                          int32_t *status) {
 #pragma clang fp contract(off)
     const int tid = threadIdx.x;
     __shared__ double s_d[256];
     __shared__ int s_e[256];
     __shared__ int s_prev;
-    if (tid == 0) { s_prev = INT32_MIN; shift[0] = 0.0; *st.join_status = 0; }
+    if (tid == 0) { s_prev = INT32_MIN; shift[0] = 0.0; *status = 0; }
     __syncthreads();
-    const int W = st.W;
-    for (int k = 0; k + 1 < st.h; ++k) {
-        const int sa = st.start[k], sb = st.start[k + 1];
+    const int W = v.W;
+    for (int k = 0; k + 1 < v.h; ++k) {
+        const int sa = v.start[k], sb = v.start[k + 1];
         int lo = sb;
         if (s_prev != INT32_MIN && s_prev + 1 > lo) lo = s_prev + 1;
         const int hi = sa + W - 1;
         double bestd = 0.0;
         int beste = INT32_MIN;
         for (int e = lo + tid; e <= hi; e += 256) {
-            const double ba = beta[(size_t)k * st.Wpad + (e - sa)];
-            const double bb = beta[(size_t)(k + 1) * st.Wpad + (e - sb)];
+            const double ba = beta[(size_t)k * v.Wpad + (e - sa)];
+            const double bb = beta[(size_t)(k + 1) * v.Wpad + (e - sb)];
             if (ba != ba || bb != bb) continue;
             const double d = fabs(ba - bb);
             if (beste == INT32_MIN || d < bestd) { bestd = d; beste = e; }
@@ -991,46 +1017,43 @@ __global__ __launch_bounds__(256) void k_join_cuts(DevState st, const double *be
         if (tid == 0) {
             int best = s_e[0];
             if (best == INT32_MIN) {
-                const uint8_t *va = st.visited + (size_t)k * st.Wpad;
-                const uint8_t *vb = st.visited + (size_t)(k + 1) * st.Wpad;
+                const uint8_t *va = v.vis + (size_t)k * v.Wpad;
+                const uint8_t *vb = v.vis + (size_t)(k + 1) * v.Wpad;
                 for (int e = lo; e <= hi; ++e)
                     if (va[e - sa] && vb[e - sb]) { best = e; break; }
             }
             if (best == INT32_MIN) {
-                *st.join_status = -1;
+                *status = -1;
                 best = hi;
             }
-            st.cuts[k] = best;
-            shift[k + 1] = (piece_at(st, k, best - sa) + shift[k]) - piece_at(st, k + 1, best - sb);
+            cuts[k] = best;
+            shift[k + 1] = (v.piece(k, best - sa) + shift[k]) - v.piece(k + 1, best - sb);
             s_prev = best;
         }
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void k_join_assemble(DevState st, const double *shift) {
+// (d) the joined value of bin b: piece k holds (cut_{k-1}, cut_k].
+__device__ __forceinline__ void join_assemble(const JoinView &v, const int32_t *cuts, const double *shift, int b,
+                                              double *out) {
 #pragma clang fp contract(off)
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= st.B) return;
-    const int e = st.e_lo + b;
-    const int h = st.h;
-    // piece k holds (cut_{k-1}, cut_k]
+    const int e = v.e_lo + b;
     int k = 0;
-    while (k < h - 1 && e > st.cuts[k]) ++k;
-    const int bb = e - st.start[k];
-    double out = -__builtin_inf();
-    if (bb >= 0 && bb < st.W && st.visited[(size_t)k * st.Wpad + bb])
-        out = piece_at(st, k, bb) + shift[k];
-    st.joined[b] = out;
+    while (k < v.h - 1 && e > cuts[k]) ++k;
+    const int bb = e - v.start[k];
+    double r = -__builtin_inf();
+    if (bb >= 0 && bb < v.W && v.vis[(size_t)k * v.Wpad + bb]) r = v.piece(k, bb) + shift[k];
+    out[b] = r;
 }
 
-// log-sum-exp over the joined curve in one workgroup, then the shift to
+// (e) log-sum-exp over the joined curve in one workgroup, then the shift to
 // sum_E g(E) = exp(log_total).
-__global__ __launch_bounds__(256) void k_join_normalise(DevState st, double log_total) {
+__device__ __forceinline__ void join_normalise(double *joined, int B, double log_total) {
     const int tid = threadIdx.x;
     __shared__ double s[256];
     double mx = -__builtin_inf();
-    for (int b = tid; b < st.B; b += 256) mx = fmax(mx, st.joined[b]);
+    for (int b = tid; b < B; b += 256) mx = fmax(mx, joined[b]);
     s[tid] = mx;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -1040,8 +1063,8 @@ __global__ __launch_bounds__(256) void k_join_normalise(DevState st, double log_
     mx = s[0];
     __syncthreads();
     double acc = 0.0;
-    for (int b = tid; b < st.B; b += 256) {
-        const double v = st.joined[b];
+    for (int b = tid; b < B; b += 256) {
+        const double v = joined[b];
         if (v != -__builtin_inf()) acc += exp(v - mx);
     }
     s[tid] = acc;
@@ -1051,24 +1074,25 @@ __global__ __launch_bounds__(256) void k_join_normalise(DevState st, double log_
         __syncthreads();
     }
     const double lse = mx + log(s[0]);
-    for (int b = tid; b < st.B; b += 256) {
-        const double v = st.joined[b];
-        if (v != -__builtin_inf()) st.joined[b] = (v - lse) + log_total;
+    for (int b = tid; b < B; b += 256) {
+        const double v = joined[b];
+        if (v != -__builtin_inf()) joined[b] = (v - lse) + log_total;
     }
 }
 
-// Canonical averages (Sec. 3.1, Fig. 3b) from the joined ln g, one workgroup
-// per temperature: ln Z = LSE_E(ln g(E) - E/T), U = sum P E,
-// C_v = sum P (E - U)^2 / T^2 with P = exp(ln g(E) - E/T - ln Z).
-__global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, double *out) {
-    const int t = blockIdx.x, tid = threadIdx.x;
-    const double temp = T[t];
+// Canonical averages (Sec. 3.1, Fig. 3b) from a joined ln g at temperature
+// temp, one workgroup: ln Z = LSE_E(ln g(E) - E/T), U = sum P E,
+// C_v = sum P (E - U)^2 / T^2 with P = exp(ln g(E) - E/T - ln Z); bin b at
+// energy e0 + b de.  out[0..2] = ln Z, U, C_v.
+__device__ __forceinline__ void thermo_one(const double *joined, int B, double e0, double de, double temp,
+                                           double *out) {
+    const int tid = threadIdx.x;
     __shared__ double s[256];
     double mx = -__builtin_inf();
-    for (int b = tid; b < st.B; b += 256) {
-        const double v = st.joined[b];
+    for (int b = tid; b < B; b += 256) {
+        const double v = joined[b];
         if (v == -__builtin_inf()) continue;
-        mx = fmax(mx, v - (st.th_e0 + (double)b * st.th_de) / temp);
+        mx = fmax(mx, v - (e0 + (double)b * de) / temp);
     }
     s[tid] = mx;
     __syncthreads();
@@ -1079,10 +1103,10 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     mx = s[0];
     __syncthreads();
     double z = 0.0;
-    for (int b = tid; b < st.B; b += 256) {
-        const double v = st.joined[b];
+    for (int b = tid; b < B; b += 256) {
+        const double v = joined[b];
         if (v == -__builtin_inf()) continue;
-        z += exp((v - (st.th_e0 + (double)b * st.th_de) / temp) - mx);
+        z += exp((v - (e0 + (double)b * de) / temp) - mx);
     }
     s[tid] = z;
     __syncthreads();
@@ -1093,10 +1117,10 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     const double lnz = mx + log(s[0]);
     __syncthreads();
     double u = 0.0;
-    for (int b = tid; b < st.B; b += 256) {
-        const double v = st.joined[b];
+    for (int b = tid; b < B; b += 256) {
+        const double v = joined[b];
         if (v == -__builtin_inf()) continue;
-        const double e = st.th_e0 + (double)b * st.th_de;
+        const double e = e0 + (double)b * de;
         u += exp((v - e / temp) - lnz) * e;
     }
     s[tid] = u;
@@ -1108,10 +1132,10 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
     const double U = s[0];
     __syncthreads();
     double var = 0.0;
-    for (int b = tid; b < st.B; b += 256) {
-        const double v = st.joined[b];
+    for (int b = tid; b < B; b += 256) {
+        const double v = joined[b];
         if (v == -__builtin_inf()) continue;
-        const double e = st.th_e0 + (double)b * st.th_de;
+        const double e = e0 + (double)b * de;
         const double d = e - U;
         var += exp((v - e / temp) - lnz) * d * d;
     }
@@ -1122,10 +1146,36 @@ __global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, do
         __syncthreads();
     }
     if (tid == 0) {
-        out[3 * t + 0] = lnz;
-        out[3 * t + 1] = U;
-        out[3 * t + 2] = s[0] / (temp * temp);
+        out[0] = lnz;
+        out[1] = U;
+        out[2] = s[0] / (temp * temp);
     }
+}
+
+__global__ __launch_bounds__(256) void k_beta(DevState st, double *beta) {
+    const int k = blockIdx.y;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= st.W) return;
+    join_beta(view_of(st), k, b, beta);
+}
+
+__global__ __launch_bounds__(256) void k_join_cuts(DevState st, const double *beta, double *shift) {
+    join_cuts(view_of(st), beta, shift, st.cuts, st.join_status);
+}
+
+__global__ __launch_bounds__(256) void k_join_assemble(DevState st, const double *shift) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= st.B) return;
+    join_assemble(view_of(st), st.cuts, shift, b, st.joined);
+}
+
+__global__ __launch_bounds__(256) void k_join_normalise(DevState st, double log_total) {
+    join_normalise(st.joined, st.B, log_total);
+}
+
+__global__ __launch_bounds__(256) void k_thermo(DevState st, const double *T, double *out) {
+    const int t = blockIdx.x;
+    thermo_one(st.joined, st.B, st.th_e0, st.th_de, T[t], out + 3 * t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1281,6 +1331,138 @@ __global__ void k_status_batch(const DevState *__restrict__ descs, int n, BatchS
     out[i].round = conv ? st.stop[1] : st.ctl[1];
 }
 
+// ---------------------------------------------------------------------------
+// Bootstrap error analysis (Sec. 2: the simulation is repeated, the results
+// resampled, and every resampled global g(E) joined anew, so its joining
+// points move).  The R instances of a batch are R independent runs of one
+// system.  Replicate j draws R run indices with replacement (Philox words,
+// four per block (j, i/4, 0, BOOT), r = floor(w R / 2^32)), averages the
+// drawn runs' pieces window by window (summed in draw order, divided by R),
+// joins them over the union of the runs' visited flags, normalises, and
+// evaluates U and C_v.  Replicates are independent workgroups.
+struct BootView {
+    int R, h, W, Wpad, B, Bpad, e_lo, m, nboot;
+    const int32_t *start;   // [h]
+    int32_t *draws;         // [nboot][R]
+    double *pieces;         // [nboot][h][Wpad]
+    uint8_t *vis;           // [h][Wpad] union of the runs' flags
+    double *beta;           // [nboot][h][Wpad]
+    double *shift;          // [nboot][h]
+    int32_t *cuts;          // [nboot][h]
+    int32_t *status;        // [nboot]
+    double *joined;         // [nboot][Bpad]
+    __device__ JoinView view(int j) const {
+        JoinView v;
+        v.h = h; v.W = W; v.Wpad = Wpad; v.B = B; v.e_lo = e_lo;
+        v.start = start;
+        v.vis = vis;
+        v.p64 = pieces + (size_t)j * h * Wpad;
+        v.phi = v.plo = nullptr;
+        v.kstride = (size_t)Wpad;
+        return v;
+    }
+};
+
+__global__ __launch_bounds__(256) void k_boot_draws(BootView bv, uint32_t key0, uint32_t key1) {
+    const int nblk = (bv.R + 3) / 4;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)bv.nboot * nblk) return;
+    const int j = (int)(t / nblk), c = (int)(t % nblk);
+    const U4 w = philox10((uint32_t)j, (uint32_t)c, 0u, kDomBoot << 24, key0, key1);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    for (int q = 0; q < 4; ++q) {
+        const int i = 4 * c + q;
+        if (i < bv.R) bv.draws[(size_t)j * bv.R + i] = (int32_t)mul_shift(ws[q], (uint32_t)bv.R);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_boot_visited(BootView bv, const DevState *__restrict__ descs) {
+    const int k = blockIdx.y;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bv.W) return;
+    uint8_t v = 0;
+    for (int r = 0; r < bv.R; ++r) v |= descs[r].visited[(size_t)k * bv.Wpad + b] ? 1 : 0;
+    bv.vis[(size_t)k * bv.Wpad + b] = v;
+}
+
+__global__ __launch_bounds__(256) void k_boot_pieces(BootView bv, const DevState *__restrict__ descs) {
+#pragma clang fp contract(off)
+    const int k = blockIdx.y, j = blockIdx.z;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bv.W) return;
+    const int32_t *dr = bv.draws + (size_t)j * bv.R;
+    double sum = 0.0;
+    for (int i = 0; i < bv.R; ++i) {
+        const DevState &st = descs[dr[i]];
+        sum = sum + lng_at(st, k * bv.m, b, st.precision);
+    }
+    bv.pieces[((size_t)j * bv.h + k) * bv.Wpad + b] = sum / (double)bv.R;
+}
+
+__global__ __launch_bounds__(256) void k_boot_beta(BootView bv) {
+    const int k = blockIdx.y, j = blockIdx.z;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bv.W) return;
+    join_beta(bv.view(j), k, b, bv.beta + (size_t)j * bv.h * bv.Wpad);
+}
+
+__global__ __launch_bounds__(256) void k_boot_cuts(BootView bv) {
+    const int j = blockIdx.x;
+    join_cuts(bv.view(j), bv.beta + (size_t)j * bv.h * bv.Wpad, bv.shift + (size_t)j * bv.h,
+              bv.cuts + (size_t)j * bv.h, bv.status + j);
+}
+
+__global__ __launch_bounds__(256) void k_boot_assemble(BootView bv) {
+    const int j = blockIdx.y;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bv.B) return;
+    join_assemble(bv.view(j), bv.cuts + (size_t)j * bv.h, bv.shift + (size_t)j * bv.h, b,
+                  bv.joined + (size_t)j * bv.Bpad);
+}
+
+__global__ __launch_bounds__(256) void k_boot_normalise(BootView bv, double log_total) {
+    join_normalise(bv.joined + (size_t)blockIdx.x * bv.Bpad, bv.B, log_total);
+}
+
+__global__ __launch_bounds__(256) void k_boot_thermo(BootView bv, const double *T, int nT, double e0, double de,
+                                                    double *out) {
+    const int t = blockIdx.x, j = blockIdx.y;
+    thermo_one(bv.joined + (size_t)j * bv.Bpad, bv.B, e0, de, T[t], out + ((size_t)j * nT + t) * 3);
+}
+
+// Mean and sample standard deviation over the replicates where the value is
+// finite (mean -inf, std 0 if none), summed in replicate order.
+__device__ __forceinline__ void finite_stats(const double *x, int n, size_t stride, double *mean, double *sd) {
+#pragma clang fp contract(off)
+    double s = 0.0;
+    int c = 0;
+    for (int j = 0; j < n; ++j) {
+        const double v = x[(size_t)j * stride];
+        if (__builtin_isfinite(v)) { s += v; ++c; }
+    }
+    if (c == 0) { *mean = -__builtin_inf(); *sd = 0.0; return; }
+    const double mu = s / (double)c;
+    double q = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double v = x[(size_t)j * stride];
+        if (__builtin_isfinite(v)) { const double d = v - mu; q += d * d; }
+    }
+    *mean = mu;
+    *sd = c > 1 ? sqrt(q / (double)(c - 1)) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_boot_stats(BootView bv, const double *th, int nT, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < bv.B) {
+        finite_stats(bv.joined + i, bv.nboot, (size_t)bv.Bpad, out + i, out + bv.B + i);
+    } else if (i < bv.B + nT) {
+        const int t = i - bv.B;
+        double *o = out + 2 * (size_t)bv.B;
+        finite_stats(th + (size_t)t * 3 + 1, bv.nboot, (size_t)nT * 3, o + t, o + nT + t);
+        finite_stats(th + (size_t)t * 3 + 2, bv.nboot, (size_t)nT * 3, o + 2 * nT + t, o + 3 * nT + t);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1384,6 +1566,28 @@ hipError_t launch_join(const DevState &st, double log_total, hipStream_t s) {
     hipLaunchKernelGGL(k_join_assemble, dim3((st.B + 255) / 256), dim3(256), 0, s, st,
                        (const double *)shift);
     hipLaunchKernelGGL(k_join_normalise, dim3(1), dim3(256), 0, s, st, log_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_bootstrap(const BootArgs &a, const DevState *descs, hipStream_t s) {
+    BootView bv;
+    bv.R = a.R; bv.h = a.h; bv.W = a.W; bv.Wpad = a.Wpad; bv.B = a.B; bv.Bpad = a.Bpad; bv.e_lo = a.e_lo;
+    bv.m = a.m; bv.nboot = a.nboot;
+    bv.start = a.start; bv.draws = a.draws; bv.pieces = a.pieces; bv.vis = a.vis; bv.beta = a.beta;
+    bv.shift = a.shift; bv.cuts = a.cuts; bv.status = a.status; bv.joined = a.joined;
+    const long long ndraw = (long long)a.nboot * ((a.R + 3) / 4);
+    const unsigned wb = (unsigned)((a.W + 255) / 256);
+    hipLaunchKernelGGL(k_boot_draws, dim3((unsigned)((ndraw + 255) / 256)), dim3(256), 0, s, bv, a.key0, a.key1);
+    hipLaunchKernelGGL(k_boot_visited, dim3(wb, a.h), dim3(256), 0, s, bv, descs);
+    hipLaunchKernelGGL(k_boot_pieces, dim3(wb, a.h, a.nboot), dim3(256), 0, s, bv, descs);
+    hipLaunchKernelGGL(k_boot_beta, dim3(wb, a.h, a.nboot), dim3(256), 0, s, bv);
+    hipLaunchKernelGGL(k_boot_cuts, dim3(a.nboot), dim3(256), 0, s, bv);
+    hipLaunchKernelGGL(k_boot_assemble, dim3((unsigned)((a.B + 255) / 256), a.nboot), dim3(256), 0, s, bv);
+    hipLaunchKernelGGL(k_boot_normalise, dim3(a.nboot), dim3(256), 0, s, bv, a.log_total);
+    if (a.nT > 0)
+        hipLaunchKernelGGL(k_boot_thermo, dim3(a.nT, a.nboot), dim3(256), 0, s, bv, a.T, a.nT, a.e0, a.de, a.th);
+    hipLaunchKernelGGL(k_boot_stats, dim3((unsigned)((a.B + a.nT + 255) / 256)), dim3(256), 0, s, bv,
+                       (const double *)a.th, a.nT, a.out);
     return hipGetLastError();
 }
 
