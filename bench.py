@@ -477,6 +477,84 @@ def production(args):
     print(json.dumps(out), flush=True)
 
 
+def bootstrap_bench(args):
+    """Error analysis of Sec. 2 on the GPU: R = 64 independent runs of the
+    potts_q10_L8 workload (instances of one batch, different Philox streams
+    and starting lattices) to convergence, then 1,000 bootstrap resamples, each
+    joined anew, with U and C_v on 201 temperatures; the oracle's bootstrap of
+    the same runs is timed beside it."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    cfg = dict(workloads.CONFIGS["potts_q10_L8"])
+    L, q, h, m = cfg["L"], cfg["q"], cfg["windows"], cfg["walkers"]
+    R, nboot = 64, 1000
+    T = np.linspace(0.5, 1.0, 201)
+    insts, spins = [], []
+    for i in range(R):
+        insts.append(dict(L=L, q=q, windows=h, overlap=cfg["overlap"], walkers=m, seed=cfg["seed"], instance=i,
+                          flat=cfg["flat"], lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"],
+                          schedule=cfg["schedule"], sync_attempts=cfg["sync_attempts"], exchange=cfg["exchange"],
+                          precision=cfg["precision"]))
+        spins.append(workloads.init_spins(L, q, h * m, cfg["seed"] + i))
+    torch.cuda.set_device(0)
+    b = pk.Batch(insts, spins)
+    t0 = time.perf_counter()
+    b.walkin()
+    while b.run(200) != pk.CONVERGED:
+        log(f"[bench] bootstrap workload: {b.progress()[1]}/{R} runs converged")
+    torch.cuda.synchronize()
+    converge_s = time.perf_counter() - t0
+    log(f"[bench] {R} runs converged in {converge_s:.1f} s")
+    b.bootstrap(10, 1, T)                       # first call: module load and allocation
+    reps = []
+    for k in range(3):
+        t0 = time.perf_counter()
+        out = b.bootstrap(nboot, 11, T)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
+    gpu_s = min(reps)
+    peak = int(np.argmax(out["C_mean"]))
+    log(f"[bench] GPU bootstrap: {nboot} resamples in {gpu_s * 1e3:.1f} ms; C_v peak {out['C_mean'][peak]:.4g} "
+        f"+- {out['C_std'][peak]:.2g} at T = {T[peak]:.4f}")
+    res = {"metric": "bootstrap resamples/s (1 GPU), 64 converged q=10 Potts L=8 runs, 201 temperatures",
+           "value": nboot / gpu_s, "unit": "resamples/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": gpu_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{R} independent runs of potts_q10_L8 ({h} windows x {m} walker, ln f 1 -> "
+                                  f"1e-6), {nboot} bootstrap resamples, U and C_v at {len(T)} temperatures",
+                      "runs": R, "resamples": nboot, "temperatures": len(T)},
+           "runs_to_convergence_s": converge_s,
+           "cv_peak": {"T": float(T[peak]), "C_mean": float(out["C_mean"][peak]),
+                       "C_std": float(out["C_std"][peak])},
+           "lng_std_max": float(np.max(out["lng_std"]))}
+    if not args.no_cpu_baseline:
+        pv = []
+        for i in range(R):
+            inst = b.instance(i)
+            pv.append((np.stack([inst.walker(k * m)["lng"] for k in range(h)]),
+                       np.stack([inst.window(k)["visited"] for k in range(h)])))
+        t0 = time.perf_counter()
+        st, ref = oracle.bootstrap(np.stack([p for p, _ in pv]), np.stack([v for _, v in pv]), b.instance(0).starts,
+                                   -2 * L * L, 2 * L * L + 1, L * L * math.log(q), nboot, 11, T)
+        cpu_s = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": nboot / cpu_s, "unit": "resamples/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's bootstrap of the same {R} runs, {nboot} resamples, "
+                                         f"{len(T)} temperatures, one thread"}
+        fin = np.isfinite(ref["lng_mean"])
+        res["max_abs_diff_vs_oracle"] = {
+            "lng_mean": float(np.max(np.abs(out["lng_mean"][fin] - ref["lng_mean"][fin]))),
+            "lng_std": float(np.max(np.abs(out["lng_std"] - ref["lng_std"]))),
+            "C_mean_rel": float(np.max(np.abs(out["C_mean"] - ref["C_mean"]) / np.abs(ref["C_mean"])))}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,12 +572,13 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
                          "times first: the reference for the HBM byte counters of a profiler run")
-    ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer", "production"),
+    ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer", "production", "bootstrap"),
                     default="potts",
                     help="potts: the single-run workload (--config); batched: 256 instances; "
                          "precision: the L=80 workload in binary64 and in the binary32 pair form; "
                          "trimer: the continuous-move workload; production: the single-run workload "
-                         "with frozen weights and H(E, O) sampling")
+                         "with frozen weights and H(E, O) sampling; bootstrap: error analysis over 64 "
+                         "independent L=8 runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
@@ -527,6 +606,8 @@ def main():
         return trimer(args)
     if args.workload == "production":
         return production(args)
+    if args.workload == "bootstrap":
+        return bootstrap_bench(args)
 
     import torch
 

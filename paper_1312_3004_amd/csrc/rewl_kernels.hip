@@ -1424,42 +1424,107 @@ __global__ __launch_bounds__(256) void k_boot_normalise(BootView bv, double log_
     join_normalise(bv.joined + (size_t)blockIdx.x * bv.Bpad, bv.B, log_total);
 }
 
-__global__ __launch_bounds__(256) void k_boot_thermo(BootView bv, const double *T, int nT, double e0, double de,
-                                                    double *out) {
-    const int t = blockIdx.x, j = blockIdx.y;
-    thermo_one(bv.joined + (size_t)j * bv.Bpad, bv.B, e0, de, T[t], out + ((size_t)j * nT + t) * 3);
+// Canonical averages of replicate j at temperature T[t], one wavefront: the
+// same four passes as thermo_one, reduced across lanes with shuffles.
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
-// Mean and sample standard deviation over the replicates where the value is
-// finite (mean -inf, std 0 if none), summed in replicate order.
-__device__ __forceinline__ void finite_stats(const double *x, int n, size_t stride, double *mean, double *sd) {
-#pragma clang fp contract(off)
-    double s = 0.0;
-    int c = 0;
-    for (int j = 0; j < n; ++j) {
-        const double v = x[(size_t)j * stride];
-        if (__builtin_isfinite(v)) { s += v; ++c; }
+__global__ __launch_bounds__(64) void k_boot_thermo(BootView bv, const double *T, int nT, double e0, double de,
+                                                   double *out) {
+    const int t = blockIdx.x, j = blockIdx.y, lane = threadIdx.x;
+    const double *joined = bv.joined + (size_t)j * bv.Bpad;
+    const double temp = T[t];
+    double mx = -__builtin_inf();
+    for (int b = lane; b < bv.B; b += 64) {
+        const double v = joined[b];
+        if (v != -__builtin_inf()) mx = fmax(mx, v - (e0 + (double)b * de) / temp);
     }
-    if (c == 0) { *mean = -__builtin_inf(); *sd = 0.0; return; }
-    const double mu = s / (double)c;
+    mx = wave_max(mx);
+    double z = 0.0;
+    for (int b = lane; b < bv.B; b += 64) {
+        const double v = joined[b];
+        if (v != -__builtin_inf()) z += exp((v - (e0 + (double)b * de) / temp) - mx);
+    }
+    const double lnz = mx + log(wave_sum(z));
+    double u = 0.0;
+    for (int b = lane; b < bv.B; b += 64) {
+        const double v = joined[b];
+        if (v == -__builtin_inf()) continue;
+        const double e = e0 + (double)b * de;
+        u += exp((v - e / temp) - lnz) * e;
+    }
+    const double U = wave_sum(u);
+    double var = 0.0;
+    for (int b = lane; b < bv.B; b += 64) {
+        const double v = joined[b];
+        if (v == -__builtin_inf()) continue;
+        const double e = e0 + (double)b * de;
+        const double d = e - U;
+        var += exp((v - e / temp) - lnz) * d * d;
+    }
+    var = wave_sum(var);
+    if (lane == 0) {
+        double *o = out + ((size_t)j * nT + t) * 3;
+        o[0] = lnz;
+        o[1] = U;
+        o[2] = var / (temp * temp);
+    }
+}
+
+// Mean and sample standard deviation of one series over the replicates
+// (x[j * stride], j < n) where it is finite, one workgroup of 256 threads
+// (two passes, tree sums); mean -inf and std 0 if no value is finite.
+__device__ __forceinline__ void finite_stats_wg(const double *x, int n, size_t stride, double *mean, double *sd) {
+    const int tid = threadIdx.x;
+    __shared__ double s_v[256];
+    __shared__ int s_c[256];
+    double acc = 0.0;
+    int c = 0;
+    for (int j = tid; j < n; j += 256) {
+        const double v = x[(size_t)j * stride];
+        if (__builtin_isfinite(v)) { acc += v; ++c; }
+    }
+    s_v[tid] = acc; s_c[tid] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) { s_v[tid] += s_v[tid + o]; s_c[tid] += s_c[tid + o]; }
+        __syncthreads();
+    }
+    const int cnt = s_c[0];
+    const double mu = cnt ? s_v[0] / (double)cnt : 0.0;
+    __syncthreads();
     double q = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = tid; j < n; j += 256) {
         const double v = x[(size_t)j * stride];
         if (__builtin_isfinite(v)) { const double d = v - mu; q += d * d; }
     }
-    *mean = mu;
-    *sd = c > 1 ? sqrt(q / (double)(c - 1)) : 0.0;
+    s_v[tid] = q;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s_v[tid] += s_v[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        *mean = cnt ? mu : -__builtin_inf();
+        *sd = cnt > 1 ? sqrt(s_v[0] / (double)(cnt - 1)) : 0.0;
+    }
 }
 
+// Series i < B: ln g of bin i; then U and C_v of every temperature.
 __global__ __launch_bounds__(256) void k_boot_stats(BootView bv, const double *th, int nT, double *out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x;
     if (i < bv.B) {
-        finite_stats(bv.joined + i, bv.nboot, (size_t)bv.Bpad, out + i, out + bv.B + i);
-    } else if (i < bv.B + nT) {
-        const int t = i - bv.B;
-        double *o = out + 2 * (size_t)bv.B;
-        finite_stats(th + (size_t)t * 3 + 1, bv.nboot, (size_t)nT * 3, o + t, o + nT + t);
-        finite_stats(th + (size_t)t * 3 + 2, bv.nboot, (size_t)nT * 3, o + 2 * nT + t, o + 3 * nT + t);
+        finite_stats_wg(bv.joined + i, bv.nboot, (size_t)bv.Bpad, out + i, out + bv.B + i);
+    } else {
+        const int t = (i - bv.B) >> 1, which = (i - bv.B) & 1;   // 0: U, 1: C_v
+        double *o = out + 2 * (size_t)bv.B + (size_t)which * 2 * nT;
+        finite_stats_wg(th + (size_t)t * 3 + 1 + which, bv.nboot, (size_t)nT * 3, o + t, o + nT + t);
     }
 }
 
@@ -1585,9 +1650,9 @@ hipError_t launch_bootstrap(const BootArgs &a, const DevState *descs, hipStream_
     hipLaunchKernelGGL(k_boot_assemble, dim3((unsigned)((a.B + 255) / 256), a.nboot), dim3(256), 0, s, bv);
     hipLaunchKernelGGL(k_boot_normalise, dim3(a.nboot), dim3(256), 0, s, bv, a.log_total);
     if (a.nT > 0)
-        hipLaunchKernelGGL(k_boot_thermo, dim3(a.nT, a.nboot), dim3(256), 0, s, bv, a.T, a.nT, a.e0, a.de, a.th);
-    hipLaunchKernelGGL(k_boot_stats, dim3((unsigned)((a.B + a.nT + 255) / 256)), dim3(256), 0, s, bv,
-                       (const double *)a.th, a.nT, a.out);
+        hipLaunchKernelGGL(k_boot_thermo, dim3(a.nT, a.nboot), dim3(64), 0, s, bv, a.T, a.nT, a.e0, a.de, a.th);
+    hipLaunchKernelGGL(k_boot_stats, dim3((unsigned)(a.B + 2 * a.nT)), dim3(256), 0, s, bv, (const double *)a.th,
+                       a.nT, a.out);
     return hipGetLastError();
 }
 
