@@ -20,12 +20,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic LDS traffic of one Potts attempt: the flipped site and its four
-# neighbours (5 B), ln g(E') (8 B), read-modify-write of ln g(E) (16 B) and of
-# H(E) (8 B), and the accepted spin (1 B).
+# Algorithmic ALU work of one Potts attempt, in 32-bit lane operations (a
+# binary64 operation counts two: the fp64 vector rate is half the fp32 rate):
+# Philox4x32-10 block 98 (10 rounds of 2 mul_lo + 2 mul_hi + 4 xor, 9 key
+# bumps of 2 adds), proposal 4, neighbour indices 12, energy change 15, ln u 34
+# (binary64 log and scaling), decision 6, window test 2, updates of ln g, H
+# and E 4.
+ALU_OPS_PER_ATTEMPT = 175
+# MI355X vector ALU peak in 32-bit lane operations: 256 CUs x 128 lanes x
+# 2.4 GHz = 7.86e13/s (157.3 TFLOP/s fp32 counts an FMA as two flops).
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Algorithmic LDS bytes per attempt (site and neighbours 5, ln g(E') 8, ln g(E)
+# read-modify-write 16, H 8, spin 1), reported beside the ALU roofline.
 LDS_BYTES_PER_ATTEMPT = 38
-# MI355X LDS bandwidth: 256 CUs x 128 B/clk x 2.4 GHz.
-LDS_PEAK_GBS = 256 * 128 * 2.4
 # HBM bytes per k_sweep launch of the potts_q10_L32 workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg copy of known size
 # (profiles/k_sweep_potts_q10_L32_pmc.md).  Valid for the kernel as profiled.
@@ -651,7 +658,7 @@ def main():
 
     avg_ms = sweep_ms / max(launches, 1)
     attempts_per_launch = nw * S
-    achieved = LDS_BYTES_PER_ATTEMPT * attempts_per_launch / (avg_ms * 1e-3) / 1e9
+    achieved = ALU_OPS_PER_ATTEMPT * attempts_per_launch / (avg_ms * 1e-3) / 1e12
     per_walker = S * args.steps / elapsed
     W = g.W
     lnf_final = cfg["lnf_final"]
@@ -674,11 +681,12 @@ def main():
                                f"{int(cfg['overlap'] * 100)}% overlap, {m} walkers/window",
                    "L": L, "q": q, "windows": h, "walkers_per_window": m, "walkers": nw,
                    "attempts_per_step_per_walker": S, "attempts_per_step": nw * S},
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS,
                      "traffic": K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" else None,
                      "kernel": "k_sweep", "kernel_avg_ms": avg_ms, "kernel_launches": launches,
-                     "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT},
+                     "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
+                     "lds_gb_per_s": LDS_BYTES_PER_ATTEMPT * attempts_per_launch / (avg_ms * 1e-3) / 1e9},
         "valu": ({"instructions_per_attempt": K_SWEEP_L32_VALU_PER_ATTEMPT,
                   "achieved_lane_ops_per_s": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch /
                   (avg_ms * 1e-3),

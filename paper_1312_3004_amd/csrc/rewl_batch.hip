@@ -317,7 +317,7 @@ bool plan_layout(const rewl_batch *b, int wpc, int policy, std::vector<int> *nta
     *lds_max = 0;
     for (int i = 0; i < b->n; ++i) {
         const DevState &d = b->inst[i]->st;
-        const size_t state = sweep_state_lds(d.Npad, d.Wpad);
+        const size_t state = sweep_state_lds(d.Npad, d.Wpad, false);
         if (state + 64 * 8 > share) return false;
         (*ntag)[i] = policy == 0 ? tag_entries(d.N, share - state) : 64;
         (*lds)[i] = state + (size_t)(*ntag)[i] * 8;
@@ -341,7 +341,7 @@ int apply_mixed(rewl_batch *b, rewl_batch_plan *p) {
     for (int i = 0; i < b->n; ++i) {
         const DevState &d = b->inst[i]->st;
         ntag[i] = capped_tags(d.N, p->tag_bytes);
-        lds[i] = sweep_state_lds(d.Npad, d.Wpad) + (size_t)ntag[i] * 8;
+        lds[i] = sweep_state_lds(d.Npad, d.Wpad, false) + (size_t)ntag[i] * 8;
         size_t &cl = cls_lds[b->cls_of[i]];
         cl = std::max(cl, round_up(lds[i], 256));
     }
@@ -536,7 +536,7 @@ int rewl_batch_create(rewl_batch_t **out, int n, const rewl_instance *inst, cons
         std::vector<std::pair<size_t, int>> keys;   // (need, sites) per instance
         for (int i = 0; i < n; ++i) {
             const DevState &d = b->inst[i]->st;
-            keys.push_back({sweep_state_lds(d.Npad, d.Wpad) + (size_t)std::min(d.N, 4096) * 8, d.N});
+            keys.push_back({sweep_state_lds(d.Npad, d.Wpad, false) + (size_t)std::min(d.N, 4096) * 8, d.N});
         }
         std::vector<std::pair<size_t, int>> uniq = keys;
         std::sort(uniq.begin(), uniq.end(), [](const auto &x, const auto &y) { return x > y; });
@@ -622,12 +622,13 @@ int rewl_batch_tune(rewl_batch_t *b, int steps_per_plan, rewl_batch_plan *tried,
     if (steps_per_plan < 1) return fail(REWL_EINVAL, "steps_per_plan must be >= 1");
     int st = walkin_all(b, int64_t(1) << 40);
     if (st != REWL_OK) return st;
-    // candidates: every walkers-per-CU count the LDS and registers allow, for
-    // both tag policies; a plan whose layout equals an earlier one is skipped
+    // candidates: walkers-per-CU counts (1..6, then every second or fourth up
+    // to what the LDS and registers allow), for both tag policies; a plan
+    // whose layout equals an earlier one is skipped
     std::vector<rewl_batch_plan> cands;
     std::vector<std::vector<int>> seen;
     for (int policy = 0; policy <= (b->nclasses > 1 ? 0 : 1); ++policy) {
-        for (int c = 1; c <= 64; ++c) {
+        for (int c = 1; c <= 64; c += (c < 6 ? 1 : c < 16 ? 2 : 4)) {
             std::vector<int> ntag;
             std::vector<size_t> lds;
             size_t lds_max = 0;
@@ -655,11 +656,11 @@ int rewl_batch_tune(rewl_batch_t *b, int steps_per_plan, rewl_batch_plan *tried,
         std::vector<double> work(b->nclasses, 0.0);
         for (int i = 0; i < b->n; ++i)
             work[b->cls_of[i]] += (double)b->inst[i]->st.nw * (double)b->inst[i]->opts.sync_attempts;
-        for (int tag_bytes : {4096, 8192}) {
+        for (int tag_bytes : {4096, 8192, 16384}) {
             std::vector<size_t> cl(b->nclasses, 0);
             for (int i = 0; i < b->n; ++i) {
                 const DevState &d = b->inst[i]->st;
-                const size_t need = sweep_state_lds(d.Npad, d.Wpad) + (size_t)capped_tags(d.N, tag_bytes) * 8;
+                const size_t need = sweep_state_lds(d.Npad, d.Wpad, false) + (size_t)capped_tags(d.N, tag_bytes) * 8;
                 cl[b->cls_of[i]] = std::max(cl[b->cls_of[i]], round_up(need, 256));
             }
             std::vector<std::pair<double, std::vector<int>>> ranked;

@@ -20,8 +20,10 @@ size_t round_up(size_t x, size_t a);
 // Entries of the attempt kernel's conflict-tag table for N sites when
 // `lds_free` bytes of LDS are left (a power of two in [64, 4096]).
 int tag_entries(int N, size_t lds_free);
-// LDS of the attempt kernel without its conflict-tag table.
-size_t sweep_state_lds(int Npad, int Wpad);
+// LDS of the attempt kernel without its conflict-tag table: the lattice, plus
+// the walker's ln g and H rows when they are staged in LDS (the single-run
+// kernel; the batched kernels keep them in device memory).
+size_t sweep_state_lds(int Npad, int Wpad, bool lng_in_lds = true);
 
 #define HIP_TRY(expr)                                                                              \
     do {                                                                                           \

@@ -221,7 +221,10 @@ __device__ __forceinline__ void walker_sync() {
     else __syncthreads();
 }
 
-template <int PREC, bool WAVE = false>
+// GLOB: the walker's ln g and H rows stay in device memory (read and written
+// only when the register cache moves, H by atomic increments), so a walker
+// needs LDS for its lattice and tag table alone and more walkers fit a CU.
+template <int PREC, bool WAVE = false, bool GLOB = false>
 __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t s0, int64_t n,
                                              unsigned char *smem) {
 #pragma clang fp contract(off)
@@ -229,25 +232,39 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     const int lane = threadIdx.x & 63;
     const int k = w / st.m;
     const int W = st.W, Wpad = st.Wpad;
+    const size_t row = (size_t)w * Wpad;
     int8_t *sp = (int8_t *)smem;
-    double *g = (double *)(smem + st.Npad);
-    float *gh = (float *)(smem + st.Npad);
-    float *gl = gh + Wpad;
-    uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
-    unsigned long long *tag = (unsigned long long *)(smem + st.Npad + (size_t)Wpad * 12);
+    double *g;
+    float *gh, *gl;
+    uint32_t *H;
+    unsigned long long *tag;
+    if (GLOB) {
+        g = PREC == 0 ? st.lng + row : nullptr;
+        gh = PREC == 1 ? st.lng_hi + row : nullptr;
+        gl = PREC == 1 ? st.lng_lo + row : nullptr;
+        H = st.H + row;
+        tag = (unsigned long long *)(smem + st.Npad);
+    } else {
+        g = (double *)(smem + st.Npad);
+        gh = (float *)(smem + st.Npad);
+        gl = gh + Wpad;
+        H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
+        tag = (unsigned long long *)(smem + st.Npad + (size_t)Wpad * 12);
+    }
     const uint32_t tag_mask = (uint32_t)st.Ntag - 1u;
 
     const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)sp)[i] = gsp[i];
-    const size_t row = (size_t)w * Wpad;
-    for (int b = lane; b < W; b += 64) {
-        if (PREC == 0) {
-            g[b] = st.lng[row + b];
-        } else {
-            gh[b] = st.lng_hi[row + b];
-            gl[b] = st.lng_lo[row + b];
+    if (!GLOB) {
+        for (int b = lane; b < W; b += 64) {
+            if (PREC == 0) {
+                g[b] = st.lng[row + b];
+            } else {
+                gh[b] = st.lng_hi[row + b];
+                gl[b] = st.lng_lo[row + b];
+            }
+            H[b] = st.H[row + b];
         }
-        H[b] = st.H[row + b];
     }
     for (int i = lane; i < st.Ntag; i += 64) tag[i] = 0ull;
     walker_sync<WAVE>();
@@ -275,6 +292,9 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             if (PREC == 0) g[b] = c64;
             else { gh[b] = ch; gl[b] = cl; }
         }
+        // device-memory rows: the stores land before the lanes read the moved
+        // cache range back (the ranges overlap)
+        if (GLOB) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     };
     cache_load();
     int erel = 32;  // E - ebase
@@ -467,14 +487,16 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     walker_sync<WAVE>();
     uint32_t *osp = (uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = lane; i < st.Npad / 4; i += 64) osp[i] = ((uint32_t *)sp)[i];
-    for (int b = lane; b < W; b += 64) {
-        if (PREC == 0) {
-            st.lng[row + b] = g[b];
-        } else {
-            st.lng_hi[row + b] = gh[b];
-            st.lng_lo[row + b] = gl[b];
+    if (!GLOB) {
+        for (int b = lane; b < W; b += 64) {
+            if (PREC == 0) {
+                st.lng[row + b] = g[b];
+            } else {
+                st.lng_hi[row + b] = gh[b];
+                st.lng_lo[row + b] = gl[b];
+            }
+            st.H[row + b] = H[b];
         }
-        st.H[row + b] = H[b];
     }
     if (lane == 0) st.E[w] = E;
 }
@@ -1232,7 +1254,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (!PERSISTENT) {
         const BatchTask t = tasks[task_lo + (int)blockIdx.x];
         const DevState st = descs[t.inst];
-        sweep_walker<PREC>(st, t.idx, st.ctl[0], st.sync_attempts, smem);
+        sweep_walker<PREC, false, true>(st, t.idx, st.ctl[0], st.sync_attempts, smem);
         return;
     }
     for (;;) {
@@ -1242,7 +1264,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (ti >= ntasks) break;
         const BatchTask t = tasks[ti];
         const DevState &st = descs[t.inst];
-        sweep_walker<PREC>(st, t.idx, st.ctl[0], st.sync_attempts, smem);
+        sweep_walker<PREC, false, true>(st, t.idx, st.ctl[0], st.sync_attempts, smem);
         __syncthreads();
     }
 }
@@ -1269,7 +1291,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
             if (ti >= nt) break;
             const BatchTask t = tasks[lo + ti];
             const DevState &st = descs[t.inst];
-            sweep_walker<PREC, true>(st, t.idx, st.ctl[0], st.sync_attempts, mine);
+            sweep_walker<PREC, true, true>(st, t.idx, st.ctl[0], st.sync_attempts, mine);
             walker_sync<true>();
         }
     }

@@ -37,8 +37,8 @@ int tag_entries(int N, size_t lds_free) {
     return t;
 }
 
-size_t sweep_state_lds(int Npad, int Wpad) {
-    return (size_t)Npad + (size_t)Wpad * 12;
+size_t sweep_state_lds(int Npad, int Wpad, bool lng_in_lds) {
+    return (size_t)Npad + (lng_in_lds ? (size_t)Wpad * 12 : 0);
 }
 
 }  // namespace rewl_host
