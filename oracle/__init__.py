@@ -41,6 +41,22 @@ def lib():
         L.orc_bootstrap.argtypes = [i32, i32, i32, P, i32, i32, P, P, dbl, i32, u64, P, i32, dbl, dbl,
                                     P, P, P, P, P, P]
         L.orc_bootstrap.restype = i32
+        L.orc_create_lipid.restype = P
+        L.orc_create_lipid.argtypes = [i32, i32, ctypes.c_float, dbl, u32, dbl, dbl, i32, i32, dbl, i32, u64, u32,
+                                       u32, u32, dbl, dbl, i32, i64, i32, i32, i32, P]
+        L.orc_lipid_energy.argtypes = [P, i32]
+        L.orc_lipid_energy.restype = dbl
+        L.orc_log_poly.argtypes = [dbl]
+        L.orc_log_poly.restype = dbl
+        L.orc_lipid_pair.argtypes = [P, i32, i32, i32, dbl]
+        L.orc_lipid_pair.restype = dbl
+        L.orc_lipid_state.argtypes = [P, i32, P, P, P]
+        L.orc_lipid_state.restype = None
+        L.orc_lipid_delta_move.argtypes = [P, i32, i32, P]
+        L.orc_lipid_delta_move.restype = dbl
+        L.orc_lipid_reptate.argtypes = [P, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(dbl)]
+        L.orc_lipid_reptate.restype = i32
         L.orc_get_shadow.argtypes = [P, i32, P, P]
         L.orc_get_replicas.argtypes = [P, P, P]
         L.orc_get_replicas.restype = None
@@ -200,6 +216,15 @@ def run_pieces(o):
     return pieces, vis
 
 
+def rep_threshold(p):
+    """32-bit threshold of a reptation probability p: a move is a reptation when its word is below it."""
+    return min(int(round(p * 2.0**32)), 2**32 - 1)
+
+
+def log_poly(x):
+    return lib().orc_log_poly(float(x))
+
+
 def obs_thermo(lng, mu, e_first, T, de=1.0):
     """Canonical average of an observable from ln g(E) and its microcanonical mean mu(E)."""
     g = np.ascontiguousarray(lng, dtype=np.float64)
@@ -269,6 +294,61 @@ class Rewl:
         self.starts = np.zeros(windows, dtype=np.int32)
         lib().orc_starts(self.h_, _ptr(self.starts))
         return self
+
+    @classmethod
+    def lipid(cls, nlip, nsol, box, e_min, bin_w, bins, windows, overlap, walkers, init_coords, eps_ww=1.0,
+              rep_prob=None, seed=1, instance=0, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
+              sync_attempts=1000, exchange=1, fixed_lnf=0, walkin_slack=16, threads=1):
+        """REWL run of the lipid model with explicit solvent; init_coords float32 [walkers, np, 3].
+
+        rep_prob: reptation probability per update (default 3 nlip / (10 np))."""
+        self = cls.__new__(cls)
+        np_ = 3 * nlip + nsol
+        self.h, self.m, self.precision, self.nlip, self.np = windows, walkers, 0, nlip, np_
+        self.obs_bins = 0
+        if rep_prob is None:
+            rep_prob = 3.0 * nlip / (10.0 * np_)
+        self.rep_thr = rep_threshold(rep_prob)
+        x = np.ascontiguousarray(init_coords, dtype=np.float32).reshape(-1)
+        if x.size != windows * walkers * np_ * 3:
+            raise ValueError("init_coords must hold np particles x 3 coordinates per walker")
+        self._keep = x
+        self.h_ = lib().orc_create_lipid(nlip, nsol, box, eps_ww, self.rep_thr, e_min, bin_w, bins, windows,
+                                         overlap, walkers, seed, instance, flat[0], flat[1], lnf_init, lnf_final,
+                                         schedule, sync_attempts, exchange, fixed_lnf, walkin_slack, _ptr(x))
+        if not self.h_:
+            raise ValueError("oracle rejected the parameters")
+        lib().orc_set_threads(self.h_, threads)
+        info = self.info()
+        self.N, self.W, self.B, self.e_lo, self.nw = info[:5]
+        self.starts = np.zeros(windows, dtype=np.int32)
+        lib().orc_starts(self.h_, _ptr(self.starts))
+        return self
+
+    def lipid_state(self, w):
+        """(coords float32 [np, 3], types int8 [np] (0 P, 1 H, 2 W), lipids int32 [nlip, 3])."""
+        x = np.zeros((self.np, 3), dtype=np.float32)
+        t = np.zeros(self.np, dtype=np.int8)
+        lp = np.zeros((self.nlip, 3), dtype=np.int32)
+        lib().orc_lipid_state(self.h_, w, _ptr(x), _ptr(t), _ptr(lp))
+        return x, t, lp
+
+    def lipid_energy(self, w):
+        return lib().orc_lipid_energy(self.h_, w)
+
+    def lipid_delta_move(self, w, b, xn):
+        return lib().orc_lipid_delta_move(self.h_, w, b, _ptr(np.ascontiguousarray(xn, dtype=np.float32)))
+
+    def lipid_reptate(self, w, lipid, end, pick):
+        """Apply a reptation; returns (n_c, n_r, energy change) or None if no solvent is near that end."""
+        nc, nr, de = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        if not lib().orc_lipid_reptate(self.h_, w, lipid, end, pick, ctypes.byref(nc), ctypes.byref(nr),
+                                       ctypes.byref(de)):
+            return None
+        return nc.value, nr.value, de.value
+
+    def lipid_pair(self, ti, tj, bonded, r2):
+        return lib().orc_lipid_pair(self.h_, ti, tj, bonded, r2)
 
     def energy(self, w):
         """Current energy of walker w (the trimer model's continuous energy)."""

@@ -38,7 +38,7 @@ enum { ORC_OK = 0, ORC_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENOMEM = -2,
 enum { DOM_MOVE = 0, DOM_WALKIN = 2, DOM_EXCH = 3, DOM_MOVE_U = 5, DOM_WALKIN_U = 6, DOM_BOOT = 7 };
 
 /* Models. */
-enum { MODEL_POTTS2D = 0, MODEL_TRIMER3D = 1 };
+enum { MODEL_POTTS2D = 0, MODEL_TRIMER3D = 1, MODEL_LIPID3D = 2 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and
@@ -193,7 +193,15 @@ typedef struct {
     int nmol, nb;
     float box;
     double e_min, bin_w;
-    double *Ed;            /* [nw] continuous energy of each walker (trimer)  */
+    double *Ed;            /* [nw] continuous energy of each walker (trimer, lipid) */
+    /* lipid model (explicit solvent): np particles, nlip P-H-H lipids, the
+     * rest solvent W; per-walker bytes: coordinates float[np][3], types
+     * int8[np] (padded to 4), lipid table int32[nlip][3] (head first),
+     * position table int32[np] (3 lipid + bead, -1 for solvent)            */
+    int np, nlip;
+    double eps_ww;         /* W-W Lennard-Jones depth                         */
+    uint32_t rep_thr;      /* reptation when a 32-bit word is below this      */
+    size_t off_type, off_lip, off_where;
     int L, q, N;
     int h, m, nw;          /* windows, walkers per window, walkers            */
     int W, B, e_lo;        /* bins per window, global bins, lowest energy     */
@@ -729,10 +737,472 @@ orc_t *orc_create_trimer(int nmol, float box, double e_min, double bin_w, int bi
 
 /* Test exports of the trimer model. */
 double orc_trimer_energy(const orc_t *o, int w) { return tri_energy(o, (const float *)(o->spin + (size_t)w * o->N)); }
-double orc_get_energy(const orc_t *o, int w) { return o->model == MODEL_TRIMER3D ? o->Ed[w] : (double)o->E[w]; }
+double orc_get_energy(const orc_t *o, int w) { return o->model != MODEL_POTTS2D ? o->Ed[w] : (double)o->E[w]; }
 double orc_trimer_delta(const orc_t *o, int w, int b, const float *xn)
 {
     return tri_delta_e(o, (const float *)(o->spin + (size_t)w * o->N), b, xn);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lipid model with explicit solvent (Sec. 3.2, Eqs. (3)-(5), Fig. 5).
+ * Particles: nlip amphiphiles of a polar head P and two hydrophobic tails H
+ * (P-H-H), the rest solvent W, in a periodic cube.  Non-bonded pairs: H-W
+ * and H-P repel by 4 (1.05/r)^9 (Eq. 3); all other pairs (H-H, P-P, P-W,
+ * W-W) are Lennard-Jones 4 eps (r^-12 - r^-6) (Eq. 4) with eps = 1, or
+ * eps_ww for W-W; both cut at r = 2.5 without shift.  Bonded neighbours of a
+ * lipid: FENE with K = 30, R = 1.3 plus the WCA repulsion (LJ + 1 below
+ * 2^(1/6), 0 above) (Eq. 5); r >= R is forbidden.  Moves: with probability
+ * rep_thr / 2^32 a reptation (Fig. 5), else a displacement of one particle
+ * by 0.1 (2u - 1) per axis.  Reptation: a lipid and one of its ends are
+ * drawn; one of the n_c solvent particles within R of that end is captured
+ * and becomes the new end bead, the lipid's beads shift along the chain and
+ * the bead at the other end is released as solvent; positions do not
+ * change.  The reverse move would capture the released particle among the
+ * n_r solvent particles within R of the new end next to it, so the
+ * acceptance carries the ratio of selection probabilities n_c / n_r.      */
+static const double LIP_RC2 = 6.25;                      /* 2.5^2                 */
+static const double LIP_WCA_RC2 = 0x1.428a2f98d728bp+0;  /* RN(2^(1/3))           */
+static const double LIP_R2 = 1.69;                       /* FENE R^2, R = 1.3     */
+static const double LIP_SQRT2 = 0x1.6a09e667f3bcdp+0;    /* RN(sqrt 2)            */
+enum { LIP_P = 0, LIP_H = 1, LIP_W = 2 };
+
+/* Natural logarithm of a positive normal x from basic IEEE operations: x =
+ * 2^k m with m in [sqrt(1/2), sqrt(2)), f = (m - 1)/(m + 1), ln m = 2 atanh f
+ * = 2 f (1 + s/3 + s^2/5 + ... + s^12/25) with s = f^2 by Horner (no fused
+ * operations; coefficients 1/(2n + 1) rounded once), and ln x = k C1 +
+ * (k C2 + ln m) with the Cody-Waite split of ln 2 used by exp_poly.         */
+static double log_poly(double x)
+{
+    int k;
+    double m = frexp(x, &k);
+    m = m * 2.0;
+    k -= 1;
+    if (m > LIP_SQRT2) { m = m * 0.5; k += 1; }
+    double f = (m - 1.0) / (m + 1.0);
+    double s2 = f * f;
+    double p = 1.0 / 25.0;
+    for (int n = 11; n >= 0; --n) {
+        double t = s2 * p;
+        p = 1.0 / (double)(2 * n + 1) + t;
+    }
+    double lm = (2.0 * f) * p;
+    return (double)k * ORC_LN2_C1 + ((double)k * ORC_LN2_C2 + lm);
+}
+
+static float *lip_x(const orc_t *o, int w) { return (float *)(o->spin + (size_t)w * o->N); }
+static int8_t *lip_type(const orc_t *o, int w) { return (int8_t *)(o->spin + (size_t)w * o->N + o->off_type); }
+static int32_t *lip_lip(const orc_t *o, int w) { return (int32_t *)(o->spin + (size_t)w * o->N + o->off_lip); }
+static int32_t *lip_where(const orc_t *o, int w) { return (int32_t *)(o->spin + (size_t)w * o->N + o->off_where); }
+
+/* Squared minimum-image distance (per-axis difference in binary32). */
+static double lip_r2(float box, const float *a, const float *b)
+{
+    double d[3];
+    tri_min_image(box, a, b, d);
+    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+/* Pair energy of particles of types ti, tj at squared distance r2; bonded
+ * marks consecutive beads of one lipid.                                     */
+static double lip_pair(const orc_t *o, int ti, int tj, int bonded, double r2)
+{
+    if (bonded) {
+        if (r2 >= LIP_R2) return INFINITY;
+        double fene = -(0.5 * 30.0 * 1.69) * log_poly(1.0 - r2 / LIP_R2);
+        double wca = 0.0;
+        if (r2 < LIP_WCA_RC2) {
+            double s2 = 1.0 / r2;
+            double s6 = (s2 * s2) * s2;
+            wca = 4.0 * ((s6 * s6) - s6) + 1.0;
+        }
+        return fene + wca;
+    }
+    if (r2 >= LIP_RC2) return 0.0;
+    int rep = (ti == LIP_H && tj != LIP_H) || (tj == LIP_H && ti != LIP_H);
+    if (rep) {
+        double q = 1.05 / sqrt(r2);
+        double q3 = (q * q) * q;
+        return 4.0 * ((q3 * q3) * q3);
+    }
+    double s2 = 1.0 / r2;
+    double s6 = (s2 * s2) * s2;
+    double v = 4.0 * ((s6 * s6) - s6);
+    return (ti == LIP_W && tj == LIP_W) ? o->eps_ww * v : v;
+}
+
+static int lip_bonded(const int32_t *where, int i, int j)
+{
+    int a = where[i], b = where[j];
+    if (a < 0 || b < 0 || a / 3 != b / 3) return 0;
+    return (a - b == 1) || (b - a == 1);
+}
+
+/* Energy of the pair (i, j) with particle i at xi. */
+static double lip_pair_ij(const orc_t *o, const float *x, const int8_t *type, const int32_t *where, int i,
+                          const float *xi, int j)
+{
+    return lip_pair(o, type[i], type[j], lip_bonded(where, i, j), lip_r2(o->box, xi, x + 3 * j));
+}
+
+/* Total energy, pairs i < j in order (creation and tests only). */
+static double lip_energy(const orc_t *o, int w)
+{
+    const float *x = lip_x(o, w);
+    const int8_t *type = lip_type(o, w);
+    const int32_t *where = lip_where(o, w);
+    double e = 0.0;
+    for (int i = 0; i < o->np; ++i)
+        for (int j = i + 1; j < o->np; ++j) e = e + lip_pair_ij(o, x, type, where, i, x + 3 * i, j);
+    return e;
+}
+
+/* Fixed summation order of an energy change from partner terms t_j,
+ * j = 0 .. np-1: per lane l = j mod 64 left to right over j, then lanes
+ * halving (l += l + h for h = 32 .. 1), as for the trimer model.             */
+static double lip_reduce(double *t, int np)
+{
+    int slots = (np + 63) / 64 * 64;
+    double s[64];
+    for (int l = 0; l < 64; ++l) {
+        double acc = 0.0;
+        for (int j = l; j < slots; j += 64) {
+            double v = j < np ? t[j] : 0.0;
+            acc = j == l ? v : acc + v;
+        }
+        s[l] = acc;
+    }
+    for (int h = 32; h >= 1; h /= 2)
+        for (int l = 0; l < h; ++l) s[l] = s[l] + s[l + h];
+    return s[0];
+}
+
+/* Energy change of displacing particle b to xn: t_j = V(b at xn, j) - V(b, j). */
+static double lip_delta_move(const orc_t *o, int w, int b, const float *xn, double *t)
+{
+    const float *x = lip_x(o, w);
+    const int8_t *type = lip_type(o, w);
+    const int32_t *where = lip_where(o, w);
+    for (int j = 0; j < o->np; ++j) {
+        t[j] = 0.0;
+        if (j != b)
+            t[j] = lip_pair_ij(o, x, type, where, b, xn, j) - lip_pair_ij(o, x, type, where, b, x + 3 * b, j);
+    }
+    return lip_reduce(t, o->np);
+}
+
+/* A reptation proposal: the four particles whose role changes (captured,
+ * and the lipid's three beads), sorted ascending, with their new types and
+ * positions in the chain; the new lipid row; n_c and n_r.                   */
+typedef struct {
+    int c[4];
+    int8_t nt[4];
+    int32_t nwh[4];
+    int32_t nlip[3];
+    int lipid, nc, nr;
+} lip_rep_t;
+
+/* Solvent particles within R of particle e under the given types (counted
+ * in index order); if pick >= 0, the pick-th of them is returned in *found. */
+static int lip_near_solvent(const orc_t *o, const float *x, const int8_t *type, int e, int pick, int *found)
+{
+    int n = 0;
+    for (int j = 0; j < o->np; ++j) {
+        if (j == e || type[j] != LIP_W) continue;
+        if (lip_r2(o->box, x + 3 * e, x + 3 * j) < LIP_R2) {
+            if (n == pick) *found = j;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* Build the reptation of `lipid` at its head (end 0) or tail (end 1), the
+ * captured particle being the pick_word-selected solvent particle near that
+ * end.  Returns 0 (no proposal) when no solvent particle is within R.       */
+static int lip_reptation(const orc_t *o, int w, int lipid, int end, uint32_t pick_word, lip_rep_t *rp)
+{
+    const float *x = lip_x(o, w);
+    const int8_t *type = lip_type(o, w);
+    const int32_t *lp = lip_lip(o, w) + 3 * lipid;
+    int e = end == 0 ? lp[0] : lp[2];
+    int nc = lip_near_solvent(o, x, type, e, -1, NULL);
+    if (nc == 0) return 0;
+    int cap = -1;
+    lip_near_solvent(o, x, type, e, (int)(((uint64_t)pick_word * (uint64_t)nc) >> 32), &cap);
+    int nl[3], rel;
+    if (end == 0) { nl[0] = cap; nl[1] = lp[0]; nl[2] = lp[1]; rel = lp[2]; }
+    else          { nl[0] = lp[1]; nl[1] = lp[2]; nl[2] = cap; rel = lp[0]; }
+    int all[4] = { cap, lp[0], lp[1], lp[2] };
+    for (int a = 1; a < 4; ++a)                 /* sort ascending */
+        for (int b = a; b > 0 && all[b - 1] > all[b]; --b) { int t = all[b]; all[b] = all[b - 1]; all[b - 1] = t; }
+    for (int a = 0; a < 4; ++a) {
+        int p = all[a];
+        rp->c[a] = p;
+        if (p == rel) { rp->nt[a] = LIP_W; rp->nwh[a] = -1; }
+        else {
+            int pos = p == nl[0] ? 0 : (p == nl[1] ? 1 : 2);
+            rp->nt[a] = pos == 0 ? LIP_P : LIP_H;
+            rp->nwh[a] = 3 * lipid + pos;
+        }
+    }
+    for (int a = 0; a < 3; ++a) rp->nlip[a] = nl[a];
+    rp->lipid = lipid;
+    rp->nc = nc;
+    /* n_r: solvent near the new end next to the released particle (lp[1]) */
+    int8_t *t2 = (int8_t *)malloc((size_t)o->np);
+    memcpy(t2, type, (size_t)o->np);
+    for (int a = 0; a < 4; ++a) t2[rp->c[a]] = rp->nt[a];
+    rp->nr = lip_near_solvent(o, x, t2, lp[1], -1, NULL);
+    free(t2);
+    return 1;
+}
+
+/* Energy change of a reptation: t_j = sum over changed particles i (ascending,
+ * i != j, and i < j when j is changed too) of V_new(i, j) - V_old(i, j).    */
+static double lip_delta_rep(const orc_t *o, int w, const lip_rep_t *rp, double *t)
+{
+    const float *x = lip_x(o, w);
+    const int8_t *type = lip_type(o, w);
+    const int32_t *where = lip_where(o, w);
+    int8_t *nt = (int8_t *)malloc((size_t)o->np);
+    int32_t *nw = (int32_t *)malloc((size_t)o->np * sizeof(int32_t));
+    memcpy(nt, type, (size_t)o->np);
+    memcpy(nw, where, (size_t)o->np * sizeof(int32_t));
+    for (int a = 0; a < 4; ++a) { nt[rp->c[a]] = rp->nt[a]; nw[rp->c[a]] = rp->nwh[a]; }
+    for (int j = 0; j < o->np; ++j) {
+        int jin = j == rp->c[0] || j == rp->c[1] || j == rp->c[2] || j == rp->c[3];
+        double acc = 0.0;
+        int first = 1;
+        for (int a = 0; a < 4; ++a) {
+            int i = rp->c[a];
+            if (i == j || (jin && i > j)) continue;
+            double r2 = lip_r2(o->box, x + 3 * i, x + 3 * j);
+            double v = lip_pair(o, nt[i], nt[j], lip_bonded(nw, i, j), r2) -
+                       lip_pair(o, type[i], type[j], lip_bonded(where, i, j), r2);
+            acc = first ? v : acc + v;
+            first = 0;
+        }
+        t[j] = acc;
+    }
+    free(nt); free(nw);
+    return lip_reduce(t, o->np);
+}
+
+static void lip_apply_rep(orc_t *o, int w, const lip_rep_t *rp)
+{
+    int8_t *type = lip_type(o, w);
+    int32_t *where = lip_where(o, w);
+    for (int a = 0; a < 4; ++a) { type[rp->c[a]] = rp->nt[a]; where[rp->c[a]] = rp->nwh[a]; }
+    for (int a = 0; a < 3; ++a) lip_lip(o, w)[3 * rp->lipid + a] = rp->nlip[a];
+}
+
+/* Acceptance of a reptation with Wang-Landau weights and the selection
+ * ratio: accept with probability min[1, e^d n_c / n_r], d = ln g(old) -
+ * ln g(new), decided with u = r / 2^32 as
+ *   d >= 0:  (u n_r) exp_poly(-d) < n_c,     d < 0:  u n_r < exp_poly(d) n_c. */
+static int lip_accept_rep(double d, uint32_t r, int nc, int nr)
+{
+    double u = (double)r * 0x1p-32;
+    if (d >= 0.0) return (u * (double)nr) * exp_poly(-d) < (double)nc;
+    return u * (double)nr < exp_poly(d) * (double)nc;
+}
+
+/* One lipid-model attempt of walker w from Philox blocks (cnt, w, dom) and
+ * (cnt, w, domu): block words a0 particle (or lipid), a1..a3 displacement;
+ * u0 acceptance, u1 move type, u2 end (top bit), u3 captured particle.
+ * lng_of(b) gives the walker's ln g at bin b; returns 1 if accepted.        */
+typedef struct { double e_new; int bn; int ok; int is_rep; lip_rep_t rp; int b; float xn[3]; int nc, nr; } lip_prop_t;
+
+static void lip_propose(const orc_t *o, int w, uint64_t cnt, uint32_t dom, uint32_t domu, uint32_t u_out[4],
+                        lip_prop_t *pr, double *t)
+{
+    uint32_t ctr[4] = { (uint32_t)cnt, (uint32_t)(cnt >> 32), (uint32_t)w, (dom << 24) | o->instance };
+    uint32_t a[4];
+    philox4x32_10(ctr, o->key, a);
+    ctr[3] = (domu << 24) | o->instance;
+    philox4x32_10(ctr, o->key, u_out);
+    pr->ok = 0;
+    pr->is_rep = u_out[1] < o->rep_thr;
+    double de;
+    if (pr->is_rep) {
+        int lipid = (int)(((uint64_t)a[0] * (uint64_t)o->nlip) >> 32);
+        if (!lip_reptation(o, w, lipid, (int)(u_out[2] >> 31), u_out[3], &pr->rp)) return;
+        de = lip_delta_rep(o, w, &pr->rp, t);
+    } else {
+        const float *x = lip_x(o, w);
+        pr->b = (int)(((uint64_t)a[0] * (uint64_t)o->np) >> 32);
+        for (int c = 0; c < 3; ++c) pr->xn[c] = tri_wrap(x[3 * pr->b + c] + tri_disp(a[1 + c]), o->box);
+        de = lip_delta_move(o, w, pr->b, pr->xn, t);
+    }
+    if (!isfinite(de)) return;              /* a bond stretched to R or beyond */
+    pr->e_new = o->Ed[w] + de;
+    pr->bn = tri_bin(o, pr->e_new);
+    pr->ok = 1;
+}
+
+static void lip_apply(orc_t *o, int w, const lip_prop_t *pr)
+{
+    if (pr->is_rep) lip_apply_rep(o, w, &pr->rp);
+    else {
+        float *x = lip_x(o, w);
+        for (int c = 0; c < 3; ++c) x[3 * pr->b + c] = pr->xn[c];
+    }
+    o->Ed[w] = pr->e_new;
+    o->E[w] = pr->bn;
+}
+
+static int lip_decide(const lip_prop_t *pr, double d, uint32_t u0)
+{
+    return pr->is_rep ? lip_accept_rep(d, u0, pr->rp.nc, pr->rp.nr) : accept64(d, u0);
+}
+
+static void lipid_attempt(orc_t *o, int w, int k, double lnf, uint64_t cnt, double *t)
+{
+    int W = o->W;
+    uint32_t u[4];
+    lip_prop_t pr;
+    lip_propose(o, w, cnt, DOM_MOVE, DOM_MOVE_U, u, &pr, t);
+    int lo = o->start[k], hi = o->start[k] + W - 1;
+    if (pr.ok && pr.bn >= lo && pr.bn <= hi) {
+        size_t io = (size_t)w * W + (o->E[w] - lo), in = (size_t)w * W + (pr.bn - lo);
+        if (lip_decide(&pr, o->lng[io] - o->lng[in], u[0])) lip_apply(o, w, &pr);
+    }
+    size_t ib = (size_t)w * W + (o->E[w] - lo);
+    o->lng[ib] += lnf;
+    o->H[ib] += 1u;
+    if (!o->finished[k]) o->vis[ib] = 1;
+}
+
+/* Walk-in of a lipid walker: the trimer walk-in rule with the lipid moves. */
+static int lipid_walkin(orc_t *o, int w, int64_t max_attempts)
+{
+    int k = w / o->m;
+    int lo = o->start[k], hi = o->start[k] + o->W - 1;
+    double *g = (double *)calloc((size_t)o->B, sizeof(double));
+    double *t = (double *)malloc((size_t)o->np * sizeof(double));
+    if (!g || !t) { free(g); free(t); return ORC_ENOMEM; }
+    int64_t n = 0;
+    int slack = o->walkin_slack;
+    int down = o->E[w] > hi;
+    int bound = down ? o->E[w] + slack : o->E[w] - slack;
+    int status = ORC_OK;
+    while (!(o->E[w] >= lo && o->E[w] <= hi)) {
+        if (n >= max_attempts) { status = ORC_EBUDGET; break; }
+        uint32_t u[4];
+        lip_prop_t pr;
+        lip_propose(o, w, (uint64_t)n, DOM_WALKIN, DOM_WALKIN_U, u, &pr, t);
+        if (pr.ok) {
+            int co = o->E[w] < 0 ? 0 : (o->E[w] >= o->B ? o->B - 1 : o->E[w]);
+            int cn = pr.bn < 0 ? 0 : (pr.bn >= o->B ? o->B - 1 : pr.bn);
+            int inside = slack == 0 || (down ? pr.bn <= bound : pr.bn >= bound);
+            if (inside && lip_decide(&pr, g[co] - g[cn], u[0])) {
+                lip_apply(o, w, &pr);
+                if (slack && down && o->E[w] + slack < bound) bound = o->E[w] + slack;
+                if (slack && !down && o->E[w] - slack > bound) bound = o->E[w] - slack;
+            }
+        }
+        int ci = o->E[w] < 0 ? 0 : (o->E[w] >= o->B ? o->B - 1 : o->E[w]);
+        g[ci] += 1.0;
+        ++n;
+    }
+    o->walkin_att[w] = n;
+    free(g); free(t);
+    return status;
+}
+
+/* Create a REWL run of the lipid model: nlip lipids and nsol solvent
+ * particles in a periodic cube of side box; particles 3i, 3i+1, 3i+2 start as
+ * lipid i (head, tail, tail), the rest as solvent.  rep_thr: reptation when
+ * a word is below it (2^32 * 3 nlip / (10 np) in the paper's protocol).
+ * Energy bins and windows as for the trimer model; binary64 ln g only.
+ * init_coords: [h*m][np][3] in [0, box).  NULL on invalid arguments.        */
+orc_t *orc_create_lipid(int nlip, int nsol, float box, double eps_ww, uint32_t rep_thr, double e_min,
+                        double bin_w, int bins, int h, double overlap, int m, uint64_t seed, uint32_t instance,
+                        uint32_t flat_num, uint32_t flat_den, double lnf_init, double lnf_final, int schedule,
+                        int64_t sync_attempts, int exchange, int fixed_lnf, int walkin_slack,
+                        const float *init_coords)
+{
+    if (nlip < 1 || nsol < 0 || nlip * 3 + nsol > 4096 || !(box > 0.0f) || !(bin_w > 0.0) || bins < 8 ||
+        !init_coords || !(eps_ww >= 0.0))
+        return NULL;
+    int np = 3 * nlip + nsol;
+    size_t off_type = (size_t)np * 12;
+    size_t off_lip = off_type + ((size_t)np + 3) / 4 * 4;
+    size_t off_where = off_lip + (size_t)nlip * 12;
+    size_t bytes = off_where + (size_t)np * 4;
+    orc_t *o = orc_new(bins, 0, (int)bytes, h, overlap, m, seed, instance, flat_num, flat_den, lnf_init,
+                       lnf_final, schedule, sync_attempts, exchange, 0, fixed_lnf, 0, walkin_slack);
+    if (!o) return NULL;
+    o->model = MODEL_LIPID3D;
+    o->np = np; o->nlip = nlip; o->box = box; o->eps_ww = eps_ww; o->rep_thr = rep_thr;
+    o->e_min = e_min; o->bin_w = bin_w;
+    o->off_type = off_type; o->off_lip = off_lip; o->off_where = off_where;
+    o->Ed = (double *)calloc((size_t)o->nw, sizeof(double));
+    if (!o->Ed) { orc_free(o); return NULL; }
+    for (int w = 0; w < o->nw; ++w) {
+        float *x = lip_x(o, w);
+        for (int i = 0; i < 3 * np; ++i) {
+            float v = init_coords[(size_t)w * 3 * np + i];
+            if (!(v >= 0.0f && v < box)) { orc_free(o); return NULL; }
+            x[i] = v;
+        }
+        int8_t *type = lip_type(o, w);
+        int32_t *where = lip_where(o, w), *lp = lip_lip(o, w);
+        for (int i = 0; i < np; ++i) {
+            int lipid = i < 3 * nlip;
+            type[i] = lipid ? (i % 3 == 0 ? LIP_P : LIP_H) : LIP_W;
+            where[i] = lipid ? i : -1;
+        }
+        for (int i = 0; i < 3 * nlip; ++i) lp[i] = i;
+        o->Ed[w] = lip_energy(o, w);
+        if (!isfinite(o->Ed[w])) { orc_free(o); return NULL; }
+        o->E[w] = tri_bin(o, o->Ed[w]);
+    }
+    return o;
+}
+
+/* Test exports of the lipid model. */
+double orc_lipid_energy(const orc_t *o, int w) { return lip_energy(o, w); }
+double orc_log_poly(double x) { return log_poly(x); }
+double orc_lipid_pair(const orc_t *o, int ti, int tj, int bonded, double r2) { return lip_pair(o, ti, tj, bonded, r2); }
+
+/* Particles of walker w: coordinates [np][3], types [np], lipid rows [nlip][3]. */
+void orc_lipid_state(const orc_t *o, int w, float *x, int8_t *type, int32_t *lip)
+{
+    if (x) memcpy(x, lip_x(o, w), (size_t)o->np * 12);
+    if (type) memcpy(type, lip_type(o, w), (size_t)o->np);
+    if (lip) memcpy(lip, lip_lip(o, w), (size_t)o->nlip * 12);
+}
+
+/* Energy change of displacing particle b of walker w to xn (no state change). */
+double orc_lipid_delta_move(const orc_t *o, int w, int b, const float *xn)
+{
+    double *t = (double *)malloc((size_t)o->np * sizeof(double));
+    double d = lip_delta_move(o, w, b, xn, t);
+    free(t);
+    return d;
+}
+
+/* Apply the reptation of `lipid` at `end` capturing the pick-th nearby
+ * solvent particle (the word pick * 2^32 / n_c selects it); out: n_c, n_r,
+ * energy change.  Returns 0 if no solvent particle is near that end.       */
+int orc_lipid_reptate(orc_t *o, int w, int lipid, int end, int pick, int *nc, int *nr, double *de)
+{
+    const float *x = lip_x(o, w);
+    int e = end == 0 ? lip_lip(o, w)[3 * lipid] : lip_lip(o, w)[3 * lipid + 2];
+    int n = lip_near_solvent(o, x, lip_type(o, w), e, -1, NULL);
+    if (n == 0 || pick < 0 || pick >= n) return 0;
+    uint32_t word = (uint32_t)((((uint64_t)pick << 32) + (uint64_t)n - 1) / (uint64_t)n);
+    lip_rep_t rp;
+    if (!lip_reptation(o, w, lipid, end, word, &rp)) return 0;
+    double *t = (double *)malloc((size_t)o->np * sizeof(double));
+    double d = lip_delta_rep(o, w, &rp, t);
+    free(t);
+    lip_apply_rep(o, w, &rp);
+    o->Ed[w] += d;
+    o->E[w] = tri_bin(o, o->Ed[w]);
+    *nc = rp.nc; *nr = rp.nr; *de = d;
+    return 1;
 }
 
 /* Placement before the run: each walker must carry a configuration whose
@@ -755,8 +1225,9 @@ int orc_walkin(orc_t *o, int64_t max_attempts)
     (void)nt;
 #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
     for (int w = 0; w < o->nw; ++w) {
-        if (o->model == MODEL_TRIMER3D) {
-            int st = trimer_walkin(o, w, max_attempts);
+        if (o->model == MODEL_TRIMER3D || o->model == MODEL_LIPID3D) {
+            int st = o->model == MODEL_TRIMER3D ? trimer_walkin(o, w, max_attempts)
+                                                : lipid_walkin(o, w, max_attempts);
             if (st != ORC_OK) {
 #pragma omp atomic write
                 status = st;
@@ -1143,7 +1614,11 @@ int orc_run(orc_t *o, int64_t attempts, int64_t walkin_budget)
         for (int w = 0; w < o->nw; ++w) {
             int k = w / o->m;
             double lnf = o->lnf[k];
-            if (o->model == MODEL_TRIMER3D)
+            if (o->model == MODEL_LIPID3D) {
+                double *tb = (double *)malloc((size_t)o->np * sizeof(double));
+                for (int64_t t = 0; t < seg; ++t) lipid_attempt(o, w, k, lnf, (uint64_t)(s0 + t), tb);
+                free(tb);
+            } else if (o->model == MODEL_TRIMER3D)
                 for (int64_t t = 0; t < seg; ++t) trimer_attempt(o, w, k, lnf, (uint64_t)(s0 + t));
             else
                 for (int64_t t = 0; t < seg; ++t) potts_attempt(o, w, k, lnf, DOM_MOVE, (uint64_t)(s0 + t));

@@ -891,3 +891,167 @@ def test_bootstrap_spread_matches_the_spread_of_independent_runs():
     ratio = np.median(out["lng_std"][fin] / direct)
     assert 0.8 < ratio < 1.25, ratio
     assert np.all(out["U_std"] > 0) and np.all(out["C_std"] > 0)
+
+
+# --------------------------------------------------------------------------
+# Lipid model with explicit solvent (Sec. 3.2, Eqs. (3)-(5), Fig. 5).
+
+P_, H_, W_ = 0, 1, 2
+
+
+def _lipid_small(nlip=4, nsol=20, box=4.3, seed=3, walkers=1, **kw):
+    x = workloads.init_lipids(nlip, nsol, box, walkers, seed)
+    args = dict(lnf_init=0.0, fixed_lnf=1, sync_attempts=10**9)
+    args.update(kw)
+    return oracle.Rewl.lipid(nlip, nsol, box, -2000.0, 1.0, 6000, 1, 0.0, walkers, x, **args), x
+
+
+def _np_pair(ti, tj, bonded, r2, eps_ww=1.0):
+    """Eqs. (3)-(5) written out with mpmath-grade numpy (independent of the oracle)."""
+    if bonded:
+        if r2 >= 1.69:
+            return np.inf
+        v = -0.5 * 30.0 * 1.69 * math.log(1.0 - r2 / 1.69)
+        if r2 < 2 ** (1 / 3):
+            v += 4.0 * (r2 ** -6 - r2 ** -3) + 1.0
+        return v
+    if r2 >= 6.25:
+        return 0.0
+    if (ti == H_) != (tj == H_):
+        return 4.0 * (1.05 ** 2 / r2) ** 4.5
+    v = 4.0 * (r2 ** -6 - r2 ** -3)
+    return eps_ww * v if ti == W_ and tj == W_ else v
+
+
+def _np_energy(x, types, lipids, box, eps_ww=1.0):
+    n = len(types)
+    pos = {}
+    for k, row in enumerate(lipids):
+        for p, i in enumerate(row):
+            pos[int(i)] = (k, p)
+    e = 0.0
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = (x[j] - x[i]).astype(np.float32)
+            d = np.where(d > np.float32(box / 2), d - np.float32(box), np.where(d < -np.float32(box / 2),
+                                                                              d + np.float32(box), d))
+            r2 = float(np.sum(d.astype(np.float64) ** 2))
+            a, b = pos.get(i), pos.get(j)
+            bonded = a is not None and b is not None and a[0] == b[0] and abs(a[1] - b[1]) == 1
+            e += _np_pair(types[i], types[j], bonded, r2, eps_ww)
+    return e
+
+
+def test_log_poly_accuracy():
+    # the logarithm built from basic operations (FENE term of Eq. (5))
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([rng.uniform(1e-6, 1, 2000), rng.uniform(0.999, 1, 200), 10 ** rng.uniform(-15, 0, 500)])
+    for x in xs:
+        ref = float(mp.log(mp.mpf(float(x))))
+        assert abs(oracle.log_poly(x) - ref) <= 3 * np.spacing(abs(ref)) + 1e-300
+    assert oracle.log_poly(1.0) == 0.0 and oracle.log_poly(0.5) == -math.log(2.0)
+
+
+def test_lipid_potentials_closed_forms():
+    o, _ = _lipid_small(eps_ww=0.7)
+    assert o.lipid_pair(H_, W_, 0, 1.05 ** 2) == pytest.approx(4.0, rel=1e-14)   # Eq. (3) at r = sigma_rep
+    assert o.lipid_pair(H_, P_, 0, 1.05 ** 2) == pytest.approx(4.0, rel=1e-14)
+    assert o.lipid_pair(P_, W_, 0, 2 ** (1 / 3)) == pytest.approx(-1.0, rel=1e-14)  # Eq. (4) minimum
+    assert o.lipid_pair(H_, H_, 0, 2 ** (1 / 3)) == pytest.approx(-1.0, rel=1e-14)
+    assert o.lipid_pair(W_, W_, 0, 2 ** (1 / 3)) == pytest.approx(-0.7, rel=1e-14)  # eps_WW
+    assert o.lipid_pair(W_, W_, 0, 6.25) == 0.0 and o.lipid_pair(H_, W_, 0, 6.3) == 0.0
+    fene = float(-0.5 * 30 * 1.69 * mp.log(1 - mp.mpf(1) / mp.mpf("1.69")))
+    assert o.lipid_pair(P_, H_, 1, 1.0) == pytest.approx(fene + 1.0, rel=1e-14)   # Eq. (5), WCA part 1 at r = 1
+    r2 = mp.mpf("1.21")                                                         # r = 1.1 < 2^(1/6)
+    ref = -0.5 * 30 * mp.mpf("1.69") * mp.log(1 - r2 / mp.mpf("1.69")) + 4 * (r2 ** -6 - r2 ** -3) + 1
+    assert o.lipid_pair(H_, H_, 1, 1.21) == pytest.approx(float(ref), rel=1e-14)
+    r2 = mp.mpf("1.44")                                                         # r = 1.2: FENE alone
+    assert o.lipid_pair(H_, H_, 1, 1.44) == pytest.approx(float(-0.5 * 30 * mp.mpf("1.69") * mp.log(1 - r2 / mp.mpf("1.69"))), rel=1e-14)
+    assert o.lipid_pair(H_, H_, 1, 1.69) == np.inf
+    for (ti, tj, b, r2) in [(H_, W_, 0, 1.7), (W_, W_, 0, 1.2), (P_, H_, 1, 0.9), (H_, H_, 0, 2.0)]:
+        assert o.lipid_pair(ti, tj, b, r2) == pytest.approx(_np_pair(ti, tj, b, r2, 0.7), rel=1e-12)
+
+
+def test_lipid_energy_and_displacement_match_direct_sums():
+    o, x0 = _lipid_small(eps_ww=0.7)
+    x, t, lp = o.lipid_state(0)
+    assert list(t[:6]) == [P_, H_, H_, P_, H_, H_] and np.all(t[12:] == W_)
+    e = _np_energy(x, t, lp, 4.3, 0.7)
+    assert o.lipid_energy(0) == pytest.approx(e, rel=1e-10) and o.energy(0) == o.lipid_energy(0)
+    rng = np.random.default_rng(5)
+    for b in (0, 1, 2, 7, 13, 23):
+        xn = np.mod(x[b] + rng.uniform(-0.1, 0.1, 3), 4.3).astype(np.float32)
+        x2 = x.copy()
+        x2[b] = xn
+        ref = _np_energy(x2, t, lp, 4.3, 0.7) - e
+        assert o.lipid_delta_move(0, b, xn) == pytest.approx(ref, rel=1e-9, abs=1e-9)
+
+
+def _near_solvent(x, t, e, box):
+    d = x - x[e]
+    d = np.where(d > box / 2, d - box, np.where(d < -box / 2, d + box, d)).astype(np.float64)
+    r2 = np.sum(d * d, axis=1)
+    return [j for j in range(len(t)) if j != e and t[j] == W_ and r2[j] < 1.69]
+
+
+def test_lipid_reptation_moves_bonds_types_and_reverses():
+    # Fig. 5: a solvent particle near one end becomes the new end bead, the
+    # beads shift along the chain, the far end is released as solvent.
+    o, _ = _lipid_small(nlip=6, nsol=30, box=4.3, seed=7)
+    done = 0
+    for lipid in range(6):
+        for end in (0, 1):
+            x, t, lp = o.lipid_state(0)
+            e0 = o.energy(0)
+            cand = _near_solvent(x, t, lp[lipid][0 if end == 0 else 2], 4.3)
+            if not cand:
+                assert o.lipid_reptate(0, lipid, end, 0) is None
+                continue
+            pick = len(cand) // 2
+            cap = cand[pick]
+            nc, nr, de = o.lipid_reptate(0, lipid, end, pick)
+            x2, t2, lp2 = o.lipid_state(0)
+            old = list(lp[lipid])
+            new = [cap] + old[:2] if end == 0 else old[1:] + [cap]
+            released = old[2] if end == 0 else old[0]
+            assert list(lp2[lipid]) == new and [t2[i] for i in new] == [P_, H_, H_] and t2[released] == W_
+            assert nc == len(cand) and nr == len(_near_solvent(x2, t2, old[1], 4.3))
+            assert released in _near_solvent(x2, t2, old[1], 4.3)
+            assert de == pytest.approx(_np_energy(x2, t2, lp2, 4.3) - _np_energy(x, t, lp, 4.3), rel=1e-9, abs=1e-9)
+            # the reverse move: capture the released particle at the other end
+            back = _near_solvent(x2, t2, old[1], 4.3).index(released)
+            nc2, nr2, de2 = o.lipid_reptate(0, lipid, 1 - end, back)
+            x3, t3, lp3 = o.lipid_state(0)
+            assert np.array_equal(t3, t) and np.array_equal(lp3, lp) and (nc2, nr2) == (nr, nc)
+            assert o.energy(0) == pytest.approx(e0, abs=1e-9)
+            done += 1
+    assert done >= 4
+
+
+def test_lipid_reptation_bias_correction_gives_uniform_states():
+    # One lipid and six solvent particles frozen on a 3x3 square lattice
+    # (spacing 1: only edge neighbours are within R = 1.3), reptation moves
+    # only, flat weights: the acceptance min[1, n_c / n_r] makes every lipid
+    # placement (an ordered self-avoiding 3-site path) equally likely,
+    # although the number of candidates differs from site to site.
+    box = 8.0
+    sites = np.array([[i, j, 0.0] for j in range(3) for i in range(3)], dtype=np.float32) + 2.0
+    order = [0, 1, 2, 3, 4, 5, 6, 7, 8]
+    x = sites[order][None]
+    o = oracle.Rewl.lipid(1, 6, box, -1000.0, 1.0, 3000, 1, 0.0, 1, x, rep_prob=1.0, lnf_init=0.0, fixed_lnf=1,
+                          sync_attempts=10**9)
+    counts = {}
+    for _ in range(30000):
+        o.run(1)
+        key = tuple(o.lipid_state(0)[2][0])
+        counts[key] = counts.get(key, 0) + 1
+    # reachable placements: ordered paths of 3 edge-adjacent sites
+    adj = {s: [t for t in range(9) if abs(s % 3 - t % 3) + abs(s // 3 - t // 3) == 1] for s in range(9)}
+    paths = {(a, b, c) for a in range(9) for b in adj[a] for c in adj[b] if c != a}
+    assert set(counts) <= paths and len(counts) == len(paths)
+    freq = np.array([counts[p] for p in sorted(paths)], dtype=np.float64)
+    expected = freq.sum() / len(paths)
+    chi2 = float(np.sum((freq - expected) ** 2 / expected))
+    # correlated samples: allow a generous bound (dof = 43); a missing n_c/n_r
+    # factor drives chi2 into the thousands
+    assert chi2 < 400, chi2

@@ -46,6 +46,47 @@ TRIMER = dict(model="trimer", nmol=64, box=10.0, e_min=-460.0, bin_w=0.5, bins=1
               sync_attempts=20_000, exchange=1, precision=0, seed=1)
 
 
+def init_lipids(nlip, nsol, box, n_walkers, seed, jitter=0.05):
+    """Starting configurations of the lipid model: float32 [n_walkers, np, 3].
+
+    Particles sit on a simple cubic lattice of n = ceil(np^(1/3)) sites per
+    side (spacing a = box / n).  Lipid i (particles 3i head, 3i+1, 3i+2 tails)
+    takes three consecutive sites of one x-row, in a row slot and orientation
+    drawn at random; solvent particles take random free sites; every
+    coordinate then moves by a uniform jitter of +-jitter * a.
+    """
+    np_ = 3 * nlip + nsol
+    n = 1
+    while n ** 3 < np_:
+        n += 1
+    a = box / n
+    if nlip > n * n * (n // 3):
+        raise ValueError("too many lipids for the lattice rows")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((n_walkers, np_, 3), dtype=np.float32)
+    for w in range(n_walkers):
+        slots = [(row, k) for row in range(n * n) for k in range(n // 3)]
+        pick = rng.permutation(len(slots))[:nlip]
+        used = set()
+        sites = []
+        for i in pick:
+            row, k = slots[i]
+            run = [(row, 3 * k + t) for t in range(3)]
+            if rng.integers(2):
+                run = run[::-1]
+            used.update(run)
+            sites.extend(run)
+        free = [(row, x) for row in range(n * n) for x in range(n) if (row, x) not in used]
+        for i in rng.permutation(len(free))[:nsol]:
+            sites.append(free[i])
+        pos = np.array([[x, row % n, row // n] for row, x in sites], dtype=np.float64) * a
+        pos += rng.uniform(-jitter * a, jitter * a, size=pos.shape)
+        pos = np.mod(pos, box).astype(np.float32)
+        pos[pos >= np.float32(box)] = np.float32(0.0)
+        out[w] = pos
+    return out
+
+
 def init_trimers(nmol, box, n_walkers, seed, min_dist=0.9):
     """Starting configurations: float32 [n_walkers, 3 nmol, 3] in [0, box).
 
