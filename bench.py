@@ -152,11 +152,10 @@ def batched(args):
     print(json.dumps(out), flush=True)
 
 
-def walkin_with_progress(g, tag):
+def walkin_with_progress(g, tag, budget=1 << 22):
     """Walk-in in growing attempt budgets, logging progress (placed walkers)."""
     import paper_1312_3004_amd as pk
 
-    budget = 1 << 22
     t0 = time.perf_counter()
     while True:
         try:
@@ -280,6 +279,11 @@ def precision_study(args):
 # moved bead against each of its 191 partners; cut-off tests, potentials and
 # the sum come on top.
 TRIMER_FLOPS_PER_ATTEMPT = 2 * 191 * 5
+# Lipid model, binary64 flops of one displacement attempt: the squared
+# minimum-image distance (3 mul + 2 add) to each of the 999 partners at the
+# old and the new position, and the Lennard-Jones / r^-9 term (1 div + 5
+# mul/add) of the ~52 partners inside the 2.5 cut-off at density 0.8, twice.
+LIPID_FLOPS_PER_ATTEMPT = 2 * 999 * 5 + 2 * 52 * 6
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -338,6 +342,81 @@ def trimer(args):
         "per_walker_attempts_per_s": S * args.steps / el,
         "walkin_s": walkin_s,
     }
+    print(json.dumps(out), flush=True)
+
+
+def lipid(args):
+    """The paper's lipid system (Sec. 3.2): 125 P-H-H lipids in 625 solvent
+    particles at density 0.8, displacement and reptation moves; the CPU
+    oracle is timed on a bounded sample of the same run."""
+    import numpy as np
+    import torch
+
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    cfg = workloads.LIPID
+    h, m = cfg["windows"], cfg["walkers"]
+    nw, S = h * m, cfg["sync_attempts"]
+    np_ = 3 * cfg["nlip"] + cfg["nsol"]
+    x = workloads.init_lipids(cfg["nlip"], cfg["nsol"], cfg["box"], nw, cfg["seed"])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    kw = dict(seed=cfg["seed"], flat=cfg["flat"], lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"],
+              schedule=cfg["schedule"], sync_attempts=S, exchange=cfg["exchange"])
+    g = pk.Rewl.lipid(cfg["nlip"], cfg["nsol"], cfg["box"], cfg["e_min"], cfg["bin_w"], cfg["bins"], h,
+                      cfg["overlap"], m, x, eps_ww=cfg["eps_ww"], device=dev, **kw)
+    walkin_s = walkin_with_progress(g, "lipid", budget=1 << 13)
+    log(f"[bench] lipid walk-in done in {walkin_s:.1f} s")
+    if args.warmup:
+        g.run(args.warmup * S)
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        g.run(S)
+        if i % 20 == 19:
+            torch.cuda.synchronize()
+            log(f"[bench] lipid step {i + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sweep_ms, launches, sync_ms, syncs = g.timing()
+    g.set_timing(False)
+    value = nw * S * args.steps / el
+    avg_ms = sweep_ms / max(launches, 1)
+    flops = LIPID_FLOPS_PER_ATTEMPT
+    achieved = flops * nw * S / (avg_ms * 1e-3) / 1e12
+    reps = sum(int(not np.array_equal(g.lipid_state(w)[2], np.arange(3 * cfg["nlip"]).reshape(-1, 3)))
+               for w in range(nw))
+    out = {
+        "metric": "particle-move attempts/s (1 GPU), lipid model with explicit solvent (N=1000) REWL",
+        "value": value, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "lipid: 125 P-H-H lipids + 625 solvent particles, density 0.8, reptation "
+                               "probability 0.0375, bins of 1 over [7000, 7800), 16 windows at 75% overlap, "
+                               "4 walkers each", "walkers": nw, "attempts_per_step_per_walker": S},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_lipid_sweep",
+                     "kernel_avg_ms": avg_ms, "kernel_launches": launches, "flops_per_attempt": flops},
+        "per_walker_attempts_per_s": S * args.steps / el,
+        "walkin_s": walkin_s,
+        "walkers_with_reptated_lipids": reps,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = max(1, min(16, os.cpu_count() or 1, nw))
+        o = oracle.Rewl.lipid(cfg["nlip"], cfg["nsol"], cfg["box"], cfg["e_min"], cfg["bin_w"], cfg["bins"], h,
+                              cfg["overlap"], m, x, eps_ww=cfg["eps_ww"], threads=threads, **kw)
+        o.walkin()
+        n = 1000
+        t0 = time.perf_counter()
+        o.run(n)
+        cs = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": nw * n / cs, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+                               "sample": f"oracle walk-in (excluded) then {n:,} attempts per walker of the same "
+                                         f"workload ({nw} walkers), {threads} OpenMP threads"}
     print(json.dumps(out), flush=True)
 
 
@@ -579,13 +658,14 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
                          "times first: the reference for the HBM byte counters of a profiler run")
-    ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer", "production", "bootstrap"),
+    ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer", "production", "bootstrap",
+                                           "lipid"),
                     default="potts",
                     help="potts: the single-run workload (--config); batched: 256 instances; "
                          "precision: the L=80 workload in binary64 and in the binary32 pair form; "
                          "trimer: the continuous-move workload; production: the single-run workload "
                          "with frozen weights and H(E, O) sampling; bootstrap: error analysis over 64 "
-                         "independent L=8 runs")
+                         "independent L=8 runs; lipid: the explicit-solvent lipid system (N = 1000)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
@@ -615,6 +695,8 @@ def main():
         return production(args)
     if args.workload == "bootstrap":
         return bootstrap_bench(args)
+    if args.workload == "lipid":
+        return lipid(args)
 
     import torch
 

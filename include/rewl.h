@@ -44,7 +44,8 @@ extern "C" {
 
 typedef struct rewl rewl_t; /* opaque handle, owned by the library */
 
-enum rewl_model { REWL_POTTS2D = 0, REWL_TRIMER3D = 1 /* rewl_create_trimer */ };
+enum rewl_model { REWL_POTTS2D = 0, REWL_TRIMER3D = 1 /* rewl_create_trimer */,
+                  REWL_LIPID3D = 2 /* rewl_create_lipid */ };
 
 enum rewl_status {
     REWL_OK = 0,
@@ -109,6 +110,41 @@ int rewl_create(rewl_t **out, int model, int L, int q, int windows, double overl
                 size_t ws_bytes, void *hip_stream);
 
 void rewl_destroy(rewl_t *r);
+
+/* ---- Lipid model with explicit solvent (Sec. 3.2, Eqs. (3)-(5), Fig. 5) ---
+ * nlip lipids of a polar head P and two hydrophobic tails H (P-H-H) and nsol
+ * solvent particles W in a periodic cube of side `box`; particles 3i, 3i+1,
+ * 3i+2 start as lipid i (head first), the others as solvent.  Non-bonded
+ * pairs: H-W and H-P repel by 4 (1.05/r)^9 (Eq. 3), all other pairs are
+ * Lennard-Jones 4 eps (r^-12 - r^-6) (Eq. 4) with eps = 1, or eps_ww for
+ * W-W; both cut at r = 2.5 unshifted.  Bonded neighbours of a lipid: FENE,
+ * -0.5 K R^2 ln(1 - (r/R)^2) with K = 30, R = 1.3, plus the WCA repulsion
+ * (LJ + 1 below 2^(1/6)) (Eq. 5); r >= R is forbidden.  Moves: with
+ * probability rep_prob (a negative value selects the paper's 3 nlip /
+ * (10 np), np = 3 nlip + nsol) a reptation: a uniformly drawn lipid and end;
+ * one of the n_c solvent particles within R of that end (drawn uniformly, in
+ * index order) becomes the new end bead, the beads shift along the chain and
+ * the far end is released as solvent; positions are unchanged; acceptance
+ * min[1, g(E)/g(E') n_c / n_r] with n_r the solvent particles within R of the
+ * new end next to the released particle.  Otherwise a displacement of one
+ * uniformly drawn particle by a uniform vector in [-0.1, 0.1)^3.  Energy
+ * changes are summed over partners in the fixed order of the trimer model;
+ * the FENE logarithm is computed from basic IEEE operations, so runs are
+ * reproducible bit for bit.  Energy bins and windows as for the trimer model.
+ * init_coords: host float[windows*walkers][np][3] in [0, box).  opts:
+ * precision 0, shadow 0 and obs_bins 0 only.  rewl_get_particles returns a
+ * walker's coordinates, types (0 P, 1 H, 2 W) and lipid rows (particle
+ * indices, head first).  Limits: nlip >= 1, np <= 4096, the state row plus
+ * 12 bytes per window bin within the 160 KiB LDS of a CU.
+ * Errors: REWL_EINVAL on invalid arguments, REWL_ENOMEM if the workspace is
+ * too small, REWL_EDEVICE on a HIP failure.                                   */
+size_t rewl_lipid_workspace_bytes(int nlip, int nsol, float box, double eps_ww, double rep_prob, double e_min,
+                                  double bin_w, int bins, int windows, double overlap, int walkers,
+                                  const rewl_opts *opts);
+int rewl_create_lipid(rewl_t **out, int nlip, int nsol, float box, double eps_ww, double rep_prob, double e_min,
+                      double bin_w, int bins, int windows, double overlap, int walkers, const rewl_opts *opts,
+                      const float *init_coords, void *dev_workspace, size_t ws_bytes, void *hip_stream);
+int rewl_get_particles(rewl_t *r, int walker, float *coords, int8_t *types, int32_t *lipids);
 
 /* ---- Continuous-move model: amphiphilic trimers ---------------------------
  * nmol head-tail-tail molecules (bead 3i the head, 3i+1 and 3i+2 its tails)

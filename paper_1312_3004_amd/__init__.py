@@ -102,6 +102,12 @@ def lib():
         L.rewl_create_trimer.argtypes = [ctypes.POINTER(P), i32, flt, dbl, dbl, i32, i32, dbl, i32,
                                          ctypes.POINTER(Opts), P, P, ctypes.c_size_t, P]
         L.rewl_window_layout_bins.argtypes = [i32, i32, dbl, P, P]
+        L.rewl_lipid_workspace_bytes.argtypes = [i32, i32, flt, dbl, dbl, dbl, dbl, i32, i32, dbl, i32,
+                                                 ctypes.POINTER(Opts)]
+        L.rewl_lipid_workspace_bytes.restype = ctypes.c_size_t
+        L.rewl_create_lipid.argtypes = [ctypes.POINTER(P), i32, i32, flt, dbl, dbl, dbl, dbl, i32, i32, dbl, i32,
+                                        ctypes.POINTER(Opts), P, P, ctypes.c_size_t, P]
+        L.rewl_get_particles.argtypes = [P, i32, P, P, P]
         L.rewl_get_energy.argtypes = [P, i32, ctypes.POINTER(dbl)]
         L.rewl_save.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.rewl_load.argtypes = [P, P, ctypes.c_size_t]
@@ -252,6 +258,54 @@ class Rewl:
                                             ctypes.c_void_p(self._stream.cuda_stream)))
         self._h = h
         return self
+
+    @classmethod
+    def lipid(cls, nlip, nsol, box, e_min, bin_w, bins, windows, overlap, walkers, init_coords, eps_ww=1.0,
+              rep_prob=None, device=None, stream=None, **opts):
+        """A run of the lipid model with explicit solvent; init_coords float32 [windows*walkers, np, 3].
+
+        rep_prob: reptation probability per update (default 3 nlip / (10 np))."""
+        import torch
+
+        self = cls.__new__(cls)
+        o = make_opts(**opts)
+        self.h, self.m, self.nw = windows, walkers, windows * walkers
+        self.opts, self.precision, self.obs_bins = o, o.precision, o.obs_bins
+        self.nlip, self.np, self.box, self.e_min, self.bin_w = nlip, 3 * nlip + nsol, box, e_min, bin_w
+        self.L = self.q = 0
+        # bytes of a walker's state row: coordinates, types (padded to 4), lipid rows, position table
+        self.N = 12 * self.np + (self.np + 3) // 4 * 4 + 12 * nlip + 4 * self.np
+        self.B, self.e_lo = bins, 0
+        W = ctypes.c_int32(0)
+        self.starts = np.zeros(windows, dtype=np.int32)
+        _check(lib().rewl_window_layout_bins(bins, windows, overlap, ctypes.byref(W), _ptr(self.starts)))
+        self.W = W.value
+        x = np.ascontiguousarray(init_coords, dtype=np.float32).reshape(-1)
+        if x.size != self.nw * 3 * self.np:
+            raise ValueError("init_coords must hold np particles x 3 coordinates per walker")
+        rp = -1.0 if rep_prob is None else float(rep_prob)
+        args = (nlip, nsol, box, eps_ww, rp, e_min, bin_w, bins, windows, overlap, walkers, ctypes.byref(o))
+        nbytes = lib().rewl_lipid_workspace_bytes(*args)
+        if nbytes == 0:
+            _check(lib().rewl_create_lipid(ctypes.byref(ctypes.c_void_p()), *args, _ptr(x), None, 0, None))
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().rewl_create_lipid(ctypes.byref(h), *args, _ptr(x),
+                                           ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                           ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+        return self
+
+    def lipid_state(self, w):
+        """(coords float32 [np, 3], types int8 [np] (0 P, 1 H, 2 W), lipids int32 [nlip, 3])."""
+        x = np.zeros((self.np, 3), dtype=np.float32)
+        t = np.zeros(self.np, dtype=np.int8)
+        lp = np.zeros((self.nlip, 3), dtype=np.int32)
+        _check(lib().rewl_get_particles(self._h, w, _ptr(x), _ptr(t), _ptr(lp)))
+        return x, t, lp
 
     def save(self):
         """Checkpoint of the whole run (bytes)."""

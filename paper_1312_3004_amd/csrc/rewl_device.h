@@ -19,6 +19,7 @@ constexpr uint32_t kDomBoot = 7;    // bootstrap: run indices drawn for the resa
 
 constexpr int kModelPotts2D = 0;
 constexpr int kModelTrimer3D = 1;
+constexpr int kModelLipid3D = 2;
 
 // Everything a kernel needs to find one run's state in the device workspace.
 // Per-walker rows are padded so every row starts on a 256-byte boundary.
@@ -33,7 +34,13 @@ struct DevState {
     // coordinates), B energy bins of width bin_w from e_min, e_lo = 0 and
     // E[] holds each walker's bin, Ed[] its energy.
     int L, q, N, h, m, nw, W, B, e_lo;
-    int nmol, nb;                // trimer: molecules, beads
+    int nmol, nb;                // trimer: molecules, beads; lipid model: lipids, particles
+    // lipid model: W-W Lennard-Jones depth, reptation threshold of a 32-bit
+    // word, and byte offsets of the types, lipid rows and position table in
+    // a walker's state row
+    double lip_eps_ww;
+    uint32_t lip_rep_thr;
+    int lip_off_type, lip_off_lip, lip_off_where;
     float box;                   // trimer: side of the periodic cube
     double e_min, bin_w;         // trimer: energy of bin 0's lower edge, bin width
     double th_e0, th_de;         // energy of bin b for thermodynamics: th_e0 + b th_de
@@ -285,6 +292,10 @@ size_t walkin_lds_bytes(const DevState &st);
 
 // Trimer model (rewl_trimer.hip).
 hipError_t launch_trimer_init(const DevState &st, hipStream_t s);
+hipError_t launch_lipid_init(const DevState &st, hipStream_t s);
+hipError_t launch_lipid_walkin(const DevState &st, int64_t chunk, int64_t budget, hipStream_t s);
+hipError_t launch_lipid_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s);
+size_t lipid_sweep_lds_bytes(const DevState &st);
 hipError_t launch_trimer_walkin(const DevState &st, int64_t chunk, int64_t budget, hipStream_t s);
 hipError_t launch_trimer_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s);
 size_t trimer_sweep_lds_bytes(const DevState &st);

@@ -1568,12 +1568,14 @@ static hipError_t allow_lds(const void *fn, size_t bytes) {
 
 hipError_t launch_init_energy(const DevState &st, hipStream_t s) {
     if (st.model == kModelTrimer3D) return launch_trimer_init(st, s);
+    if (st.model == kModelLipid3D) return launch_lipid_init(st, s);
     hipLaunchKernelGGL(k_init_energy, dim3(st.nw), dim3(256), 0, s, st);
     return hipGetLastError();
 }
 
 hipError_t launch_walkin(const DevState &st, int64_t chunk, int64_t budget, hipStream_t s) {
     if (st.model == kModelTrimer3D) return launch_trimer_walkin(st, chunk, budget, s);
+    if (st.model == kModelLipid3D) return launch_lipid_walkin(st, chunk, budget, s);
     const size_t lds = walkin_lds_bytes(st);
     hipError_t e = allow_lds((const void *)k_walkin, lds);
     if (e != hipSuccess) return e;
@@ -1583,6 +1585,7 @@ hipError_t launch_walkin(const DevState &st, int64_t chunk, int64_t budget, hipS
 
 hipError_t launch_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s) {
     if (st.model == kModelTrimer3D) return launch_trimer_sweep(st, s0, n, s);
+    if (st.model == kModelLipid3D) return launch_lipid_sweep(st, s0, n, s);
     const size_t lds = sweep_lds_bytes(st);
     if (st.precision == 0) {
         hipError_t e = allow_lds((const void *)k_sweep<0>, lds);

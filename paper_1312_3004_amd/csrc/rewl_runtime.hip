@@ -150,13 +150,52 @@ int check_opts(int h, int m, const rewl_opts &op) {
     return REWL_OK;
 }
 
-// Geometry of the trimer model (rewl_create_trimer).
+// Geometry of the continuous models (rewl_create_trimer, rewl_create_lipid).
 struct TrimerGeom {
     int nmol;
     float box;
     double e_min, bin_w;
     int bins;
+    int model = rewl_gpu::kModelTrimer3D;
+    int nsol = 0;                 // lipid model: solvent particles
+    double eps_ww = 1.0;          // lipid model: W-W depth
+    uint32_t rep_thr = 0;         // lipid model: reptation threshold
+    int off_type = 0, off_lip = 0, off_where = 0;
 };
+
+// Lipid model: check the geometry and lay out a walker's state row.
+int check_lipid(TrimerGeom &g, int h, double o, int m, const rewl_opts &op, Params *p,
+                std::vector<int32_t> *starts) {
+    if (g.nmol < 1 || g.nsol < 0 || 3 * g.nmol + g.nsol > 4096)
+        return fail(REWL_EINVAL, "lipids >= 1, solvent >= 0, at most 4096 particles");
+    if (!(g.box > 0.0f) || !(g.box < 1e6f)) return fail(REWL_EINVAL, "box must be positive");
+    if (!(g.bin_w > 0.0) || !std::isfinite(g.e_min)) return fail(REWL_EINVAL, "bin_w must be > 0, e_min finite");
+    if (!(g.eps_ww >= 0.0) || !std::isfinite(g.eps_ww)) return fail(REWL_EINVAL, "eps_ww must be >= 0");
+    if (g.bins < 8) return fail(REWL_EINVAL, "at least 8 energy bins");
+    int st = check_opts(h, m, op);
+    if (st != REWL_OK) return st;
+    if (op.precision != 0 || op.shadow != 0 || op.obs_bins != 0)
+        return fail(REWL_EINVAL, "the lipid model runs in binary64 without shadow or observable sampling");
+    starts->assign((size_t)std::max(h, 1), 0);
+    int W = 0;
+    st = layout_bins(g.bins, 0, h, o, &W, starts->data());
+    if (st != REWL_OK) return st;
+    const int np = 3 * g.nmol + g.nsol;
+    g.off_type = 12 * np;
+    g.off_lip = g.off_type + (np + 3) / 4 * 4;
+    g.off_where = g.off_lip + 12 * g.nmol;
+    p->L = 0; p->q = 0; p->N = g.off_where + 4 * np; p->h = h; p->m = m; p->nw = h * m;
+    p->W = W; p->B = g.bins; p->e_lo = 0;
+    p->Npad = (int)round_up((size_t)p->N, kAlign);
+    p->Wpad = (int)round_up((size_t)W, 64);
+    p->Bpad = (int)round_up((size_t)p->B, 64);
+    p->Ntag = 64;
+    if ((size_t)p->Npad + (size_t)p->Wpad * 12 > (size_t)kMaxLds)
+        return fail(REWL_EINVAL, "particle state plus window state exceed the 160 KiB LDS of a CU");
+    if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
+        return fail(REWL_EINVAL, "walk-in counts over all bins exceed the 160 KiB LDS (too many bins)");
+    return REWL_OK;
+}
 
 int check_trimer(const TrimerGeom &g, int h, double o, int m, const rewl_opts &op, Params *p,
                  std::vector<int32_t> *starts) {
@@ -337,9 +376,11 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     unsigned char *b = r->ws;
     DevState &d = r->st;
     std::memset(&d, 0, sizeof(d));
-    d.model = geom ? rewl_gpu::kModelTrimer3D : rewl_gpu::kModelPotts2D;
+    d.model = geom ? geom->model : rewl_gpu::kModelPotts2D;
     if (geom) {
-        d.nmol = geom->nmol; d.nb = 3 * geom->nmol; d.box = geom->box;
+        d.nmol = geom->nmol; d.nb = 3 * geom->nmol + geom->nsol; d.box = geom->box;
+        d.lip_eps_ww = geom->eps_ww; d.lip_rep_thr = geom->rep_thr;
+        d.lip_off_type = geom->off_type; d.lip_off_lip = geom->off_lip; d.lip_off_where = geom->off_where;
         d.e_min = geom->e_min; d.bin_w = geom->bin_w;
         d.th_e0 = geom->e_min + 0.5 * geom->bin_w;   // bin centres
         d.th_de = geom->bin_w;
@@ -463,6 +504,74 @@ size_t rewl_trimer_workspace_bytes(int nmol, float box, double e_min, double bin
     return make_layout(p, op.precision, op.shadow, true, op.obs_bins).total;
 }
 
+size_t rewl_lipid_workspace_bytes(int nlip, int nsol, float box, double eps_ww, double rep_prob, double e_min,
+                                  double bin_w, int bins, int windows, double overlap, int walkers,
+                                  const rewl_opts *opts) {
+    rewl_opts op;
+    if (opts) op = *opts; else rewl_default_opts(&op);
+    Params p;
+    std::vector<int32_t> starts;
+    TrimerGeom g{nlip, box, e_min, bin_w, bins};
+    g.model = rewl_gpu::kModelLipid3D; g.nsol = nsol; g.eps_ww = eps_ww;
+    (void)rep_prob;
+    if (check_lipid(g, windows, overlap, walkers, op, &p, &starts) != REWL_OK) return 0;
+    return make_layout(p, op.precision, op.shadow, true, op.obs_bins).total;
+}
+
+int rewl_create_lipid(rewl_t **out, int nlip, int nsol, float box, double eps_ww, double rep_prob, double e_min,
+                      double bin_w, int bins, int windows, double overlap, int walkers, const rewl_opts *opts,
+                      const float *init_coords, void *dev_workspace, size_t ws_bytes, void *hip_stream) {
+    if (!out) return fail(REWL_EINVAL, "null handle pointer");
+    *out = nullptr;
+    rewl_opts op;
+    if (opts) op = *opts; else rewl_default_opts(&op);
+    Params p;
+    std::vector<int32_t> starts;
+    TrimerGeom g{nlip, box, e_min, bin_w, bins};
+    g.model = rewl_gpu::kModelLipid3D; g.nsol = nsol; g.eps_ww = eps_ww;
+    const int np = 3 * nlip + nsol;
+    if (rep_prob < 0.0) rep_prob = 3.0 * nlip / (10.0 * np);
+    if (!(rep_prob <= 1.0)) return fail(REWL_EINVAL, "rep_prob must be <= 1");
+    const double thr = std::nearbyint(rep_prob * 4294967296.0);
+    g.rep_thr = thr >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)thr;
+    int st = check_lipid(g, windows, overlap, walkers, op, &p, &starts);
+    if (st != REWL_OK) return st;
+    if (!init_coords) return fail(REWL_EINVAL, "init_coords is required");
+    for (size_t i = 0; i < (size_t)p.nw * 3 * np; ++i)
+        if (!(init_coords[i] >= 0.0f && init_coords[i] < box))
+            return fail(REWL_EINVAL, "coordinate outside [0, box)");
+    // state rows: particles 3i, 3i+1, 3i+2 start as lipid i (head, tail, tail)
+    std::vector<unsigned char> rows((size_t)p.nw * p.N, 0);
+    for (int w = 0; w < p.nw; ++w) {
+        unsigned char *row = rows.data() + (size_t)w * p.N;
+        std::memcpy(row, init_coords + (size_t)w * 3 * np, (size_t)12 * np);
+        int8_t *type = (int8_t *)(row + g.off_type);
+        int32_t *lip = (int32_t *)(row + g.off_lip);
+        int32_t *where = (int32_t *)(row + g.off_where);
+        for (int i = 0; i < np; ++i) {
+            const bool in_lipid = i < 3 * nlip;
+            type[i] = (int8_t)(in_lipid ? (i % 3 == 0 ? 0 : 1) : 2);
+            where[i] = in_lipid ? i : -1;
+        }
+        for (int i = 0; i < 3 * nlip; ++i) lip[i] = i;
+    }
+    return create_run(out, p, starts, op, &g, rows.data(), dev_workspace, ws_bytes, hip_stream);
+}
+
+int rewl_get_particles(rewl_t *r, int w, float *coords, int8_t *types, int32_t *lipids) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    const DevState &d = r->st;
+    if (d.model != rewl_gpu::kModelLipid3D) return fail(REWL_EINVAL, "not a run of the lipid model");
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    const unsigned char *row = (const unsigned char *)(d.spins + (size_t)w * d.Npad);
+    if (coords) HIP_TRY(hipMemcpyAsync(coords, row, (size_t)12 * d.nb, hipMemcpyDeviceToHost, r->stream));
+    if (types) HIP_TRY(hipMemcpyAsync(types, row + d.lip_off_type, (size_t)d.nb, hipMemcpyDeviceToHost, r->stream));
+    if (lipids)
+        HIP_TRY(hipMemcpyAsync(lipids, row + d.lip_off_lip, (size_t)12 * d.nmol, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return REWL_OK;
+}
+
 int rewl_create_trimer(rewl_t **out, int nmol, float box, double e_min, double bin_w, int bins, int windows,
                        double overlap, int walkers, const rewl_opts *opts, const float *init_coords,
                        void *dev_workspace, size_t ws_bytes, void *hip_stream) {
@@ -542,7 +651,9 @@ int rewl_walkin(rewl_t *r, int64_t max_attempts) {
     std::vector<int32_t> done(nw);
     std::vector<int64_t> att(nw);
     for (;;) {
-        HIP_TRY(rewl_gpu::launch_walkin(r->st, kWalkinChunk, max_attempts, r->stream));
+        // the lipid model's attempts cost thousands of pair terms: shorter launches
+        const int64_t chunk = r->st.model == rewl_gpu::kModelLipid3D ? int64_t(1) << 12 : kWalkinChunk;
+        HIP_TRY(rewl_gpu::launch_walkin(r->st, chunk, max_attempts, r->stream));
         HIP_TRY(hipMemcpyAsync(done.data(), r->st.walkin_done, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, r->stream));
         HIP_TRY(hipMemcpyAsync(att.data(), r->st.walkin_att, sizeof(int64_t) * nw, hipMemcpyDeviceToHost, r->stream));
         HIP_TRY(hipStreamSynchronize(r->stream));

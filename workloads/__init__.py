@@ -46,6 +46,17 @@ TRIMER = dict(model="trimer", nmol=64, box=10.0, e_min=-460.0, bin_w=0.5, bins=1
               sync_attempts=20_000, exchange=1, precision=0, seed=1)
 
 
+# Lipid model with explicit solvent (the paper's system size): 125 P-H-H
+# lipids and 625 solvent particles (N = 1000) at number density 0.8 (box
+# (1000/0.8)^(1/3)), eps_WW = 1, reptation probability 3M/(10N) = 0.0375,
+# 16 windows at 75% overlap with 4 walkers each over 800 one-unit energy bins
+# from 7000 (the band just below the lattice starts of init_lipids, 7230 ..
+# 7620), binary64 ln g, ln f 1 -> 1e-6 by halving, sync every 2000 attempts.
+LIPID = dict(model="lipid", nlip=125, nsol=625, box=(1000 / 0.8) ** (1 / 3), eps_ww=1.0, e_min=7000.0, bin_w=1.0,
+             bins=800, windows=16, overlap=0.75, walkers=4, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
+             sync_attempts=2000, exchange=1, precision=0, seed=1)
+
+
 def init_lipids(nlip, nsol, box, n_walkers, seed, jitter=0.05):
     """Starting configurations of the lipid model: float32 [n_walkers, np, 3].
 
