@@ -24,8 +24,10 @@
 // int8[np] (0 P, 1 H, 2 W; padded to 4 bytes), lipid rows int32[nmol][3]
 // (head first), position table int32[np] (3 lipid + bead, -1 solvent).
 //
-// Mapping: one walker per 64-lane wavefront, its state, ln g and H in LDS.
-// Attempts are sequential; every energy change is a sum of per-partner
+// Mapping: one walker per workgroup (the attempt kernel: up to 16 wavefronts
+// sharing the 64-partner chunks; walk-in and set-up: one wavefront), its
+// state, ln g and H in LDS.  Attempts are sequential; every energy change is
+// a sum of per-partner
 // terms t_j (j = 0 .. np-1) taken in a fixed order: per lane l left to right
 // over j = l, l + 64, ..., then across lanes by halving (lane l adds lane
 // l + h for h = 32, 16, ..., 1).
@@ -432,58 +434,208 @@ __global__ __launch_bounds__(64) void k_lipid_walkin(DevState st, int64_t chunk,
 // whose new bin leaves the window is rejected, else accepted with
 // min[1, g(old)/g(new)] (times n_c / n_r for a reptation); then
 // ln g += ln f and H += 1 at the bin after the decision.
-__global__ __launch_bounds__(64) void k_lipid_sweep(DevState st, int64_t s0, int64_t n) {
+//
+// One workgroup per walker with up to 16 wavefronts: wave v takes the
+// 64-partner chunks c = v, v + nwave, ...; the partner terms go to LDS
+// (tbuf[c][lane]) and wave 0 sums them in the fixed order (per lane over c,
+// then halving), decides and applies the move.  Reptation candidates are
+// found with one ballot mask per chunk, written to LDS and read by every
+// wave.  All branches that contain a barrier depend only on the attempt's
+// random words or on values every wave reads from LDS, so the waves agree.
+__global__ __launch_bounds__(1024) void k_lipid_sweep(DevState st, int64_t s0, int64_t n) {
 #pragma clang fp contract(off)
     const int w = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nwave = (int)(blockDim.x >> 6);
     if (*st.converged) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int W = st.W, Wpad = st.Wpad;
+    const int nch = (st.nb + 63) / 64;
     double *g = (double *)(smem + st.Npad);
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
+    double *tbuf = (double *)(smem + st.Npad + (size_t)Wpad * 12);
+    unsigned long long *mask1 = (unsigned long long *)(tbuf + (size_t)nch * 64);
+    unsigned long long *mask2 = mask1 + nch;
     const uint32_t *gx = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
-    for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)smem)[i] = gx[i];
+    for (int i = threadIdx.x; i < st.Npad / 4; i += blockDim.x) ((uint32_t *)smem)[i] = gx[i];
     const size_t row = (size_t)w * Wpad;
-    for (int b = lane; b < W; b += 64) {
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
         g[b] = st.lng[row + b];
         H[b] = st.H[row + b];
     }
     __syncthreads();
     const LipView v = lip_view(st, smem);
+    const float box = st.box, half = 0.5f * st.box;
     const int k = w / st.m;
     const int lo = st.start[k], hi = lo + W - 1;
     const double lnf = st.lnf[k];
     int E = st.E[w];
     double Ed = st.Ed[w];
-    if (E < lo || E > hi) return;   // not walked in
+    if (E < lo || E > hi) return;   // not walked in (every wave reads the same E)
+    U4 la, lu;   // random words of attempt t0 + lane, drawn 64 attempts at a time
     for (int64_t t = 0; t < n; ++t) {
+        const int j64 = (int)(t & 63);
+        if (j64 == 0) lip_words(st, (uint64_t)(s0 + t + lane), (uint32_t)w, kDomMove, kDomMoveU, la, lu);
         U4 a, u;
-        lip_words(st, (uint64_t)(s0 + t), (uint32_t)w, kDomMove, kDomMoveU, a, u);
+        a.x = __builtin_amdgcn_readlane(la.x, j64); a.y = __builtin_amdgcn_readlane(la.y, j64);
+        a.z = __builtin_amdgcn_readlane(la.z, j64); a.w = __builtin_amdgcn_readlane(la.w, j64);
+        u.x = __builtin_amdgcn_readlane(lu.x, j64); u.y = __builtin_amdgcn_readlane(lu.y, j64);
+        u.z = __builtin_amdgcn_readlane(lu.z, j64); u.w = __builtin_amdgcn_readlane(lu.w, j64);
         LipProp p;
-        lip_propose(st, v, Ed, a, u, p, lane);
-        if (p.ok) {
-            const double e_new = Ed + p.de;
-            const int bn = lip_bin(st, e_new);
-            if (bn >= lo && bn <= hi && lip_accept(p, g[E - lo] - g[bn - lo], u.x)) {
-                lip_apply(st, v, p, lane);
-                Ed = e_new;
-                E = bn;
+        p.ok = true;
+        p.rep = u.y < st.lip_rep_thr;
+        if (!p.rep) {
+            const int b = (int)mul_shift(a.x, (uint32_t)st.nb);
+            p.b = b;
+            const float o[3] = {v.x[3 * b], v.x[3 * b + 1], v.x[3 * b + 2]};
+            p.xn[0] = lip_wrap(o[0] + lip_disp(a.y), box);
+            p.xn[1] = lip_wrap(o[1] + lip_disp(a.z), box);
+            p.xn[2] = lip_wrap(o[2] + lip_disp(a.w), box);
+            const int tb = v.type[b], wb = v.where[b];
+            for (int c = wave; c < nch; c += nwave) {
+                const int j = c * 64 + lane;
+                double tj = 0.0;
+                if (j < st.nb && j != b) {
+                    const float *xj = v.x + 3 * j;
+                    const int tjt = v.type[j];
+                    const bool bd = lip_bonded(wb, v.where[j]);
+                    tj = lip_pair(tb, tjt, bd, lip_r2(p.xn, xj, box, half), st.lip_eps_ww) -
+                         lip_pair(tb, tjt, bd, lip_r2(o, xj, box, half), st.lip_eps_ww);
+                }
+                tbuf[c * 64 + lane] = tj;
+            }
+        } else {
+            const int lipid = (int)mul_shift(a.x, (uint32_t)st.nmol);
+            p.lipid = lipid;
+            const int end = (int)(u.z >> 31);
+            const int l0 = v.lip[3 * lipid], l1 = v.lip[3 * lipid + 1], l2 = v.lip[3 * lipid + 2];
+            const int e = end == 0 ? l0 : l2;
+            const float xe[3] = {v.x[3 * e], v.x[3 * e + 1], v.x[3 * e + 2]};
+            for (int c = wave; c < nch; c += nwave) {
+                const int j = c * 64 + lane;
+                bool hit = false;
+                if (j < st.nb && j != e && v.type[j] == kW) hit = lip_r2(xe, v.x + 3 * j, box, half) < kLipR2;
+                const unsigned long long m = __ballot(hit);
+                if (lane == 0) mask1[c] = m;
+            }
+            __syncthreads();
+            int nc = 0;
+            for (int c = 0; c < nch; ++c) nc += __builtin_popcountll(mask1[c]);
+            if (nc == 0) {
+                p.ok = false;
+            } else {
+                int pick = (int)mul_shift(u.w, (uint32_t)nc);
+                int cap = -1;
+                for (int c = 0; c < nch && cap < 0; ++c) {
+                    unsigned long long m = mask1[c];
+                    const int cnt = __builtin_popcountll(m);
+                    if (pick < cnt) {
+                        for (int r = pick; r > 0; --r) m &= m - 1ull;
+                        cap = c * 64 + (int)__builtin_ctzll(m);
+                    } else {
+                        pick -= cnt;
+                    }
+                }
+                int rel;
+                if (end == 0) { p.nl[0] = cap; p.nl[1] = l0; p.nl[2] = l1; rel = l2; }
+                else { p.nl[0] = l1; p.nl[1] = l2; p.nl[2] = cap; rel = l0; }
+                int all[4] = {cap, l0, l1, l2};
+                for (int i = 1; i < 4; ++i)
+                    for (int q = i; q > 0 && all[q - 1] > all[q]; --q) {
+                        const int tq = all[q]; all[q] = all[q - 1]; all[q - 1] = tq;
+                    }
+                for (int i = 0; i < 4; ++i) {
+                    const int q = all[i];
+                    p.c[i] = q;
+                    if (q == rel) { p.nt[i] = kW; p.nwh[i] = -1; }
+                    else {
+                        const int pos = q == p.nl[0] ? 0 : (q == p.nl[1] ? 1 : 2);
+                        p.nt[i] = pos == 0 ? kP : kH;
+                        p.nwh[i] = 3 * lipid + pos;
+                    }
+                }
+                p.nc = nc;
+                // n_r: solvent within R of l1 under the new types
+                const float x1[3] = {v.x[3 * l1], v.x[3 * l1 + 1], v.x[3 * l1 + 2]};
+                for (int c = wave; c < nch; c += nwave) {
+                    const int j = c * 64 + lane;
+                    bool hit = false;
+                    if (j < st.nb && j != l1) {
+                        int tj = v.type[j];
+                        for (int i = 0; i < 4; ++i)
+                            if (p.c[i] == j) tj = p.nt[i];
+                        if (tj == kW) hit = lip_r2(x1, v.x + 3 * j, box, half) < kLipR2;
+                    }
+                    const unsigned long long m = __ballot(hit);
+                    if (lane == 0) mask2[c] = m;
+                }
+                // partner terms of the reptation (see lip_propose)
+                for (int c = wave; c < nch; c += nwave) {
+                    const int j = c * 64 + lane;
+                    double tj = 0.0;
+                    if (j < st.nb) {
+                        const int tjo = v.type[j], wjo = v.where[j];
+                        int tjn = tjo, wjn = wjo;
+                        bool jin = false;
+                        for (int i = 0; i < 4; ++i)
+                            if (p.c[i] == j) { jin = true; tjn = p.nt[i]; wjn = p.nwh[i]; }
+                        bool first = true;
+                        for (int i = 0; i < 4; ++i) {
+                            const int ci = p.c[i];
+                            if (ci == j || (jin && ci > j)) continue;
+                            const double r2 = lip_r2(v.x + 3 * ci, v.x + 3 * j, box, half);
+                            const double vn = lip_pair(p.nt[i], tjn, lip_bonded(p.nwh[i], wjn), r2, st.lip_eps_ww);
+                            const double vo =
+                                lip_pair(v.type[ci], tjo, lip_bonded(v.where[ci], wjo), r2, st.lip_eps_ww);
+                            const double d = vn - vo;
+                            tj = first ? d : tj + d;
+                            first = false;
+                        }
+                    }
+                    tbuf[c * 64 + lane] = tj;
+                }
             }
         }
-        if (lane == 0) {
-            g[E - lo] = g[E - lo] + lnf;
-            H[E - lo] += 1u;
+        __syncthreads();
+        if (wave == 0) {
+            if (p.ok) {
+                double acc = 0.0;
+                for (int c = 0; c < nch; ++c) {
+                    const double tj = tbuf[c * 64 + lane];
+                    acc = c == 0 ? tj : acc + tj;
+                }
+                p.de = lip_halve(acc, lane);
+                if (p.rep) {
+                    int nr = 0;
+                    for (int c = 0; c < nch; ++c) nr += __builtin_popcountll(mask2[c]);
+                    p.nr = nr;
+                }
+                if (__builtin_isfinite(p.de)) {
+                    const double e_new = Ed + p.de;
+                    const int bn = lip_bin(st, e_new);
+                    if (bn >= lo && bn <= hi && lip_accept(p, g[E - lo] - g[bn - lo], u.x)) {
+                        lip_apply(st, v, p, lane);
+                        Ed = e_new;
+                        E = bn;
+                    }
+                }
+            }
+            if (lane == 0) {
+                g[E - lo] = g[E - lo] + lnf;
+                H[E - lo] += 1u;
+            }
         }
         __syncthreads();
     }
     const uint32_t *sx = (const uint32_t *)smem;
     uint32_t *ox = (uint32_t *)(st.spins + (size_t)w * st.Npad);
-    for (int i = lane; i < st.Npad / 4; i += 64) ox[i] = sx[i];
-    for (int b = lane; b < W; b += 64) {
+    for (int i = threadIdx.x; i < st.Npad / 4; i += blockDim.x) ox[i] = sx[i];
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
         st.lng[row + b] = g[b];
         st.H[row + b] = H[b];
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         st.E[w] = E;
         st.Ed[w] = Ed;
     }
@@ -496,7 +648,14 @@ hipError_t lip_allow(const void *fn, size_t bytes) {
 
 }  // namespace
 
-size_t lipid_sweep_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Wpad * 12; }
+static int lipid_waves(const DevState &st) {
+    const int nch = (st.nb + 63) / 64;
+    return nch < 16 ? nch : 16;
+}
+size_t lipid_sweep_lds_bytes(const DevState &st) {
+    const int nch = (st.nb + 63) / 64;
+    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)nch * 64 * 8 + (size_t)nch * 16;
+}
 size_t lipid_walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
 
 hipError_t launch_lipid_init(const DevState &st, hipStream_t s) {
@@ -516,7 +675,7 @@ hipError_t launch_lipid_sweep(const DevState &st, int64_t s0, int64_t n, hipStre
     const size_t lds = lipid_sweep_lds_bytes(st);
     hipError_t e = lip_allow((const void *)k_lipid_sweep, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lipid_sweep, dim3(st.nw), dim3(64), lds, s, st, s0, n);
+    hipLaunchKernelGGL(k_lipid_sweep, dim3(st.nw), dim3(64 * lipid_waves(st)), lds, s, st, s0, n);
     return hipGetLastError();
 }
 

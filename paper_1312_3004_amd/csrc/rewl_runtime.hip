@@ -190,7 +190,8 @@ int check_lipid(TrimerGeom &g, int h, double o, int m, const rewl_opts &op, Para
     p->Wpad = (int)round_up((size_t)W, 64);
     p->Bpad = (int)round_up((size_t)p->B, 64);
     p->Ntag = 64;
-    if ((size_t)p->Npad + (size_t)p->Wpad * 12 > (size_t)kMaxLds)
+    const size_t nch = (size_t)(np + 63) / 64;   // partner chunks of the attempt kernel's term buffer
+    if ((size_t)p->Npad + (size_t)p->Wpad * 12 + nch * 64 * 8 + nch * 16 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "particle state plus window state exceed the 160 KiB LDS of a CU");
     if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "walk-in counts over all bins exceed the 160 KiB LDS (too many bins)");
