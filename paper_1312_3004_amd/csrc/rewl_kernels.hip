@@ -431,7 +431,9 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     const int dEj = __builtin_amdgcn_readlane(dE, j);
                     const double luj = readlane_d(lnu, j);
                     int idx = erel + dEj;
-                    if ((unsigned)idx >= 64u) {
+                    // rare: the proposed energy lies outside the register cache
+                    // (laid out of line, the common case falls through)
+                    if (__builtin_expect((unsigned)idx >= 64u, 0)) {
                         cache_store();
                         ebase += idx - 32;
                         cache_load();
