@@ -36,7 +36,7 @@ LDS_BYTES_PER_ATTEMPT = 38
 # HBM bytes per k_sweep launch of the potts_q10_L32 workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg copy of known size
 # (profiles/k_sweep_potts_q10_L32_pmc.md).  Valid for the kernel as profiled.
-K_SWEEP_L32_HBM_BYTES = 932_000
+K_SWEEP_L32_HBM_BYTES = 935_000
 # VALU instructions (wave64) per attempt of the same kernel, rocprofv3 SQ_INSTS_VALU
 # over the same workload (same profile); the VALU lane-op peak is the binary32
 # vector rate, 157.3 TFLOP/s / 2 (an FMA counts two flops).
