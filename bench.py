@@ -563,6 +563,81 @@ def production(args):
     print(json.dumps(out), flush=True)
 
 
+# Structural observables of one lipid configuration (Sec. 3.2, Eqs. 6-8),
+# algorithmic ALU work in 32-bit lane operations (binary64 counts two): the
+# tail-contact test over the M (M - 1) / 2 lipid pairs, 4 tail pairs each, at
+# 3 binary32 differences + 3 wrap tests + 3 widenings + 3 binary64 products +
+# 2 binary64 sums + 1 compare = 20 ops; S_mol, the cluster search and the
+# unfolding add O(M) and are left out.
+def structure_ops_per_config(M):
+    return M * (M - 1) // 2 * 4 * 20
+
+
+def structure_bench(args):
+    """Structural observables of the N = 1000 lipid system (125 lipids in 625
+    solvent particles, density 0.8) for a batch of 4,096 configurations in one
+    launch (one wavefront each), timed with HIP events on the launching stream;
+    the oracle's structure() of a sample of the same configurations is timed
+    beside it."""
+    import numpy as np
+    import torch
+
+    import paper_1312_3004_amd as pk
+    import workloads
+
+    c = workloads.LIPID
+    nconf, M = 4096, c["nlip"]
+    xs = workloads.init_lipids(c["nlip"], c["nsol"], c["box"], nconf, c["seed"])
+    lips = np.broadcast_to(np.arange(3 * M, dtype=np.int32).reshape(1, M, 3), (nconf, M, 3)).copy()
+    torch.cuda.set_device(0)
+    x = torch.from_numpy(xs).cuda()
+    lp = torch.from_numpy(lips).cuda()
+    out = torch.empty((nconf, 8), dtype=torch.float64, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        pk.lipid_structure(x, lp, c["box"], out=out)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 200))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        pk.lipid_structure(x, lp, c["box"], out=out)
+        b.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    rec = out.cpu().numpy()
+    ops = structure_ops_per_config(M) * nconf
+    achieved = ops / (kern_ms * 1e-3) / 1e12
+    log(f"[bench] structure: {nconf} configurations per launch, kernel {kern_ms:.3f} ms; largest cluster "
+        f"{rec[:, 3].mean():.1f} lipids on average, {rec[:, 2].mean():.1f} clusters")
+    res = {"metric": "configurations analysed/s (1 GPU), lipid structure observables (S_mol, clusters, "
+                     "gyration tensor, prolateness), N = 1000",
+           "value": nconf / (kern_ms * 1e-3), "unit": "configurations/s", "n_gpus": 1, "steps": steps,
+           "warmup": max(args.warmup, 1), "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{nconf} configurations of the lipid system (125 lipids, 625 solvent, "
+                                  f"box {c['box']:.3f}), one launch", "configurations": nconf, "lipids": M},
+           "kernel_avg_ms": kern_ms,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                        "frac": achieved / ALU_PEAK_TOPS, "traffic": None},
+           "mean_largest_cluster": float(rec[:, 3].mean()), "mean_clusters": float(rec[:, 2].mean())}
+    if not args.no_cpu_baseline:
+        from oracle import structure as S
+
+        n, t0 = 0, time.perf_counter()
+        while n < nconf and (n < 8 or time.perf_counter() - t0 < 10.0):
+            ref = S.structure(xs[n], lips[n], c["box"])
+            if not (ref[2] == rec[n, 2] and ref[3] == rec[n, 3]):
+                raise RuntimeError(f"configuration {n}: clusters differ from the oracle")
+            n += 1
+        cpu_s = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": n / cpu_s, "unit": "configurations/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's structure() of the first {n} of the same configurations, "
+                                         f"one thread"}
+    print(json.dumps(res), flush=True)
+
+
 def bootstrap_bench(args):
     """Error analysis of Sec. 2 on the GPU: R = 64 independent runs of the
     potts_q10_L8 workload (instances of one batch, different Philox streams
@@ -659,13 +734,14 @@ def main():
                     help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
                          "times first: the reference for the HBM byte counters of a profiler run")
     ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer", "production", "bootstrap",
-                                           "lipid"),
+                                           "lipid", "structure"),
                     default="potts",
                     help="potts: the single-run workload (--config); batched: 256 instances; "
                          "precision: the L=80 workload in binary64 and in the binary32 pair form; "
                          "trimer: the continuous-move workload; production: the single-run workload "
                          "with frozen weights and H(E, O) sampling; bootstrap: error analysis over 64 "
-                         "independent L=8 runs; lipid: the explicit-solvent lipid system (N = 1000)")
+                         "independent L=8 runs; lipid: the explicit-solvent lipid system (N = 1000); "
+                         "structure: its structural observables over 4,096 configurations")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
@@ -697,6 +773,8 @@ def main():
         return bootstrap_bench(args)
     if args.workload == "lipid":
         return lipid(args)
+    if args.workload == "structure":
+        return structure_bench(args)
 
     import torch
 

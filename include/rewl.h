@@ -146,6 +146,48 @@ int rewl_create_lipid(rewl_t **out, int nlip, int nsol, float box, double eps_ww
                       const float *init_coords, void *dev_workspace, size_t ws_bytes, void *hip_stream);
 int rewl_get_particles(rewl_t *r, int walker, float *coords, int8_t *types, int32_t *lipids);
 
+/* ---- Structural observables of lipid configurations (Sec. 3.2, Eqs. 6-8) --
+ * For each configuration, an 8-double record:
+ *   [0] S_mol^head (Eq. 6): (3 <cos^2 theta> - 1) / 2 over the bonds from each
+ *       lipid's head to its first tail bead, theta measured against the box
+ *       axis that maximises it;  [1] that axis (0 x, 1 y, 2 z; the first on
+ *       ties);
+ *   [2] number of lipid clusters: lipids are neighbours when a tail bead of
+ *       one lies within 1.4 of a tail bead of the other (squared minimum-image
+ *       distance < 1.96), clusters are the connected components;
+ *   [3] lipids in the largest cluster (the one holding the lowest lipid index
+ *       on ties);
+ *   [4..6] Q_xx, Q_yy, Q_zz (Eq. 7 with the square): the diagonal of the
+ *       gyration tensor of the 3 x [3] beads of the largest cluster in unfolded
+ *       coordinates, all beads of equal mass;
+ *   [7] prolateness P = 9 sum_i (Q_ii - lambda)^3 / (sum_i Q_ii)^3 with lambda
+ *       = (sum_i Q_ii) / 3 (Eq. 8): 2 for a rod, -1/4 for a flat disc.
+ * Unfolding grows the cluster breadth first from its lowest-index lipid; a
+ * lipid found at level k+1 hangs from the lowest-index lipid of level k it
+ * touches and is placed through their first touching tail pair (parent
+ * centre, then end bead; child centre, then end bead), its other beads through
+ * its bonds; the root keeps its stored head position.  Minimum images are
+ * taken per axis in binary32 (one wrap by +-box), everything else in binary64.
+ * Integer fields are exact; floating fields agree with a plain evaluation to
+ * rounding (lane sums are taken in butterfly order).
+ *
+ * rewl_lipid_structure: device pointers.  Configuration c has coordinates
+ *   float[np][3] at (char *)coords + c * coord_stride and lipid rows int32
+ *   [nlip][3] (particle indices, head first) at (char *)lipids + c *
+ *   lipid_stride; out double[nconf][8].  The work is queued on hip_stream
+ *   (NULL: the default stream) and the call returns without waiting.  A
+ *   configuration holding a particle index outside [0, np) gets a NaN record.
+ *   Limits: 1 <= nlip <= 512, np >= 3 nlip; pointers and strides 4-byte
+ *   aligned, out 8-byte aligned.  REWL_EINVAL on invalid arguments,
+ *   REWL_EDEVICE if the launch fails.
+ * rewl_structure: the records of every walker of a lipid-model run (walker
+ *   order), into host out double[windows * walkers][8]; waits for the result.
+ *   REWL_EINVAL for a null argument or a run of another model, REWL_EDEVICE
+ *   on a HIP failure.                                                         */
+int rewl_lipid_structure(const float *coords, size_t coord_stride, const int32_t *lipids, size_t lipid_stride,
+                         int nconf, int np, int nlip, float box, double *out, void *hip_stream);
+int rewl_structure(rewl_t *r, double *out);
+
 /* ---- Continuous-move model: amphiphilic trimers ---------------------------
  * nmol head-tail-tail molecules (bead 3i the head, 3i+1 and 3i+2 its tails)
  * in a periodic cube of side `box` (the paper's bead-spring amphiphile with

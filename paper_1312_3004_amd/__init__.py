@@ -108,6 +108,8 @@ def lib():
         L.rewl_create_lipid.argtypes = [ctypes.POINTER(P), i32, i32, flt, dbl, dbl, dbl, dbl, i32, i32, dbl, i32,
                                         ctypes.POINTER(Opts), P, P, ctypes.c_size_t, P]
         L.rewl_get_particles.argtypes = [P, i32, P, P, P]
+        L.rewl_lipid_structure.argtypes = [P, ctypes.c_size_t, P, ctypes.c_size_t, i32, i32, i32, flt, P, P]
+        L.rewl_structure.argtypes = [P, P]
         L.rewl_get_energy.argtypes = [P, i32, ctypes.POINTER(dbl)]
         L.rewl_save.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.rewl_load.argtypes = [P, P, ctypes.c_size_t]
@@ -306,6 +308,13 @@ class Rewl:
         lp = np.zeros((self.nlip, 3), dtype=np.int32)
         _check(lib().rewl_get_particles(self._h, w, _ptr(x), _ptr(t), _ptr(lp)))
         return x, t, lp
+
+    def structure(self):
+        """Structural observables (Eqs. 6-8) of every walker's configuration: float64 [walkers, 8]
+        = (S_mol, axis, clusters, largest, Q_xx, Q_yy, Q_zz, prolateness)."""
+        out = np.zeros((self.nw, 8), dtype=np.float64)
+        _check(lib().rewl_structure(self._h, _ptr(out)))
+        return out
 
     def save(self):
         """Checkpoint of the whole run (bytes)."""
@@ -606,3 +615,33 @@ class Batch:
         ms, n = ctypes.c_double(0), ctypes.c_int64(0)
         _check(lib().rewl_batch_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def lipid_structure(coords, lipids, box, out=None, stream=None):
+    """Structural observables (Sec. 3.2, Eqs. 6-8) of lipid configurations on the GPU.
+
+    coords: CUDA float32 [nconf, np, 3]; lipids: CUDA int32 [nconf, nlip, 3]
+    (particle indices, head first), both contiguous.  Returns CUDA float64
+    [nconf, 8] = (S_mol, axis, clusters, largest, Q_xx, Q_yy, Q_zz,
+    prolateness), queued on ``stream`` (default: the current stream)."""
+    import torch
+
+    if coords.dim() != 3 or coords.shape[2] != 3 or lipids.dim() != 3 or lipids.shape[2] != 3:
+        raise ValueError("coords must be [nconf, np, 3] and lipids [nconf, nlip, 3]")
+    if coords.dtype != torch.float32 or lipids.dtype != torch.int32:
+        raise TypeError("coords must be float32 and lipids int32")
+    if not (coords.is_cuda and lipids.is_cuda) or not (coords.is_contiguous() and lipids.is_contiguous()):
+        raise ValueError("coords and lipids must be contiguous CUDA tensors")
+    nconf, np_, nlip = coords.shape[0], coords.shape[1], lipids.shape[1]
+    if lipids.shape[0] != nconf:
+        raise ValueError("coords and lipids hold different numbers of configurations")
+    if out is None:
+        out = torch.empty((nconf, 8), dtype=torch.float64, device=coords.device)
+    elif out.shape != (nconf, 8) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 [nconf, 8] tensor")
+    s = stream if stream is not None else torch.cuda.current_stream(coords.device)
+    _check(lib().rewl_lipid_structure(ctypes.c_void_p(coords.data_ptr()), 12 * np_,
+                                      ctypes.c_void_p(lipids.data_ptr()), 12 * nlip, nconf, np_, nlip,
+                                      float(box), ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(s.cuda_stream)))
+    return out

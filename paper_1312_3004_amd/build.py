@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librewl.so")
 SOURCES = [os.path.join(CSRC, "rewl_kernels.hip"), os.path.join(CSRC, "rewl_runtime.hip"),
            os.path.join(CSRC, "rewl_batch.hip"), os.path.join(CSRC, "rewl_trimer.hip"),
-           os.path.join(CSRC, "rewl_lipid.hip")]
+           os.path.join(CSRC, "rewl_lipid.hip"), os.path.join(CSRC, "rewl_structure.hip")]
 HEADERS = [os.path.join(CSRC, "rewl_device.h"), os.path.join(CSRC, "rewl_host.h"),
            os.path.join(os.path.dirname(HERE), "include", "rewl.h")]
 

@@ -1,0 +1,358 @@
+// rewl_structure.hip -- structural observables of lipid configurations
+// (Sec. 3.2, Eqs. 6-8): the bond order parameter S_mol of the head bonds, the
+// clusters of lipids whose tails touch, and the gyration tensor and
+// prolateness of the largest cluster in unfolded coordinates.
+//
+// One wavefront per configuration.  The lipid beads go to LDS; the contact
+// graph is held as one bit row per lipid (built 64 partners at a time with a
+// ballot); clusters are grown level by level, the frontier and each level's
+// finds as bit masks; the largest cluster is then unfolded level by level in
+// binary64 and reduced.  Sums across lanes use butterfly shuffles, so the
+// floating-point outputs agree with a plain evaluation to rounding, while
+// every integer output (cluster count and sizes, the tree that unfolds a
+// cluster) is decided by the same binary32/binary64 operations as in the
+// definition and is exact.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rewl_host.h"
+
+namespace rewl_gpu {
+
+namespace {
+
+constexpr int kStructMaxLipids = 512;
+constexpr int kStructWords = kStructMaxLipids / 64;
+constexpr double kTailContact2 = 1.96;   // (1.4 sigma)^2
+
+__device__ __forceinline__ double st_min_image(float a, float b, float box, float half) {
+    float x = b - a;
+    if (x > half) x = x - box;
+    else if (x < -half) x = x + box;
+    return (double)x;
+}
+
+__device__ __forceinline__ void st_diff(const float *a, const float *b, float box, float half, double d[3]) {
+    d[0] = st_min_image(a[0], b[0], box, half);
+    d[1] = st_min_image(a[1], b[1], box, half);
+    d[2] = st_min_image(a[2], b[2], box, half);
+}
+
+__device__ __forceinline__ double st_r2(const double d[3]) { return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ bool tails_touch(const float *xi, const float *xj, float box, float half) {
+    // xi, xj: the lipid's three beads (head, centre, end) as 9 floats.
+    double d[3];
+    bool hit = false;
+    for (int a = 1; a < 3; ++a)
+        for (int b = 1; b < 3; ++b) {
+            st_diff(xi + 3 * a, xj + 3 * b, box, half, d);
+            hit = hit || (st_r2(d) < kTailContact2);
+        }
+    return hit;
+}
+
+// Place the beads of a lipid other than `b` through its bonds, starting from
+// bead b (0 head, 1 centre, 2 end) already at u[3 b].
+__device__ __forceinline__ void st_chain(const float *x, double *u, int b, float box, float half) {
+    double d[3];
+    if (b == 1) {
+        st_diff(x + 3, x, box, half, d);
+        for (int a = 0; a < 3; ++a) u[a] = u[3 + a] + d[a];
+        st_diff(x + 3, x + 6, box, half, d);
+        for (int a = 0; a < 3; ++a) u[6 + a] = u[3 + a] + d[a];
+    } else if (b == 2) {
+        st_diff(x + 6, x + 3, box, half, d);
+        for (int a = 0; a < 3; ++a) u[3 + a] = u[6 + a] + d[a];
+        st_diff(x + 3, x, box, half, d);
+        for (int a = 0; a < 3; ++a) u[a] = u[3 + a] + d[a];
+    } else {
+        st_diff(x, x + 3, box, half, d);
+        for (int a = 0; a < 3; ++a) u[3 + a] = u[a] + d[a];
+        st_diff(x + 3, x + 6, box, half, d);
+        for (int a = 0; a < 3; ++a) u[6 + a] = u[3 + a] + d[a];
+    }
+}
+
+// LDS layout for M lipids (W = ceil(M / 64) mask words):
+//   xs  float [M][9]      bead coordinates (head, centre, end)
+//   adj u64   [M][W]      contact rows
+//   u   double[M][9]      unfolded beads of the largest cluster
+//   root, level, parent int32[M]
+//   front u64 [8]         frontier mask
+__global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xbase, size_t xstride,
+                                                       const unsigned char *lbase, size_t lstride, int np, int M,
+                                                       float box, double *out) {
+    extern __shared__ __align__(16) unsigned char st_lds[];
+    const int W = (M + 63) >> 6;
+    uint64_t *adj = (uint64_t *)st_lds;
+    double *u = (double *)(adj + (size_t)M * W);
+    float *xs = (float *)(u + (size_t)M * 9);
+    int *root = (int *)(xs + (size_t)M * 9);
+    int *level = root + M;
+    int *parent = level + M;
+    uint64_t *front = (uint64_t *)(((uintptr_t)(parent + M) + 7) & ~(uintptr_t)7);
+
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x;
+    const float half = 0.5f * box;
+    const float *x = (const float *)(xbase + (size_t)c * xstride);
+    const int32_t *lp = (const int32_t *)(lbase + (size_t)c * lstride);
+    double *rec = out + (size_t)c * 8;
+
+    // Beads to LDS; an index outside [0, np) turns the record into NaN.
+    bool bad = false;
+    for (int l = lane; l < M; l += 64) {
+        for (int b = 0; b < 3; ++b) {
+            const int p = lp[3 * l + b];
+            const bool ok = p >= 0 && p < np;
+            bad = bad || !ok;
+            const int q = ok ? p : 0;
+            for (int a = 0; a < 3; ++a) xs[9 * l + 3 * b + a] = x[3 * q + a];
+        }
+        root[l] = -1;
+    }
+    if (__any(bad)) {
+        if (lane < 8) rec[lane] = __builtin_nan("");
+        return;
+    }
+    __syncthreads();
+
+    // Eq. 6: <cos^2> of the head-to-centre bonds along each axis.
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int l = lane; l < M; l += 64) {
+        double d[3];
+        st_diff(xs + 9 * l, xs + 9 * l + 3, box, half, d);
+        const double r2 = st_r2(d);
+        cx += d[0] * d[0] / r2;
+        cy += d[1] * d[1] / r2;
+        cz += d[2] * d[2] / r2;
+    }
+    cx = wave_sum(cx);
+    cy = wave_sum(cy);
+    cz = wave_sum(cz);
+
+    // Contact rows: row i, word w holds partners j = 64 w + lane.
+    for (int i = 0; i < M; ++i) {
+        const float *xi = xs + 9 * i;
+        for (int w = 0; w < W; ++w) {
+            const int j = 64 * w + lane;
+            const bool hit = j < M && j != i && tails_touch(xi, xs + 9 * j, box, half);
+            const uint64_t m = __ballot(hit);
+            if (lane == 0) adj[(size_t)i * W + w] = m;
+        }
+    }
+    __syncthreads();
+
+    // Clusters, grown breadth first from their lowest free lipid.
+    int ncl = 0, best_root = -1, best_size = 0, best_depth = 0;
+    int start = 0;
+    for (;;) {
+        int r = -1;
+        for (int w = start >> 6; w < W; ++w) {
+            const int j = 64 * w + lane;
+            const uint64_t m = __ballot(j < M && root[j] < 0);
+            if (m) {
+                r = 64 * w + __builtin_ctzll(m);
+                break;
+            }
+        }
+        if (r < 0) break;
+        ++ncl;
+        __syncthreads();
+        if (lane == 0) {
+            root[r] = r;
+            level[r] = 0;
+            parent[r] = -1;
+        }
+        if (lane < kStructWords) front[lane] = (lane == (r >> 6)) ? (1ull << (r & 63)) : 0ull;
+        __syncthreads();
+        int size = 1, k = 0;
+        for (;;) {
+            uint64_t found[kStructWords];
+            int nfound = 0;
+#pragma unroll
+            for (int w = 0; w < kStructWords; ++w) {
+                found[w] = 0;
+                if (w < W) {
+                    const int j = 64 * w + lane;
+                    int p = -1;
+                    if (j < M && root[j] < 0) {
+                        for (int v = 0; v < W; ++v) {
+                            const uint64_t t = adj[(size_t)j * W + v] & front[v];
+                            if (t) {
+                                p = 64 * v + __builtin_ctzll(t);
+                                break;
+                            }
+                        }
+                    }
+                    found[w] = __ballot(p >= 0);
+                    if (p >= 0) {
+                        root[j] = r;
+                        level[j] = k + 1;
+                        parent[j] = p;
+                    }
+                    nfound += __builtin_popcountll(found[w]);
+                }
+            }
+            __syncthreads();
+            if (nfound == 0) break;
+            size += nfound;
+            ++k;
+#pragma unroll
+            for (int w = 0; w < kStructWords; ++w)
+                if (lane == w) front[w] = found[w];
+            __syncthreads();
+        }
+        if (size > best_size) {
+            best_size = size;
+            best_root = r;
+            best_depth = k;
+        }
+        start = r + 1;
+    }
+
+    // Unfold the largest cluster level by level.
+    for (int k = 0; k <= best_depth; ++k) {
+        for (int j = lane; j < M; j += 64) {
+            if (root[j] != best_root || level[j] != k) continue;
+            const float *xj = xs + 9 * j;
+            double *uj = u + 9 * j;
+            if (k == 0) {
+                for (int a = 0; a < 3; ++a) uj[a] = (double)xj[a];
+                st_chain(xj, uj, 0, box, half);
+                continue;
+            }
+            const int i = parent[j];
+            const float *xi = xs + 9 * i;
+            const double *ui = u + 9 * i;
+            int b = 0;
+            for (int pr = 0; pr < 4 && b == 0; ++pr) {
+                const int ba = 1 + (pr >> 1), bb = 1 + (pr & 1);
+                double d[3];
+                st_diff(xi + 3 * ba, xj + 3 * bb, box, half, d);
+                if (st_r2(d) < kTailContact2) {
+                    for (int a = 0; a < 3; ++a) uj[3 * bb + a] = ui[3 * ba + a] + d[a];
+                    b = bb;
+                }
+            }
+            st_chain(xj, uj, b, box, half);
+        }
+        __syncthreads();
+    }
+
+    // Eq. 7 over the 3 x best_size beads, then Eq. 8.
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int j = lane; j < M; j += 64) {
+        if (root[j] != best_root) continue;
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) s[a] += u[9 * j + 3 * b + a];
+    }
+    const double n = 3.0 * (double)best_size;
+    double com[3], q[3];
+    for (int a = 0; a < 3; ++a) com[a] = wave_sum(s[a]) / n;
+    for (int a = 0; a < 3; ++a) s[a] = 0.0;
+    for (int j = lane; j < M; j += 64) {
+        if (root[j] != best_root) continue;
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                const double e = u[9 * j + 3 * b + a] - com[a];
+                s[a] += e * e;
+            }
+    }
+    for (int a = 0; a < 3; ++a) q[a] = wave_sum(s[a]) / n;
+
+    if (lane == 0) {
+        const double sx = 1.5 * (cx / (double)M) - 0.5;
+        const double sy = 1.5 * (cy / (double)M) - 0.5;
+        const double sz = 1.5 * (cz / (double)M) - 0.5;
+        double smax = sx;
+        int axis = 0;
+        if (sy > smax) { smax = sy; axis = 1; }
+        if (sz > smax) { smax = sz; axis = 2; }
+        const double tr = q[0] + q[1] + q[2];
+        const double lam = tr / 3.0;
+        const double e0 = q[0] - lam, e1 = q[1] - lam, e2 = q[2] - lam;
+        const double num = e0 * e0 * e0 + e1 * e1 * e1 + e2 * e2 * e2;
+        rec[0] = smax;
+        rec[1] = (double)axis;
+        rec[2] = (double)ncl;
+        rec[3] = (double)best_size;
+        rec[4] = q[0];
+        rec[5] = q[1];
+        rec[6] = q[2];
+        rec[7] = 9.0 * num / (tr * tr * tr);
+    }
+}
+
+}  // namespace
+
+size_t lipid_structure_lds_bytes(int M) {
+    const size_t W = (size_t)(M + 63) / 64;
+    return (size_t)M * W * 8 + (size_t)M * 72 + (size_t)M * 36 + (size_t)M * 12 + 8 + kStructWords * 8;
+}
+
+hipError_t launch_lipid_structure(const void *coords, size_t xstride, const void *lipids, size_t lstride, int nconf,
+                                  int np, int M, float box, double *out, hipStream_t s) {
+    const size_t lds = lipid_structure_lds_bytes(M);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_lipid_structure,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_lipid_structure, dim3(nconf), dim3(64), lds, s,
+                       (const unsigned char *)coords, xstride, (const unsigned char *)lipids, lstride, np, M, box, out);
+    return hipGetLastError();
+}
+
+}  // namespace rewl_gpu
+
+using rewl_host::fail;
+
+static int check_structure_args(int nconf, int np, int nlip, float box) {
+    if (nconf < 0) return fail(REWL_EINVAL, "nconf must be >= 0");
+    if (nlip < 1 || nlip > rewl_gpu::kStructMaxLipids) return fail(REWL_EINVAL, "nlip must be in [1, 512]");
+    if (np < 3 * nlip) return fail(REWL_EINVAL, "np must be >= 3 nlip");
+    if (!(box > 0.0f) || !(box < 1e30f)) return fail(REWL_EINVAL, "box must be positive and finite");
+    return REWL_OK;
+}
+
+extern "C" int rewl_lipid_structure(const float *coords, size_t coord_stride, const int32_t *lipids,
+                                    size_t lipid_stride, int nconf, int np, int nlip, float box, double *out,
+                                    void *hip_stream) {
+    int st = check_structure_args(nconf, np, nlip, box);
+    if (st != REWL_OK) return st;
+    if (nconf == 0) return REWL_OK;
+    if (!coords || !lipids || !out) return fail(REWL_EINVAL, "null pointer");
+    if (((uintptr_t)coords & 3) || ((uintptr_t)lipids & 3) || ((uintptr_t)out & 7) || (coord_stride & 3) ||
+        (lipid_stride & 3))
+        return fail(REWL_EINVAL, "coords and lipids must be 4-byte aligned (strides too), out 8-byte aligned");
+    if (nconf > 1 && (coord_stride < (size_t)12 * np || lipid_stride < (size_t)12 * nlip))
+        return fail(REWL_EINVAL, "strides smaller than one configuration");
+    HIP_TRY(rewl_gpu::launch_lipid_structure(coords, coord_stride, lipids, lipid_stride, nconf, np, nlip, box, out,
+                                             (hipStream_t)hip_stream));
+    return REWL_OK;
+}
+
+extern "C" int rewl_structure(rewl_t *r, double *out) {
+    if (!r || !out) return fail(REWL_EINVAL, "null argument");
+    const rewl_gpu::DevState &d = r->st;
+    if (d.model != rewl_gpu::kModelLipid3D) return fail(REWL_EINVAL, "not a run of the lipid model");
+    int st = check_structure_args(d.nw, d.nb, d.nmol, d.box);
+    if (st != REWL_OK) return st;
+    double *dev = nullptr;
+    const size_t bytes = (size_t)d.nw * 8 * sizeof(double);
+    HIP_TRY(hipMalloc((void **)&dev, bytes));
+    hipError_t e = rewl_gpu::launch_lipid_structure(d.spins, (size_t)d.Npad, (const unsigned char *)d.spins + d.lip_off_lip,
+                                                    (size_t)d.Npad, d.nw, d.nb, d.nmol, d.box, dev, r->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dev, bytes, hipMemcpyDeviceToHost, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("structure kernel: ") + hipGetErrorString(e));
+    return REWL_OK;
+}

@@ -113,3 +113,15 @@ def test_batch_structs_and_workspace(lib):
     mixed[1].opts.precision = 1
     st = lib.rewl_batch_create(ctypes.byref(h), 2, mixed, None, None, 0, None)
     assert st == pk.EINVAL and b"precision" in lib.rewl_last_error()
+
+
+def test_structure_argument_checks(lib):
+    L = lib
+    EINVAL = -1
+    assert L.rewl_lipid_structure(None, 0, None, 0, 0, 30, 10, ctypes.c_float(10.0), None, None) == 0
+    assert L.rewl_lipid_structure(None, 0, None, 0, 1, 30, 0, ctypes.c_float(10.0), None, None) == EINVAL
+    assert L.rewl_lipid_structure(None, 0, None, 0, 1, 30, 513, ctypes.c_float(10.0), None, None) == EINVAL
+    assert L.rewl_lipid_structure(None, 0, None, 0, 1, 29, 10, ctypes.c_float(10.0), None, None) == EINVAL
+    assert L.rewl_lipid_structure(None, 0, None, 0, 1, 30, 10, ctypes.c_float(0.0), None, None) == EINVAL
+    assert L.rewl_lipid_structure(None, 0, None, 0, 1, 30, 10, ctypes.c_float(10.0), None, None) == EINVAL
+    assert L.rewl_structure(None, None) == EINVAL

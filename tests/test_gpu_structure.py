@@ -1,0 +1,138 @@
+"""GPU parity of the structural observables of the lipid model (Sec. 3.2,
+Eqs. 6-8) with the oracle: cluster count, largest-cluster size and the axis
+of S_mol exact; S_mol, Q_ii and the prolateness to rounding (the kernel sums
+across lanes in butterfly order, the oracle with numpy)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import structure as S
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-10, 1e-12
+
+
+def _pk():
+    import paper_1312_3004_amd as pk
+    return pk
+
+
+def gpu_records(coords, lips, box):
+    import torch
+
+    x = torch.from_numpy(np.ascontiguousarray(coords, dtype=np.float32)).cuda()
+    lp = torch.from_numpy(np.ascontiguousarray(lips, dtype=np.int32)).cuda()
+    out = _pk().lipid_structure(x, lp, box)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_same_record(got, ref, what):
+    # integers: cluster count and largest size exact
+    assert got[2] == ref[2] and got[3] == ref[3], (what, got[:4], ref[:4])
+    # the axis is decided in binary64 on both sides; accept a different axis only on a near tie
+    if got[1] != ref[1]:
+        assert abs(got[0] - ref[0]) <= 1e-12, (what, got[:2], ref[:2])
+    np.testing.assert_allclose(got[[0, 4, 5, 6]], ref[[0, 4, 5, 6]], rtol=RTOL, atol=ATOL, err_msg=what)
+    # P = 9 sum (Q - lambda)^3 / tr^3: absolute rounding scale 1
+    np.testing.assert_allclose(got[7], ref[7], rtol=1e-9, atol=1e-11, err_msg=what)
+
+
+def random_configs(nconf, M, nsol, box, seed, bond=0.97):
+    rng = np.random.default_rng(seed)
+    np_ = 3 * M + nsol
+    xs = rng.uniform(0, box, (nconf, np_, 3))
+    lips = np.zeros((nconf, M, 3), dtype=np.int32)
+    for c in range(nconf):
+        perm = rng.permutation(np_)[:3 * M].reshape(M, 3)   # lipid beads scattered over the indices
+        o = rng.uniform(0, box, (M, 3))
+        v = rng.normal(size=(M, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        w = rng.normal(size=(M, 3))
+        w /= np.linalg.norm(w, axis=1)[:, None]
+        xs[c, perm[:, 0]] = o
+        xs[c, perm[:, 1]] = o + bond * v
+        xs[c, perm[:, 2]] = o + bond * v + bond * w
+        lips[c] = perm
+    return (xs % box).astype(np.float32), lips
+
+
+@pytest.mark.parametrize("nconf,M,nsol,box,seed", [
+    (3, 1, 5, 6.0, 0),        # one lipid
+    (4, 20, 30, 8.0, 1),      # sparse: many small clusters
+    (5, 63, 10, 6.0, 2),      # one mask word, dense
+    (5, 64, 0, 6.5, 3),       # exactly one word
+    (4, 65, 7, 7.0, 4),       # ragged second word
+    (3, 200, 100, 9.0, 5),    # four words, percolating
+    (2, 512, 64, 11.0, 6),    # the maximum: LDS beyond 64 KiB
+])
+def test_random_configurations(nconf, M, nsol, box, seed):
+    print(f"[case] structure random nconf={nconf} M={M} nsol={nsol} box={box} seed={seed}", flush=True)
+    sys.stdout.flush()
+    xs, lips = random_configs(nconf, M, nsol, box, seed)
+    got = gpu_records(xs, lips, box)
+    for c in range(nconf):
+        assert_same_record(got[c], S.structure(xs[c], lips[c], box), f"conf {c}")
+
+
+def test_rods_and_hand_built_clusters():
+    # a ring of 10 lipids closing through the boundary, and a straight rod
+    K, s = 10, 0.6
+    box = 3 * K * s
+    beads = np.zeros((K, 3, 3))
+    beads[:, :, 0] = (s * np.arange(3 * K)).reshape(K, 3)
+    beads[:, :, 1:] = 5.0
+    ring = beads.reshape(-1, 3).astype(np.float32)
+    lip = np.arange(3 * K, dtype=np.int32).reshape(K, 3)
+    print("[case] structure ring", flush=True)
+    got = gpu_records(ring[None], lip[None], box)[0]
+    ref = S.structure(ring, lip, box)
+    assert_same_record(got, ref, "ring")
+    assert got[3] == K and got[4] == pytest.approx(s * s * ((3 * K) ** 2 - 1) / 12, rel=1e-5)
+
+
+def test_bad_index_gives_nan_record_and_others_unaffected():
+    xs, lips = random_configs(3, 10, 5, 6.0, 9)
+    lips = lips.copy()
+    lips[1, 4, 2] = 35  # np = 35: one past the end
+    print("[case] structure bad index", flush=True)
+    got = gpu_records(xs, lips, 6.0)
+    assert np.all(np.isnan(got[1]))
+    for c in (0, 2):
+        assert_same_record(got[c], S.structure(xs[c], lips[c], 6.0), f"conf {c}")
+
+
+def test_empty_batch_and_argument_errors():
+    import torch
+
+    pk = _pk()
+    x = torch.zeros((0, 30, 3), dtype=torch.float32, device="cuda")
+    lp = torch.zeros((0, 10, 3), dtype=torch.int32, device="cuda")
+    assert pk.lipid_structure(x, lp, 5.0).shape == (0, 8)
+    x = torch.zeros((1, 30, 3), dtype=torch.float32, device="cuda")
+    lp = torch.zeros((1, 11, 3), dtype=torch.int32, device="cuda")
+    with pytest.raises(pk.RewlError):
+        pk.lipid_structure(x, lp, 5.0)   # np < 3 nlip
+
+
+def test_run_walkers_on_the_paper_system():
+    # the paper's system (125 lipids, 625 solvent, density 0.8): every walker's
+    # configuration after a short run, against the oracle run's own states
+    c = workloads.LIPID
+    h, m = 4, 2
+    x0 = workloads.init_lipids(c["nlip"], c["nsol"], c["box"], h * m, 1)
+    print("[case] structure on lipid runs (125 lipids, 8 walkers)", flush=True)
+    g = _pk().Rewl.lipid(c["nlip"], c["nsol"], c["box"], c["e_min"], c["bin_w"], c["bins"], h, 0.75, m, x0,
+                         lnf_init=1.0, sync_attempts=400, seed=c["seed"])
+    o = oracle.Rewl.lipid(c["nlip"], c["nsol"], c["box"], c["e_min"], c["bin_w"], c["bins"], h, 0.75, m, x0,
+                          threads=8, lnf_init=1.0, sync_attempts=400, seed=c["seed"])
+    g.run(1200)
+    o.run(1200)
+    got = g.structure()
+    for w in range(h * m):
+        xw, _, lw = o.lipid_state(w)
+        assert_same_record(got[w], S.structure(xw, lw, c["box"]), f"walker {w}")
