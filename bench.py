@@ -622,6 +622,32 @@ def structure_bench(args):
            "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
                         "frac": achieved / ALU_PEAK_TOPS, "traffic": None},
            "mean_largest_cluster": float(rec[:, 3].mean()), "mean_clusters": float(rec[:, 2].mean())}
+    # The production phase of the lipid workload with H(E, O), O = lipids in the
+    # largest cluster, sampled at every sync point (64 walkers, 2,000 attempts each).
+    h, m, S_att = c["windows"], c["walkers"], c["sync_attempts"]
+    x0 = workloads.init_lipids(c["nlip"], c["nsol"], c["box"], h * m, c["seed"])
+    g = pk.Rewl.lipid(c["nlip"], c["nsol"], c["box"], c["e_min"], c["bin_w"], c["bins"], h, c["overlap"], m, x0,
+                      eps_ww=c["eps_ww"], seed=c["seed"], flat=c["flat"], lnf_init=c["lnf_init"],
+                      lnf_final=c["lnf_final"], schedule=c["schedule"], sync_attempts=S_att, exchange=c["exchange"],
+                      obs_bins=M + 1)
+    g.walkin()
+    g.run(2 * S_att)
+    g.begin_production()
+    g.run(2 * S_att)
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    nsteps = 50
+    t0 = time.perf_counter()
+    g.run(nsteps * S_att)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sweep_ms, launches, sync_ms, syncs = g.timing()
+    g.set_timing(False)
+    _, cnt = g.obs_micro()
+    res["production"] = {"attempts_per_s": h * m * S_att * nsteps / el, "steps": nsteps,
+                         "k_lipid_sweep_avg_ms": sweep_ms / max(launches, 1),
+                         "sync_point_avg_ms": sync_ms / max(syncs, 1), "samples": int(cnt.sum())}
+    log(f"[bench] lipid production with H(E, O): {res['production']}")
     if not args.no_cpu_baseline:
         from oracle import structure as S
 

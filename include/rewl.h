@@ -75,10 +75,13 @@ typedef struct {
     int32_t shadow;         /* [0] 1: keep an exact reference of ln g (see           */
                             /*     rewl_get_shadow); costs 20 bytes per bin and walker */
     int32_t walkin_slack;   /* [16] walk-in lid width (energy units), 0 = no lid    */
-    int32_t obs_bins;       /* [0] Potts only: > 0 samples O = max_s n_s at every    */
-                            /*     sync point into H(E, O) with this many O bins   */
-                            /*     (at most L*L+1; see rewl_get_obs); costs        */
-                            /*     4*obs_bins + 12 bytes per bin and walker        */
+    int32_t obs_bins;       /* [0] > 0 samples an observable O at every sync point  */
+                            /*     into H(E, O) with this many O bins (see         */
+                            /*     rewl_get_obs): Potts O = max_s n_s, at most     */
+                            /*     L*L+1 bins; lipid model O = lipids in the       */
+                            /*     largest cluster (rewl_structure), at most       */
+                            /*     nlip+1 bins; costs 4*obs_bins + 12 bytes per    */
+                            /*     bin and walker                                  */
     int32_t reserved;       /* [0] must be 0                                        */
 } rewl_opts;
 
@@ -132,7 +135,9 @@ void rewl_destroy(rewl_t *r);
  * the FENE logarithm is computed from basic IEEE operations, so runs are
  * reproducible bit for bit.  Energy bins and windows as for the trimer model.
  * init_coords: host float[windows*walkers][np][3] in [0, box).  opts:
- * precision 0, shadow 0 and obs_bins 0 only.  rewl_get_particles returns a
+ * precision 0 and shadow 0 only; obs_bins > 0 (at most nlip + 1, with nlip
+ * <= 512) samples H(E, O) with O the lipids in the largest cluster (see
+ * rewl_structure and rewl_get_obs).  rewl_get_particles returns a
  * walker's coordinates, types (0 P, 1 H, 2 W) and lipid rows (particle
  * indices, head first).  Limits: nlip >= 1, np <= 4096, the state row plus
  * 12 bytes per window bin within the 160 KiB LDS of a CU.
@@ -273,10 +278,11 @@ int rewl_begin_production(rewl_t *r);
 
 /* Observable record of walker w (runs with opts.obs_bins > 0).  At every
  * sync point, after its exchange round, each walker adds the configuration it
- * holds: with O = max_s n_s (the population of the most occupied state; the
- * order parameter is (q O / N - 1) / (q - 1)) and b its energy bin in the
- * window, hist[b][floor(O * obs_bins / (N + 1))] += 1, sum[b] += O,
- * count[b] += 1.  Host buffers hist uint32[W][obs_bins], sum uint64[W],
+ * holds: with O = max_s n_s for the Potts model (the population of the most
+ * occupied state; the order parameter is (q O / N - 1) / (q - 1)), or O = the
+ * lipids in the largest cluster for the lipid model (record field [3] of
+ * rewl_structure, with N read as nlip), and b its energy bin in the window,
+ * hist[b][floor(O * obs_bins / (N + 1))] += 1, sum[b] += O, count[b] += 1.  Host buffers hist uint32[W][obs_bins], sum uint64[W],
  * count uint32[W]; any may be NULL.  Errors: REWL_EINVAL on a null handle,
  * w out of range, or a run without observable sampling.                      */
 int rewl_get_obs(rewl_t *r, int walker, uint32_t *hist, uint64_t *sum, uint32_t *count);

@@ -74,6 +74,7 @@ struct DevState {
     unsigned long long *obs_sum; // [nw][Wpad] sum of O per energy bin
     uint32_t *obs_cnt;           // [nw][Wpad] samples per energy bin
     int32_t *production;         // [1] 1: weights frozen, no termination
+    double *obs_rec;             // [nw][8] lipid model: structural records of the last measurement
     int64_t *walkin_att;         // [nw]
     int32_t *walkin_done;        // [nw]
     int32_t *walkin_bound;       // [nw] walk-in lid (walker above its window) or floor
@@ -282,6 +283,9 @@ hipError_t launch_check(const DevState &st, int64_t step, int64_t round_after, h
 hipError_t launch_track(const DevState &st, hipStream_t s);
 hipError_t launch_measure(const DevState &st, hipStream_t s);
 hipError_t launch_begin_production(const DevState &st, hipStream_t s);
+// Lipid model: structural records of every walker, then H(E, O) with O the
+// lipids in the largest cluster (rewl_structure.hip).
+hipError_t launch_lipid_measure(const DevState &st, hipStream_t s);
 hipError_t launch_obs_micro(const DevState &st, double *mean, unsigned long long *count, hipStream_t s);
 hipError_t launch_obs_thermo(const DevState &st, const double *T, int nT, const double *mean, double *out,
                              hipStream_t s);

@@ -47,7 +47,7 @@ struct Layout {
     size_t start, spins, E, Ed, lng, lng_hi, lng_lo, H, sh_hi, sh_lo, hprev, replica, rep_end, rep_trips, rep_visits, walkin_att, walkin_done,
         walkin_bound, walkin_cnt,
         lnf, lnf_last, regime, finished, iterations, visited, x_att, x_acc, converged, stop, joined,
-        cuts, join_status, scratch, T, thermo_out, obs_hist, obs_sum, obs_cnt, production, obs_mean, obs_count,
+        cuts, join_status, scratch, T, thermo_out, obs_hist, obs_sum, obs_cnt, production, obs_mean, obs_count, obs_rec,
         total;
 };
 

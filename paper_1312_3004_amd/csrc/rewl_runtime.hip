@@ -102,6 +102,7 @@ Layout make_layout(const Params &p, int precision, int shadow, bool trimer, int 
         l.obs_cnt = take(sizeof(uint32_t) * (size_t)p.nw * p.Wpad);
         l.obs_mean = take(sizeof(double) * p.Bpad);
         l.obs_count = take(sizeof(unsigned long long) * p.Bpad);
+        if (trimer) l.obs_rec = take(sizeof(double) * 8 * (size_t)p.nw);
     }
     l.total = off;
     return l;
@@ -174,8 +175,10 @@ int check_lipid(TrimerGeom &g, int h, double o, int m, const rewl_opts &op, Para
     if (g.bins < 8) return fail(REWL_EINVAL, "at least 8 energy bins");
     int st = check_opts(h, m, op);
     if (st != REWL_OK) return st;
-    if (op.precision != 0 || op.shadow != 0 || op.obs_bins != 0)
-        return fail(REWL_EINVAL, "the lipid model runs in binary64 without shadow or observable sampling");
+    if (op.precision != 0 || op.shadow != 0)
+        return fail(REWL_EINVAL, "the lipid model runs in binary64 without shadow");
+    if (op.obs_bins > 0 && (op.obs_bins > g.nmol + 1 || g.nmol > 512))
+        return fail(REWL_EINVAL, "lipid observable sampling: obs_bins at most nlip+1, nlip at most 512");
     starts->assign((size_t)std::max(h, 1), 0);
     int W = 0;
     st = layout_bins(g.bins, 0, h, o, &W, starts->data());
@@ -418,6 +421,7 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     d.obs_hist = op.obs_bins > 0 ? (uint32_t *)(b + lay.obs_hist) : nullptr;
     d.obs_sum = op.obs_bins > 0 ? (unsigned long long *)(b + lay.obs_sum) : nullptr;
     d.obs_cnt = op.obs_bins > 0 ? (uint32_t *)(b + lay.obs_cnt) : nullptr;
+    d.obs_rec = op.obs_bins > 0 && geom != nullptr ? (double *)(b + lay.obs_rec) : nullptr;
     d.production = (int32_t *)(b + lay.production);
     d.walkin_att = (int64_t *)(b + lay.walkin_att);
     d.walkin_done = (int32_t *)(b + lay.walkin_done);
@@ -713,7 +717,12 @@ int rewl_run_attempts(rewl_t *r, int64_t attempts) {
                 HIP_TRY(rewl_gpu::launch_exchange(r->st, (uint32_t)r->round, r->stream));
                 r->round += 1;
             }
-            if (r->st.obs_bins > 0) HIP_TRY(rewl_gpu::launch_measure(r->st, r->stream));
+            if (r->st.obs_bins > 0) {
+                if (r->st.model == rewl_gpu::kModelLipid3D)
+                    HIP_TRY(rewl_gpu::launch_lipid_measure(r->st, r->stream));
+                else
+                    HIP_TRY(rewl_gpu::launch_measure(r->st, r->stream));
+            }
             HIP_TRY(rewl_gpu::launch_check(r->st, r->step, r->round, r->stream));
             HIP_TRY(timer_end(r, 1, ev));
             if (!r->opts.fixed_lnf && ++syncs_since_read >= 64) {

@@ -3,11 +3,12 @@
 // clusters of lipids whose tails touch, and the gyration tensor and
 // prolateness of the largest cluster in unfolded coordinates.
 //
-// One wavefront per configuration.  The lipid beads go to LDS; the contact
-// graph is held as one bit row per lipid (built 64 partners at a time with a
-// ballot); clusters are grown level by level, the frontier and each level's
-// finds as bit masks; the largest cluster is then unfolded level by level in
-// binary64 and reduced.  Sums across lanes use butterfly shuffles, so the
+// One workgroup of four wavefronts per configuration.  The lipid beads go to
+// LDS; the contact graph is held as one bit row per lipid (built 64 partners
+// at a time with a ballot, the rows shared among the four wavefronts); then
+// wavefront 0 alone takes S_mol, grows the clusters level by level (the
+// frontier and each level's finds as bit masks), unfolds the largest one
+// level by level in binary64 and reduces it.  Sums across lanes use butterfly shuffles, so the
 // floating-point outputs agree with a plain evaluation to rounding, while
 // every integer output (cluster count and sizes, the tree that unfolds a
 // cluster) is decided by the same binary32/binary64 operations as in the
@@ -24,12 +25,20 @@ namespace {
 constexpr int kStructMaxLipids = 512;
 constexpr int kStructWords = kStructMaxLipids / 64;
 constexpr double kTailContact2 = 1.96;   // (1.4 sigma)^2
+constexpr int kStructWaves = 4;          // wavefronts per configuration for the contact rows
 
+// Orders a wavefront's own LDS writes before its later reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// b - a moved once by -+box when beyond +-box/2 (selects, no branches).
 __device__ __forceinline__ double st_min_image(float a, float b, float box, float half) {
-    float x = b - a;
-    if (x > half) x = x - box;
-    else if (x < -half) x = x + box;
-    return (double)x;
+    const float x = b - a;
+    const float lo = x - box, hi = x + box;
+    return (double)(x > half ? lo : (x < -half ? hi : x));
 }
 
 __device__ __forceinline__ void st_diff(const float *a, const float *b, float box, float half, double d[3]) {
@@ -48,13 +57,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ bool tails_touch(const float *xi, const float *xj, float box, float half) {
     // xi, xj: the lipid's three beads (head, centre, end) as 9 floats.
     double d[3];
-    bool hit = false;
+    int hit = 0;
+#pragma unroll
     for (int a = 1; a < 3; ++a)
+#pragma unroll
         for (int b = 1; b < 3; ++b) {
             st_diff(xi + 3 * a, xj + 3 * b, box, half, d);
-            hit = hit || (st_r2(d) < kTailContact2);
+            hit |= (int)(st_r2(d) < kTailContact2);
         }
-    return hit;
+    return hit != 0;
 }
 
 // Place the beads of a lipid other than `b` through its bonds, starting from
@@ -85,7 +96,7 @@ __device__ __forceinline__ void st_chain(const float *x, double *u, int b, float
 //   u   double[M][9]      unfolded beads of the largest cluster
 //   root, level, parent int32[M]
 //   front u64 [8]         frontier mask
-__global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xbase, size_t xstride,
+__global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xbase, size_t xstride,
                                                        const unsigned char *lbase, size_t lstride, int np, int M,
                                                        float box, double *out) {
     extern __shared__ __align__(16) unsigned char st_lds[];
@@ -98,7 +109,9 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
     int *parent = level + M;
     uint64_t *front = (uint64_t *)(((uintptr_t)(parent + M) + 7) & ~(uintptr_t)7);
 
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int c = blockIdx.x;
     const float half = 0.5f * box;
     const float *x = (const float *)(xbase + (size_t)c * xstride);
@@ -107,7 +120,7 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
 
     // Beads to LDS; an index outside [0, np) turns the record into NaN.
     bool bad = false;
-    for (int l = lane; l < M; l += 64) {
+    for (int l = tid; l < M; l += 64 * kStructWaves) {
         for (int b = 0; b < 3; ++b) {
             const int p = lp[3 * l + b];
             const bool ok = p >= 0 && p < np;
@@ -117,11 +130,31 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
         }
         root[l] = -1;
     }
-    if (__any(bad)) {
-        if (lane < 8) rec[lane] = __builtin_nan("");
+    if (__syncthreads_or(bad)) {
+        if (tid < 8) rec[tid] = __builtin_nan("");
         return;
     }
+
+    // Contact rows: row i, word w holds partners j = 64 w + lane; wavefront v
+    // builds rows i = v mod 4.  Each lane keeps its own lipid's beads in
+    // registers (NaN past the end, which never touches) and reads lipid i's,
+    // the same address for all lanes.
+    for (int w = 0; w < W; ++w) {
+        const int j = 64 * w + lane;
+        float tj[9];
+        for (int a = 0; a < 9; ++a) tj[a] = j < M ? xs[9 * j + a] : __builtin_nanf("");
+#pragma unroll 4
+        for (int i = wave; i < M; i += kStructWaves) {
+            const bool hit = tails_touch(xs + 9 * i, tj, box, half) & (j != i);
+            const uint64_t m = __ballot(hit);
+            if (lane == 0) adj[(size_t)i * W + w] = m;
+        }
+    }
     __syncthreads();
+    // The rest runs on wavefront 0 alone: the others leave after the last
+    // workgroup barrier, and wavefront 0 orders its LDS traffic with
+    // wave-level fences from here on.
+    if (wave != 0) return;
 
     // Eq. 6: <cos^2> of the head-to-centre bonds along each axis.
     double cx = 0.0, cy = 0.0, cz = 0.0;
@@ -136,18 +169,6 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
     cx = wave_sum(cx);
     cy = wave_sum(cy);
     cz = wave_sum(cz);
-
-    // Contact rows: row i, word w holds partners j = 64 w + lane.
-    for (int i = 0; i < M; ++i) {
-        const float *xi = xs + 9 * i;
-        for (int w = 0; w < W; ++w) {
-            const int j = 64 * w + lane;
-            const bool hit = j < M && j != i && tails_touch(xi, xs + 9 * j, box, half);
-            const uint64_t m = __ballot(hit);
-            if (lane == 0) adj[(size_t)i * W + w] = m;
-        }
-    }
-    __syncthreads();
 
     // Clusters, grown breadth first from their lowest free lipid.
     int ncl = 0, best_root = -1, best_size = 0, best_depth = 0;
@@ -164,14 +185,14 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
         }
         if (r < 0) break;
         ++ncl;
-        __syncthreads();
+        wave_sync();
         if (lane == 0) {
             root[r] = r;
             level[r] = 0;
             parent[r] = -1;
         }
         if (lane < kStructWords) front[lane] = (lane == (r >> 6)) ? (1ull << (r & 63)) : 0ull;
-        __syncthreads();
+        wave_sync();
         int size = 1, k = 0;
         for (;;) {
             uint64_t found[kStructWords];
@@ -200,14 +221,14 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
                     nfound += __builtin_popcountll(found[w]);
                 }
             }
-            __syncthreads();
+            wave_sync();
             if (nfound == 0) break;
             size += nfound;
             ++k;
 #pragma unroll
             for (int w = 0; w < kStructWords; ++w)
                 if (lane == w) front[w] = found[w];
-            __syncthreads();
+            wave_sync();
         }
         if (size > best_size) {
             best_size = size;
@@ -243,7 +264,7 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
             }
             st_chain(xj, uj, b, box, half);
         }
-        __syncthreads();
+        wave_sync();
     }
 
     // Eq. 7 over the 3 x best_size beads, then Eq. 8.
@@ -290,6 +311,23 @@ __global__ __launch_bounds__(64) void k_lipid_structure(const unsigned char *xba
     }
 }
 
+// H(E, O) of the lipid model at a sync point (Sec. 3.2), one thread per
+// walker: O = lipids in the largest cluster of the record just computed,
+// O bin O obs_bins / (nlip + 1), added at the walker's energy bin within its
+// window (each walker owns its cells: no atomics).
+__global__ __launch_bounds__(64) void k_measure_lipid(DevState st) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= st.nw || *st.converged) return;
+    const int O = (int)st.obs_rec[(size_t)w * 8 + 3];
+    const int b = st.E[w] - st.start[w / st.m];
+    if (b < 0 || b >= st.W) return;
+    const size_t cell = (size_t)w * st.Wpad + b;
+    const int ob = (int)(((long long)O * st.obs_bins) / (st.nmol + 1));
+    st.obs_hist[cell * st.obs_bins + ob] += 1u;
+    st.obs_sum[cell] += (unsigned long long)O;
+    st.obs_cnt[cell] += 1u;
+}
+
 }  // namespace
 
 size_t lipid_structure_lds_bytes(int M) {
@@ -305,8 +343,17 @@ hipError_t launch_lipid_structure(const void *coords, size_t xstride, const void
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_lipid_structure, dim3(nconf), dim3(64), lds, s,
+    hipLaunchKernelGGL(k_lipid_structure, dim3(nconf), dim3(64 * kStructWaves), lds, s,
                        (const unsigned char *)coords, xstride, (const unsigned char *)lipids, lstride, np, M, box, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lipid_measure(const DevState &st, hipStream_t s) {
+    const unsigned char *rows = (const unsigned char *)st.spins;
+    hipError_t e = launch_lipid_structure(rows, (size_t)st.Npad, rows + st.lip_off_lip, (size_t)st.Npad, st.nw, st.nb,
+                                          st.nmol, st.box, st.obs_rec, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_measure_lipid, dim3((unsigned)((st.nw + 63) / 64)), dim3(64), 0, s, st);
     return hipGetLastError();
 }
 

@@ -136,3 +136,56 @@ def test_run_walkers_on_the_paper_system():
     for w in range(h * m):
         xw, _, lw = o.lipid_state(w)
         assert_same_record(got[w], S.structure(xw, lw, c["box"]), f"walker {w}")
+
+
+def oracle_obs(o, nlip, box, obs_bins, hist, sums, cnt):
+    """Add every walker's sample at a sync point: O = lipids in the largest cluster."""
+    for w in range(o.nw):
+        xw, _, lw = o.lipid_state(w)
+        O = int(S.structure(xw, lw, box)[3])
+        b = o.walker(w)["E"] - int(o.starts[w // o.m])
+        if 0 <= b < o.W:
+            hist[w, b, O * obs_bins // (nlip + 1)] += 1
+            sums[w, b] += O
+            cnt[w, b] += 1
+
+
+@pytest.mark.parametrize("nlip,nsol,box,e_min,bins,h,m,S_att,syncs,rep_prob,obs_bins", [
+    (6, 60, 5.0, 300.0, 320, 3, 2, 300, 8, 0.3, 7),
+    (10, 40, 5.0, 300.0, 400, 2, 2, 250, 8, 0.5, 4),
+])
+def test_lipid_production_h_of_e_and_largest_cluster(nlip, nsol, box, e_min, bins, h, m, S_att, syncs, rep_prob,
+                                                     obs_bins):
+    # H(E, O) of the production phase (Sec. 3.2) against the oracle run's own
+    # states, sampled by the oracle's structure() at each sync point
+    x0 = workloads.init_lipids(nlip, nsol, box, h * m, 2)
+    print(f"[case] lipid production H(E, O) nlip={nlip} nsol={nsol} h={h} m={m} obs_bins={obs_bins}", flush=True)
+    opts = dict(rep_prob=rep_prob, lnf_init=0.05, fixed_lnf=1, sync_attempts=S_att, exchange=1, seed=4)
+    g = _pk().Rewl.lipid(nlip, nsol, box, e_min, 0.5, bins, h, 0.75, m, x0, obs_bins=obs_bins, **opts)
+    o = oracle.Rewl.lipid(nlip, nsol, box, e_min, 0.5, bins, h, 0.75, m, x0, threads=8, **opts)
+    g.run(2 * S_att)
+    o.run(2 * S_att)
+    g.begin_production()
+    o.begin_production()
+    nw, W = h * m, o.W
+    hist = np.zeros((nw, W, obs_bins), dtype=np.uint32)
+    sums = np.zeros((nw, W), dtype=np.uint64)
+    cnt = np.zeros((nw, W), dtype=np.uint32)
+    for _ in range(syncs):
+        o.run(S_att)
+        oracle_obs(o, nlip, box, obs_bins, hist, sums, cnt)
+    g.run(syncs * S_att)
+    for w in range(nw):
+        gh, gs, gc = g.obs(w)
+        assert np.array_equal(gh, hist[w]), f"H(E, O) of walker {w}"
+        assert np.array_equal(gs, sums[w]) and np.array_equal(gc, cnt[w]), f"sum/count of walker {w}"
+    assert cnt.sum() == nw * syncs  # walkers never leave their windows
+    mean, c = g.obs_micro()
+    assert c.sum() == cnt.sum()
+
+
+def test_lipid_obs_bins_limits():
+    pk = _pk()
+    x = workloads.init_lipids(4, 20, 4.3, 2, 1)
+    with pytest.raises(pk.RewlError):
+        pk.Rewl.lipid(4, 20, 4.3, 200.0, 0.5, 160, 1, 0.75, 2, x, obs_bins=6)   # more than nlip + 1 bins
