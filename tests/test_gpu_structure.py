@@ -189,3 +189,33 @@ def test_lipid_obs_bins_limits():
     x = workloads.init_lipids(4, 20, 4.3, 2, 1)
     with pytest.raises(pk.RewlError):
         pk.Rewl.lipid(4, 20, 4.3, 200.0, 0.5, 160, 1, 0.75, 2, x, obs_bins=6)   # more than nlip + 1 bins
+
+
+def test_lipid_production_h_of_e_on_the_paper_system():
+    # 125 lipids in 625 solvent particles: H(E, O) over three production sync
+    # intervals, O = lipids in the largest cluster in all 126 bins
+    c = workloads.LIPID
+    h, m, S_att, syncs = 4, 2, 400, 3
+    nlip, box, obs_bins = c["nlip"], c["box"], c["nlip"] + 1
+    x0 = workloads.init_lipids(nlip, c["nsol"], box, h * m, 3)
+    print("[case] lipid production H(E, O) on the paper system", flush=True)
+    opts = dict(lnf_init=1.0, sync_attempts=S_att, seed=c["seed"])
+    g = _pk().Rewl.lipid(nlip, c["nsol"], box, c["e_min"], c["bin_w"], c["bins"], h, 0.75, m, x0,
+                         obs_bins=obs_bins, **opts)
+    o = oracle.Rewl.lipid(nlip, c["nsol"], box, c["e_min"], c["bin_w"], c["bins"], h, 0.75, m, x0, threads=8,
+                          **opts)
+    g.run(S_att)
+    o.run(S_att)
+    g.begin_production()
+    o.begin_production()
+    hist = np.zeros((h * m, o.W, obs_bins), dtype=np.uint32)
+    sums = np.zeros((h * m, o.W), dtype=np.uint64)
+    cnt = np.zeros((h * m, o.W), dtype=np.uint32)
+    for _ in range(syncs):
+        o.run(S_att)
+        oracle_obs(o, nlip, box, obs_bins, hist, sums, cnt)
+    g.run(syncs * S_att)
+    for w in range(h * m):
+        gh, gs, gc = g.obs(w)
+        assert np.array_equal(gh, hist[w]) and np.array_equal(gs, sums[w]) and np.array_equal(gc, cnt[w]), w
+    assert cnt.sum() == h * m * syncs
