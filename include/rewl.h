@@ -79,9 +79,9 @@ typedef struct {
                             /*     into H(E, O) with this many O bins (see         */
                             /*     rewl_get_obs): Potts O = max_s n_s, at most     */
                             /*     L*L+1 bins; lipid model O = lipids in the       */
-                            /*     largest cluster (rewl_structure), at most       */
-                            /*     nlip+1 bins; costs 4*obs_bins + 12 bytes per    */
-                            /*     bin and walker                                  */
+                            /*     largest cluster or another structural field     */
+                            /*     (rewl_lipid_obs_field), at most 4096 bins;      */
+                            /*     costs 4*obs_bins + 12 bytes per bin and walker  */
     int32_t reserved;       /* [0] must be 0                                        */
 } rewl_opts;
 
@@ -135,9 +135,10 @@ void rewl_destroy(rewl_t *r);
  * the FENE logarithm is computed from basic IEEE operations, so runs are
  * reproducible bit for bit.  Energy bins and windows as for the trimer model.
  * init_coords: host float[windows*walkers][np][3] in [0, box).  opts:
- * precision 0 and shadow 0 only; obs_bins > 0 (at most nlip + 1, with nlip
- * <= 512) samples H(E, O) with O the lipids in the largest cluster (see
- * rewl_structure and rewl_get_obs).  rewl_get_particles returns a
+ * precision 0 and shadow 0 only; obs_bins > 0 (at most 4096, with nlip <=
+ * 512) samples H(E, O) with O the lipids in the largest cluster or another
+ * structural field (see rewl_structure, rewl_lipid_obs_field and
+ * rewl_get_obs).  rewl_get_particles returns a
  * walker's coordinates, types (0 P, 1 H, 2 W) and lipid rows (particle
  * indices, head first).  Limits: nlip >= 1, np <= 4096, the state row plus
  * 12 bytes per window bin within the 160 KiB LDS of a CU.
@@ -192,6 +193,19 @@ int rewl_get_particles(rewl_t *r, int walker, float *coords, int8_t *types, int3
 int rewl_lipid_structure(const float *coords, size_t coord_stride, const int32_t *lipids, size_t lipid_stride,
                          int nconf, int np, int nlip, float box, double *out, void *hip_stream);
 int rewl_structure(rewl_t *r, double *out);
+
+/* Which structural observable a lipid run with obs_bins > 0 histograms in
+ * H(E, O) (Sec. 3.2 records H(E, O) for S_mol, Q_ii and P).  field 3 (the
+ * default at creation): O = lipids in the largest cluster, O bin O obs_bins /
+ * (nlip + 1).  field 0, 4, 5, 6 or 7 (S_mol, Q_xx, Q_yy, Q_zz, P of the
+ * rewl_structure record): O = floor((v - lo) / (hi - lo) * obs_bins), held to
+ * [0, obs_bins - 1], is both the O bin and the value summed by rewl_get_obs
+ * (rewl_obs_micro then gives the mean bin index).  Applies from the next sync
+ * point; rewl_begin_production clears what was sampled before.  Not part of a
+ * checkpoint: after rewl_load the default applies.  Errors: REWL_EINVAL for a
+ * null handle, a run of another model or without obs_bins, another field, or
+ * lo, hi not finite with lo < hi.                                            */
+int rewl_lipid_obs_field(rewl_t *r, int field, double lo, double hi);
 
 /* ---- Continuous-move model: amphiphilic trimers ---------------------------
  * nmol head-tail-tail molecules (bead 3i the head, 3i+1 and 3i+2 its tails)
@@ -281,9 +295,10 @@ int rewl_begin_production(rewl_t *r);
  * holds: with O = max_s n_s for the Potts model (the population of the most
  * occupied state; the order parameter is (q O / N - 1) / (q - 1)), or O = the
  * lipids in the largest cluster for the lipid model (record field [3] of
- * rewl_structure, with N read as nlip), and b its energy bin in the window,
- * hist[b][floor(O * obs_bins / (N + 1))] += 1, sum[b] += O, count[b] += 1.  Host buffers hist uint32[W][obs_bins], sum uint64[W],
- * count uint32[W]; any may be NULL.  Errors: REWL_EINVAL on a null handle,
+ * rewl_structure, with N read as nlip; rewl_lipid_obs_field selects another
+ * field), and b its energy bin in the window, hist[b][floor(O * obs_bins /
+ * (N + 1))] += 1, sum[b] += O, count[b] += 1.  Host buffers hist
+ * uint32[W][obs_bins], sum uint64[W], count uint32[W]; any may be NULL.  Errors: REWL_EINVAL on a null handle,
  * w out of range, or a run without observable sampling.                      */
 int rewl_get_obs(rewl_t *r, int walker, uint32_t *hist, uint64_t *sum, uint32_t *count);
 

@@ -110,6 +110,7 @@ def lib():
         L.rewl_get_particles.argtypes = [P, i32, P, P, P]
         L.rewl_lipid_structure.argtypes = [P, ctypes.c_size_t, P, ctypes.c_size_t, i32, i32, i32, flt, P, P]
         L.rewl_structure.argtypes = [P, P]
+        L.rewl_lipid_obs_field.argtypes = [P, i32, dbl, dbl]
         L.rewl_get_energy.argtypes = [P, i32, ctypes.POINTER(dbl)]
         L.rewl_save.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.rewl_load.argtypes = [P, P, ctypes.c_size_t]
@@ -315,6 +316,11 @@ class Rewl:
         out = np.zeros((self.nw, 8), dtype=np.float64)
         _check(lib().rewl_structure(self._h, _ptr(out)))
         return out
+
+    def lipid_obs_field(self, field, lo=0.0, hi=0.0):
+        """Record field binned as O in H(E, O): 3 (largest cluster, the default), or 0, 4-7
+        (S_mol, Q_xx, Q_yy, Q_zz, prolateness) in obs_bins bins over [lo, hi)."""
+        _check(lib().rewl_lipid_obs_field(self._h, int(field), float(lo), float(hi)))
 
     def save(self):
         """Checkpoint of the whole run (bytes)."""

@@ -70,6 +70,8 @@ struct DevState {
     uint32_t *rep_visits;        // [nw][nw] lookups that found replica r in slot w (null above
                                  // kMaxVisitWalkers walkers)
     int obs_bins;                // O bins of H(E, O); 0: observables not sampled
+    int obs_field;               // lipid model: record field binned as O (3: largest cluster)
+    double obs_lo, obs_hi;       // lipid model: range of a floating-point O field
     uint32_t *obs_hist;          // [nw][Wpad][obs_bins] H(E, O) per walker
     unsigned long long *obs_sum; // [nw][Wpad] sum of O per energy bin
     uint32_t *obs_cnt;           // [nw][Wpad] samples per energy bin

@@ -177,8 +177,8 @@ int check_lipid(TrimerGeom &g, int h, double o, int m, const rewl_opts &op, Para
     if (st != REWL_OK) return st;
     if (op.precision != 0 || op.shadow != 0)
         return fail(REWL_EINVAL, "the lipid model runs in binary64 without shadow");
-    if (op.obs_bins > 0 && (op.obs_bins > g.nmol + 1 || g.nmol > 512))
-        return fail(REWL_EINVAL, "lipid observable sampling: obs_bins at most nlip+1, nlip at most 512");
+    if (op.obs_bins > 0 && (op.obs_bins > 4096 || g.nmol > 512))
+        return fail(REWL_EINVAL, "lipid observable sampling: obs_bins at most 4096, nlip at most 512");
     starts->assign((size_t)std::max(h, 1), 0);
     int W = 0;
     st = layout_bins(g.bins, 0, h, o, &W, starts->data());
@@ -422,6 +422,8 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     d.obs_sum = op.obs_bins > 0 ? (unsigned long long *)(b + lay.obs_sum) : nullptr;
     d.obs_cnt = op.obs_bins > 0 ? (uint32_t *)(b + lay.obs_cnt) : nullptr;
     d.obs_rec = op.obs_bins > 0 && geom != nullptr ? (double *)(b + lay.obs_rec) : nullptr;
+    d.obs_field = 3;
+    d.obs_lo = d.obs_hi = 0.0;
     d.production = (int32_t *)(b + lay.production);
     d.walkin_att = (int64_t *)(b + lay.walkin_att);
     d.walkin_done = (int32_t *)(b + lay.walkin_done);

@@ -312,17 +312,27 @@ __global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xb
 }
 
 // H(E, O) of the lipid model at a sync point (Sec. 3.2), one thread per
-// walker: O = lipids in the largest cluster of the record just computed,
-// O bin O obs_bins / (nlip + 1), added at the walker's energy bin within its
-// window (each walker owns its cells: no atomics).
+// walker, from the record just computed: O = lipids in the largest cluster
+// (field 3), O bin O obs_bins / (nlip + 1); or, for a floating-point field v,
+// O = its bin floor((v - lo) / (hi - lo) * obs_bins) held to [0, obs_bins).
+// The sample goes to the walker's energy bin within its window (each walker
+// owns its cells: no atomics).
 __global__ __launch_bounds__(64) void k_measure_lipid(DevState st) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= st.nw || *st.converged) return;
-    const int O = (int)st.obs_rec[(size_t)w * 8 + 3];
     const int b = st.E[w] - st.start[w / st.m];
     if (b < 0 || b >= st.W) return;
+    int O, ob;
+    if (st.obs_field == 3) {
+        O = (int)st.obs_rec[(size_t)w * 8 + 3];
+        ob = (int)(((long long)O * st.obs_bins) / (st.nmol + 1));
+    } else {
+        const double v = st.obs_rec[(size_t)w * 8 + st.obs_field];
+        const double t = (v - st.obs_lo) / (st.obs_hi - st.obs_lo) * (double)st.obs_bins;
+        O = t >= 0.0 ? (t < (double)st.obs_bins ? (int)t : st.obs_bins - 1) : 0;
+        ob = O;
+    }
     const size_t cell = (size_t)w * st.Wpad + b;
-    const int ob = (int)(((long long)O * st.obs_bins) / (st.nmol + 1));
     st.obs_hist[cell * st.obs_bins + ob] += 1u;
     st.obs_sum[cell] += (unsigned long long)O;
     st.obs_cnt[cell] += 1u;
@@ -383,6 +393,24 @@ extern "C" int rewl_lipid_structure(const float *coords, size_t coord_stride, co
         return fail(REWL_EINVAL, "strides smaller than one configuration");
     HIP_TRY(rewl_gpu::launch_lipid_structure(coords, coord_stride, lipids, lipid_stride, nconf, np, nlip, box, out,
                                              (hipStream_t)hip_stream));
+    return REWL_OK;
+}
+
+extern "C" int rewl_lipid_obs_field(rewl_t *r, int field, double lo, double hi) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    rewl_gpu::DevState &d = r->st;
+    if (d.model != rewl_gpu::kModelLipid3D) return fail(REWL_EINVAL, "not a run of the lipid model");
+    if (d.obs_bins <= 0) return fail(REWL_EINVAL, "the run samples no observable (opts.obs_bins = 0)");
+    if (field == 3) {
+        d.obs_field = 3;
+        d.obs_lo = d.obs_hi = 0.0;
+        return REWL_OK;
+    }
+    if (field != 0 && (field < 4 || field > 7)) return fail(REWL_EINVAL, "field must be 0, 3, 4, 5, 6 or 7");
+    if (!(lo > -1e300 && hi < 1e300 && hi > lo)) return fail(REWL_EINVAL, "need finite lo < hi");
+    d.obs_field = field;
+    d.obs_lo = lo;
+    d.obs_hi = hi;
     return REWL_OK;
 }
 

@@ -188,7 +188,7 @@ def test_lipid_obs_bins_limits():
     pk = _pk()
     x = workloads.init_lipids(4, 20, 4.3, 2, 1)
     with pytest.raises(pk.RewlError):
-        pk.Rewl.lipid(4, 20, 4.3, 200.0, 0.5, 160, 1, 0.75, 2, x, obs_bins=6)   # more than nlip + 1 bins
+        pk.Rewl.lipid(4, 20, 4.3, 200.0, 0.5, 160, 1, 0.75, 2, x, obs_bins=4097)   # more than 4096 bins
 
 
 def test_lipid_production_h_of_e_on_the_paper_system():
@@ -219,3 +219,59 @@ def test_lipid_production_h_of_e_on_the_paper_system():
         gh, gs, gc = g.obs(w)
         assert np.array_equal(gh, hist[w]) and np.array_equal(gs, sums[w]) and np.array_equal(gc, cnt[w]), w
     assert cnt.sum() == h * m * syncs
+
+
+def binned(v, lo, hi, bins):
+    t = (v - lo) / (hi - lo) * bins
+    q = int(t) if 0.0 <= t < bins else (bins - 1 if t >= bins else 0)
+    return q, abs(t - round(t)) if 0.0 < t < bins else 1.0
+
+
+@pytest.mark.parametrize("field,lo,hi,obs_bins", [(0, -0.5, 1.0, 12), (7, -0.25, 2.0, 9), (4, 0.0, 3.0, 10)])
+def test_lipid_h_of_e_for_a_floating_point_field(field, lo, hi, obs_bins):
+    # H(E, O) over S_mol, the prolateness or Q_xx in obs_bins bins over [lo, hi)
+    nlip, nsol, box, e_min, bins, h, m, S_att, syncs = 6, 60, 5.0, 300.0, 320, 3, 2, 300, 8
+    x0 = workloads.init_lipids(nlip, nsol, box, h * m, 2)
+    print(f"[case] lipid production H(E, O) field={field} range=[{lo}, {hi}) bins={obs_bins}", flush=True)
+    opts = dict(rep_prob=0.3, lnf_init=0.05, fixed_lnf=1, sync_attempts=S_att, exchange=1, seed=4)
+    g = _pk().Rewl.lipid(nlip, nsol, box, e_min, 0.5, bins, h, 0.75, m, x0, obs_bins=obs_bins, **opts)
+    o = oracle.Rewl.lipid(nlip, nsol, box, e_min, 0.5, bins, h, 0.75, m, x0, threads=8, **opts)
+    g.lipid_obs_field(field, lo, hi)
+    g.run(2 * S_att)
+    o.run(2 * S_att)
+    g.begin_production()
+    o.begin_production()
+    nw, W = h * m, o.W
+    hist = np.zeros((nw, W, obs_bins), dtype=np.uint32)
+    sums = np.zeros((nw, W), dtype=np.uint64)
+    edge = 1.0
+    for _ in range(syncs):
+        o.run(S_att)
+        for w in range(nw):
+            xw, _, lw = o.lipid_state(w)
+            q, e = binned(S.structure(xw, lw, box)[field], lo, hi, obs_bins)
+            edge = min(edge, e)
+            b = o.walker(w)["E"] - int(o.starts[w // m])
+            hist[w, b, q] += 1
+            sums[w, b] += q
+    g.run(syncs * S_att)
+    got = np.stack([g.obs(w)[0] for w in range(nw)])
+    gsum = np.stack([g.obs(w)[1] for w in range(nw)])
+    if edge > 1e-9:   # no sample within rounding of a bin edge: the histograms agree exactly
+        assert np.array_equal(got, hist) and np.array_equal(gsum, sums)
+    else:
+        assert np.abs(got.astype(np.int64) - hist).sum() <= 2 and got.sum() == hist.sum()
+    assert hist.sum() == nw * syncs and len(np.unique(np.nonzero(hist)[2])) >= 2
+
+
+def test_lipid_obs_field_argument_errors():
+    pk = _pk()
+    x = workloads.init_lipids(4, 20, 4.3, 2, 1)
+    g = pk.Rewl.lipid(4, 20, 4.3, 200.0, 0.5, 160, 1, 0.75, 2, x, obs_bins=5)
+    for args in [(1, 0.0, 1.0), (8, 0.0, 1.0), (0, 1.0, 1.0), (0, 0.0, float("inf"))]:
+        with pytest.raises(pk.RewlError):
+            g.lipid_obs_field(*args)
+    g.lipid_obs_field(3)
+    g2 = pk.Rewl.lipid(4, 20, 4.3, 200.0, 0.5, 160, 1, 0.75, 2, x)
+    with pytest.raises(pk.RewlError):
+        g2.lipid_obs_field(0, -0.5, 1.0)   # no observable sampling
