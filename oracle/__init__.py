@@ -4,7 +4,8 @@ Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  The product library never loads it: it exists to prove
 the GPU path right.  The arithmetic lives in rewl_oracle.c (plain C, binary64,
 no FMA); this module only loads that library and marshals arguments, plus the
-brute-force density of states in bruteforce.py.
+brute-force density of states in bruteforce.py and the lipid model's
+structural observables (numpy) in structure.py.
 """
 import ctypes
 import os
