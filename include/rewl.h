@@ -328,6 +328,12 @@ int rewl_get_progress(rewl_t *r, int64_t *step, int64_t *round, int32_t *converg
 int rewl_get_walker(rewl_t *r, int walker, int8_t *spins, int32_t *E, uint32_t *H, double *lng,
                     uint32_t *replica, int64_t *walkin_attempts);
 
+/* The walker's state in one call (any pointer may be NULL): spins, E, H and
+ * ln g as rewl_get_walker, and lnf, the current ln f of the walker's window
+ * as rewl_get_window.  Errors: REWL_EINVAL on a null handle or w out of
+ * range, REWL_EDEVICE on a HIP failure.                                       */
+int rewl_get_state(rewl_t *r, int walker, int8_t *spins, int32_t *E, uint32_t *H, double *lng, double *lnf);
+
 /* State of window k (any pointer may be NULL): current ln f (0 once
  * finished), the ln f that finished it, regime (0 halving, 1 1/t), finished
  * flag, number of ln f reductions, visited flags uint8[W] (union over the

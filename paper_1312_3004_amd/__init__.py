@@ -88,6 +88,7 @@ def lib():
         L.rewl_get_progress.argtypes = [P, P, P, P]
         L.rewl_get_walker.argtypes = [P, i32, P, P, P, P, P, P]
         L.rewl_get_window.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+        L.rewl_get_state.argtypes = [P, i32, P, P, P, P, P]
         L.rewl_set_lng.argtypes = [P, i32, P]
         L.rewl_get_shadow.argtypes = [P, i32, P, P]
         L.rewl_get_replicas.argtypes = [P, P, P]
@@ -396,6 +397,17 @@ class Rewl:
         _check(lib().rewl_get_walker(self._h, w, _ptr(spins), ctypes.byref(E), _ptr(H), _ptr(lng),
                                      ctypes.byref(rep), ctypes.byref(wa)))
         return dict(spins=spins, E=E.value, H=H, lng=lng, replica=rep.value, walkin_attempts=wa.value)
+
+    def state(self, w):
+        """Walker w's spins, E, H, ln g and its window's current ln f in one call."""
+        spins = np.zeros(self.N, dtype=np.int8)
+        E = ctypes.c_int32(0)
+        H = np.zeros(self.W, dtype=np.uint32)
+        lng = np.zeros(self.W)
+        lnf = ctypes.c_double(0)
+        _check(lib().rewl_get_state(self._h, w, _ptr(spins), ctypes.byref(E), _ptr(H), _ptr(lng),
+                                    ctypes.byref(lnf)))
+        return dict(spins=spins, E=E.value, H=H, lng=lng, lnf=lnf.value)
 
     def window(self, k):
         lnf, lnf_last = ctypes.c_double(0), ctypes.c_double(0)

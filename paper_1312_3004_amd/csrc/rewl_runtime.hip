@@ -875,6 +875,14 @@ int rewl_get_walker(rewl_t *r, int w, int8_t *spins, int32_t *E, uint32_t *H, do
     return REWL_OK;
 }
 
+int rewl_get_state(rewl_t *r, int w, int8_t *spins, int32_t *E, uint32_t *H, double *lng, double *lnf) {
+    if (!r) return fail(REWL_EINVAL, "null handle");
+    if (w < 0 || w >= r->st.nw) return fail(REWL_EINVAL, "walker index out of range");
+    const int st = rewl_get_walker(r, w, spins, E, H, lng, nullptr, nullptr);
+    if (st != REWL_OK || !lnf) return st;
+    return rewl_get_window(r, w / r->st.m, lnf, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
 int rewl_get_window(rewl_t *r, int k, double *lnf, double *lnf_last, int32_t *regime, int32_t *finished,
                     int64_t *iterations, uint8_t *visited, uint64_t *x_att, uint64_t *x_acc) {
     if (!r) return fail(REWL_EINVAL, "null handle");

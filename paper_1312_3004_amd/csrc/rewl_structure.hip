@@ -68,6 +68,34 @@ __device__ __forceinline__ bool tails_touch(const float *xi, const float *xj, fl
     return hit != 0;
 }
 
+// The same decision from binary32 squared distances where they settle it:
+// fl32((dx^2 + dy^2) + dz^2) of the binary32 differences is within 3 ulp
+// (1.8e-7 relative) of the exact sum, and the binary64 sum within 2.3e-16, so
+// a value below 1.959997 (1.96 (1 - 1.5e-6)) is a contact and one above
+// 1.960003 is not.  *unsure is set when a pair falls between (NaN never
+// does); the caller then takes tails_touch.
+__device__ __forceinline__ bool tails_touch_fast(const float *xi, const float *xj, float box, float half,
+                                                 bool *unsure) {
+    int hit = 0, amb = 0;
+#pragma unroll
+    for (int a = 1; a < 3; ++a)
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+            float d[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float x = xj[3 * b + c] - xi[3 * a + c];
+                const float lo = x - box, hi = x + box;
+                d[c] = x > half ? lo : (x < -half ? hi : x);
+            }
+            const float r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            hit |= (int)(r2 < 1.959997f);
+            amb |= (int)(r2 >= 1.959997f && r2 <= 1.960003f);
+        }
+    *unsure = amb != 0;
+    return hit != 0;
+}
+
 // Place the beads of a lipid other than `b` through its bonds, starting from
 // bead b (0 head, 1 centre, 2 end) already at u[3 b].
 __device__ __forceinline__ void st_chain(const float *x, double *u, int b, float box, float half) {
@@ -136,16 +164,29 @@ __global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xb
     }
 
     // Contact rows: row i, word w holds partners j = 64 w + lane; wavefront v
-    // builds rows i = v mod 4.  Each lane keeps its own lipid's beads in
+    // builds rows i = v mod 4, words from the one holding i onwards (the test
+    // is symmetric in i and j).  Each lane keeps its own lipid's beads in
     // registers (NaN past the end, which never touches) and reads lipid i's,
     // the same address for all lanes.
     for (int w = 0; w < W; ++w) {
         const int j = 64 * w + lane;
         float tj[9];
         for (int a = 0; a < 9; ++a) tj[a] = j < M ? xs[9 * j + a] : __builtin_nanf("");
-#pragma unroll 4
-        for (int i = wave; i < M; i += kStructWaves) {
-            const bool hit = tails_touch(xs + 9 * i, tj, box, half) & (j != i);
+        for (int i = wave; i < M && (i >> 6) <= w; i += kStructWaves) {
+            bool unsure;
+            bool hit = tails_touch_fast(xs + 9 * i, tj, box, half, &unsure);
+            if (__any(unsure)) hit = tails_touch(xs + 9 * i, tj, box, half);
+            const uint64_t m = __ballot(hit & (j != i));
+            if (lane == 0) adj[(size_t)i * W + w] = m;
+        }
+    }
+    __syncthreads();
+    // Words left of row i's own block, by transposing: bit j of row i is bit
+    // i of row j, a word already built above.
+    for (int i = 64 + wave; i < M; i += kStructWaves) {
+        for (int w = 0; w < (i >> 6); ++w) {
+            const int j = 64 * w + lane;
+            const bool hit = (adj[(size_t)j * W + (i >> 6)] >> (i & 63)) & 1ull;
             const uint64_t m = __ballot(hit);
             if (lane == 0) adj[(size_t)i * W + w] = m;
         }

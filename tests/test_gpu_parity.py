@@ -294,3 +294,19 @@ def test_checkpoint_resume_bitexact():
     bad = _pk().Rewl(10, 6, 4, 0.75, 2, spins, **dict(args, seed=13))
     with pytest.raises(_pk().RewlError):
         bad.load(blob)
+
+
+def test_get_state_matches_the_oracle():
+    # rewl_get_state: spins, E, H, ln g of a walker and its window's ln f in one call
+    g, o = make_pair(8, 10, 4, 2, lnf_init=1.0, lnf_final=1e-3, sync_attempts=640, seed=5)
+    g.run(640 * 40)
+    o.run(640 * 40)
+    for w in range(8):
+        st, ow = g.state(w), o.walker(w)
+        assert np.array_equal(st["spins"], ow["spins"]) and st["E"] == ow["E"]
+        assert np.array_equal(st["H"], ow["H"])
+        assert np.array_equal(st["lng"].view(np.uint64), ow["lng"].view(np.uint64))
+        lnf = o.window(w // 2)["lnf"]
+        assert np.float64(st["lnf"]).view(np.uint64) == np.float64(lnf).view(np.uint64)
+    with pytest.raises(_pk().RewlError):
+        g.state(8)

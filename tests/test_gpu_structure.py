@@ -275,3 +275,37 @@ def test_lipid_obs_field_argument_errors():
     g2 = pk.Rewl.lipid(4, 20, 4.3, 200.0, 0.5, 160, 1, 0.75, 2, x)
     with pytest.raises(pk.RewlError):
         g2.lipid_obs_field(0, -0.5, 1.0)   # no observable sampling
+
+
+def test_contacts_within_ulps_of_the_threshold():
+    # 100 isolated pairs of lipids on the x axis whose tail gap steps through
+    # float32 values around 1.4: the kernel's binary32 screen leaves those near
+    # 1.4 to its binary64 test, and every decision must equal the definition
+    K = 100
+    base = np.float32(3.4)
+    # the float32 grid around 3.4: base moved by -50 .. +49 ulps
+    grid = [base]
+    lo, hi = base, base
+    for _ in range(50):
+        lo = np.nextafter(lo, np.float32(0))
+        grid.insert(0, lo)
+    for _ in range(49):
+        hi = np.nextafter(hi, np.float32(10))
+        grid.append(hi)
+    assert len(grid) == K
+    beads = np.zeros((2 * K, 3, 3), dtype=np.float32)
+    for k, xc in enumerate(grid):
+        y, z = np.float32(5 * (k % 10) + 2), np.float32(5 * (k // 10) + 2)
+        beads[2 * k] = [[0.0, y, z], [1.0, y, z], [2.0, y, z]]            # A: head, centre, end at x = 2
+        beads[2 * k + 1] = [[xc + np.float32(2.0), y, z], [xc + np.float32(1.0), y, z], [xc, y, z]]  # B: end at xc
+    x = beads.reshape(-1, 3)
+    lip = np.arange(6 * K, dtype=np.int32).reshape(2 * K, 3)
+    box = 60.0
+    gap = np.array([np.float64(np.float32(xc - np.float32(2.0))) for xc in grid])
+    contacts = int(np.sum(gap * gap < 1.96))
+    assert 0 < contacts < K
+    print(f"[case] structure threshold pairs: {contacts} of {K} touch", flush=True)
+    got = gpu_records(x[None], lip[None], box)[0]
+    ref = S.structure(x, lip, box)
+    assert ref[2] == 2 * K - contacts
+    assert_same_record(got, ref, "threshold pairs")
