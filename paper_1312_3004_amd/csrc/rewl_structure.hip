@@ -123,7 +123,6 @@ __device__ __forceinline__ void st_chain(const float *x, double *u, int b, float
 //   adj u64   [M][W]      contact rows
 //   u   double[M][9]      unfolded beads of the largest cluster
 //   root, level, parent int32[M]
-//   front u64 [8]         frontier mask
 __global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xbase, size_t xstride,
                                                        const unsigned char *lbase, size_t lstride, int np, int M,
                                                        float box, double *out) {
@@ -135,7 +134,6 @@ __global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xb
     int *root = (int *)(xs + (size_t)M * 9);
     int *level = root + M;
     int *parent = level + M;
-    uint64_t *front = (uint64_t *)(((uintptr_t)(parent + M) + 7) & ~(uintptr_t)7);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -211,45 +209,51 @@ __global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xb
     cy = wave_sum(cy);
     cz = wave_sum(cz);
 
-    // Clusters, grown breadth first from their lowest free lipid.
+    // Clusters, grown breadth first from their lowest free lipid.  The
+    // visited set and the frontier are bit masks held by every lane alike;
+    // the search reads only the contact rows and writes root, level and
+    // parent for the unfolding, so it needs no LDS ordering.
+    uint64_t vis[kStructWords], front[kStructWords];
+#pragma unroll
+    for (int w = 0; w < kStructWords; ++w) {
+        const int left = M - 64 * w;   // lipids in word w
+        vis[w] = left >= 64 ? 0ull : (left <= 0 ? ~0ull : ~((1ull << left) - 1ull));
+        front[w] = 0ull;
+    }
     int ncl = 0, best_root = -1, best_size = 0, best_depth = 0;
-    int start = 0;
     for (;;) {
         int r = -1;
-        for (int w = start >> 6; w < W; ++w) {
-            const int j = 64 * w + lane;
-            const uint64_t m = __ballot(j < M && root[j] < 0);
-            if (m) {
-                r = 64 * w + __builtin_ctzll(m);
-                break;
-            }
-        }
+#pragma unroll
+        for (int w = kStructWords - 1; w >= 0; --w)
+            if (~vis[w]) r = 64 * w + __builtin_ctzll(~vis[w]);
         if (r < 0) break;
         ++ncl;
-        wave_sync();
         if (lane == 0) {
             root[r] = r;
             level[r] = 0;
             parent[r] = -1;
         }
-        if (lane < kStructWords) front[lane] = (lane == (r >> 6)) ? (1ull << (r & 63)) : 0ull;
-        wave_sync();
+#pragma unroll
+        for (int w = 0; w < kStructWords; ++w) {
+            front[w] = w == (r >> 6) ? 1ull << (r & 63) : 0ull;
+            vis[w] |= front[w];
+        }
         int size = 1, k = 0;
         for (;;) {
             uint64_t found[kStructWords];
             int nfound = 0;
 #pragma unroll
             for (int w = 0; w < kStructWords; ++w) {
-                found[w] = 0;
+                found[w] = 0ull;
                 if (w < W) {
                     const int j = 64 * w + lane;
                     int p = -1;
-                    if (j < M && root[j] < 0) {
-                        for (int v = 0; v < W; ++v) {
-                            const uint64_t t = adj[(size_t)j * W + v] & front[v];
-                            if (t) {
-                                p = 64 * v + __builtin_ctzll(t);
-                                break;
+                    if (!((vis[w] >> lane) & 1ull)) {   // free, and j < M
+#pragma unroll
+                        for (int v = 0; v < kStructWords; ++v) {
+                            if (v < W) {
+                                const uint64_t t = adj[(size_t)j * W + v] & front[v];
+                                if (p < 0 && t) p = 64 * v + __builtin_ctzll(t);
                             }
                         }
                     }
@@ -262,22 +266,22 @@ __global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xb
                     nfound += __builtin_popcountll(found[w]);
                 }
             }
-            wave_sync();
             if (nfound == 0) break;
             size += nfound;
             ++k;
 #pragma unroll
-            for (int w = 0; w < kStructWords; ++w)
-                if (lane == w) front[w] = found[w];
-            wave_sync();
+            for (int w = 0; w < kStructWords; ++w) {
+                front[w] = found[w];
+                vis[w] |= found[w];
+            }
         }
         if (size > best_size) {
             best_size = size;
             best_root = r;
             best_depth = k;
         }
-        start = r + 1;
     }
+    wave_sync();
 
     // Unfold the largest cluster level by level.
     for (int k = 0; k <= best_depth; ++k) {
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(64) void k_measure_lipid(DevState st) {
 
 size_t lipid_structure_lds_bytes(int M) {
     const size_t W = (size_t)(M + 63) / 64;
-    return (size_t)M * W * 8 + (size_t)M * 72 + (size_t)M * 36 + (size_t)M * 12 + 8 + kStructWords * 8;
+    return (size_t)M * W * 8 + (size_t)M * 72 + (size_t)M * 36 + (size_t)M * 12;
 }
 
 hipError_t launch_lipid_structure(const void *coords, size_t xstride, const void *lipids, size_t lstride, int nconf,
