@@ -4,15 +4,17 @@
 // prolateness of the largest cluster in unfolded coordinates.
 //
 // One workgroup of four wavefronts per configuration.  The lipid beads go to
-// LDS; the contact graph is held as one bit row per lipid (built 64 partners
-// at a time with a ballot, the rows shared among the four wavefronts); then
-// wavefront 0 alone takes S_mol, grows the clusters level by level (the
-// frontier and each level's finds as bit masks), unfolds the largest one
-// level by level in binary64 and reduces it.  Sums across lanes use butterfly shuffles, so the
-// floating-point outputs agree with a plain evaluation to rounding, while
-// every integer output (cluster count and sizes, the tree that unfolds a
-// cluster) is decided by the same binary32/binary64 operations as in the
-// definition and is exact.
+// LDS; the contact graph is held as one bit row per lipid, built 64 partners
+// at a time with a ballot, each pair tested once (the rows are shared among
+// the four wavefronts, the blocks left of the diagonal filled by transposing
+// bits).  Then wavefront 0 alone takes S_mol, grows the clusters level by
+// level (visited set, frontier and each level's finds as register bit
+// masks), unfolds the largest one level by level in binary64 and reduces it.
+// Sums across lanes use butterfly shuffles, so the floating-point outputs
+// agree with a plain evaluation to rounding, while every integer output
+// (cluster count and sizes, the tree that unfolds a cluster) is decided as in
+// the definition (binary32 minimum images, binary64 squared distances, a
+// binary32 screen settling only the pairs it provably can) and is exact.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
