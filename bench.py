@@ -573,6 +573,14 @@ def structure_ops_per_config(M):
     return M * (M - 1) // 2 * 4 * 20
 
 
+# HBM bytes of one k_lipid_structure launch over the 4,096 configurations of the
+# structure workload: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a
+# 256 MiB torch.neg copy in the same program), 12,588.7 KiB and 256.0 KiB.  The
+# algorithmic bytes are 4,096 x (lipid rows 1,500 + bead coordinates 4,500 +
+# record 64) = 24.84 MB.
+STRUCT_4096_HBM_BYTES = 26_043_000
+
+
 def structure_bench(args):
     """Structural observables of the N = 1000 lipid system (125 lipids in 625
     solvent particles, density 0.8) for a batch of 4,096 configurations in one
@@ -620,7 +628,9 @@ def structure_bench(args):
                                   f"box {c['box']:.3f}), one launch", "configurations": nconf, "lipids": M},
            "kernel_avg_ms": kern_ms,
            "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                        "frac": achieved / ALU_PEAK_TOPS, "traffic": None},
+                        "frac": achieved / ALU_PEAK_TOPS,
+                        "traffic": STRUCT_4096_HBM_BYTES if (nconf, M) == (4096, 125) else None,
+                        "hbm_gb_per_s": STRUCT_4096_HBM_BYTES / (kern_ms * 1e-3) / 1e9},
            "mean_largest_cluster": float(rec[:, 3].mean()), "mean_clusters": float(rec[:, 2].mean())}
     # The production phase of the lipid workload with H(E, O), O = lipids in the
     # largest cluster, sampled at every sync point (64 walkers, 2,000 attempts each).
