@@ -188,8 +188,8 @@ int rewl_get_particles(rewl_t *r, int walker, float *coords, int8_t *types, int3
  *   REWL_EDEVICE if the launch fails.
  * rewl_structure: the records of every walker of a lipid-model run (walker
  *   order), into host out double[windows * walkers][8]; waits for the result.
- *   REWL_EINVAL for a null argument or a run of another model, REWL_EDEVICE
- *   on a HIP failure.                                                         */
+ *   REWL_EINVAL for a null argument, a run of another model or one of more
+ *   than 512 lipids, REWL_EDEVICE on a HIP failure.                           */
 int rewl_lipid_structure(const float *coords, size_t coord_stride, const int32_t *lipids, size_t lipid_stride,
                          int nconf, int np, int nlip, float box, double *out, void *hip_stream);
 int rewl_structure(rewl_t *r, double *out);
