@@ -371,7 +371,9 @@ __global__ __launch_bounds__(64) void k_measure_lipid(DevState st) {
     if (b < 0 || b >= st.W) return;
     int O, ob;
     if (st.obs_field == 3) {
-        O = (int)st.obs_rec[(size_t)w * 8 + 3];
+        const double v = st.obs_rec[(size_t)w * 8 + 3];
+        if (!(v >= 1.0 && v <= (double)st.nmol)) return;   // only a NaN record (never in a run)
+        O = (int)v;
         ob = (int)(((long long)O * st.obs_bins) / (st.nmol + 1));
     } else {
         const double v = st.obs_rec[(size_t)w * 8 + st.obs_field];
