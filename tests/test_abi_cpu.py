@@ -125,3 +125,9 @@ def test_structure_argument_checks(lib):
     assert L.rewl_lipid_structure(None, 0, None, 0, 1, 30, 10, ctypes.c_float(0.0), None, None) == EINVAL
     assert L.rewl_lipid_structure(None, 0, None, 0, 1, 30, 10, ctypes.c_float(10.0), None, None) == EINVAL
     assert L.rewl_structure(None, None) == EINVAL
+
+
+def test_state_and_obs_field_reject_null_handles(lib):
+    EINVAL = -1
+    assert lib.rewl_get_state(None, 0, None, None, None, None, None) == EINVAL
+    assert lib.rewl_lipid_obs_field(None, 0, ctypes.c_double(-0.5), ctypes.c_double(1.0)) == EINVAL
