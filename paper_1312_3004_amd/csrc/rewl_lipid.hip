@@ -345,22 +345,38 @@ __device__ __forceinline__ void lip_words(const DevState &st, uint64_t t, uint32
 }
 
 // ---------------------------------------------------------------------------
-// Energy of every walker's starting configuration: pairs i < j in order on
-// one lane (the order fixes the rounding; this runs once per run).
+// Energy of every walker's starting configuration: the pairs i < j summed in
+// order on lane 0 (the order fixes the rounding; this runs once per run),
+// their terms computed 64 at a time by the wavefront and handed over in LDS.
 __global__ __launch_bounds__(64) void k_lipid_init(DevState st) {
 #pragma clang fp contract(off)
+    __shared__ double terms[64];
     const int w = blockIdx.x;
-    if (threadIdx.x != 0) return;
+    const int lane = threadIdx.x;
     unsigned char *row = (unsigned char *)(st.spins + (size_t)w * st.Npad);
     const LipView v = lip_view(st, row);
     const float box = st.box, half = 0.5f * st.box;
     double e = 0.0;
-    for (int i = 0; i < st.nb; ++i)
-        for (int j = i + 1; j < st.nb; ++j)
-            e = e + lip_pair(v.type[i], v.type[j], lip_bonded(v.where[i], v.where[j]),
+    for (int i = 0; i < st.nb; ++i) {
+        for (int j0 = i + 1; j0 < st.nb; j0 += 64) {
+            const int j = j0 + lane;
+            double t = 0.0;
+            if (j < st.nb)
+                t = lip_pair(v.type[i], v.type[j], lip_bonded(v.where[i], v.where[j]),
                              lip_r2(v.x + 3 * i, v.x + 3 * j, box, half), st.lip_eps_ww);
-    st.Ed[w] = e;
-    st.E[w] = lip_bin(st, e);
+            terms[lane] = t;
+            __syncthreads();
+            if (lane == 0) {
+                const int n = st.nb - j0 < 64 ? st.nb - j0 : 64;
+                for (int k = 0; k < n; ++k) e = e + terms[k];
+            }
+            __syncthreads();
+        }
+    }
+    if (lane == 0) {
+        st.Ed[w] = e;
+        st.E[w] = lip_bin(st, e);
+    }
 }
 
 // Walk-in (the trimer walk-in rule with the lipid moves): Wang-Landau with
