@@ -397,7 +397,7 @@ size_t lipid_structure_lds_bytes(int M) {
 hipError_t launch_lipid_structure(const void *coords, size_t xstride, const void *lipids, size_t lstride, int nconf,
                                   int np, int M, float box, double *out, hipStream_t s) {
     const size_t lds = lipid_structure_lds_bytes(M);
-    if (lds > 65536) {
+    if (lds > 48 * 1024) {   // with margin for the kernel's own static LDS
         const hipError_t e = hipFuncSetAttribute((const void *)k_lipid_structure,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
