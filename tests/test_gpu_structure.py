@@ -67,6 +67,8 @@ def random_configs(nconf, M, nsol, box, seed, bond=0.97):
     (5, 63, 10, 6.0, 2),      # one mask word, dense
     (5, 64, 0, 6.5, 3),       # exactly one word
     (4, 65, 7, 7.0, 4),       # ragged second word
+    (3, 128, 20, 8.0, 7),     # exactly two words
+    (3, 129, 20, 8.0, 8),     # one lipid in the third word
     (3, 200, 100, 9.0, 5),    # four words, percolating
     (2, 512, 64, 11.0, 6),    # the maximum: LDS beyond 64 KiB
 ])

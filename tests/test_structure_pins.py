@@ -270,3 +270,27 @@ def test_unfolded_cluster_realises_every_contact_in_free_space(seed):
             if adj[i, j]:
                 d = min(np.linalg.norm(u[i, a] - u[j, b]) for a in (1, 2) for b in (1, 2))
                 assert d < 1.4 + 1e-6
+
+
+def test_binary32_contact_screen_never_contradicts_binary64():
+    # The GPU kernel screens tail contacts with fl32((dx^2 + dy^2) + dz^2) of the
+    # binary32 minimum-image differences: below 1.959997 it calls a contact,
+    # above 1.960003 none, and leaves the band between to the binary64 test of
+    # the definition.  The binary32 sum is within 3 ulp (1.8e-7 relative) of the
+    # exact one, the band is 1.5e-6 wide on each side, so the screen can never
+    # contradict the binary64 decision; checked here on 2 million differences,
+    # most of them within a few ulp of the threshold.
+    rng = np.random.default_rng(11)
+    n = 2_000_000
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    r = np.where(rng.random(n) < 0.8, 1.4 + rng.normal(scale=2e-6, size=n), rng.uniform(0.0, 3.0, n))
+    d = (v * r[:, None]).astype(np.float32)
+    r2f = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    dd = d.astype(np.float64)
+    r2d = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
+    lo, hi = np.float32(1.959997), np.float32(1.960003)
+    settled = (r2f < lo) | (r2f > hi)
+    assert np.array_equal((r2f < lo)[settled], (r2d < S.TAIL_CONTACT2)[settled])
+    assert np.max(np.abs(r2f - r2d) / np.maximum(r2d, 1e-30)) < 1.8e-7
+    assert (~settled).sum() > 1000   # the band is exercised
