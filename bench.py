@@ -284,6 +284,10 @@ TRIMER_FLOPS_PER_ATTEMPT = 2 * 191 * 5
 # old and the new position, and the Lennard-Jones / r^-9 term (1 div + 5
 # mul/add) of the ~52 partners inside the 2.5 cut-off at density 0.8, twice.
 LIPID_FLOPS_PER_ATTEMPT = 2 * 999 * 5 + 2 * 52 * 6
+# HBM bytes of one k_lipid_sweep launch of the lipid workload (64 walkers x 2,000
+# attempts): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB
+# torch.neg copy in the same program), 907.1 KiB and 1,302.0 KiB per launch.
+LIPID_SWEEP_HBM_BYTES = 3_191_000
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -397,7 +401,7 @@ def lipid(args):
                                "probability 0.0375, bins of 1 over [7000, 7800), 16 windows at 75% overlap, "
                                "4 walkers each", "walkers": nw, "attempts_per_step_per_walker": S},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_lipid_sweep",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": LIPID_SWEEP_HBM_BYTES, "kernel": "k_lipid_sweep",
                      "kernel_avg_ms": avg_ms, "kernel_launches": launches, "flops_per_attempt": flops},
         "per_walker_attempts_per_s": S * args.steps / el,
         "walkin_s": walkin_s,
