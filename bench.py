@@ -283,6 +283,10 @@ TRIMER_FLOPS_PER_ATTEMPT = 2 * 191 * 5
 # minimum-image distance (3 mul + 2 add) to each of the 999 partners at the
 # old and the new position, and the Lennard-Jones / r^-9 term (1 div + 5
 # mul/add) of the ~52 partners inside the 2.5 cut-off at density 0.8, twice.
+# HBM bytes of one k_trimer_sweep launch of the trimer workload (64 walkers x
+# 20,000 attempts): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a
+# 256 MiB torch.neg copy in the same program), 242.5 KiB and 308.0 KiB.
+TRIMER_SWEEP_HBM_BYTES = 812_000
 LIPID_FLOPS_PER_ATTEMPT = 2 * 999 * 5 + 2 * 52 * 6
 # HBM bytes of one k_lipid_sweep launch of the lipid workload (64 walkers x 2,000
 # attempts): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB
@@ -340,7 +344,7 @@ def trimer(args):
                                "over [-460, 40), 16 windows at 75% overlap, 4 walkers each",
                    "walkers": nw, "attempts_per_step_per_walker": S},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_trimer_sweep",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": TRIMER_SWEEP_HBM_BYTES, "kernel": "k_trimer_sweep",
                      "kernel_avg_ms": avg_ms, "kernel_launches": launches,
                      "flops_per_attempt": TRIMER_FLOPS_PER_ATTEMPT},
         "per_walker_attempts_per_s": S * args.steps / el,
