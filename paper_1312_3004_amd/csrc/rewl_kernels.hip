@@ -730,14 +730,32 @@ __device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t r, in
         st.x_acc[k] += nacc;
     }
     __syncthreads();
-    const int words = st.Npad / 4;
+    // Rows are 256-byte aligned and padded: swap them in 16-byte words, four
+    // per lane in flight before any is stored.
+    const int n16 = st.Npad / 16;
     for (int j = 0; j < m; ++j) {
         if (!s_acc[j]) continue;
         const int a = k * m + j, b = (k + 1) * m + s_perm[j];
-        uint32_t *pa = (uint32_t *)(st.spins + (size_t)a * st.Npad);
-        uint32_t *pb = (uint32_t *)(st.spins + (size_t)b * st.Npad);
-        for (int i = threadIdx.x; i < words; i += blockDim.x) {
-            const uint32_t t = pa[i]; pa[i] = pb[i]; pb[i] = t;
+        uint4 *__restrict__ pa = (uint4 *)(st.spins + (size_t)a * st.Npad);
+        uint4 *__restrict__ pb = (uint4 *)(st.spins + (size_t)b * st.Npad);
+        for (int i0 = 0; i0 < n16; i0 += 4 * (int)blockDim.x) {
+            uint4 ta[4], tb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (i < n16) {
+                    ta[u] = pa[i];
+                    tb[u] = pb[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (i < n16) {
+                    pa[i] = tb[u];
+                    pb[i] = ta[u];
+                }
+            }
         }
         if (threadIdx.x == 0) {
             const int t = st.E[a]; st.E[a] = st.E[b]; st.E[b] = t;
