@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_lipid_structure(const unsigned char *xb
             const bool ok = p >= 0 && p < np;
             bad = bad || !ok;
             const int q = ok ? p : 0;
-            for (int a = 0; a < 3; ++a) xs[9 * l + 3 * b + a] = x[3 * q + a];
+            for (int a = 0; a < 3; ++a) xs[9 * l + 3 * b + a] = x[3 * (size_t)q + a];
         }
         root[l] = -1;
     }
