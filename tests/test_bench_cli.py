@@ -1,0 +1,28 @@
+"""Host-side checks of the benchmark's command line (no GPU work): more than
+one GPU is refused with a message, and the per-unit constants behind the
+roofline entries are the documented products."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_roofline_constants():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    # contact tests of the structure kernel: M (M - 1) / 2 lipid pairs x 4 tail pairs x 20 ops
+    assert bench.structure_ops_per_config(125) == 7750 * 4 * 20
+    # HBM bytes: FETCH_SIZE x 2 + WRITE_SIZE x 1, in KiB, as recorded with the profiles
+    assert abs(bench.STRUCT_4096_HBM_BYTES - (12588.7 * 2 + 256.0) * 1024) < 1000
+    assert abs(bench.LIPID_SWEEP_HBM_BYTES - (907.06 * 2 + 1302.0) * 1024) < 1000
+    assert abs(bench.TRIMER_SWEEP_HBM_BYTES - (242.5 * 2 + 308.0) * 1024) < 1000
+    assert abs(bench.K_SWEEP_L32_HBM_BYTES - (261.568 * 2 + 390.0) * 1024) < 1000
