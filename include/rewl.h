@@ -362,8 +362,8 @@ int rewl_get_shadow(rewl_t *r, int walker, double *hi, double *lo);
 int rewl_save(rewl_t *r, void *buf, size_t cap, size_t *n);
 int rewl_load(rewl_t *r, const void *buf, size_t n);
 
-/* Overwrite ln g of walker w from host double[W] (fixed-weight sampling,
- * Sec. 3.2: "continued generating data with fixed weights 1/g(E)").         */
+/* Overwrite ln g of walker w from host double[W] (sampling with the fixed
+ * weights 1/g(E) of a converged run, Sec. 3.2).                             */
 int rewl_set_lng(rewl_t *r, int walker, const double *lng);
 
 /* ln g of window k (walker 0 of the window) into host double[W], or with

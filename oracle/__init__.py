@@ -88,6 +88,10 @@ def lib():
         L.orc_get_walker.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.orc_get_window.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.orc_set_lng.argtypes = [P, i32, P]
+        L.orc_plant_walker.argtypes = [P, i32, P, P]
+        L.orc_set_step.argtypes = [P, i64]
+        L.orc_set_window.argtypes = [P, i32, dbl, i32]
+        L.orc_sync_window.argtypes = [P, i32]
         L.orc_join.argtypes = [P, P, P]
         L.orc_join.restype = i32
         L.orc_join_pieces.argtypes = [i32, i32, P, i32, i32, P, P, dbl, P, P]
@@ -466,6 +470,24 @@ class Rewl:
         a = np.ascontiguousarray(lng, dtype=np.float64)
         assert a.size == self.W
         lib().orc_set_lng(self.h_, w, _ptr(a))
+
+    def plant_walker(self, w, H, visited):
+        """Overwrite walker w's histogram H [W] and its own visited flags [W]."""
+        H = np.ascontiguousarray(H, dtype=np.uint32)
+        v = np.ascontiguousarray(visited, dtype=np.uint8)
+        assert H.size == self.W and v.size == self.W
+        lib().orc_plant_walker(self.h_, w, _ptr(H), _ptr(v))
+
+    def set_step(self, step):
+        """Set the main-phase attempts per walker (the t of the 1/t rule is step / W)."""
+        lib().orc_set_step(self.h_, int(step))
+
+    def set_window(self, k, lnf, regime=0):
+        lib().orc_set_window(self.h_, k, float(lnf), int(regime))
+
+    def sync_window(self, k):
+        """Run window k's sync step (flatness, averaging, ln f, termination) on the current state."""
+        lib().orc_sync_window(self.h_, k)
 
     def join(self):
         out = np.zeros(self.B)

@@ -1374,7 +1374,8 @@ static void shadow_average(orc_t *o, int k)
 }
 
 /* Average the m estimators of window k and hand the mean back to every
- * walker (Sec. 2: "averaged and redistributed").  The mean is taken of ln g,
+ * walker (Sec. 2: the window's estimators are averaged and every walker
+ * continues from the mean).  The mean is taken of ln g,
  * summed in walker order and divided by m.                                   */
 static void window_average(orc_t *o, int k)
 {
@@ -1700,6 +1701,27 @@ void orc_get_shadow(const orc_t *o, int w, double *hi, double *lo)
         lo[b] = o->shadow ? o->sh_lo[(size_t)w * W + b] : 0.0;
     }
 }
+
+/* Test hooks for the sync step on its own: plant walker w's histogram and
+ * the bins it has visited, the main-phase attempt count (which fixes the 1/t
+ * value W/t), and window k's ln f and regime; then run window k's sync step
+ * (flatness, averaging, ln f reduction, termination) without any attempts.  */
+void orc_plant_walker(orc_t *o, int w, const uint32_t *H, const uint8_t *vis)
+{
+    size_t W = (size_t)o->W;
+    memcpy(o->H + (size_t)w * W, H, W * sizeof(uint32_t));
+    memcpy(o->vis + (size_t)w * W, vis, W);
+}
+
+void orc_set_step(orc_t *o, int64_t step) { o->step = step; }
+
+void orc_set_window(orc_t *o, int k, double lnf, int regime)
+{
+    o->lnf[k] = lnf;
+    o->regime[k] = regime;
+}
+
+void orc_sync_window(orc_t *o, int k) { window_sync(o, k); }
 
 /* Test hook: overwrite the ln g of walker w (precision 0 or 1); the shadow
  * restarts from the given values.                                           */
