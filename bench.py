@@ -20,28 +20,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic ALU work of one Potts attempt, in 32-bit lane operations (a
-# binary64 operation counts two: the fp64 vector rate is half the fp32 rate):
-# Philox4x32-10 block 98 (10 rounds of 2 mul_lo + 2 mul_hi + 4 xor, 9 key
-# bumps of 2 adds), proposal 4, neighbour indices 12, energy change 15, ln u 34
-# (binary64 log and scaling), decision 6, window test 2, updates of ln g, H
-# and E 4.
-ALU_OPS_PER_ATTEMPT = 175
-# MI355X vector ALU peak in 32-bit lane operations: 256 CUs x 128 lanes x
-# 2.4 GHz = 7.86e13/s (157.3 TFLOP/s fp32 counts an FMA as two flops).
-ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Algorithmic ALU work of one Potts attempt, in VALU issue slots per lane (a
+# full-rate 32-bit or binary64 vector operation is one slot: unpacked fp32 and
+# fp64 both issue at one operation per lane per clock on this part; a 32x32->64
+# integer multiply is quarter rate, four slots):
+#   Philox4x32-10 block: 10 rounds x (2 multiplies x 4 + 4 xor) + 9 key bumps x 2 adds = 138
+#   proposal: site and new value by multiply-high (2 x 4) + add, compare, subtract      =  11
+#   neighbour indices with periodic wrap: 4 x 3                                          =  12
+#   energy change: 8 compares + 8 adds                                                   =  16
+#   window test and E': 2 compares + 1 add                                               =   3
+#   acceptance: d (1) + sign test (1) + uniform (3) + exp_poly (32) in the half of the
+#     attempts with d < 0 (16)                                                           =  21
+#   WL update: ln g add, H add, E select (2)                                             =   4
+ALU_SLOTS_ITEMS = dict(philox=10 * (2 * 4 + 4) + 9 * 2, proposal=2 * 4 + 3, neighbours=4 * 3, delta_e=16,
+                       window=3, acceptance=1 + 1 + 3 + 32 // 2, update=4)
+ALU_SLOTS_PER_ATTEMPT = sum(ALU_SLOTS_ITEMS.values())
+# MI355X vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13
+# lane-slots/s (the 157.3 TFLOP/s fp32 figure counts packed FMAs as four flops;
+# these kernels issue no packed fp32 and no FMA).
+CU, SIMD_LANES, CLOCK_HZ = 256, 4 * 16, 2.4e9
+VALU_LANE_SLOTS_PEAK = CU * SIMD_LANES * CLOCK_HZ
+ALU_PEAK_TOPS = VALU_LANE_SLOTS_PEAK / 1e12
+# Binary64 vector peak without FMA: one operation per lane per clock, 39.3
+# TFLOP/s (the published 78.6 TFLOP/s counts an FMA as two flops).
+FP64_UNFUSED_PEAK_TFLOPS = VALU_LANE_SLOTS_PEAK / 1e12
 # Algorithmic LDS bytes per attempt (site and neighbours 5, ln g(E') 8, ln g(E)
-# read-modify-write 16, H 8, spin 1), reported beside the ALU roofline.
+# read-modify-write 16, H 8, spin 1); spec LDS peak 256 CUs x 128 B/clock x 2.4 GHz.
 LDS_BYTES_PER_ATTEMPT = 38
+LDS_PEAK_GBS = CU * 128 * CLOCK_HZ / 1e9
 # HBM bytes per k_sweep launch of the potts_q10_L32 workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg copy of known size
 # (profiles/k_sweep_potts_q10_L32_pmc.md).  Valid for the kernel as profiled.
 K_SWEEP_L32_HBM_BYTES = 935_000
 # VALU instructions (wave64) per attempt of the same kernel, rocprofv3 SQ_INSTS_VALU
-# over the same workload (same profile); the VALU lane-op peak is the binary32
-# vector rate, 157.3 TFLOP/s / 2 (an FMA counts two flops).
+# over the same workload (same profile).
 K_SWEEP_L32_VALU_PER_ATTEMPT = 27.6
-VALU_LANE_OPS_PEAK = 157.3e12 / 2
 # 1/t phase ends once W/t < 1e-8, i.e. after W/1e-8 attempts per walker.
 
 
@@ -49,10 +62,51 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """Host cores this process may use, and what the machine reports.
+
+    usable = the CPUs in this process's affinity mask, capped by a cgroup CPU
+    quota when one is set (a container's share of a larger host)."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = os.cpu_count() or 1
+    info["affinity"] = aff
+    usable = aff
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            quota, period = f.read().split()[:2]
+        if quota != "max":
+            info["cgroup_quota_cpus"] = int(quota) / int(period)
+            usable = max(1, min(usable, int(int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    info["usable"] = usable
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    info["model"] = model
+    return info
+
+
+def oracle_threads(n_walkers):
+    """One oracle thread per usable host core, at most one per walker."""
+    hc = host_cpu()
+    return max(1, min(hc["usable"], n_walkers)), hc
+
+
 def cpu_baseline(cfg, spins, attempts_per_walker):
     import oracle
 
-    threads = max(1, min(16, os.cpu_count() or 1, cfg["windows"] * cfg["walkers"]))
+    nw = cfg["windows"] * cfg["walkers"]
+    threads, hc = oracle_threads(nw)
     o = oracle.Rewl(cfg["L"], cfg["q"], cfg["windows"], cfg["overlap"], cfg["walkers"], spins,
                     seed=cfg["seed"], flat=cfg["flat"], lnf_init=cfg["lnf_init"],
                     lnf_final=cfg["lnf_final"], schedule=cfg["schedule"],
@@ -63,12 +117,11 @@ def cpu_baseline(cfg, spins, attempts_per_walker):
     t1 = time.perf_counter()
     o.run(attempts_per_walker)
     t2 = time.perf_counter()
-    nw = cfg["windows"] * cfg["walkers"]
     return dict(value=nw * attempts_per_walker / (t2 - t1), unit="attempts/s", cores=threads,
-                kind="oracle",
+                kind="oracle", host=hc,
                 sample=(f"oracle walk-in ({t1 - t0:.1f} s, excluded) then {attempts_per_walker:,} "
                         f"main-phase attempts per walker of the same workload ({nw} walkers), "
-                        f"{threads} OpenMP threads"))
+                        f"{threads} OpenMP threads on {hc['model']}"))
 
 
 def batched(args):
@@ -292,7 +345,6 @@ LIPID_FLOPS_PER_ATTEMPT = 2 * 999 * 5 + 2 * 52 * 6
 # attempts): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB
 # torch.neg copy in the same program), 907.1 KiB and 1,302.0 KiB per launch.
 LIPID_SWEEP_HBM_BYTES = 3_191_000
-FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def trimer(args):
@@ -343,8 +395,8 @@ def trimer(args):
         "config": {"workload": "trimer: 64 head-tail-tail trimers in a periodic cube of side 10, bins of 0.5 "
                                "over [-460, 40), 16 windows at 75% overlap, 4 walkers each",
                    "walkers": nw, "attempts_per_step_per_walker": S},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": TRIMER_SWEEP_HBM_BYTES, "kernel": "k_trimer_sweep",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_UNFUSED_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_UNFUSED_PEAK_TFLOPS, "traffic": TRIMER_SWEEP_HBM_BYTES, "kernel": "k_trimer_sweep",
                      "kernel_avg_ms": avg_ms, "kernel_launches": launches,
                      "flops_per_attempt": TRIMER_FLOPS_PER_ATTEMPT},
         "per_walker_attempts_per_s": S * args.steps / el,
@@ -404,8 +456,8 @@ def lipid(args):
         "config": {"workload": "lipid: 125 P-H-H lipids + 625 solvent particles, density 0.8, reptation "
                                "probability 0.0375, bins of 1 over [7000, 7800), 16 windows at 75% overlap, "
                                "4 walkers each", "walkers": nw, "attempts_per_step_per_walker": S},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": LIPID_SWEEP_HBM_BYTES, "kernel": "k_lipid_sweep",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_UNFUSED_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_UNFUSED_PEAK_TFLOPS, "traffic": LIPID_SWEEP_HBM_BYTES, "kernel": "k_lipid_sweep",
                      "kernel_avg_ms": avg_ms, "kernel_launches": launches, "flops_per_attempt": flops},
         "per_walker_attempts_per_s": S * args.steps / el,
         "walkin_s": walkin_s,
@@ -414,7 +466,7 @@ def lipid(args):
     if not args.no_cpu_baseline:
         import oracle
 
-        threads = max(1, min(16, os.cpu_count() or 1, nw))
+        threads, hc = oracle_threads(nw)
         o = oracle.Rewl.lipid(cfg["nlip"], cfg["nsol"], cfg["box"], cfg["e_min"], cfg["bin_w"], cfg["bins"], h,
                               cfg["overlap"], m, x, eps_ww=cfg["eps_ww"], threads=threads, **kw)
         o.walkin()
@@ -423,6 +475,7 @@ def lipid(args):
         o.run(n)
         cs = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": nw * n / cs, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+                               "host": hc,
                                "sample": f"oracle walk-in (excluded) then {n:,} attempts per walker of the same "
                                          f"workload ({nw} walkers), {threads} OpenMP threads"}
     print(json.dumps(out), flush=True)
@@ -503,12 +556,12 @@ def to_convergence(args):
            "config": {"workload": args.config, "L": L, "q": q, "windows": h, "walkers_per_window": m},
            "gpu": {"converged": st == pk.CONVERGED, "seconds": gpu_s, "attempts_per_walker": g.step}}
     if not args.no_cpu_baseline:
-        threads = max(1, min(16, os.cpu_count() or 1, h * m))
+        threads, hc = oracle_threads(h * m)
         t0 = time.perf_counter()
         o = oracle.Rewl(L, q, h, cfg["overlap"], m, spins, threads=threads, **kw)
         ost = o.run(10**13)
         out["cpu_oracle"] = {"converged": ost == oracle.CONVERGED, "seconds": time.perf_counter() - t0,
-                             "attempts_per_walker": o.step, "cores": threads,
+                             "attempts_per_walker": o.step, "cores": threads, "host": hc,
                              "same_state": o.step == g.step and o.round == g.round}
     out["value"] = gpu_s
     print(json.dumps(out), flush=True)
@@ -572,13 +625,13 @@ def production(args):
 
 
 # Structural observables of one lipid configuration (Sec. 3.2, Eqs. 6-8),
-# algorithmic ALU work in 32-bit lane operations (binary64 counts two): the
-# tail-contact test over the M (M - 1) / 2 lipid pairs, 4 tail pairs each, at
-# 3 binary32 differences + 3 wrap tests + 3 widenings + 3 binary64 products +
-# 2 binary64 sums + 1 compare = 20 ops; S_mol, the cluster search and the
-# unfolding add O(M) and are left out.
+# algorithmic ALU work in VALU issue slots (binary32 and binary64 operations
+# one slot each): the tail-contact test over the M (M - 1) / 2 lipid pairs, 4
+# tail pairs each, at 3 binary32 differences + 3 wrap tests + 3 widenings + 3
+# binary64 products + 2 binary64 sums + 1 compare = 15 ops; S_mol, the cluster
+# search and the unfolding add O(M) and are left out.
 def structure_ops_per_config(M):
-    return M * (M - 1) // 2 * 4 * 20
+    return M * (M - 1) // 2 * 4 * 15
 
 
 # HBM bytes of one k_lipid_structure launch over the 4,096 configurations of the
@@ -635,7 +688,7 @@ def structure_bench(args):
            "config": {"workload": f"{nconf} configurations of the lipid system (125 lipids, 625 solvent, "
                                   f"box {c['box']:.3f}), one launch", "configurations": nconf, "lipids": M},
            "kernel_avg_ms": kern_ms,
-           "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                         "frac": achieved / ALU_PEAK_TOPS,
                         "traffic": STRUCT_4096_HBM_BYTES if (nconf, M) == (4096, 125) else None,
                         "hbm_gb_per_s": STRUCT_4096_HBM_BYTES / (kern_ms * 1e-3) / 1e9},
@@ -760,6 +813,20 @@ def bootstrap_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def potts_roofline(attempts_per_launch, avg_ms, launches, traffic):
+    """Roofline entry of the Potts attempt kernel: ALU issue slots (the binding
+    roof) with the LDS bandwidth roof beside it, per launch of avg_ms."""
+    sec = avg_ms * 1e-3
+    achieved = ALU_SLOTS_PER_ATTEMPT * attempts_per_launch / sec / 1e12
+    lds = LDS_BYTES_PER_ATTEMPT * attempts_per_launch / sec / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic, "kernel": "k_sweep",
+            "kernel_avg_ms": avg_ms, "kernel_launches": launches,
+            "slots_per_attempt": ALU_SLOTS_PER_ATTEMPT, "attempts_per_launch": attempts_per_launch,
+            "lds": {"achieved_gb_per_s": lds, "peak_gb_per_s": LDS_PEAK_GBS, "frac": lds / LDS_PEAK_GBS,
+                    "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -862,7 +929,6 @@ def main():
 
     avg_ms = sweep_ms / max(launches, 1)
     attempts_per_launch = nw * S
-    achieved = ALU_OPS_PER_ATTEMPT * attempts_per_launch / (avg_ms * 1e-3) / 1e12
     per_walker = S * args.steps / elapsed
     W = g.W
     lnf_final = cfg["lnf_final"]
@@ -885,18 +951,14 @@ def main():
                                f"{int(cfg['overlap'] * 100)}% overlap, {m} walkers/window",
                    "L": L, "q": q, "windows": h, "walkers_per_window": m, "walkers": nw,
                    "attempts_per_step_per_walker": S, "attempts_per_step": nw * S},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS,
-                     "traffic": K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" else None,
-                     "kernel": "k_sweep", "kernel_avg_ms": avg_ms, "kernel_launches": launches,
-                     "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
-                     "lds_gb_per_s": LDS_BYTES_PER_ATTEMPT * attempts_per_launch / (avg_ms * 1e-3) / 1e9},
+        "roofline": potts_roofline(attempts_per_launch, avg_ms, launches,
+                                   K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" else None),
         "valu": ({"instructions_per_attempt": K_SWEEP_L32_VALU_PER_ATTEMPT,
-                  "achieved_lane_ops_per_s": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch /
+                  "achieved_lane_slots_per_s": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch /
                   (avg_ms * 1e-3),
-                  "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK,
+                  "peak_lane_slots_per_s": VALU_LANE_SLOTS_PEAK,
                   "frac": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch / (avg_ms * 1e-3) /
-                  VALU_LANE_OPS_PEAK} if args.config == "potts_q10_L32" else None),
+                  VALU_LANE_SLOTS_PEAK} if args.config == "potts_q10_L32" else None),
         "per_walker_attempts_per_s": per_walker,
         "sync_point_avg_ms": sync_ms / max(syncs, 1),
         "walkin_s": walkin_s,

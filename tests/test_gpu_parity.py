@@ -55,6 +55,22 @@ def test_fixed_lnf_trajectories_bitexact(L, q, h, m, attempts, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_fixed_lnf_L80_precision_shape_bitexact(precision):
+    # The precision workload's shape: L = 80, 64 windows x 16 walkers (1,024
+    # walkers: several per CU, the hashed conflict-tag table of 6,400 sites),
+    # walk-in under the lid, then fixed-ln f sync intervals with exchange
+    # rounds; ln f is not a binary fraction, so both formats round.
+    c = workloads.CONFIGS["potts_q10_L80"]
+    g, o = make_pair(c["L"], c["q"], c["windows"], c["walkers"], lnf_init=1.0 / (3 * 2**17), fixed_lnf=1,
+                     sync_attempts=c["sync_attempts"], exchange=1, precision=precision, seed=c["seed"],
+                     threads=16)
+    for n in (12_345, 17_655):
+        g.run(n)
+        o.run(n)
+    assert_same_state(g, o)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_full_protocol_L8_bitexact_to_convergence(precision):
     c = workloads.CONFIGS["potts_q10_L8"]
     g, o = make_pair(c["L"], c["q"], c["windows"], c["walkers"], seed=c["seed"], flat=c["flat"],

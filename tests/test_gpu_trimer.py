@@ -53,6 +53,21 @@ def test_trimer_fixed_lnf_bitexact(nmol, box, e_min, bins, h, m, attempts, preci
     assert_same_energies(g, o)
 
 
+def test_trimer_workload_shape_bitexact():
+    # The trimer workload's shape: 64 trimers in the 10-wide box, 16 windows x
+    # 4 walkers over its 1,000 bins from e_min = -460: walk-in from the
+    # starting energies, then fixed-ln f sync intervals with exchange rounds.
+    t = workloads.TRIMER
+    g, o = make_pair(t["nmol"], t["box"], t["e_min"], t["bin_w"], t["bins"], t["windows"], t["walkers"],
+                     coords_seed=t["seed"], lnf_init=0.01, fixed_lnf=1, sync_attempts=1000, exchange=1,
+                     seed=t["seed"], threads=16)
+    g.run(2500)
+    o.run(2500)
+    assert_same_state(g, o)
+    assert_same_energies(g, o)
+    assert max(g.walker(w)["walkin_attempts"] for w in range(g.nw)) > 0
+
+
 def test_trimer_full_protocol_bitexact_and_join():
     g, o = make_pair(2, 4.0, -6.0, 0.5, 24, 2, 2, coords_seed=8, lnf_init=1.0, lnf_final=1e-3,
                      sync_attempts=2000, seed=1)
