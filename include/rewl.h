@@ -194,6 +194,17 @@ int rewl_lipid_structure(const float *coords, size_t coord_stride, const int32_t
                          int nconf, int np, int nlip, float box, double *out, void *hip_stream);
 int rewl_structure(rewl_t *r, double *out);
 
+/* rewl_structure for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same records, staged in a static device buffer of 4,096 records (256
+ * KiB on every GPU the library runs on, held until the process ends) instead
+ * of an allocation per call.  Calls no hipMalloc or hipFree.  Every call on
+ * one GPU shares that GPU's buffer: calls that overlap on one GPU (from
+ * several host threads or streams) race and must be serialised by the caller.
+ * Errors as rewl_structure, and REWL_EINVAL for a run of more than 4,096
+ * walkers.                                                                   */
+int rewl_structure_noalloc(rewl_t *r, double *out);
+
 /* Which structural observable a lipid run with obs_bins > 0 histograms in
  * H(E, O) (Sec. 3.2 records H(E, O) for S_mol, Q_ii and P).  field 3 (the
  * default at creation): O = lipids in the largest cluster, O bin O obs_bins /

@@ -111,6 +111,7 @@ def lib():
         L.rewl_get_particles.argtypes = [P, i32, P, P, P]
         L.rewl_lipid_structure.argtypes = [P, ctypes.c_size_t, P, ctypes.c_size_t, i32, i32, i32, flt, P, P]
         L.rewl_structure.argtypes = [P, P]
+        L.rewl_structure_noalloc.argtypes = [P, P]
         L.rewl_lipid_obs_field.argtypes = [P, i32, dbl, dbl]
         L.rewl_get_energy.argtypes = [P, i32, ctypes.POINTER(dbl)]
         L.rewl_save.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
@@ -316,6 +317,12 @@ class Rewl:
         = (S_mol, axis, clusters, largest, Q_xx, Q_yy, Q_zz, prolateness)."""
         out = np.zeros((self.nw, 8), dtype=np.float64)
         _check(lib().rewl_structure(self._h, _ptr(out)))
+        return out
+
+    def structure_noalloc(self):
+        """structure() through the entry point that allocates no device memory (static record buffer)."""
+        out = np.zeros((self.nw, 8), dtype=np.float64)
+        _check(lib().rewl_structure_noalloc(self._h, _ptr(out)))
         return out
 
     def lipid_obs_field(self, field, lo=0.0, hi=0.0):

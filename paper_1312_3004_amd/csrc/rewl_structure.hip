@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "rewl_host.h"
 
 namespace rewl_gpu {
@@ -460,6 +462,60 @@ extern "C" int rewl_lipid_obs_field(rewl_t *r, int field, double lo, double hi) 
     d.obs_field = field;
     d.obs_lo = lo;
     d.obs_hi = hi;
+    return REWL_OK;
+}
+
+// Record buffer of rewl_structure_noalloc: a file-scope device array (one
+// copy on every GPU the library runs on, held until the process ends) for
+// callers that cannot allocate device memory.  Host code never passes the
+// array's name to a kernel: it takes the device address of each GPU's copy
+// once, with that GPU current, and passes that address.
+constexpr int kNoallocMaxWalkers = 4096;
+static __device__ __align__(256) double scratch[kNoallocMaxWalkers * 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of GPU `dev`'s copy of `scratch`.
+int scratch_on(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(REWL_EDEVICE, "device index beyond the record buffers kept");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) HIP_TRY(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return fail(REWL_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return REWL_OK;
+}
+}  // namespace
+
+extern "C" int rewl_structure_noalloc(rewl_t *r, double *out) {
+    if (!r || !out) return fail(REWL_EINVAL, "null argument");
+    const rewl_gpu::DevState &d = r->st;
+    if (d.model != rewl_gpu::kModelLipid3D) return fail(REWL_EINVAL, "not a run of the lipid model");
+    int st = check_structure_args(d.nw, d.nb, d.nmol, d.box);
+    if (st != REWL_OK) return st;
+    if (d.nw > kNoallocMaxWalkers)
+        return fail(REWL_EINVAL, "more than 4096 walkers: the static record buffer holds 4096 records");
+    int dev = 0;
+    HIP_TRY(hipStreamGetDevice(r->stream, &dev));
+    double *buf = nullptr;
+    st = scratch_on(dev, &buf);
+    if (st != REWL_OK) return st;
+    const size_t bytes = (size_t)d.nw * 8 * sizeof(double);
+    HIP_TRY(rewl_gpu::launch_lipid_structure(d.spins, (size_t)d.Npad, (const unsigned char *)d.spins + d.lip_off_lip,
+                                             (size_t)d.Npad, d.nw, d.nb, d.nmol, d.box, buf, r->stream));
+    HIP_TRY(hipMemcpyAsync(out, buf, bytes, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
     return REWL_OK;
 }
 
