@@ -198,6 +198,10 @@ __global__ __launch_bounds__(64) void k_walkin(DevState st, int64_t chunk, int64
 // written at once).
 constexpr double kMargin64 = 1e-10;   // log-domain slack of the exact-mode test (binary64)
 constexpr double kMargin32 = 1e-5;    // log-domain slack of the exact-mode test (binary32)
+// Blocks of a window whose ln f is at most this run the speculative phase:
+// the ln g drift inside a block (64 ln f at most) is then small against the
+// spread of d - ln u, so few attempts fall inside the decision margin.
+constexpr double kSpecLnf = 0x1p-8;
 
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
@@ -210,6 +214,26 @@ __device__ __forceinline__ double readlane_d(double v, int j) {
 }
 __device__ __forceinline__ float readlane_f(float v, int j) {
     return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), j));
+}
+// Set bits of m in the lanes below this one.
+__device__ __forceinline__ int mbcnt64(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+// v of lane src (a different lane per lane) by ds_bpermute; every lane active.
+__device__ __forceinline__ double lane_read_d(double v, int src) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ float lane_read_f(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+// Orders this wavefront's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 // Orders this wavefront's LDS traffic at a phase boundary of a walker.  With
 // one walker per workgroup a workgroup barrier; with several independent
@@ -252,6 +276,10 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
         tag = (unsigned long long *)(smem + st.Npad + (size_t)Wpad * 12);
     }
     const uint32_t tag_mask = (uint32_t)st.Ntag - 1u;
+    // visit counts of the register cache's 64 energies during the serial
+    // phase, in the first 256 bytes of the tag table (all zero outside the
+    // lane-parallel phase, at least 64 entries of 8 bytes)
+    uint32_t *cnt = (uint32_t *)tag;
 
     const uint32_t *gsp = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = lane; i < st.Npad / 4; i += 64) ((uint32_t *)sp)[i] = gsp[i];
@@ -273,6 +301,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     const int q = st.q;
     const double lnf = st.lnf[k];
     const float lnf32 = (float)lnf;
+    const bool spec = lnf <= kSpecLnf;
     int E = st.E[w];
     if (E < lo || E > hi) return;  // not walked in: leave the walker untouched
 
@@ -318,19 +347,23 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
         else { gEh = readlane_f(ch, erel); gEl = readlane_f(cl, erel); }
         // ---- lane-parallel phase: proposal, energy change, conflicts, ln u
         const Proposal p = propose(st, kDomMove, (uint64_t)(s0 + base + lane), (uint32_t)w);
-        const int sc = sp[p.site];
-        int nv = sc + 1 + p.off;
+        // spins of the site and its neighbours at block start
+        int x0 = sp[p.site], x1 = sp[p.nb0], x2 = sp[p.nb1], x3 = sp[p.nb2], x4 = sp[p.nb3];
+        int nv = x0 + 1 + p.off;
         if (nv >= q) nv -= q;
-        const int dE = delta_e(sp, sc, nv, p.nb0, p.nb1, p.nb2, p.nb3);
+        int dE = (int)(x0 == x1) + (int)(x0 == x2) + (int)(x0 == x3) + (int)(x0 == x4) - (int)(nv == x1) -
+                 (int)(nv == x2) - (int)(nv == x3) - (int)(nv == x4);
         const uint32_t ti = (uint32_t)p.site & tag_mask;
         if (live) atomicOr(&tag[ti], 1ull << lane);
-        const unsigned long long hits = tag[ti] | tag[(uint32_t)p.nb0 & tag_mask] |
-                                        tag[(uint32_t)p.nb1 & tag_mask] |
-                                        tag[(uint32_t)p.nb2 & tag_mask] |
-                                        tag[(uint32_t)p.nb3 & tag_mask];
-        const unsigned long long conf = hits & ((1ull << lane) - 1ull);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        // earlier proposals of the block whose site is (or hashes like) this
+        // proposal's site, resp. one of its neighbours
+        unsigned long long W0 = tag[ti] & below, W1 = tag[(uint32_t)p.nb0 & tag_mask] & below,
+                           W2 = tag[(uint32_t)p.nb1 & tag_mask] & below, W3 = tag[(uint32_t)p.nb2 & tag_mask] & below,
+                           W4 = tag[(uint32_t)p.nb3 & tag_mask] & below;
+        unsigned long long conf = W0 | W1 | W2 | W3 | W4;
         if (live) tag[ti] = 0ull;
-        const unsigned long long anyconf = __ballot(conf != 0ull);
+        unsigned long long anyconf = __ballot(conf != 0ull);
         double lnu;
         if (PREC == 0) lnu = p.u == 0u ? -64.0 : log((double)p.u * 0x1p-32);
         else lnu = (p.u >> 8) == 0u ? -64.0 : log((double)(p.u >> 8) * 0x1p-24);
@@ -419,7 +452,200 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             hist = writelane_i32(ebase + erel, j, hist);
         };
 
-        {
+        if (spec) {
+            // ---- speculative phase (small ln f): every lane evaluates its own
+            // attempt from a guess of the earlier attempts of its segment (their
+            // decisions and new values); the guesses are refined until they
+            // reproduce themselves.  Attempt j depends only on attempts before
+            // it, so the fixed point is the sequential result, reached after at
+            // most one round per attempt.  Per round, lane j takes
+            //  * its energy before the attempt: E0 plus dE of the accepted
+            //    earlier lanes (bit counts over ballots of the dE bits),
+            //  * the spins of its site and neighbours: the new value of the last
+            //    accepted earlier lane that flips that site, else the spin at
+            //    segment start; from them its new value and dE,
+            //  * its decision from the register cache's ln g at segment start,
+            //    settled only outside a margin that bounds the ln g drift of
+            //    the segment's earlier visits.
+            // An attempt that cannot be settled so (inside the margin, or an
+            // energy outside the cache) ends the segment and runs through
+            // slow_attempt; the next segment starts after it.
+            const unsigned long long livem = todo == 64 ? ~0ull : ((1ull << todo) - 1ull);
+            if (st.Ntag < st.N) {
+                // hashed tag table: keep only proposals on exactly the same site
+                unsigned long long cand = conf;
+                while (__ballot(cand != 0ull)) {
+                    const int i = cand ? 63 - __builtin_clzll(cand) : lane;
+                    const int si = __builtin_amdgcn_ds_bpermute(i << 2, p.site);
+                    const unsigned long long bit = cand ? (1ull << i) : 0ull;
+                    W0 = si == p.site ? W0 : W0 & ~bit;
+                    W1 = si == p.nb0 ? W1 : W1 & ~bit;
+                    W2 = si == p.nb1 ? W2 : W2 & ~bit;
+                    W3 = si == p.nb2 ? W3 : W3 & ~bit;
+                    W4 = si == p.nb3 ? W4 : W4 & ~bit;
+                    cand &= ~bit;
+                }
+            }
+            int start = 0;
+            while (start < todo) {
+                if ((unsigned)(erel - 16) >= 32u) {   // keep the walker near the cache centre
+                    cache_store();
+                    ebase += erel - 32;
+                    erel = 32;
+                    cache_load();
+                }
+                const int E0 = ebase + erel;
+                const unsigned long long act = livem & (~0ull << start);
+                const bool mine = (act >> lane) & 1ull;
+                const double slack = (double)(lane - start + 2);
+                const unsigned long long Wany = W0 | W1 | W2 | W3 | W4;
+                unsigned long long A = 0ull, Sg = 0ull;
+                int c = todo, pre = E0, nvi = nv, dEi = dE;
+                bool conv = false;
+                for (int it = 0; it < 66 && !conv; ++it) {
+                    const unsigned long long Aa = A & act;
+                    // energy before the attempt, from the previous round's lanes
+                    const int de4 = dEi + 4;   // in [0, 8]
+                    const unsigned long long B0 = __ballot(de4 & 1), B1 = __ballot(de4 & 2);
+                    const unsigned long long B2 = __ballot(de4 & 4), B3 = __ballot(de4 & 8);
+                    pre = E0 - 4 * mbcnt64(Aa) + mbcnt64(B0 & Aa) + 2 * mbcnt64(B1 & Aa) +
+                          4 * mbcnt64(B2 & Aa) + 8 * mbcnt64(B3 & Aa);
+                    // new value and dE from the spins the earlier accepted lanes left
+                    int nvn = nv, dEn = dE;
+                    if (__ballot((Wany & Aa) != 0ull)) {
+                        int y0 = x0, y1 = x1, y2 = x2, y3 = x3, y4 = x4;
+                        const unsigned long long a0 = W0 & Aa, a1 = W1 & Aa, a2 = W2 & Aa, a3 = W3 & Aa,
+                                                 a4 = W4 & Aa;
+                        const int r0 = __builtin_amdgcn_ds_bpermute((a0 ? 63 - __builtin_clzll(a0) : lane) << 2, nvi);
+                        const int r1 = __builtin_amdgcn_ds_bpermute((a1 ? 63 - __builtin_clzll(a1) : lane) << 2, nvi);
+                        const int r2 = __builtin_amdgcn_ds_bpermute((a2 ? 63 - __builtin_clzll(a2) : lane) << 2, nvi);
+                        const int r3 = __builtin_amdgcn_ds_bpermute((a3 ? 63 - __builtin_clzll(a3) : lane) << 2, nvi);
+                        const int r4 = __builtin_amdgcn_ds_bpermute((a4 ? 63 - __builtin_clzll(a4) : lane) << 2, nvi);
+                        y0 = a0 ? r0 : y0;
+                        y1 = a1 ? r1 : y1;
+                        y2 = a2 ? r2 : y2;
+                        y3 = a3 ? r3 : y3;
+                        y4 = a4 ? r4 : y4;
+                        nvn = y0 + 1 + p.off;
+                        if (nvn >= q) nvn -= q;
+                        dEn = (int)(y0 == y1) + (int)(y0 == y2) + (int)(y0 == y3) + (int)(y0 == y4) -
+                              (int)(nvn == y1) - (int)(nvn == y2) - (int)(nvn == y3) - (int)(nvn == y4);
+                    }
+                    const int En = pre + dEn;
+                    const bool in_win = En >= lo && En <= hi;
+                    const int ip = pre - ebase, inn = En - ebase;
+                    const bool ok = (unsigned)ip < 64u && (!in_win || (unsigned)inn < 64u);
+                    bool acc, sure;
+                    if (PREC == 0) {
+                        const double a = lane_read_d(c64, ip & 63), b = lane_read_d(c64, inn & 63);
+                        const double d0 = a - b;
+                        const double t0 = d0 - lnu;
+                        const double M = kMargin64 + slack * (lnf * (1.0 + 0x1p-50) +
+                                                              (fabs(a) + fabs(b) + 1.0) * 0x1p-50);
+                        acc = dEn == 0 || d0 > M || t0 > M;
+                        sure = acc || t0 < -M;
+                    } else {
+                        const float aH = lane_read_f(ch, ip & 63), bH = lane_read_f(ch, inn & 63);
+                        const float aL = lane_read_f(cl, ip & 63), bL = lane_read_f(cl, inn & 63);
+                        const float d0 = (aH - bH) + (aL - bL);
+                        const double t0 = (double)d0 - lnu;
+                        const double M = kMargin32 +
+                                         slack * ((double)lnf32 * (1.0 + 0x1p-20) +
+                                                  ((double)fabs(aH) + (double)fabs(bH) + 1.0) * 0x1p-46) +
+                                         ((double)fabs(d0) + 1.0) * 0x1p-19;
+                        acc = dEn == 0 || (double)d0 > M || t0 > M;
+                        sure = acc || t0 < -M;
+                    }
+                    acc = in_win && acc;
+                    sure = !in_win || sure;
+                    const bool stop = mine && !(ok && sure);
+                    const unsigned long long An = __ballot(mine && acc && !stop);
+                    const unsigned long long Sn = __ballot(stop);
+                    const unsigned long long Cn = __ballot(mine && (nvn != nvi || dEn != dEi));
+                    c = Sn ? (int)__builtin_ctzll(Sn) : todo;
+                    const unsigned long long R = act & (c >= 63 ? ~0ull : ((2ull << c) - 1ull));
+                    conv = ((An ^ A) & R) == 0ull && ((Sn ^ Sg) & R) == 0ull && (Cn & R) == 0ull;
+                    A = An;
+                    Sg = Sn;
+                    nvi = nvn;
+                    dEi = dEn;
+                }
+                if (!conv) c = start;   // not reached (see above); the exact path is always right
+                // commit attempts [start, c): spins, visits, ln g increments per bin
+                const unsigned long long seg = act & (c >= 64 ? ~0ull : ((1ull << c) - 1ull));
+                const unsigned long long aseg = A & seg;
+                const bool inseg = (seg >> lane) & 1ull;
+                const bool mine_acc = (aseg >> lane) & 1ull;
+                const int ej = pre + (mine_acc ? dEi : 0);
+                if (seg) {
+                    // a flip is written unless a later accepted flip of the segment
+                    // hits the same site
+                    unsigned long long sup = 0ull;
+                    if (__ballot(mine_acc && (W0 & aseg) != 0ull)) {
+                        if (mine_acc && (W0 & aseg) != 0ull) atomicOr(&tag[32], W0 & aseg);
+                        wave_lds_sync();
+                        sup = tag[32];
+                        wave_lds_sync();
+                        if (lane == 0) tag[32] = 0ull;
+                    }
+                    if (mine_acc && !((sup >> lane) & 1ull)) sp[p.site] = (int8_t)nvi;
+                    nv = inseg ? nvi : nv;
+                    dE = inseg ? dEi : dE;
+                    hist = inseg ? ej : hist;
+                    if (inseg) atomicAdd(&cnt[ej - ebase], 1u);
+                    wave_lds_sync();
+                    uint32_t nb = cnt[lane];
+                    cnt[lane] = 0u;
+                    while (__ballot(nb != 0u)) {
+                        if (PREC == 0) {
+                            const double x = c64 + lnf_v;
+                            c64 = nb != 0u ? x : c64;
+                        } else {
+                            float xh = ch, xl = cl;
+                            two_sum_add(xh, xl, lnf32);
+                            ch = nb != 0u ? xh : ch;
+                            cl = nb != 0u ? xl : cl;
+                        }
+                        nb = nb != 0u ? nb - 1u : 0u;
+                    }
+                    erel = __builtin_amdgcn_readlane(ej, c - 1) - ebase;
+                }
+                accepted |= aseg;
+                flushed |= aseg;
+                if (c >= todo) break;
+                // attempt c on the exact path, with the walker's current ln g
+                // (its own new value and dE are settled there from the lattice)
+                wave_lds_sync();
+                if (PREC == 0) { gEs = readlane_d(c64, erel); gEv = gEs; }
+                else { gEh = readlane_f(ch, erel); gEl = readlane_f(cl, erel); }
+                slow_attempt(c);
+                start = c + 1;
+                // every accepted flip so far goes to the lattice; proposals after
+                // c that one of them touched read their spins from it again
+                if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
+                flushed = accepted;
+                wave_lds_sync();
+                if (lane >= start && (conf & accepted) != 0ull) {
+                    x0 = sp[p.site];
+                    x1 = sp[p.nb0];
+                    x2 = sp[p.nb1];
+                    x3 = sp[p.nb2];
+                    x4 = sp[p.nb3];
+                    nv = x0 + 1 + p.off;
+                    if (nv >= q) nv -= q;
+                    dE = (int)(x0 == x1) + (int)(x0 == x2) + (int)(x0 == x3) + (int)(x0 == x4) -
+                         (int)(nv == x1) - (int)(nv == x2) - (int)(nv == x3) - (int)(nv == x4);
+                }
+                const unsigned long long keep = start >= 64 ? 0ull : (~0ull << start);
+                conf &= keep;
+                W0 &= keep;
+                W1 &= keep;
+                W2 &= keep;
+                W3 &= keep;
+                W4 &= keep;
+                anyconf = __ballot(conf != 0ull);
+            }
+        } else {
             // ---- serial phase: runs of attempts with no possible conflict take the
             // inline path; the others go through slow_attempt (which settles the
             // conflict first)
