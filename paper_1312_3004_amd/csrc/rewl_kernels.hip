@@ -497,8 +497,21 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 const int E0 = ebase + erel;
                 const unsigned long long act = livem & (~0ull << start);
                 const bool mine = (act >> lane) & 1ull;
+                // decision margin of lane j: the exact-mode slack plus, for each of
+                // the segment's earlier visits and the two subtractions, ln f and
+                // the rounding of values up to gmax (the largest finite cached ln g)
                 const double slack = (double)(lane - start + 2);
-                const unsigned long long Wany = W0 | W1 | W2 | W3 | W4;
+                double M;
+                if (PREC == 0) {
+                    double gm = c64 < __builtin_inf() ? fabs(c64) : 0.0;
+                    for (int o = 1; o < 64; o <<= 1) gm = fmax(gm, __shfl_xor(gm, o));
+                    M = kMargin64 + slack * (lnf * (1.0 + 0x1p-50) + (2.0 * gm + 64.0 * lnf + 1.0) * 0x1p-50);
+                } else {
+                    float gm = ch < __builtin_inff() ? fabsf(ch) : 0.0f;
+                    for (int o = 1; o < 64; o <<= 1) gm = fmaxf(gm, __shfl_xor(gm, o));
+                    M = kMargin32 + slack * ((double)lnf32 * (1.0 + 0x1p-20) +
+                                             (2.0 * (double)gm + 64.0 * lnf + 1.0) * 0x1p-46);
+                }
                 unsigned long long A = 0ull, Sg = 0ull;
                 int c = todo, pre = E0, nvi = nv, dEi = dE;
                 bool conv = false;
@@ -511,8 +524,8 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     pre = E0 - 4 * mbcnt64(Aa) + mbcnt64(B0 & Aa) + 2 * mbcnt64(B1 & Aa) +
                           4 * mbcnt64(B2 & Aa) + 8 * mbcnt64(B3 & Aa);
                     // new value and dE from the spins the earlier accepted lanes left
-                    int nvn = nv, dEn = dE;
-                    if (__ballot((Wany & Aa) != 0ull)) {
+                    int nvn, dEn;
+                    {
                         int y0 = x0, y1 = x1, y2 = x2, y3 = x3, y4 = x4;
                         const unsigned long long a0 = W0 & Aa, a1 = W1 & Aa, a2 = W2 & Aa, a3 = W3 & Aa,
                                                  a4 = W4 & Aa;
@@ -540,8 +553,6 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                         const double a = lane_read_d(c64, ip & 63), b = lane_read_d(c64, inn & 63);
                         const double d0 = a - b;
                         const double t0 = d0 - lnu;
-                        const double M = kMargin64 + slack * (lnf * (1.0 + 0x1p-50) +
-                                                              (fabs(a) + fabs(b) + 1.0) * 0x1p-50);
                         acc = dEn == 0 || d0 > M || t0 > M;
                         sure = acc || t0 < -M;
                     } else {
@@ -549,12 +560,10 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                         const float aL = lane_read_f(cl, ip & 63), bL = lane_read_f(cl, inn & 63);
                         const float d0 = (aH - bH) + (aL - bL);
                         const double t0 = (double)d0 - lnu;
-                        const double M = kMargin32 +
-                                         slack * ((double)lnf32 * (1.0 + 0x1p-20) +
-                                                  ((double)fabs(aH) + (double)fabs(bH) + 1.0) * 0x1p-46) +
-                                         ((double)fabs(d0) + 1.0) * 0x1p-19;
-                        acc = dEn == 0 || (double)d0 > M || t0 > M;
-                        sure = acc || t0 < -M;
+                        // plus the rounding of the binary32 difference itself
+                        const double M32 = M + ((double)fabs(d0) + 1.0) * 0x1p-19;
+                        acc = dEn == 0 || (double)d0 > M32 || t0 > M32;
+                        sure = acc || t0 < -M32;
                     }
                     acc = in_win && acc;
                     sure = !in_win || sure;
@@ -596,6 +605,23 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     wave_lds_sync();
                     uint32_t nb = cnt[lane];
                     cnt[lane] = 0u;
+                    if (PREC == 0 && nb != 0u) {
+                        // n sequential adds of ln f in closed form: after the first
+                        // add, every add moves x by the same exact step d2 while x
+                        // stays in one binade (also when the adds round half-way:
+                        // the parity that decides a tie is then fixed), so
+                        // x_n = x_1 + (n - 1) d2 exactly; otherwise the loop below
+                        const double x1 = c64 + lnf_v;
+                        const double d2 = (x1 + lnf_v) - x1;
+                        int ex;
+                        (void)__builtin_frexp(x1, &ex);
+                        const double top = __builtin_ldexp(1.0, ex);
+                        const double nm1 = (double)(nb - 1u);
+                        if (d2 * 64.0 <= x1 && x1 + nm1 * d2 + 4.0 * lnf_v < top * (1.0 - 0x1p-40)) {
+                            c64 = x1 + nm1 * d2;
+                            nb = 0u;
+                        }
+                    }
                     while (__ballot(nb != 0u)) {
                         if (PREC == 0) {
                             const double x = c64 + lnf_v;
