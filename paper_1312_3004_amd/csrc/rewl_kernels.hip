@@ -12,6 +12,8 @@
 // sequence (each decision depends on the previous energy and ln g), so the
 // lanes first draw the Philox words and site neighbourhoods of the next 64
 // attempts in parallel and then walk through them in order.
+#include <type_traits>
+
 #include "rewl_device.h"
 
 namespace rewl_gpu {
@@ -332,6 +334,14 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     asm volatile("" : "+v"(lnf_v));
     double gEv = 0.0, gEs = 0.0;
     float gEh = 0.0f, gEl = 0.0f;
+    // proposal and ln u of lane j's attempt of the next block (they do not
+    // depend on the lattice, so they are drawn while the block before runs)
+    auto lnu_of = [&](uint32_t u) -> double {
+        if (PREC == 0) return u == 0u ? -64.0 : log((double)u * 0x1p-32);
+        return (u >> 8) == 0u ? -64.0 : log((double)(u >> 8) * 0x1p-24);
+    };
+    Proposal p_nx = propose(st, kDomMove, (uint64_t)(s0 + lane), (uint32_t)w);
+    double lnu_nx = lnu_of(p_nx.u);
 
     for (int64_t base = 0; base < n; base += 64) {
         const int todo = (int)((n - base) < 64 ? (n - base) : 64);
@@ -346,7 +356,8 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
         if (PREC == 0) { gEs = readlane_d(c64, erel); gEv = gEs; }
         else { gEh = readlane_f(ch, erel); gEl = readlane_f(cl, erel); }
         // ---- lane-parallel phase: proposal, energy change, conflicts, ln u
-        const Proposal p = propose(st, kDomMove, (uint64_t)(s0 + base + lane), (uint32_t)w);
+        const Proposal p = p_nx;
+        const double lnu = lnu_nx;
         // spins of the site and its neighbours at block start
         int x0 = sp[p.site], x1 = sp[p.nb0], x2 = sp[p.nb1], x3 = sp[p.nb2], x4 = sp[p.nb3];
         int nv = x0 + 1 + p.off;
@@ -364,9 +375,6 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
         unsigned long long conf = W0 | W1 | W2 | W3 | W4;
         if (live) tag[ti] = 0ull;
         unsigned long long anyconf = __ballot(conf != 0ull);
-        double lnu;
-        if (PREC == 0) lnu = p.u == 0u ? -64.0 : log((double)p.u * 0x1p-32);
-        else lnu = (p.u >> 8) == 0u ? -64.0 : log((double)(p.u >> 8) * 0x1p-24);
 
         unsigned long long accepted = 0ull, flushed = 0ull;
         int hist = 0;
@@ -499,23 +507,21 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 const bool mine = (act >> lane) & 1ull;
                 // decision margin of lane j: the exact-mode slack plus, for each of
                 // the segment's earlier visits and the two subtractions, ln f and
-                // the rounding of values up to gmax (the largest finite cached ln g)
+                // the rounding of values up to |a| + |b| (the two ln g read)
                 const double slack = (double)(lane - start + 2);
-                double M;
-                if (PREC == 0) {
-                    double gm = c64 < __builtin_inf() ? fabs(c64) : 0.0;
-                    for (int o = 1; o < 64; o <<= 1) gm = fmax(gm, __shfl_xor(gm, o));
-                    M = kMargin64 + slack * (lnf * (1.0 + 0x1p-50) + (2.0 * gm + 64.0 * lnf + 1.0) * 0x1p-50);
-                } else {
-                    float gm = ch < __builtin_inff() ? fabsf(ch) : 0.0f;
-                    for (int o = 1; o < 64; o <<= 1) gm = fmaxf(gm, __shfl_xor(gm, o));
-                    M = kMargin32 + slack * ((double)lnf32 * (1.0 + 0x1p-20) +
-                                             (2.0 * (double)gm + 64.0 * lnf + 1.0) * 0x1p-46);
-                }
+                const double M0 = PREC == 0 ? kMargin64 + slack * lnf * (1.0 + 0x1p-50)
+                                            : kMargin32 + slack * ((double)lnf32 * (1.0 + 0x1p-20) + 64.0 * lnf * 0x1p-46);
+                const double Mr = slack * (PREC == 0 ? 0x1p-50 : 0x1p-46);
                 unsigned long long A = 0ull, Sg = 0ull;
                 int c = todo, pre = E0, nvi = nv, dEi = dE;
                 bool conv = false;
-                for (int it = 0; it < 66 && !conv; ++it) {
+                // one round; the first of a segment also draws the next block's
+                // proposals (independent work that fills the round's waits)
+                auto round = [&](auto first) {
+                    if constexpr (decltype(first)::value) {
+                        p_nx = propose(st, kDomMove, (uint64_t)(s0 + base + 64 + lane), (uint32_t)w);
+                        lnu_nx = lnu_of(p_nx.u);
+                    }
                     const unsigned long long Aa = A & act;
                     // energy before the attempt, from the previous round's lanes
                     const int de4 = dEi + 4;   // in [0, 8]
@@ -523,6 +529,21 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     const unsigned long long B2 = __ballot(de4 & 4), B3 = __ballot(de4 & 8);
                     pre = E0 - 4 * mbcnt64(Aa) + mbcnt64(B0 & Aa) + 2 * mbcnt64(B1 & Aa) +
                           4 * mbcnt64(B2 & Aa) + 8 * mbcnt64(B3 & Aa);
+                    const int ip = pre - ebase;
+                    // ln g before the attempt, and after it for the segment-start dE
+                    // (read now; a lane whose dE changed reads again below)
+                    double a = 0.0, b = 0.0;
+                    float aH = 0.0f, aL = 0.0f, bH = 0.0f, bL = 0.0f;
+                    const int ib0 = ip + dE;
+                    if (PREC == 0) {
+                        a = lane_read_d(c64, ip & 63);
+                        b = lane_read_d(c64, ib0 & 63);
+                    } else {
+                        aH = lane_read_f(ch, ip & 63);
+                        aL = lane_read_f(cl, ip & 63);
+                        bH = lane_read_f(ch, ib0 & 63);
+                        bL = lane_read_f(cl, ib0 & 63);
+                    }
                     // new value and dE from the spins the earlier accepted lanes left
                     int nvn, dEn;
                     {
@@ -546,24 +567,33 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     }
                     const int En = pre + dEn;
                     const bool in_win = En >= lo && En <= hi;
-                    const int ip = pre - ebase, inn = En - ebase;
+                    const int inn = En - ebase;
+                    if (__ballot(mine && dEn != dE)) {
+                        if (PREC == 0) {
+                            const double b2 = lane_read_d(c64, inn & 63);
+                            b = dEn != dE ? b2 : b;
+                        } else {
+                            const float b2H = lane_read_f(ch, inn & 63), b2L = lane_read_f(cl, inn & 63);
+                            bH = dEn != dE ? b2H : bH;
+                            bL = dEn != dE ? b2L : bL;
+                        }
+                    }
                     const bool ok = (unsigned)ip < 64u && (!in_win || (unsigned)inn < 64u);
                     bool acc, sure;
                     if (PREC == 0) {
-                        const double a = lane_read_d(c64, ip & 63), b = lane_read_d(c64, inn & 63);
                         const double d0 = a - b;
                         const double t0 = d0 - lnu;
+                        const double M = M0 + ((fabs(a) + fabs(b)) + 1.0) * Mr;
                         acc = dEn == 0 || d0 > M || t0 > M;
                         sure = acc || t0 < -M;
                     } else {
-                        const float aH = lane_read_f(ch, ip & 63), bH = lane_read_f(ch, inn & 63);
-                        const float aL = lane_read_f(cl, ip & 63), bL = lane_read_f(cl, inn & 63);
                         const float d0 = (aH - bH) + (aL - bL);
                         const double t0 = (double)d0 - lnu;
                         // plus the rounding of the binary32 difference itself
-                        const double M32 = M + ((double)fabs(d0) + 1.0) * 0x1p-19;
-                        acc = dEn == 0 || (double)d0 > M32 || t0 > M32;
-                        sure = acc || t0 < -M32;
+                        const double M = M0 + (((double)fabs(aH) + (double)fabs(bH)) + 1.0) * Mr +
+                                         ((double)fabs(d0) + 1.0) * 0x1p-19;
+                        acc = dEn == 0 || (double)d0 > M || t0 > M;
+                        sure = acc || t0 < -M;
                     }
                     acc = in_win && acc;
                     sure = !in_win || sure;
@@ -573,12 +603,14 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     const unsigned long long Cn = __ballot(mine && (nvn != nvi || dEn != dEi));
                     c = Sn ? (int)__builtin_ctzll(Sn) : todo;
                     const unsigned long long R = act & (c >= 63 ? ~0ull : ((2ull << c) - 1ull));
-                    conv = ((An ^ A) & R) == 0ull && ((Sn ^ Sg) & R) == 0ull && (Cn & R) == 0ull;
+                    conv = (((An ^ A) | (Sn ^ Sg) | Cn) & R) == 0ull;
                     A = An;
                     Sg = Sn;
                     nvi = nvn;
                     dEi = dEn;
-                }
+                };
+                round(std::true_type{});
+                for (int it = 1; it < 66 && !conv; ++it) round(std::false_type{});
                 if (!conv) c = start;   // not reached (see above); the exact path is always right
                 // commit attempts [start, c): spins, visits, ln g increments per bin
                 const unsigned long long seg = act & (c >= 64 ? ~0ull : ((1ull << c) - 1ull));
@@ -733,6 +765,10 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             }
         }
 
+        if (!spec) {
+            p_nx = propose(st, kDomMove, (uint64_t)(s0 + base + 64 + lane), (uint32_t)w);
+            lnu_nx = lnu_of(p_nx.u);
+        }
         if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
         if (live) atomicAdd(&H[hist - lo], 1u);
     }
