@@ -48,13 +48,14 @@ FP64_UNFUSED_PEAK_TFLOPS = VALU_LANE_SLOTS_PEAK / 1e12
 # read-modify-write 16, H 8, spin 1); spec LDS peak 256 CUs x 128 B/clock x 2.4 GHz.
 LDS_BYTES_PER_ATTEMPT = 38
 LDS_PEAK_GBS = CU * 128 * CLOCK_HZ / 1e9
-# HBM bytes per k_sweep launch of the potts_q10_L32 workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg copy of known size
-# (profiles/k_sweep_potts_q10_L32_pmc.md).  Valid for the kernel as profiled.
-K_SWEEP_L32_HBM_BYTES = 935_000
+# HBM bytes per k_sweep launch of the potts_q10_L32 workload in its timed (1/t)
+# phase, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg
+# copy of known size (profiles/k_sweep_potts_q10_L32_pmc.md): 282.10 KiB x 2.000
+# + 390.0 KiB x 1.000.  Valid for the kernel as profiled.
+K_SWEEP_L32_HBM_BYTES = 977_100
 # VALU instructions (wave64) per attempt of the same kernel, rocprofv3 SQ_INSTS_VALU
 # over the same workload (same profile).
-K_SWEEP_L32_VALU_PER_ATTEMPT = 27.6
+K_SWEEP_L32_VALU_PER_ATTEMPT = 9.92
 # 1/t phase ends once W/t < 1e-8, i.e. after W/1e-8 attempts per walker.
 
 
@@ -835,6 +836,8 @@ def main():
     ap.add_argument("--config", default="potts_q10_L32")
     ap.add_argument("--cpu-attempts", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-approach", action="store_true",
+                    help="time the steps right after walk-in instead of after the halving phase")
     ap.add_argument("--to-convergence", type=float, default=0.0,
                     help="run the named workload from creation to convergence (at most this many seconds) "
                          "on the GPU and, unless --no-cpu-baseline, on the CPU oracle")
@@ -908,32 +911,61 @@ def main():
     torch.cuda.synchronize()
     walkin_s = time.perf_counter() - t0
     log(f"[bench] walk-in done in {walkin_s:.2f} s")
-    if args.warmup:
-        g.run(args.warmup * S)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} steps done")
-
-    g.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = g.run(args.steps * S)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    sweep_ms, launches, sync_ms, syncs = g.timing()
-    g.set_timing(False)
-    if st == pk.CONVERGED:
-        raise RuntimeError("run converged inside the timed region; the step count is not the work done")
-    attempts = nw * S * args.steps
-    value = attempts / elapsed
-    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s: {value:.4g} attempts/s")
-
-    avg_ms = sweep_ms / max(launches, 1)
-    attempts_per_launch = nw * S
-    per_walker = S * args.steps / elapsed
     W = g.W
     lnf_final = cfg["lnf_final"]
     converge_attempts = (int(W / lnf_final) // S + 1) * S if cfg["schedule"] == 1 else None
 
+    def timed(steps):
+        g.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = g.run(steps * S)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sweep_ms, launches, sync_ms, syncs = g.timing()
+        g.set_timing(False)
+        if st == pk.CONVERGED:
+            raise RuntimeError("run converged inside a timed segment; the step count is not the work done")
+        return el, sweep_ms / max(launches, 1), launches, sync_ms / max(syncs, 1)
+
+    # The first steps after walk-in (ln f = 1, every attempt on the exact serial path).
+    n_early = min(args.steps, 200)
+    el, k_ms, _, _ = timed(n_early)
+    early = {"steps": n_early, "attempts_per_s": nw * S * n_early / el, "k_sweep_avg_ms": k_ms,
+             "lnf": cfg["lnf_init"]}
+    log(f"[bench] early phase (ln f = {cfg['lnf_init']:g}): {early['attempts_per_s']:.4g} attempts/s")
+    # The protocol up to the phase that holds almost all of the run's attempts:
+    # every window in the 1/t regime (untimed for the value, reported).
+    approach = None
+    if cfg["schedule"] == 1 and not args.no_approach:
+        t0 = time.perf_counter()
+        s_start = g.step
+        while True:
+            g.run(2000 * S)
+            torch.cuda.synchronize()
+            ws = [g.window(k) for k in range(h)]
+            n1t = sum(1 for w in ws if w["regime"] == 1 or w["finished"])
+            log(f"[bench] halving phase: step {g.step}, {time.perf_counter() - t0:.0f} s, "
+                f"{n1t}/{h} windows in the 1/t regime")
+            if n1t == h:
+                break
+        el = time.perf_counter() - t0
+        approach = {"seconds": el, "attempts_per_walker": g.step, "attempts_per_s": nw * (g.step - s_start) / el,
+                    "lnf_max": max(w["lnf"] for w in ws)}
+    if args.warmup:
+        g.run(args.warmup * S)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} steps done")
+    step_timed = g.step
+    elapsed, avg_ms, launches, sync_avg = timed(args.steps)
+    attempts = nw * S * args.steps
+    value = attempts / elapsed
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s: {value:.4g} attempts/s")
+
+    attempts_per_launch = nw * S
+    per_walker = S * args.steps / elapsed
+    phase = ("1/t regime in every window (ln f = W/t, " +
+             f"from {step_timed:,} attempts per walker)" if approach else "the start of the run (ln f = 1)")
     out = {
         "metric": "spin-flip attempts/s (1 GPU) + time to ln f<1e-8, q=10 Potts L=32 REWL",
         "value": value,
@@ -950,21 +982,30 @@ def main():
         "config": {"workload": f"{args.config}: 2D q={q} Potts {L}x{L} periodic, {h} windows at "
                                f"{int(cfg['overlap'] * 100)}% overlap, {m} walkers/window",
                    "L": L, "q": q, "windows": h, "walkers_per_window": m, "walkers": nw,
-                   "attempts_per_step_per_walker": S, "attempts_per_step": nw * S},
+                   "attempts_per_step_per_walker": S, "attempts_per_step": nw * S,
+                   "timed_phase": phase,
+                   # one k_sweep launch per sync interval: the timed steps are these
+                   # launches of the run (0-based, for matching a profiler's trace)
+                   "timed_k_sweep_launches": [step_timed // S, step_timed // S + args.steps]},
         "roofline": potts_roofline(attempts_per_launch, avg_ms, launches,
-                                   K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" else None),
-        "valu": ({"instructions_per_attempt": K_SWEEP_L32_VALU_PER_ATTEMPT,
-                  "achieved_lane_slots_per_s": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch /
-                  (avg_ms * 1e-3),
-                  "peak_lane_slots_per_s": VALU_LANE_SLOTS_PEAK,
-                  "frac": K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch / (avg_ms * 1e-3) /
-                  VALU_LANE_SLOTS_PEAK} if args.config == "potts_q10_L32" else None),
+                                   K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" and approach else None),
         "per_walker_attempts_per_s": per_walker,
-        "sync_point_avg_ms": sync_ms / max(syncs, 1),
+        "sync_point_avg_ms": sync_avg,
         "walkin_s": walkin_s,
+        "early_phase": early,
+        "halving_phase": approach,
     }
-    if converge_attempts:
-        out["time_to_lnf_final_s_projected"] = walkin_s + converge_attempts / per_walker
+    if args.config == "potts_q10_L32" and approach and K_SWEEP_L32_VALU_PER_ATTEMPT:
+        v = K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch / (avg_ms * 1e-3)
+        out["valu"] = {"instructions_per_attempt": K_SWEEP_L32_VALU_PER_ATTEMPT, "achieved_lane_slots_per_s": v,
+                       "peak_lane_slots_per_s": VALU_LANE_SLOTS_PEAK, "frac": v / VALU_LANE_SLOTS_PEAK}
+    if converge_attempts and approach:
+        # walk-in, early segment, halving phase and warm-up as measured; the rest
+        # of the 1/t phase (ln f = W/t is fixed by the attempt count) at the
+        # timed rate
+        before = walkin_s + early["steps"] * S / (early["attempts_per_s"] / nw) + approach["seconds"] + \
+            args.warmup * S / per_walker
+        out["time_to_lnf_final_s_projected"] = before + (converge_attempts - step_timed) / per_walker
         out["attempts_per_walker_to_lnf_final"] = converge_attempts
     if args.trajectory > 0:
         out["trajectory"] = trajectory(g, S, args.trajectory, converge_attempts, walkin_s, per_walker)

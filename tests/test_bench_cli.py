@@ -33,7 +33,7 @@ def test_roofline_constants():
     assert abs(bench.STRUCT_4096_HBM_BYTES - (12588.7 * 2 + 256.0) * 1024) < 1000
     assert abs(bench.LIPID_SWEEP_HBM_BYTES - (907.06 * 2 + 1302.0) * 1024) < 1000
     assert abs(bench.TRIMER_SWEEP_HBM_BYTES - (242.5 * 2 + 308.0) * 1024) < 1000
-    assert abs(bench.K_SWEEP_L32_HBM_BYTES - (261.568 * 2 + 390.0) * 1024) < 1000
+    assert abs(bench.K_SWEEP_L32_HBM_BYTES - (282.10 * 2 + 390.0) * 1024) < 1000
 
 
 def test_host_cpu_info():
