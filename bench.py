@@ -8,7 +8,7 @@ point (flatness, averaging, ln f update) and a replica-exchange round.
 Inputs are synthetic (uniform random starting lattices from a seed) and
 resident on the GPU before the timed region; walk-in is timed separately.
 
-Prints one JSON line (see the design doc for the roofline accounting).
+Prints one JSON line; the roofline constants below carry their derivations.
 """
 import argparse
 import json
@@ -528,7 +528,16 @@ def trajectory(g, S, seconds, converge_attempts, walkin_s, early_rate):
 
 def to_convergence(args):
     """Wall time from creation to every window finished (the full protocol of
-    the named workload), on the GPU and for the CPU oracle on the same inputs."""
+    the named workload).  With --checkpoint PATH the run can span several
+    processes: an existing PATH (and its PATH.json sidecar of measured times)
+    is loaded and continued; at convergence or when this process's budget of
+    --to-convergence seconds is spent, the run is saved back to PATH.  The
+    reported time is the sum of the segments' GPU wall times (creation and
+    walk-in included, saving and loading not).  Unless --no-cpu-baseline (and
+    the run fits one process), the CPU oracle runs the same protocol too."""
+    import math
+
+    import numpy as np
     import torch
 
     import oracle
@@ -541,22 +550,65 @@ def to_convergence(args):
     kw = dict(seed=cfg["seed"], flat=cfg["flat"], lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"],
               schedule=cfg["schedule"], sync_attempts=cfg["sync_attempts"], exchange=cfg["exchange"],
               precision=cfg["precision"])
+    S = cfg["sync_attempts"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    ck = args.checkpoint
+    side = {"segments": [], "seconds": 0.0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = pk.Rewl(L, q, h, cfg["overlap"], m, spins, device=dev, **kw)
+    if ck and os.path.exists(ck):
+        with open(ck + ".json") as f:
+            side = json.load(f)
+        torch.cuda.synchronize()
+        tl = time.perf_counter()
+        with open(ck, "rb") as f:
+            g.load(f.read())
+        torch.cuda.synchronize()
+        t0 += time.perf_counter() - tl     # loading is not part of the run
+        log(f"[bench] resumed at step {g.step} after {side['seconds']:.1f} s in {len(side['segments'])} segments")
     st = pk.OK
+    last = time.perf_counter()
     while st != pk.CONVERGED and time.perf_counter() - t0 < args.to_convergence:
-        st = g.run(1000 * cfg["sync_attempts"])
-        log(f"[bench] GPU step {g.step} after {time.perf_counter() - t0:.1f} s")
+        st = g.run(1000 * S)
+        if time.perf_counter() - last > 30 or st == pk.CONVERGED:
+            torch.cuda.synchronize()
+            ws = [g.window(k) for k in range(h)]
+            lnf = [w["lnf"] if not w["finished"] else w["lnf_last"] for w in ws]
+            log(f"[bench] GPU step {g.step} after {side['seconds'] + time.perf_counter() - t0:.1f} s: "
+                f"ln f max {max(lnf):.3g}, {sum(w['finished'] for w in ws)}/{h} windows finished")
+            last = time.perf_counter()
     torch.cuda.synchronize()
-    gpu_s = time.perf_counter() - t0
+    seg_s = time.perf_counter() - t0
+    side["segments"].append({"seconds": seg_s, "end_step": g.step})
+    side["seconds"] += seg_s
+    gpu_s = side["seconds"]
+    if ck:
+        with open(ck, "wb") as f:
+            f.write(g.save())
+        with open(ck + ".json", "w") as f:
+            json.dump(side, f)
     out = {"metric": f"time to ln f < {cfg['lnf_final']:g}, {args.config}", "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
            "config": {"workload": args.config, "L": L, "q": q, "windows": h, "walkers_per_window": m},
-           "gpu": {"converged": st == pk.CONVERGED, "seconds": gpu_s, "attempts_per_walker": g.step}}
-    if not args.no_cpu_baseline:
+           "gpu": {"converged": st == pk.CONVERGED, "seconds": gpu_s, "attempts_per_walker": g.step,
+                   "segments": side["segments"]}}
+    if st == pk.CONVERGED:
+        # the joined, normalised ln g and its canonical specific heat: the peak
+        # lies near the infinite-lattice transition 1/ln(1 + sqrt(q)), shifted
+        # by the finite size (Sec. 3.1)
+        sj, lng, cuts = g.join()
+        T = np.linspace(0.60, 0.80, 2001)
+        _, U, C = g.thermo(T)
+        i = int(np.argmax(C))
+        out["joined"] = {"status": sj, "cuts": [int(c) for c in cuts],
+                         "sum_g_check": float(np.logaddexp.reduce(lng[np.isfinite(lng)]) - L * L * math.log(q)),
+                         "cv_peak_T": float(T[i]), "cv_peak": float(C[i]),
+                         "Tc_infinite": 1.0 / math.log(1.0 + math.sqrt(q))}
+        if args.save_lng:
+            np.save(args.save_lng, lng)
+    if not args.no_cpu_baseline and not ck:
         threads, hc = oracle_threads(h * m)
         t0 = time.perf_counter()
         o = oracle.Rewl(L, q, h, cfg["overlap"], m, spins, threads=threads, **kw)
@@ -841,6 +893,10 @@ def main():
     ap.add_argument("--to-convergence", type=float, default=0.0,
                     help="run the named workload from creation to convergence (at most this many seconds) "
                          "on the GPU and, unless --no-cpu-baseline, on the CPU oracle")
+    ap.add_argument("--checkpoint", default="",
+                    help="with --to-convergence: continue the run saved at this path (if present) and save it "
+                         "back there when this process's budget is spent or the run converged")
+    ap.add_argument("--save-lng", default="", help="with --to-convergence: write the joined ln g (.npy) here")
     ap.add_argument("--trajectory", type=float, default=0.0,
                     help="after the measurement, continue the run for this many seconds and report "
                          "when every window reached the 1/t regime and the time to ln f_final")

@@ -227,10 +227,16 @@ int rewl_lipid_obs_field(rewl_t *r, int field, double lo, double hi);
  * at r = 2^(1/6) and shifted by +1.  A move displaces one uniformly chosen
  * bead by a uniform vector in [-0.1, 0.1)^3 (periodic wrap).  Energies are
  * binned: bin b = floor((E - e_min) / bin_w), b in [0, bins); the windows of
- * Sec. 2 are laid over the bins exactly as over the Potts energies.  The
- * energy change of a move is summed over the partner beads in a fixed order
- * (per lane j of 64: partners j, j+64, ... left to right, then lanes pairwise
- * by halving), so that runs are reproducible bit for bit.
+ * Sec. 2 are laid over the bins exactly as over the Potts energies.
+ * Energies are fixed point in units of 2^-32: every pair term V (binary64)
+ * is rounded once, rint(V 2^32), and totals and the change of a move are
+ * exact integer sums of such terms (independent of the order of summation,
+ * so runs are reproducible bit for bit); bins are floor((E - e_min) / bin_w)
+ * on that grid, with e_min and bin_w rounded to it.  A pair term of magnitude
+ * 2^18 or more (or not finite) is a hard overlap: a move creating one is
+ * rejected, and a start holding one (or an energy of magnitude 2^29 or more)
+ * is refused with REWL_EINVAL.  Limits: bin_w in [2^-32, 2^28], |e_min| <
+ * 2^28.
  * init_coords: host float[windows*walkers][3 nmol][3], values in [0, box).
  * For these runs rewl_get_walker returns the configuration's bytes in
  * `spins` (float[3 nmol][3]) and the energy bin in `E`; rewl_get_energy
@@ -246,9 +252,12 @@ int rewl_create_trimer(rewl_t **out, int nmol, float box, double e_min, double b
 /* Windows over `bins` energy bins (bin indices, first window at 0).        */
 int rewl_window_layout_bins(int bins, int windows, double overlap, int32_t *W, int32_t *starts);
 
-/* Current energy of walker w (the Potts energy as a double, or the trimer
- * model's continuous energy).                                               */
+/* Current energy of walker w (the Potts energy as a double, or the
+ * continuous models' energy, the nearest binary64 of the fixed-point value).
+ * rewl_get_energy_fx: the continuous models' energy in units of 2^-32
+ * exactly (the Potts energy as an integer for Potts runs).                  */
 int rewl_get_energy(rewl_t *r, int walker, double *E);
+int rewl_get_energy_fx(rewl_t *r, int walker, int64_t *E);
 
 /* Walk-in: move every walker whose energy lies outside its window into it
  * (each walker starts inside its own window, Sec. 3.2 on Fig. 7) by a

@@ -45,18 +45,18 @@ def lib():
         L.orc_create_lipid.restype = P
         L.orc_create_lipid.argtypes = [i32, i32, ctypes.c_float, dbl, u32, dbl, dbl, i32, i32, dbl, i32, u64, u32,
                                        u32, u32, dbl, dbl, i32, i64, i32, i32, i32, P]
-        L.orc_lipid_energy.argtypes = [P, i32]
-        L.orc_lipid_energy.restype = dbl
+        L.orc_lipid_energy_fx.argtypes = [P, i32, ctypes.POINTER(i64)]
+        L.orc_lipid_energy_fx.restype = i32
         L.orc_log_poly.argtypes = [dbl]
         L.orc_log_poly.restype = dbl
         L.orc_lipid_pair.argtypes = [P, i32, i32, i32, dbl]
         L.orc_lipid_pair.restype = dbl
         L.orc_lipid_state.argtypes = [P, i32, P, P, P]
         L.orc_lipid_state.restype = None
-        L.orc_lipid_delta_move.argtypes = [P, i32, i32, P]
-        L.orc_lipid_delta_move.restype = dbl
+        L.orc_lipid_delta_move_fx.argtypes = [P, i32, i32, P, ctypes.POINTER(i64)]
+        L.orc_lipid_delta_move_fx.restype = i32
         L.orc_lipid_reptate.argtypes = [P, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                        ctypes.POINTER(dbl)]
+                                        ctypes.POINTER(i64)]
         L.orc_lipid_reptate.restype = i32
         L.orc_get_shadow.argtypes = [P, i32, P, P]
         L.orc_get_replicas.argtypes = [P, P, P]
@@ -65,11 +65,14 @@ def lib():
         L.orc_create_trimer.restype = P
         L.orc_create_trimer.argtypes = [i32, ctypes.c_float, dbl, dbl, i32, i32, dbl, i32, u64, u32, u32,
                                         u32, dbl, dbl, i32, i64, i32, i32, i32, i32, i32, P]
-        for name in ("orc_trimer_energy", "orc_get_energy"):
-            getattr(L, name).argtypes = [P, i32]
-            getattr(L, name).restype = dbl
-        L.orc_trimer_delta.argtypes = [P, i32, i32, P]
-        L.orc_trimer_delta.restype = dbl
+        L.orc_get_energy.argtypes = [P, i32]
+        L.orc_get_energy.restype = dbl
+        L.orc_get_energy_fx.argtypes = [P, i32]
+        L.orc_get_energy_fx.restype = i64
+        L.orc_trimer_energy_fx.argtypes = [P, i32, ctypes.POINTER(i64)]
+        L.orc_trimer_energy_fx.restype = i32
+        L.orc_trimer_delta_fx.argtypes = [P, i32, i32, P, ctypes.POINTER(i64)]
+        L.orc_trimer_delta_fx.restype = i32
         L.orc_get_shadow.restype = None
         for name, args in (("orc_dd_add", [P, P, dbl, dbl]), ("orc_dd_div_int", [P, P, i32]),
                            ("orc_dd_mul_count", [u32, dbl, P, P])):
@@ -115,6 +118,14 @@ def lib():
 
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+FX_ONE = 2.0**32   # continuous-model energies are integers in units of 2^-32
+
+
+def fx_to_float(e):
+    """Nearest binary64 of an energy given in units of 2^-32."""
+    return float(np.float64(e) / FX_ONE)
 
 
 def philox(ctr, key):
@@ -338,15 +349,30 @@ class Rewl:
         lib().orc_lipid_state(self.h_, w, _ptr(x), _ptr(t), _ptr(lp))
         return x, t, lp
 
+    def lipid_energy_fx(self, w):
+        """Total energy of walker w's configuration recomputed from scratch, in units of 2^-32
+        (None for a hard overlap)."""
+        e = ctypes.c_int64(0)
+        return e.value if lib().orc_lipid_energy_fx(self.h_, w, ctypes.byref(e)) else None
+
     def lipid_energy(self, w):
-        return lib().orc_lipid_energy(self.h_, w)
+        e = self.lipid_energy_fx(w)
+        return None if e is None else fx_to_float(e)
+
+    def lipid_delta_move_fx(self, w, b, xn):
+        """Energy change of displacing particle b to xn, in units of 2^-32 (None for a hard overlap)."""
+        e = ctypes.c_int64(0)
+        ok = lib().orc_lipid_delta_move_fx(self.h_, w, b, _ptr(np.ascontiguousarray(xn, dtype=np.float32)),
+                                           ctypes.byref(e))
+        return e.value if ok else None
 
     def lipid_delta_move(self, w, b, xn):
-        return lib().orc_lipid_delta_move(self.h_, w, b, _ptr(np.ascontiguousarray(xn, dtype=np.float32)))
+        e = self.lipid_delta_move_fx(w, b, xn)
+        return None if e is None else fx_to_float(e)
 
     def lipid_reptate(self, w, lipid, end, pick):
         """Apply a reptation; returns (n_c, n_r, energy change) or None if no solvent is near that end."""
-        nc, nr, de = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        nc, nr, de = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int64(0)
         if not lib().orc_lipid_reptate(self.h_, w, lipid, end, pick, ctypes.byref(nc), ctypes.byref(nr),
                                        ctypes.byref(de)):
             return None
@@ -356,15 +382,33 @@ class Rewl:
         return lib().orc_lipid_pair(self.h_, ti, tj, bonded, r2)
 
     def energy(self, w):
-        """Current energy of walker w (the trimer model's continuous energy)."""
+        """Current energy of walker w (the continuous models' energy, nearest binary64)."""
         return lib().orc_get_energy(self.h_, w)
 
+    def energy_fx(self, w):
+        """Current energy of walker w in units of 2^-32 (continuous models)."""
+        return lib().orc_get_energy_fx(self.h_, w)
+
+    def trimer_energy_fx(self, w):
+        """Total energy of walker w's configuration recomputed from scratch, in units of 2^-32
+        (None for a hard overlap)."""
+        e = ctypes.c_int64(0)
+        return e.value if lib().orc_trimer_energy_fx(self.h_, w, ctypes.byref(e)) else None
+
     def trimer_energy(self, w):
-        """Total energy of walker w's configuration, recomputed from scratch."""
-        return lib().orc_trimer_energy(self.h_, w)
+        e = self.trimer_energy_fx(w)
+        return None if e is None else fx_to_float(e)
+
+    def trimer_delta_fx(self, w, bead, xn):
+        """Energy change of moving bead to xn, in units of 2^-32 (None for a hard overlap)."""
+        e = ctypes.c_int64(0)
+        ok = lib().orc_trimer_delta_fx(self.h_, w, bead, _ptr(np.ascontiguousarray(xn, dtype=np.float32)),
+                                       ctypes.byref(e))
+        return e.value if ok else None
 
     def trimer_delta(self, w, bead, xn):
-        return lib().orc_trimer_delta(self.h_, w, bead, _ptr(np.ascontiguousarray(xn, dtype=np.float32)))
+        e = self.trimer_delta_fx(w, bead, xn)
+        return None if e is None else fx_to_float(e)
 
     def __del__(self):
         if getattr(self, "h_", None):

@@ -193,7 +193,8 @@ typedef struct {
     int nmol, nb;
     float box;
     double e_min, bin_w;
-    double *Ed;            /* [nw] continuous energy of each walker (trimer, lipid) */
+    int64_t *Efx;          /* [nw] energy of each walker in units of 2^-32 (trimer, lipid) */
+    int64_t emin_fx, binw_fx; /* e_min and bin_w in units of 2^-32          */
     /* lipid model (explicit solvent): np particles, nlip P-H-H lipids, the
      * rest solvent W; per-walker bytes: coordinates float[np][3], types
      * int8[np] (padded to 4), lipid table int32[nlip][3] (head first),
@@ -260,7 +261,7 @@ static void orc_free(orc_t *o)
     free(o->lng_lo); free(o->H); free(o->sh_hi); free(o->sh_lo); free(o->hprev); free(o->vis); free(o->replica); free(o->walkin_att);
     free(o->lnf); free(o->lnf_last); free(o->regime); free(o->finished);
     free(o->iterations); free(o->visited); free(o->x_att); free(o->x_acc);
-    free(o->Ed); free(o->rep_end); free(o->rep_trips); free(o->rep_visits);
+    free(o->Efx); free(o->rep_end); free(o->rep_trips); free(o->rep_visits);
     free(o->obs_hist); free(o->obs_sum); free(o->obs_cnt);
     free(o);
 }
@@ -559,48 +560,83 @@ static double tri_pair(const orc_t *o, int i, int j, const float *xi, const floa
     return tails ? v : v + 1.0;
 }
 
-/* Total energy, pairs i < j in order (only at creation and in the tests).  */
-static double tri_energy(const orc_t *o, const float *x)
+/* ------------------------------------------------------------------------ */
+/* Energies of the continuous models (trimer, lipid) in fixed point.  Each
+ * pair term V of the force field (binary64) is rounded once to a multiple of
+ * 2^-32, fx(V) = rint(V 2^32); a total or a change of energy is the exact
+ * integer sum of such terms, so it is the same in whatever order the terms
+ * are added, and a change always equals the difference of the two totals.
+ * A term of magnitude 2^18 or more, or one that is not finite, is a hard
+ * overlap: a configuration never holds one (a move that would create one is
+ * rejected, a start that holds one is refused).  Energies must stay below
+ * 2^29 in magnitude (2^61 units).  The bin of an energy E is
+ * floor((E - e_min) / bin_w) on the same grid.                              */
+static const double FX_ONE = 0x1p32;
+static const double FX_TERM_LIMIT = 0x1p18;
+#define FX_E_LIMIT (((__int128)1) << 61)
+
+static int fx_term(double v, int64_t *out)
 {
-    double e = 0.0;
+    if (!(fabs(v) < FX_TERM_LIMIT)) return 0;
+    *out = (int64_t)rint(v * FX_ONE);
+    return 1;
+}
+
+static int fx_in_range(__int128 e) { return e < FX_E_LIMIT && e > -FX_E_LIMIT; }
+
+static double fx_to_double(int64_t e) { return (double)e / FX_ONE; }
+
+/* Total energy, every pair i < j (only at creation and in the tests). */
+static int tri_energy(const orc_t *o, const float *x, int64_t *e)
+{
+    __int128 acc = 0;
     for (int i = 0; i < o->nb; ++i)
-        for (int j = i + 1; j < o->nb; ++j) e = e + tri_pair(o, i, j, x + 3 * i, x + 3 * j);
-    return e;
-}
-
-/* Energy change of moving bead b to xn.  The 191 partner terms
- * t_j = V(b at xn, j) - V(b, j) (t_b = 0, t_j = 0 beyond the last bead) are
- * summed in a fixed order: s_l = (t_l + t_{l+64}) + t_{l+128} + ... for
- * l = 0..63, then s_l = s_l + s_{l+h} for h = 32, 16, ..., 1; the result is
- * s_0.  Floating-point addition is not associative: the order is part of
- * the definition so that every implementation rounds identically.          */
-static double tri_delta_e(const orc_t *o, const float *x, int b, const float *xn)
-{
-    int slots = (o->nb + 63) / 64 * 64;
-    double s[64];
-    for (int l = 0; l < 64; ++l) {
-        double acc = 0.0;
-        for (int j = l; j < slots; j += 64) {
-            double t = 0.0;
-            if (j < o->nb && j != b)
-                t = tri_pair(o, b, j, xn, x + 3 * j) - tri_pair(o, b, j, x + 3 * b, x + 3 * j);
-            acc = j == l ? t : acc + t;
+        for (int j = i + 1; j < o->nb; ++j) {
+            int64_t t;
+            if (!fx_term(tri_pair(o, i, j, x + 3 * i, x + 3 * j), &t)) return 0;
+            acc += t;
         }
-        s[l] = acc;
-    }
-    for (int h = 32; h >= 1; h /= 2)
-        for (int l = 0; l < h; ++l) s[l] = s[l] + s[l + h];
-    return s[0];
+    if (!fx_in_range(acc)) return 0;
+    *e = (int64_t)acc;
+    return 1;
 }
 
-/* Energy bin: floor((E - e_min) / bin_w), also outside [0, B) (bounded to
- * +-2^30), so that the walk-in's lid can follow energies above the range.  */
-static int tri_bin(const orc_t *o, double e)
+/* Energy change of moving bead b to xn: the sum over its partners j of
+ * fx(V(b at xn, j)) - fx(V(b, j)).  0 if a term is a hard overlap.         */
+static int tri_delta_e(const orc_t *o, const float *x, int b, const float *xn, int64_t *de)
 {
-    double x = (e - o->e_min) / o->bin_w;
-    if (!(x >= -1073741824.0)) return -1073741824;
-    if (x >= 1073741824.0) return 1073741824;
-    return (int)floor(x);
+    __int128 acc = 0;
+    for (int j = 0; j < o->nb; ++j) {
+        if (j == b) continue;
+        int64_t tn, to;
+        if (!fx_term(tri_pair(o, b, j, xn, x + 3 * j), &tn)) return 0;
+        if (!fx_term(tri_pair(o, b, j, x + 3 * b, x + 3 * j), &to)) return 0;
+        acc += (__int128)tn - (__int128)to;
+    }
+    *de = (int64_t)acc;
+    return 1;
+}
+
+/* Energy bin: floor((E - e_min) / bin_w) in units of 2^-32, also outside
+ * [0, B) (bounded to +-2^30), so that the walk-in's lid can follow energies
+ * above the range.                                                          */
+static int tri_bin(const orc_t *o, int64_t e)
+{
+    int64_t diff = e - o->emin_fx;
+    int64_t q = diff / o->binw_fx;
+    if (diff % o->binw_fx != 0 && diff < 0) q -= 1;
+    if (q < -1073741824) return -1073741824;
+    if (q > 1073741824) return 1073741824;
+    return (int)q;
+}
+
+/* New energy of a valid move, or 0 if it leaves the energy range.          */
+static int fx_add(int64_t e, int64_t de, int64_t *out)
+{
+    __int128 s = (__int128)e + (__int128)de;
+    if (!fx_in_range(s)) return 0;
+    *out = (int64_t)s;
+    return 1;
 }
 
 /* Displacement of one axis, uniform in [-0.1, 0.1) (0.1 (2u - 1) with u a
@@ -629,11 +665,12 @@ static void trimer_attempt(orc_t *o, int w, int k, double lnf, uint64_t cnt)
     int b = (int)(((uint64_t)r[0] * (uint64_t)o->nb) >> 32);
     float xn[3];
     for (int c = 0; c < 3; ++c) xn[c] = tri_wrap(x[3 * b + c] + tri_disp(r[1 + c]), o->box);
-    double e_new = o->Ed[w] + tri_delta_e(o, x, b, xn);
-    int bn = tri_bin(o, e_new);
+    int64_t de = 0, e_new = 0;
+    int ok = tri_delta_e(o, x, b, xn, &de) && fx_add(o->Efx[w], de, &e_new);
+    int bn = ok ? tri_bin(o, e_new) : 0;
     int lo = o->start[k], hi = o->start[k] + W - 1;
     int acc = 0;
-    if (bn >= lo && bn <= hi) {
+    if (ok && bn >= lo && bn <= hi) {
         size_t io = (size_t)w * W + (o->E[w] - lo), in = (size_t)w * W + (bn - lo);
         if (o->precision == 0) {
             acc = accept64(o->lng[io] - o->lng[in], ru[0]);
@@ -644,7 +681,7 @@ static void trimer_attempt(orc_t *o, int w, int k, double lnf, uint64_t cnt)
     }
     if (acc) {
         for (int c = 0; c < 3; ++c) x[3 * b + c] = xn[c];
-        o->Ed[w] = e_new;
+        o->Efx[w] = e_new;
         o->E[w] = bn;
     }
     size_t ib = (size_t)w * W + (o->E[w] - lo);
@@ -680,15 +717,16 @@ static int trimer_walkin(orc_t *o, int w, int64_t max_attempts)
         int b = (int)(((uint64_t)r[0] * (uint64_t)o->nb) >> 32);
         float xn[3];
         for (int c = 0; c < 3; ++c) xn[c] = tri_wrap(x[3 * b + c] + tri_disp(r[1 + c]), o->box);
-        double e_new = o->Ed[w] + tri_delta_e(o, x, b, xn);
-        int bn = tri_bin(o, e_new);
+        int64_t de = 0, e_new = 0;
+        int ok = tri_delta_e(o, x, b, xn, &de) && fx_add(o->Efx[w], de, &e_new);
+        int bn = ok ? tri_bin(o, e_new) : 0;
         int co = o->E[w] < 0 ? 0 : (o->E[w] >= o->B ? o->B - 1 : o->E[w]);
         int cn = bn < 0 ? 0 : (bn >= o->B ? o->B - 1 : bn);
         double d = g[co] - g[cn];
         int inside = slack == 0 || (down ? bn <= bound : bn >= bound);
-        if (inside && accept64(d, ru[0])) {
+        if (ok && inside && accept64(d, ru[0])) {
             for (int c = 0; c < 3; ++c) x[3 * b + c] = xn[c];
-            o->Ed[w] = e_new;
+            o->Efx[w] = e_new;
             o->E[w] = bn;
             if (slack && down && o->E[w] + slack < bound) bound = o->E[w] + slack;
             if (slack && !down && o->E[w] - slack > bound) bound = o->E[w] - slack;
@@ -712,7 +750,9 @@ orc_t *orc_create_trimer(int nmol, float box, double e_min, double bin_w, int bi
                          int64_t sync_attempts, int exchange, int precision, int fixed_lnf, int shadow,
                          int walkin_slack, const float *init_coords)
 {
-    if (nmol < 1 || nmol > 1024 || !(box > 0.0f) || !(bin_w > 0.0) || bins < 8 || !init_coords) return NULL;
+    if (nmol < 1 || nmol > 1024 || !(box > 0.0f) || !(bin_w * FX_ONE >= 1.0 && bin_w * FX_ONE <= 0x1p60) ||
+        !(fabs(e_min) < 0x1p28) || bins < 8 || !init_coords)
+        return NULL;
     int nb = 3 * nmol;
     orc_t *o = orc_new(bins, 0, nb * 3 * (int)sizeof(float), h, overlap, m, seed, instance, flat_num,
                        flat_den, lnf_init, lnf_final, schedule, sync_attempts, exchange, precision,
@@ -720,8 +760,10 @@ orc_t *orc_create_trimer(int nmol, float box, double e_min, double bin_w, int bi
     if (!o) return NULL;
     o->model = MODEL_TRIMER3D;
     o->nmol = nmol; o->nb = nb; o->box = box; o->e_min = e_min; o->bin_w = bin_w;
-    o->Ed = (double *)calloc((size_t)o->nw, sizeof(double));
-    if (!o->Ed) { orc_free(o); return NULL; }
+    o->emin_fx = (int64_t)rint(e_min * FX_ONE);
+    o->binw_fx = (int64_t)rint(bin_w * FX_ONE);
+    o->Efx = (int64_t *)calloc((size_t)o->nw, sizeof(int64_t));
+    if (!o->Efx) { orc_free(o); return NULL; }
     for (int w = 0; w < o->nw; ++w) {
         float *x = (float *)(o->spin + (size_t)w * o->N);
         for (int i = 0; i < 3 * nb; ++i) {
@@ -729,18 +771,24 @@ orc_t *orc_create_trimer(int nmol, float box, double e_min, double bin_w, int bi
             if (!(v >= 0.0f && v < box)) { orc_free(o); return NULL; }
             x[i] = v;
         }
-        o->Ed[w] = tri_energy(o, x);
-        o->E[w] = tri_bin(o, o->Ed[w]);
+        if (!tri_energy(o, x, &o->Efx[w])) { orc_free(o); return NULL; }
+        o->E[w] = tri_bin(o, o->Efx[w]);
     }
     return o;
 }
 
 /* Test exports of the trimer model. */
-double orc_trimer_energy(const orc_t *o, int w) { return tri_energy(o, (const float *)(o->spin + (size_t)w * o->N)); }
-double orc_get_energy(const orc_t *o, int w) { return o->model != MODEL_POTTS2D ? o->Ed[w] : (double)o->E[w]; }
-double orc_trimer_delta(const orc_t *o, int w, int b, const float *xn)
+/* Energies in units of 2^-32 (fixed point); the return value is 0 for a
+ * hard overlap.                                                             */
+int orc_trimer_energy_fx(const orc_t *o, int w, int64_t *e)
 {
-    return tri_delta_e(o, (const float *)(o->spin + (size_t)w * o->N), b, xn);
+    return tri_energy(o, (const float *)(o->spin + (size_t)w * o->N), e);
+}
+int64_t orc_get_energy_fx(const orc_t *o, int w) { return o->model != MODEL_POTTS2D ? o->Efx[w] : (int64_t)o->E[w]; }
+double orc_get_energy(const orc_t *o, int w) { return o->model != MODEL_POTTS2D ? fx_to_double(o->Efx[w]) : (double)o->E[w]; }
+int orc_trimer_delta_fx(const orc_t *o, int w, int b, const float *xn, int64_t *de)
+{
+    return tri_delta_e(o, (const float *)(o->spin + (size_t)w * o->N), b, xn, de);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -844,50 +892,42 @@ static double lip_pair_ij(const orc_t *o, const float *x, const int8_t *type, co
     return lip_pair(o, type[i], type[j], lip_bonded(where, i, j), lip_r2(o->box, xi, x + 3 * j));
 }
 
-/* Total energy, pairs i < j in order (creation and tests only). */
-static double lip_energy(const orc_t *o, int w)
+/* Total energy in fixed point, every pair i < j (creation and tests only);
+ * 0 for a hard overlap (a bond stretched to R or beyond included).          */
+static int lip_energy(const orc_t *o, int w, int64_t *e)
 {
     const float *x = lip_x(o, w);
     const int8_t *type = lip_type(o, w);
     const int32_t *where = lip_where(o, w);
-    double e = 0.0;
+    __int128 acc = 0;
     for (int i = 0; i < o->np; ++i)
-        for (int j = i + 1; j < o->np; ++j) e = e + lip_pair_ij(o, x, type, where, i, x + 3 * i, j);
-    return e;
-}
-
-/* Fixed summation order of an energy change from partner terms t_j,
- * j = 0 .. np-1: per lane l = j mod 64 left to right over j, then lanes
- * halving (l += l + h for h = 32 .. 1), as for the trimer model.             */
-static double lip_reduce(double *t, int np)
-{
-    int slots = (np + 63) / 64 * 64;
-    double s[64];
-    for (int l = 0; l < 64; ++l) {
-        double acc = 0.0;
-        for (int j = l; j < slots; j += 64) {
-            double v = j < np ? t[j] : 0.0;
-            acc = j == l ? v : acc + v;
+        for (int j = i + 1; j < o->np; ++j) {
+            int64_t t;
+            if (!fx_term(lip_pair_ij(o, x, type, where, i, x + 3 * i, j), &t)) return 0;
+            acc += t;
         }
-        s[l] = acc;
-    }
-    for (int h = 32; h >= 1; h /= 2)
-        for (int l = 0; l < h; ++l) s[l] = s[l] + s[l + h];
-    return s[0];
+    if (!fx_in_range(acc)) return 0;
+    *e = (int64_t)acc;
+    return 1;
 }
 
-/* Energy change of displacing particle b to xn: t_j = V(b at xn, j) - V(b, j). */
-static double lip_delta_move(const orc_t *o, int w, int b, const float *xn, double *t)
+/* Energy change of displacing particle b to xn: the sum over partners j of
+ * fx(V(b at xn, j)) - fx(V(b, j)); 0 if a term is a hard overlap.          */
+static int lip_delta_move(const orc_t *o, int w, int b, const float *xn, int64_t *de)
 {
     const float *x = lip_x(o, w);
     const int8_t *type = lip_type(o, w);
     const int32_t *where = lip_where(o, w);
+    __int128 acc = 0;
     for (int j = 0; j < o->np; ++j) {
-        t[j] = 0.0;
-        if (j != b)
-            t[j] = lip_pair_ij(o, x, type, where, b, xn, j) - lip_pair_ij(o, x, type, where, b, x + 3 * b, j);
+        if (j == b) continue;
+        int64_t tn, to;
+        if (!fx_term(lip_pair_ij(o, x, type, where, b, xn, j), &tn)) return 0;
+        if (!fx_term(lip_pair_ij(o, x, type, where, b, x + 3 * b, j), &to)) return 0;
+        acc += (__int128)tn - (__int128)to;
     }
-    return lip_reduce(t, o->np);
+    *de = (int64_t)acc;
+    return 1;
 }
 
 /* A reptation proposal: the four particles whose role changes (captured,
@@ -957,9 +997,10 @@ static int lip_reptation(const orc_t *o, int w, int lipid, int end, uint32_t pic
     return 1;
 }
 
-/* Energy change of a reptation: t_j = sum over changed particles i (ascending,
- * i != j, and i < j when j is changed too) of V_new(i, j) - V_old(i, j).    */
-static double lip_delta_rep(const orc_t *o, int w, const lip_rep_t *rp, double *t)
+/* Energy change of a reptation: the sum of fx(V_new(i, j)) - fx(V_old(i, j))
+ * over the pairs that hold a changed particle i (each such pair once);
+ * positions stay, types and bonds change.  0 if a term is a hard overlap.  */
+static int lip_delta_rep(const orc_t *o, int w, const lip_rep_t *rp, int64_t *de)
 {
     const float *x = lip_x(o, w);
     const int8_t *type = lip_type(o, w);
@@ -969,23 +1010,27 @@ static double lip_delta_rep(const orc_t *o, int w, const lip_rep_t *rp, double *
     memcpy(nt, type, (size_t)o->np);
     memcpy(nw, where, (size_t)o->np * sizeof(int32_t));
     for (int a = 0; a < 4; ++a) { nt[rp->c[a]] = rp->nt[a]; nw[rp->c[a]] = rp->nwh[a]; }
-    for (int j = 0; j < o->np; ++j) {
+    __int128 acc = 0;
+    int ok = 1;
+    for (int j = 0; j < o->np && ok; ++j) {
         int jin = j == rp->c[0] || j == rp->c[1] || j == rp->c[2] || j == rp->c[3];
-        double acc = 0.0;
-        int first = 1;
         for (int a = 0; a < 4; ++a) {
             int i = rp->c[a];
             if (i == j || (jin && i > j)) continue;
             double r2 = lip_r2(o->box, x + 3 * i, x + 3 * j);
-            double v = lip_pair(o, nt[i], nt[j], lip_bonded(nw, i, j), r2) -
-                       lip_pair(o, type[i], type[j], lip_bonded(where, i, j), r2);
-            acc = first ? v : acc + v;
-            first = 0;
+            int64_t tn, to;
+            if (!fx_term(lip_pair(o, nt[i], nt[j], lip_bonded(nw, i, j), r2), &tn) ||
+                !fx_term(lip_pair(o, type[i], type[j], lip_bonded(where, i, j), r2), &to)) {
+                ok = 0;
+                break;
+            }
+            acc += (__int128)tn - (__int128)to;
         }
-        t[j] = acc;
     }
     free(nt); free(nw);
-    return lip_reduce(t, o->np);
+    if (!ok) return 0;
+    *de = (int64_t)acc;
+    return 1;
 }
 
 static void lip_apply_rep(orc_t *o, int w, const lip_rep_t *rp)
@@ -1011,10 +1056,10 @@ static int lip_accept_rep(double d, uint32_t r, int nc, int nr)
  * (cnt, w, domu): block words a0 particle (or lipid), a1..a3 displacement;
  * u0 acceptance, u1 move type, u2 end (top bit), u3 captured particle.
  * lng_of(b) gives the walker's ln g at bin b; returns 1 if accepted.        */
-typedef struct { double e_new; int bn; int ok; int is_rep; lip_rep_t rp; int b; float xn[3]; int nc, nr; } lip_prop_t;
+typedef struct { int64_t e_new; int bn; int ok; int is_rep; lip_rep_t rp; int b; float xn[3]; int nc, nr; } lip_prop_t;
 
 static void lip_propose(const orc_t *o, int w, uint64_t cnt, uint32_t dom, uint32_t domu, uint32_t u_out[4],
-                        lip_prop_t *pr, double *t)
+                        lip_prop_t *pr)
 {
     uint32_t ctr[4] = { (uint32_t)cnt, (uint32_t)(cnt >> 32), (uint32_t)w, (dom << 24) | o->instance };
     uint32_t a[4];
@@ -1023,19 +1068,21 @@ static void lip_propose(const orc_t *o, int w, uint64_t cnt, uint32_t dom, uint3
     philox4x32_10(ctr, o->key, u_out);
     pr->ok = 0;
     pr->is_rep = u_out[1] < o->rep_thr;
-    double de;
+    int64_t de = 0;
+    int valid;
     if (pr->is_rep) {
         int lipid = (int)(((uint64_t)a[0] * (uint64_t)o->nlip) >> 32);
         if (!lip_reptation(o, w, lipid, (int)(u_out[2] >> 31), u_out[3], &pr->rp)) return;
-        de = lip_delta_rep(o, w, &pr->rp, t);
+        valid = lip_delta_rep(o, w, &pr->rp, &de);
     } else {
         const float *x = lip_x(o, w);
         pr->b = (int)(((uint64_t)a[0] * (uint64_t)o->np) >> 32);
         for (int c = 0; c < 3; ++c) pr->xn[c] = tri_wrap(x[3 * pr->b + c] + tri_disp(a[1 + c]), o->box);
-        de = lip_delta_move(o, w, pr->b, pr->xn, t);
+        valid = lip_delta_move(o, w, pr->b, pr->xn, &de);
     }
-    if (!isfinite(de)) return;              /* a bond stretched to R or beyond */
-    pr->e_new = o->Ed[w] + de;
+    /* a hard overlap (a bond stretched to R or beyond included) or an energy
+     * out of range: no move                                                  */
+    if (!valid || !fx_add(o->Efx[w], de, &pr->e_new)) return;
     pr->bn = tri_bin(o, pr->e_new);
     pr->ok = 1;
 }
@@ -1047,7 +1094,7 @@ static void lip_apply(orc_t *o, int w, const lip_prop_t *pr)
         float *x = lip_x(o, w);
         for (int c = 0; c < 3; ++c) x[3 * pr->b + c] = pr->xn[c];
     }
-    o->Ed[w] = pr->e_new;
+    o->Efx[w] = pr->e_new;
     o->E[w] = pr->bn;
 }
 
@@ -1056,12 +1103,12 @@ static int lip_decide(const lip_prop_t *pr, double d, uint32_t u0)
     return pr->is_rep ? lip_accept_rep(d, u0, pr->rp.nc, pr->rp.nr) : accept64(d, u0);
 }
 
-static void lipid_attempt(orc_t *o, int w, int k, double lnf, uint64_t cnt, double *t)
+static void lipid_attempt(orc_t *o, int w, int k, double lnf, uint64_t cnt)
 {
     int W = o->W;
     uint32_t u[4];
     lip_prop_t pr;
-    lip_propose(o, w, cnt, DOM_MOVE, DOM_MOVE_U, u, &pr, t);
+    lip_propose(o, w, cnt, DOM_MOVE, DOM_MOVE_U, u, &pr);
     int lo = o->start[k], hi = o->start[k] + W - 1;
     if (pr.ok && pr.bn >= lo && pr.bn <= hi) {
         size_t io = (size_t)w * W + (o->E[w] - lo), in = (size_t)w * W + (pr.bn - lo);
@@ -1079,8 +1126,7 @@ static int lipid_walkin(orc_t *o, int w, int64_t max_attempts)
     int k = w / o->m;
     int lo = o->start[k], hi = o->start[k] + o->W - 1;
     double *g = (double *)calloc((size_t)o->B, sizeof(double));
-    double *t = (double *)malloc((size_t)o->np * sizeof(double));
-    if (!g || !t) { free(g); free(t); return ORC_ENOMEM; }
+    if (!g) return ORC_ENOMEM;
     int64_t n = 0;
     int slack = o->walkin_slack;
     int down = o->E[w] > hi;
@@ -1090,7 +1136,7 @@ static int lipid_walkin(orc_t *o, int w, int64_t max_attempts)
         if (n >= max_attempts) { status = ORC_EBUDGET; break; }
         uint32_t u[4];
         lip_prop_t pr;
-        lip_propose(o, w, (uint64_t)n, DOM_WALKIN, DOM_WALKIN_U, u, &pr, t);
+        lip_propose(o, w, (uint64_t)n, DOM_WALKIN, DOM_WALKIN_U, u, &pr);
         if (pr.ok) {
             int co = o->E[w] < 0 ? 0 : (o->E[w] >= o->B ? o->B - 1 : o->E[w]);
             int cn = pr.bn < 0 ? 0 : (pr.bn >= o->B ? o->B - 1 : pr.bn);
@@ -1106,7 +1152,7 @@ static int lipid_walkin(orc_t *o, int w, int64_t max_attempts)
         ++n;
     }
     o->walkin_att[w] = n;
-    free(g); free(t);
+    free(g);
     return status;
 }
 
@@ -1122,7 +1168,8 @@ orc_t *orc_create_lipid(int nlip, int nsol, float box, double eps_ww, uint32_t r
                         int64_t sync_attempts, int exchange, int fixed_lnf, int walkin_slack,
                         const float *init_coords)
 {
-    if (nlip < 1 || nsol < 0 || nlip * 3 + nsol > 4096 || !(box > 0.0f) || !(bin_w > 0.0) || bins < 8 ||
+    if (nlip < 1 || nsol < 0 || nlip * 3 + nsol > 4096 || !(box > 0.0f) ||
+        !(bin_w * FX_ONE >= 1.0 && bin_w * FX_ONE <= 0x1p60) || !(fabs(e_min) < 0x1p28) || bins < 8 ||
         !init_coords || !(eps_ww >= 0.0))
         return NULL;
     int np = 3 * nlip + nsol;
@@ -1136,9 +1183,11 @@ orc_t *orc_create_lipid(int nlip, int nsol, float box, double eps_ww, uint32_t r
     o->model = MODEL_LIPID3D;
     o->np = np; o->nlip = nlip; o->box = box; o->eps_ww = eps_ww; o->rep_thr = rep_thr;
     o->e_min = e_min; o->bin_w = bin_w;
+    o->emin_fx = (int64_t)rint(e_min * FX_ONE);
+    o->binw_fx = (int64_t)rint(bin_w * FX_ONE);
     o->off_type = off_type; o->off_lip = off_lip; o->off_where = off_where;
-    o->Ed = (double *)calloc((size_t)o->nw, sizeof(double));
-    if (!o->Ed) { orc_free(o); return NULL; }
+    o->Efx = (int64_t *)calloc((size_t)o->nw, sizeof(int64_t));
+    if (!o->Efx) { orc_free(o); return NULL; }
     for (int w = 0; w < o->nw; ++w) {
         float *x = lip_x(o, w);
         for (int i = 0; i < 3 * np; ++i) {
@@ -1154,15 +1203,14 @@ orc_t *orc_create_lipid(int nlip, int nsol, float box, double eps_ww, uint32_t r
             where[i] = lipid ? i : -1;
         }
         for (int i = 0; i < 3 * nlip; ++i) lp[i] = i;
-        o->Ed[w] = lip_energy(o, w);
-        if (!isfinite(o->Ed[w])) { orc_free(o); return NULL; }
-        o->E[w] = tri_bin(o, o->Ed[w]);
+        if (!lip_energy(o, w, &o->Efx[w])) { orc_free(o); return NULL; }
+        o->E[w] = tri_bin(o, o->Efx[w]);
     }
     return o;
 }
 
 /* Test exports of the lipid model. */
-double orc_lipid_energy(const orc_t *o, int w) { return lip_energy(o, w); }
+int orc_lipid_energy_fx(const orc_t *o, int w, int64_t *e) { return lip_energy(o, w, e); }
 double orc_log_poly(double x) { return log_poly(x); }
 double orc_lipid_pair(const orc_t *o, int ti, int tj, int bonded, double r2) { return lip_pair(o, ti, tj, bonded, r2); }
 
@@ -1174,19 +1222,17 @@ void orc_lipid_state(const orc_t *o, int w, float *x, int8_t *type, int32_t *lip
     if (lip) memcpy(lip, lip_lip(o, w), (size_t)o->nlip * 12);
 }
 
-/* Energy change of displacing particle b of walker w to xn (no state change). */
-double orc_lipid_delta_move(const orc_t *o, int w, int b, const float *xn)
+/* Energy change (units of 2^-32) of displacing particle b of walker w to xn
+ * (no state change); 0 for a hard overlap.                                  */
+int orc_lipid_delta_move_fx(const orc_t *o, int w, int b, const float *xn, int64_t *de)
 {
-    double *t = (double *)malloc((size_t)o->np * sizeof(double));
-    double d = lip_delta_move(o, w, b, xn, t);
-    free(t);
-    return d;
+    return lip_delta_move(o, w, b, xn, de);
 }
 
 /* Apply the reptation of `lipid` at `end` capturing the pick-th nearby
  * solvent particle (the word pick * 2^32 / n_c selects it); out: n_c, n_r,
  * energy change.  Returns 0 if no solvent particle is near that end.       */
-int orc_lipid_reptate(orc_t *o, int w, int lipid, int end, int pick, int *nc, int *nr, double *de)
+int orc_lipid_reptate(orc_t *o, int w, int lipid, int end, int pick, int *nc, int *nr, int64_t *de)
 {
     const float *x = lip_x(o, w);
     int e = end == 0 ? lip_lip(o, w)[3 * lipid] : lip_lip(o, w)[3 * lipid + 2];
@@ -1195,12 +1241,11 @@ int orc_lipid_reptate(orc_t *o, int w, int lipid, int end, int pick, int *nc, in
     uint32_t word = (uint32_t)((((uint64_t)pick << 32) + (uint64_t)n - 1) / (uint64_t)n);
     lip_rep_t rp;
     if (!lip_reptation(o, w, lipid, end, word, &rp)) return 0;
-    double *t = (double *)malloc((size_t)o->np * sizeof(double));
-    double d = lip_delta_rep(o, w, &rp, t);
-    free(t);
+    int64_t d = 0, e_new = 0;
+    if (!lip_delta_rep(o, w, &rp, &d) || !fx_add(o->Efx[w], d, &e_new)) return 0;
     lip_apply_rep(o, w, &rp);
-    o->Ed[w] += d;
-    o->E[w] = tri_bin(o, o->Ed[w]);
+    o->Efx[w] = e_new;
+    o->E[w] = tri_bin(o, o->Efx[w]);
     *nc = rp.nc; *nr = rp.nr; *de = d;
     return 1;
 }
@@ -1515,7 +1560,7 @@ static int exchange_round(orc_t *o)
                 memcpy(o->spin + (size_t)a * N, o->spin + (size_t)b * N, (size_t)N);
                 memcpy(o->spin + (size_t)b * N, tmp, (size_t)N);
                 o->E[a] = ey; o->E[b] = ex;
-                if (o->Ed) { double te = o->Ed[a]; o->Ed[a] = o->Ed[b]; o->Ed[b] = te; }
+                if (o->Efx) { int64_t te = o->Efx[a]; o->Efx[a] = o->Efx[b]; o->Efx[b] = te; }
                 uint32_t t = o->replica[a]; o->replica[a] = o->replica[b]; o->replica[b] = t;
             }
         }
@@ -1616,9 +1661,7 @@ int orc_run(orc_t *o, int64_t attempts, int64_t walkin_budget)
             int k = w / o->m;
             double lnf = o->lnf[k];
             if (o->model == MODEL_LIPID3D) {
-                double *tb = (double *)malloc((size_t)o->np * sizeof(double));
-                for (int64_t t = 0; t < seg; ++t) lipid_attempt(o, w, k, lnf, (uint64_t)(s0 + t), tb);
-                free(tb);
+                for (int64_t t = 0; t < seg; ++t) lipid_attempt(o, w, k, lnf, (uint64_t)(s0 + t));
             } else if (o->model == MODEL_TRIMER3D)
                 for (int64_t t = 0; t < seg; ++t) trimer_attempt(o, w, k, lnf, (uint64_t)(s0 + t));
             else

@@ -114,6 +114,7 @@ def lib():
         L.rewl_structure_noalloc.argtypes = [P, P]
         L.rewl_lipid_obs_field.argtypes = [P, i32, dbl, dbl]
         L.rewl_get_energy.argtypes = [P, i32, ctypes.POINTER(dbl)]
+        L.rewl_get_energy_fx.argtypes = [P, i32, ctypes.POINTER(ctypes.c_int64)]
         L.rewl_save.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.rewl_load.argtypes = [P, P, ctypes.c_size_t]
         L.rewl_get_lng.argtypes = [P, i32, P, i64, P, P]
@@ -347,6 +348,12 @@ class Rewl:
         """Energy of walker w (the trimer model's continuous energy)."""
         e = ctypes.c_double(0)
         _check(lib().rewl_get_energy(self._h, w, ctypes.byref(e)))
+        return e.value
+
+    def energy_fx(self, w):
+        """Energy of walker w in units of 2^-32 (continuous models; the Potts energy for Potts runs)."""
+        e = ctypes.c_int64(0)
+        _check(lib().rewl_get_energy_fx(self._h, w, ctypes.byref(e)))
         return e.value
 
     @classmethod

@@ -32,7 +32,7 @@ struct DevState {
     // Potts: L x L lattice, q states, N = L*L sites, energies e_lo .. e_lo+B-1.
     // Trimer: N = bytes of one configuration (3 nmol beads x 3 binary32
     // coordinates), B energy bins of width bin_w from e_min, e_lo = 0 and
-    // E[] holds each walker's bin, Ed[] its energy.
+    // E[] holds each walker's bin, Efx[] its energy (units of 2^-32).
     int L, q, N, h, m, nw, W, B, e_lo;
     int nmol, nb;                // trimer: molecules, beads; lipid model: lipids, particles
     // lipid model: W-W Lennard-Jones depth, reptation threshold of a 32-bit
@@ -43,6 +43,7 @@ struct DevState {
     int lip_off_type, lip_off_lip, lip_off_where;
     float box;                   // trimer: side of the periodic cube
     double e_min, bin_w;         // trimer: energy of bin 0's lower edge, bin width
+    int64_t emin_fx, binw_fx;    // the same in units of 2^-32 (rint(x 2^32))
     double th_e0, th_de;         // energy of bin b for thermodynamics: th_e0 + b th_de
     int Npad, Wpad, Bpad;        // row strides (elements)
     int Ntag;                    // entries of the LDS conflict-tag table (power of two)
@@ -57,7 +58,7 @@ struct DevState {
     const int32_t *start;        // [h] lowest energy of each window
     int8_t *spins;               // [nw][Npad]
     int32_t *E;                  // [nw] energy (Potts) or energy bin (trimer)
-    double *Ed;                  // [nw] trimer: continuous energy (null for Potts)
+    int64_t *Efx;                // [nw] continuous models: energy in units of 2^-32 (null for Potts)
     double *lng;                 // [nw][Wpad]            (precision 0)
     float *lng_hi, *lng_lo;      // [nw][Wpad] each       (precision 1)
     uint32_t *H;                 // [nw][Wpad]
@@ -148,6 +149,50 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 
 // floor(r * n / 2^32): Lemire's multiply-shift map of a 32-bit word to [0, n).
 __device__ __forceinline__ uint32_t mul_shift(uint32_t r, uint32_t n) { return __umulhi(r, n); }
+
+// ---------------------------------------------------------------------------
+// Energies of the continuous models (trimer, lipid) in fixed point: a pair
+// term V (binary64) is rounded once to a multiple of 2^-32, fx(V) =
+// rint(V 2^32), and a total or a change of energy is the exact int64 sum of
+// such terms, the same in whatever order the lanes add them.  A term of
+// magnitude 2^18 or more (or one that is not finite) is a hard overlap: a
+// move that would create one is rejected, a start holding one is refused.
+// Energies stay below 2^29 in magnitude (2^61 units); a change below 2^62.
+constexpr int64_t kFxBad = INT64_MIN;   // marks a hard-overlap term in buffers
+constexpr int64_t kFxELimit = (int64_t)1 << 61;
+
+__device__ __forceinline__ bool fx_term(double v, int64_t &out) {
+#pragma clang fp contract(off)
+    if (!(__builtin_fabs(v) < 0x1p18)) return false;
+    out = (int64_t)__builtin_rint(v * 0x1p32);
+    return true;
+}
+
+// E + dE if it stays in range (|E| < 2^61, |dE| < 2^62: the sum cannot overflow).
+__device__ __forceinline__ bool fx_add(int64_t e, int64_t de, int64_t &out) {
+    const int64_t s = e + de;
+    if (s >= kFxELimit || s <= -kFxELimit) return false;
+    out = s;
+    return true;
+}
+
+// Bin of a fixed-point energy: floor((E - e_min) / bin_w) on the 2^-32 grid,
+// also outside [0, B) (bounded to +-2^30) so the walk-in's lid can follow it.
+__device__ __forceinline__ int fx_bin(int64_t emin_fx, int64_t binw_fx, int64_t e) {
+    const int64_t diff = e - emin_fx;
+    int64_t q = diff / binw_fx;
+    if (q * binw_fx != diff && diff < 0) q -= 1;
+    if (q < -1073741824) return -1073741824;
+    if (q > 1073741824) return 1073741824;
+    return (int)q;
+}
+
+// Sum of an int64 over the 64 lanes (any order: integer addition is exact);
+// every lane returns the total.
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
 // ---------------------------------------------------------------------------
 // exp(x) for x < 0, the acceptance ratio min[1, g_old/g_new] of Sec. 2 written

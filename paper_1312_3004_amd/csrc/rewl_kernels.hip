@@ -1047,7 +1047,7 @@ __device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t r, in
         }
         if (threadIdx.x == 0) {
             const int t = st.E[a]; st.E[a] = st.E[b]; st.E[b] = t;
-            if (st.Ed) { const double te = st.Ed[a]; st.Ed[a] = st.Ed[b]; st.Ed[b] = te; }
+            if (st.Efx) { const int64_t te = st.Efx[a]; st.Efx[a] = st.Efx[b]; st.Efx[b] = te; }
             const uint32_t rr = st.replica[a]; st.replica[a] = st.replica[b]; st.replica[b] = rr;
         }
     }

@@ -24,13 +24,14 @@
 // int8[np] (0 P, 1 H, 2 W; padded to 4 bytes), lipid rows int32[nmol][3]
 // (head first), position table int32[np] (3 lipid + bead, -1 solvent).
 //
+// Energies are fixed point (units of 2^-32): every pair term is rounded once
+// and totals and changes are exact integer sums, so the lanes and waves may
+// add the partner terms in any order and every implementation agrees to the
+// bit.
+//
 // Mapping: one walker per workgroup (the attempt kernel: up to 16 wavefronts
 // sharing the 64-partner chunks; walk-in and set-up: one wavefront), its
-// state, ln g and H in LDS.  Attempts are sequential; every energy change is
-// a sum of per-partner
-// terms t_j (j = 0 .. np-1) taken in a fixed order: per lane l left to right
-// over j = l, l + 64, ..., then across lanes by halving (lane l adds lane
-// l + h for h = 32, 16, ..., 1).
+// state, ln g and H in LDS.  Attempts are sequential.
 #include "rewl_device.h"
 
 namespace rewl_gpu {
@@ -118,36 +119,14 @@ __device__ __forceinline__ bool lip_bonded(int a, int b) {
     return a - b == 1 || b - a == 1;
 }
 
-__device__ __forceinline__ double lip_shfl_down(double v, int d) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __shfl_down((int)(uint32_t)b, d, 64);
-    const int hi = __shfl_down((int)(uint32_t)((unsigned long long)b >> 32), d, 64);
-    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
-}
+__device__ __forceinline__ int lip_bin(const DevState &st, int64_t e) { return fx_bin(st.emin_fx, st.binw_fx, e); }
 
-__device__ __forceinline__ double lip_lane0(double v) {
-    const long long b = __double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Lane sums (acc) reduced by halving; every lane returns the total.
-__device__ __forceinline__ double lip_halve(double acc, int lane) {
-#pragma clang fp contract(off)
-    for (int h = 32; h >= 1; h >>= 1) {
-        const double other = lip_shfl_down(acc, h);
-        if (lane < h) acc = acc + other;
-    }
-    return lip_lane0(acc);
-}
-
-__device__ __forceinline__ int lip_bin(const DevState &st, double e) {
-#pragma clang fp contract(off)
-    const double x = (e - st.e_min) / st.bin_w;
-    if (!(x >= -1073741824.0)) return -1073741824;
-    if (x >= 1073741824.0) return 1073741824;
-    return (int)__builtin_floor(x);
+// fx(V_new) - fx(V_old) of one pair; false for a hard overlap.
+__device__ __forceinline__ bool lip_term(double vn, double vo, int64_t &t) {
+    int64_t a = 0, b = 0;
+    const bool ok = fx_term(vn, a) & fx_term(vo, b);
+    t = a - b;
+    return ok;
 }
 
 __device__ __forceinline__ float lip_disp(uint32_t r) {
@@ -187,7 +166,7 @@ struct LipProp {
     float xn[3];
     int lipid, nc, nr;
     int c[4], nt[4], nwh[4], nl[3];
-    double de;
+    int64_t de;   // units of 2^-32
 };
 
 // Solvent particles within R of particle e under the types `type` except the
@@ -223,13 +202,14 @@ __device__ __forceinline__ int lip_near(const DevState &st, const LipView &v, in
 
 // Build the proposal of one attempt from its Philox blocks (a: particle or
 // lipid, displacement; u: acceptance, move type, end, captured particle).
-__device__ __forceinline__ void lip_propose(const DevState &st, const LipView &v, double Ed, const U4 &a,
-                                            const U4 &u, LipProp &p, int lane) {
+__device__ __forceinline__ void lip_propose(const DevState &st, const LipView &v, const U4 &a, const U4 &u,
+                                            LipProp &p, int lane) {
 #pragma clang fp contract(off)
     const float box = st.box, half = 0.5f * st.box;
     p.ok = false;
     p.rep = u.y < st.lip_rep_thr;
-    double acc = 0.0;
+    int64_t acc = 0;
+    bool bad = false;
     if (!p.rep) {
         const int b = (int)mul_shift(a.x, (uint32_t)st.nb);
         p.b = b;
@@ -240,15 +220,15 @@ __device__ __forceinline__ void lip_propose(const DevState &st, const LipView &v
         const int tb = v.type[b], wb = v.where[b];
         for (int c0 = 0; c0 < st.nb; c0 += 64) {
             const int j = c0 + lane;
-            double t = 0.0;
             if (j < st.nb && j != b) {
                 const float *xj = v.x + 3 * j;
                 const int tj = v.type[j];
                 const bool bd = lip_bonded(wb, v.where[j]);
-                t = lip_pair(tb, tj, bd, lip_r2(p.xn, xj, box, half), st.lip_eps_ww) -
-                    lip_pair(tb, tj, bd, lip_r2(o, xj, box, half), st.lip_eps_ww);
+                int64_t t = 0;
+                bad |= !lip_term(lip_pair(tb, tj, bd, lip_r2(p.xn, xj, box, half), st.lip_eps_ww),
+                                 lip_pair(tb, tj, bd, lip_r2(o, xj, box, half), st.lip_eps_ww), t);
+                acc += t;
             }
-            acc = c0 == 0 ? t : acc + t;
         }
     } else {
         const int lipid = (int)mul_shift(a.x, (uint32_t)st.nmol);
@@ -281,36 +261,29 @@ __device__ __forceinline__ void lip_propose(const DevState &st, const LipView &v
         }
         p.nc = nc;
         p.nr = lip_near(st, v, l1, p.c, p.nt, -1, &cap, lane);
-        // t_j = sum over changed particles i (ascending; i != j, and i < j when
-        // j changes too) of V_new(i, j) - V_old(i, j)
+        // fx(V_new(i, j)) - fx(V_old(i, j)) over the pairs holding a changed
+        // particle i (each pair once: i != j, and i < j when j changes too)
         for (int c0 = 0; c0 < st.nb; c0 += 64) {
             const int j = c0 + lane;
-            double t = 0.0;
             if (j < st.nb) {
                 int tjo = v.type[j], wjo = v.where[j], tjn = tjo, wjn = wjo;
                 bool jin = false;
                 for (int i = 0; i < 4; ++i)
                     if (p.c[i] == j) { jin = true; tjn = p.nt[i]; wjn = p.nwh[i]; }
-                bool first = true;
                 for (int i = 0; i < 4; ++i) {
                     const int ci = p.c[i];
                     if (ci == j || (jin && ci > j)) continue;
                     const double r2 = lip_r2(v.x + 3 * ci, v.x + 3 * j, box, half);
-                    const double vn = lip_pair(p.nt[i], tjn, lip_bonded(p.nwh[i], wjn), r2, st.lip_eps_ww);
-                    const double vo = lip_pair(v.type[ci], tjo, lip_bonded(v.where[ci], wjo), r2, st.lip_eps_ww);
-                    const double d = vn - vo;
-                    t = first ? d : t + d;
-                    first = false;
+                    int64_t t = 0;
+                    bad |= !lip_term(lip_pair(p.nt[i], tjn, lip_bonded(p.nwh[i], wjn), r2, st.lip_eps_ww),
+                                     lip_pair(v.type[ci], tjo, lip_bonded(v.where[ci], wjo), r2, st.lip_eps_ww), t);
+                    acc += t;
                 }
             }
-            acc = c0 == 0 ? t : acc + t;
         }
     }
-    const double de = lip_halve(acc, lane);
-    if (!__builtin_isfinite(de)) return;
-    p.de = de;
-    p.ok = true;
-    (void)Ed;
+    p.de = wave_sum64(acc);
+    p.ok = __ballot(bad) == 0ull;
 }
 
 __device__ __forceinline__ bool lip_accept(const LipProp &p, double d, uint32_t r) {
@@ -345,37 +318,38 @@ __device__ __forceinline__ void lip_words(const DevState &st, uint64_t t, uint32
 }
 
 // ---------------------------------------------------------------------------
-// Energy of every walker's starting configuration: the pairs i < j summed in
-// order on lane 0 (the order fixes the rounding; this runs once per run),
-// their terms computed 64 at a time by the wavefront and handed over in LDS.
+// Energy of every walker's starting configuration: the exact sum of the
+// pair terms over i < j, rows i dealt to the lanes, each term's high and low
+// 32 bits summed separately (neither sum can overflow); a start with a hard
+// overlap (a bond at R or beyond included) or out of range gets the bin
+// INT32_MIN, which the host refuses.
 __global__ __launch_bounds__(64) void k_lipid_init(DevState st) {
 #pragma clang fp contract(off)
-    __shared__ double terms[64];
     const int w = blockIdx.x;
     const int lane = threadIdx.x;
     unsigned char *row = (unsigned char *)(st.spins + (size_t)w * st.Npad);
     const LipView v = lip_view(st, row);
     const float box = st.box, half = 0.5f * st.box;
-    double e = 0.0;
-    for (int i = 0; i < st.nb; ++i) {
-        for (int j0 = i + 1; j0 < st.nb; j0 += 64) {
-            const int j = j0 + lane;
-            double t = 0.0;
-            if (j < st.nb)
-                t = lip_pair(v.type[i], v.type[j], lip_bonded(v.where[i], v.where[j]),
-                             lip_r2(v.x + 3 * i, v.x + 3 * j, box, half), st.lip_eps_ww);
-            terms[lane] = t;
-            __syncthreads();
-            if (lane == 0) {
-                const int n = st.nb - j0 < 64 ? st.nb - j0 : 64;
-                for (int k = 0; k < n; ++k) e = e + terms[k];
-            }
-            __syncthreads();
+    int64_t shi = 0, slo = 0;
+    bool bad = false;
+    for (int i = lane; i < st.nb; i += 64) {
+        const int ti = v.type[i], wi = v.where[i];
+        for (int j = i + 1; j < st.nb; ++j) {
+            int64_t t = 0;
+            bad |= !fx_term(lip_pair(ti, v.type[j], lip_bonded(wi, v.where[j]),
+                                     lip_r2(v.x + 3 * i, v.x + 3 * j, box, half), st.lip_eps_ww), t);
+            shi += t >> 32;
+            slo += t & 0xffffffffll;
         }
     }
+    shi = wave_sum64(shi);
+    slo = wave_sum64(slo);
+    bad = __ballot(bad) != 0ull;
     if (lane == 0) {
-        st.Ed[w] = e;
-        st.E[w] = lip_bin(st, e);
+        int64_t e = 0;
+        const bool ok = !bad && shi > -(1ll << 30) && shi < (1ll << 30) && fx_add(shi * 4294967296ll, slo, e);
+        st.Efx[w] = ok ? e : 0;
+        st.E[w] = ok ? lip_bin(st, e) : INT32_MIN;
     }
 }
 
@@ -400,7 +374,7 @@ __global__ __launch_bounds__(64) void k_lipid_walkin(DevState st, int64_t chunk,
     const int lo = st.start[k], hi = lo + st.W - 1;
     const int B = st.B;
     int E = st.E[w];
-    double Ed = st.Ed[w];
+    int64_t Ef = st.Efx[w];
     int64_t t = st.walkin_att[w];
     const int slack = st.walkin_slack;
     const bool down = E > hi;
@@ -411,9 +385,9 @@ __global__ __launch_bounds__(64) void k_lipid_walkin(DevState st, int64_t chunk,
         U4 a, u;
         lip_words(st, (uint64_t)t, (uint32_t)w, kDomWalkin, kDomWalkinU, a, u);
         LipProp p;
-        lip_propose(st, v, Ed, a, u, p, lane);
-        if (p.ok) {
-            const double e_new = Ed + p.de;
+        lip_propose(st, v, a, u, p, lane);
+        int64_t e_new = 0;
+        if (p.ok && fx_add(Ef, p.de, e_new)) {
             const int bn = lip_bin(st, e_new);
             const int co = E < 0 ? 0 : (E >= B ? B - 1 : E);
             const int cn = bn < 0 ? 0 : (bn >= B ? B - 1 : bn);
@@ -421,7 +395,7 @@ __global__ __launch_bounds__(64) void k_lipid_walkin(DevState st, int64_t chunk,
             const bool inside = slack == 0 || (down ? bn <= bound : bn >= bound);
             if (inside && lip_accept(p, d, u.x)) {
                 lip_apply(st, v, p, lane);
-                Ed = e_new;
+                Ef = e_new;
                 E = bn;
                 if (slack && down && E + slack < bound) bound = E + slack;
                 if (slack && !down && E - slack > bound) bound = E - slack;
@@ -439,7 +413,7 @@ __global__ __launch_bounds__(64) void k_lipid_walkin(DevState st, int64_t chunk,
     for (int b = lane; b < B; b += 64) ocnt[b] = cnt[b];
     if (lane == 0) {
         st.E[w] = E;
-        st.Ed[w] = Ed;
+        st.Efx[w] = Ef;
         st.walkin_att[w] = t;
         st.walkin_done[w] = done ? 1 : 0;
         st.walkin_bound[w] = bound;
@@ -452,9 +426,9 @@ __global__ __launch_bounds__(64) void k_lipid_walkin(DevState st, int64_t chunk,
 // ln g += ln f and H += 1 at the bin after the decision.
 //
 // One workgroup per walker with up to 16 wavefronts: wave v takes the
-// 64-partner chunks c = v, v + nwave, ...; the partner terms go to LDS
-// (tbuf[c][lane]) and wave 0 sums them in the fixed order (per lane over c,
-// then halving), decides and applies the move.  Reptation candidates are
+// 64-partner chunks c = v, v + nwave, ...; the fixed-point partner terms go
+// to LDS (tbuf[c][lane]) and wave 0 adds them up (exact, any order), decides
+// and applies the move.  Reptation candidates are
 // found with one ballot mask per chunk, written to LDS and read by every
 // wave.  All branches that contain a barrier depend only on the attempt's
 // random words or on values every wave reads from LDS, so the waves agree.
@@ -470,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_lipid_sweep(DevState st, int64_t s0, i
     const int nch = (st.nb + 63) / 64;
     double *g = (double *)(smem + st.Npad);
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
-    double *tbuf = (double *)(smem + st.Npad + (size_t)Wpad * 12);
+    int64_t *tbuf = (int64_t *)(smem + st.Npad + (size_t)Wpad * 12);
     unsigned long long *mask1 = (unsigned long long *)(tbuf + (size_t)nch * 64);
     unsigned long long *mask2 = mask1 + nch;
     const uint32_t *gx = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
@@ -487,7 +461,7 @@ __global__ __launch_bounds__(1024) void k_lipid_sweep(DevState st, int64_t s0, i
     const int lo = st.start[k], hi = lo + W - 1;
     const double lnf = st.lnf[k];
     int E = st.E[w];
-    double Ed = st.Ed[w];
+    int64_t Ef = st.Efx[w];
     if (E < lo || E > hi) return;   // not walked in (every wave reads the same E)
     U4 la, lu;   // random words of attempt t0 + lane, drawn 64 attempts at a time
     for (int64_t t = 0; t < n; ++t) {
@@ -511,13 +485,14 @@ __global__ __launch_bounds__(1024) void k_lipid_sweep(DevState st, int64_t s0, i
             const int tb = v.type[b], wb = v.where[b];
             for (int c = wave; c < nch; c += nwave) {
                 const int j = c * 64 + lane;
-                double tj = 0.0;
+                int64_t tj = 0;
                 if (j < st.nb && j != b) {
                     const float *xj = v.x + 3 * j;
                     const int tjt = v.type[j];
                     const bool bd = lip_bonded(wb, v.where[j]);
-                    tj = lip_pair(tb, tjt, bd, lip_r2(p.xn, xj, box, half), st.lip_eps_ww) -
-                         lip_pair(tb, tjt, bd, lip_r2(o, xj, box, half), st.lip_eps_ww);
+                    if (!lip_term(lip_pair(tb, tjt, bd, lip_r2(p.xn, xj, box, half), st.lip_eps_ww),
+                                  lip_pair(tb, tjt, bd, lip_r2(o, xj, box, half), st.lip_eps_ww), tj))
+                        tj = kFxBad;
                 }
                 tbuf[c * 64 + lane] = tj;
             }
@@ -589,50 +564,53 @@ __global__ __launch_bounds__(1024) void k_lipid_sweep(DevState st, int64_t s0, i
                 // partner terms of the reptation (see lip_propose)
                 for (int c = wave; c < nch; c += nwave) {
                     const int j = c * 64 + lane;
-                    double tj = 0.0;
+                    int64_t tj = 0;
+                    bool bad = false;
                     if (j < st.nb) {
                         const int tjo = v.type[j], wjo = v.where[j];
                         int tjn = tjo, wjn = wjo;
                         bool jin = false;
                         for (int i = 0; i < 4; ++i)
                             if (p.c[i] == j) { jin = true; tjn = p.nt[i]; wjn = p.nwh[i]; }
-                        bool first = true;
                         for (int i = 0; i < 4; ++i) {
                             const int ci = p.c[i];
                             if (ci == j || (jin && ci > j)) continue;
                             const double r2 = lip_r2(v.x + 3 * ci, v.x + 3 * j, box, half);
-                            const double vn = lip_pair(p.nt[i], tjn, lip_bonded(p.nwh[i], wjn), r2, st.lip_eps_ww);
-                            const double vo =
-                                lip_pair(v.type[ci], tjo, lip_bonded(v.where[ci], wjo), r2, st.lip_eps_ww);
-                            const double d = vn - vo;
-                            tj = first ? d : tj + d;
-                            first = false;
+                            int64_t d = 0;
+                            bad |= !lip_term(lip_pair(p.nt[i], tjn, lip_bonded(p.nwh[i], wjn), r2, st.lip_eps_ww),
+                                             lip_pair(v.type[ci], tjo, lip_bonded(v.where[ci], wjo), r2,
+                                                      st.lip_eps_ww),
+                                             d);
+                            tj += d;
                         }
                     }
-                    tbuf[c * 64 + lane] = tj;
+                    tbuf[c * 64 + lane] = bad ? kFxBad : tj;
                 }
             }
         }
         __syncthreads();
         if (wave == 0) {
             if (p.ok) {
-                double acc = 0.0;
+                int64_t acc = 0;
+                bool bad = false;
                 for (int c = 0; c < nch; ++c) {
-                    const double tj = tbuf[c * 64 + lane];
-                    acc = c == 0 ? tj : acc + tj;
+                    const int64_t tj = tbuf[c * 64 + lane];
+                    if (tj == kFxBad) bad = true;
+                    else acc += tj;
                 }
-                p.de = lip_halve(acc, lane);
+                p.de = wave_sum64(acc);
+                p.ok = __ballot(bad) == 0ull;
                 if (p.rep) {
                     int nr = 0;
                     for (int c = 0; c < nch; ++c) nr += __builtin_popcountll(mask2[c]);
                     p.nr = nr;
                 }
-                if (__builtin_isfinite(p.de)) {
-                    const double e_new = Ed + p.de;
+                int64_t e_new = 0;
+                if (p.ok && fx_add(Ef, p.de, e_new)) {
                     const int bn = lip_bin(st, e_new);
                     if (bn >= lo && bn <= hi && lip_accept(p, g[E - lo] - g[bn - lo], u.x)) {
                         lip_apply(st, v, p, lane);
-                        Ed = e_new;
+                        Ef = e_new;
                         E = bn;
                     }
                 }
@@ -653,7 +631,7 @@ __global__ __launch_bounds__(1024) void k_lipid_sweep(DevState st, int64_t s0, i
     }
     if (threadIdx.x == 0) {
         st.E[w] = E;
-        st.Ed[w] = Ed;
+        st.Efx[w] = Ef;
     }
 }
 

@@ -63,7 +63,7 @@ Layout make_layout(const Params &p, int precision, int shadow, bool trimer, int 
     l.start = take(sizeof(int32_t) * p.h);
     l.spins = take((size_t)p.nw * p.Npad);
     l.E = take(sizeof(int32_t) * p.nw);
-    l.Ed = trimer ? take(sizeof(double) * p.nw) : 0;
+    l.Ed = trimer ? take(sizeof(int64_t) * p.nw) : 0;
     l.lng = precision == 0 ? take(sizeof(double) * p.nw * p.Wpad) : 0;
     l.lng_hi = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
     l.lng_lo = precision == 1 ? take(sizeof(float) * p.nw * p.Wpad) : 0;
@@ -170,7 +170,8 @@ int check_lipid(TrimerGeom &g, int h, double o, int m, const rewl_opts &op, Para
     if (g.nmol < 1 || g.nsol < 0 || 3 * g.nmol + g.nsol > 4096)
         return fail(REWL_EINVAL, "lipids >= 1, solvent >= 0, at most 4096 particles");
     if (!(g.box > 0.0f) || !(g.box < 1e6f)) return fail(REWL_EINVAL, "box must be positive");
-    if (!(g.bin_w > 0.0) || !std::isfinite(g.e_min)) return fail(REWL_EINVAL, "bin_w must be > 0, e_min finite");
+    if (!(g.bin_w * 0x1p32 >= 1.0 && g.bin_w * 0x1p32 <= 0x1p60) || !(std::fabs(g.e_min) < 0x1p28))
+        return fail(REWL_EINVAL, "bin_w must lie in [2^-32, 2^28], |e_min| below 2^28");
     if (!(g.eps_ww >= 0.0) || !std::isfinite(g.eps_ww)) return fail(REWL_EINVAL, "eps_ww must be >= 0");
     if (g.bins < 8) return fail(REWL_EINVAL, "at least 8 energy bins");
     int st = check_opts(h, m, op);
@@ -205,7 +206,8 @@ int check_trimer(const TrimerGeom &g, int h, double o, int m, const rewl_opts &o
                  std::vector<int32_t> *starts) {
     if (g.nmol < 1 || g.nmol > 1024) return fail(REWL_EINVAL, "nmol must be in [1, 1024]");
     if (!(g.box > 0.0f) || !(g.box < 1e6f)) return fail(REWL_EINVAL, "box must be positive");
-    if (!(g.bin_w > 0.0) || !std::isfinite(g.e_min)) return fail(REWL_EINVAL, "bin_w must be > 0, e_min finite");
+    if (!(g.bin_w * 0x1p32 >= 1.0 && g.bin_w * 0x1p32 <= 0x1p60) || !(std::fabs(g.e_min) < 0x1p28))
+        return fail(REWL_EINVAL, "bin_w must lie in [2^-32, 2^28], |e_min| below 2^28");
     if (g.bins < 8) return fail(REWL_EINVAL, "at least 8 energy bins");
     int st = check_opts(h, m, op);
     if (st != REWL_OK) return st;
@@ -386,9 +388,11 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
         d.lip_eps_ww = geom->eps_ww; d.lip_rep_thr = geom->rep_thr;
         d.lip_off_type = geom->off_type; d.lip_off_lip = geom->off_lip; d.lip_off_where = geom->off_where;
         d.e_min = geom->e_min; d.bin_w = geom->bin_w;
+        d.emin_fx = (int64_t)std::rint(geom->e_min * 0x1p32);
+        d.binw_fx = (int64_t)std::rint(geom->bin_w * 0x1p32);
         d.th_e0 = geom->e_min + 0.5 * geom->bin_w;   // bin centres
         d.th_de = geom->bin_w;
-        d.Ed = (double *)(b + lay.Ed);
+        d.Efx = (int64_t *)(b + lay.Ed);
     } else {
         d.th_e0 = (double)p.e_lo;
         d.th_de = 1.0;
@@ -473,8 +477,18 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     if (e == hipSuccess) e = rewl_gpu::launch_init_energy(d, r->stream);
     // replica paths start from the initial placement (replica w in slot w)
     if (e == hipSuccess) e = rewl_gpu::launch_track(d, r->stream);
+    std::vector<int32_t> e0(geom ? p.nw : 0);
+    if (e == hipSuccess && geom)
+        e = hipMemcpyAsync(e0.data(), d.E, sizeof(int32_t) * p.nw, hipMemcpyDeviceToHost, r->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) return bail(fail(REWL_EDEVICE, std::string("rewl_create: ") + hipGetErrorString(e)));
+    // continuous models: the set-up kernel marks a start that holds a hard
+    // overlap (a pair term of 2^18 or more) or lies out of the energy range
+    for (int w = 0; w < (int)e0.size(); ++w)
+        if (e0[w] == INT32_MIN)
+            return bail(fail(REWL_EINVAL, "starting configuration " + std::to_string(w) +
+                                              " holds a hard overlap (a pair energy of 2^18 or more) or an energy "
+                                              "beyond 2^29"));
     *out = r;
     return REWL_OK;
 }
@@ -612,14 +626,32 @@ int rewl_get_energy(rewl_t *r, int w, double *E) {
     if (!r || !E) return fail(REWL_EINVAL, "null argument");
     const DevState &d = r->st;
     if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
-    if (d.Ed) {
-        HIP_TRY(hipMemcpyAsync(E, d.Ed + w, sizeof(double), hipMemcpyDeviceToHost, r->stream));
+    if (d.Efx) {
+        int64_t e = 0;
+        HIP_TRY(hipMemcpyAsync(&e, d.Efx + w, sizeof(int64_t), hipMemcpyDeviceToHost, r->stream));
         HIP_TRY(hipStreamSynchronize(r->stream));
+        *E = (double)e / 0x1p32;
     } else {
         int32_t e = 0;
         HIP_TRY(hipMemcpyAsync(&e, d.E + w, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
         HIP_TRY(hipStreamSynchronize(r->stream));
         *E = (double)e;
+    }
+    return REWL_OK;
+}
+
+int rewl_get_energy_fx(rewl_t *r, int w, int64_t *E) {
+    if (!r || !E) return fail(REWL_EINVAL, "null argument");
+    const DevState &d = r->st;
+    if (w < 0 || w >= d.nw) return fail(REWL_EINVAL, "walker index out of range");
+    if (d.Efx) {
+        HIP_TRY(hipMemcpyAsync(E, d.Efx + w, sizeof(int64_t), hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+    } else {
+        int32_t e = 0;
+        HIP_TRY(hipMemcpyAsync(&e, d.E + w, sizeof(int32_t), hipMemcpyDeviceToHost, r->stream));
+        HIP_TRY(hipStreamSynchronize(r->stream));
+        *E = e;
     }
     return REWL_OK;
 }
@@ -917,7 +949,7 @@ namespace {
 // Checkpoint header: the run's identity (sizes and options that fix the
 // workspace layout and the trajectory) and its host-side counters.
 struct SaveHeader {
-    char magic[8];          // "REWLCKP1"
+    char magic[8];          // "REWLCKP1" (Potts), "REWLCKP2" (continuous models)
     uint64_t ws_bytes;
     int32_t model, L, q, N, h, m, W, B, nmol, precision, shadow, fixed_lnf, schedule, exchange;
     float box;
@@ -932,7 +964,8 @@ struct SaveHeader {
 SaveHeader make_header(const rewl *r) {
     SaveHeader h;
     std::memset(&h, 0, sizeof(h));
-    std::memcpy(h.magic, "REWLCKP1", 8);
+    // "REWLCKP2": continuous-model energies in fixed point (Potts rows unchanged)
+    std::memcpy(h.magic, r->st.model == rewl_gpu::kModelPotts2D ? "REWLCKP1" : "REWLCKP2", 8);
     const DevState &d = r->st;
     h.ws_bytes = r->lay.total;
     h.model = d.model; h.L = d.L; h.q = d.q; h.N = d.N; h.h = d.h; h.m = d.m; h.W = d.W; h.B = d.B;
@@ -971,7 +1004,7 @@ int rewl_load(rewl_t *r, const void *buf, size_t n) {
     SaveHeader h;
     std::memcpy(&h, buf, sizeof(h));
     SaveHeader mine = make_header(r);
-    if (std::memcmp(h.magic, "REWLCKP1", 8) != 0) return fail(REWL_EINVAL, "not a checkpoint");
+    if (std::memcmp(h.magic, "REWLCKP", 7) != 0) return fail(REWL_EINVAL, "not a checkpoint");
     // everything but the counters must match the handle
     SaveHeader a = h, b = mine;
     a.step = b.step = 0; a.round = b.round = 0;

@@ -12,13 +12,13 @@
 // pair energies are binary64 from those differences, the bond length by the
 // correctly rounded binary64 square root.
 //
-// Mapping: one walker per 64-lane wavefront.  Its coordinates, ln g and H
-// live in LDS.  Attempts are sequential; inside an attempt each lane
-// evaluates the energy change with partners lane, lane+64, lane+128, ... and
-// the partner terms are summed in a fixed order: per lane left to right over
-// its partners, then across lanes by halving (lane l adds lane l+h for
-// h = 32, 16, ..., 1).  That order is part of the energy-change definition,
-// so every implementation that follows it rounds identically.
+// Energies are fixed point (units of 2^-32): every pair term is rounded once
+// and totals and changes are exact integer sums, so the lanes may add the
+// partner terms in any order and every implementation agrees to the bit.
+//
+// Mapping: one walker per workgroup.  Its coordinates, ln g and H live in
+// LDS.  Attempts are sequential; inside an attempt the lanes evaluate the
+// pair terms of the moved bead with 64 partners each and add them up.
 #include "rewl_device.h"
 
 namespace rewl_gpu {
@@ -73,77 +73,72 @@ __device__ __forceinline__ float wrap(float v, float box) {
     return v;
 }
 
-__device__ __forceinline__ double shfl_down_d(double v, int d) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __shfl_down((int)(uint32_t)b, d, 64);
-    const int hi = __shfl_down((int)(uint32_t)((unsigned long long)b >> 32), d, 64);
-    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
-}
 __device__ __forceinline__ double readlane_d_tri(double v, int l) {
     const long long b = __double_as_longlong(v);
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
     const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((unsigned long long)b >> 32), l);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-__device__ __forceinline__ double lane0_d(double v) {
-    const long long b = __double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
-// Energy change of moving bead b (coordinates in LDS x) to n, in the fixed
-// summation order; every lane returns the same value.
-__device__ __forceinline__ double delta_e(const DevState &st, const float *x, int b, float n0, float n1,
-                                          float n2, int lane) {
+// Energy change of moving bead b (coordinates in LDS x) to n: the sum over
+// partners j of fx(V(b at n, j)) - fx(V(b, j)); false for a hard overlap.
+// Every lane returns the same result.
+__device__ __forceinline__ bool delta_e(const DevState &st, const float *x, int b, float n0, float n1, float n2,
+                                        int lane, int64_t &de) {
 #pragma clang fp contract(off)
     const float box = st.box, half = 0.5f * st.box;
     const float o0 = x[3 * b], o1 = x[3 * b + 1], o2 = x[3 * b + 2];
-    double acc = 0.0;
+    int64_t acc = 0;
+    bool bad = false;
     for (int c = 0; c < st.nb; c += 64) {
         const int j = c + lane;
-        double t = 0.0;
         if (j < st.nb && j != b) {
             const float r0 = x[3 * j], r1 = x[3 * j + 1], r2 = x[3 * j + 2];
-            t = pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half) -
-                pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half);
+            int64_t tn = 0, to = 0;
+            bad |= !fx_term(pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half), tn);
+            bad |= !fx_term(pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half), to);
+            acc += tn - to;
         }
-        acc = c == 0 ? t : acc + t;
     }
-    for (int h = 32; h >= 1; h >>= 1) {
-        const double other = shfl_down_d(acc, h);
-        if (lane < h) acc = acc + other;
-    }
-    return lane0_d(acc);
+    de = wave_sum64(acc);
+    return __ballot(bad) == 0ull;
 }
 
-// Bin of energy e: floor((e - e_min) / bin_w), also outside [0, B) (bounded
-// to +-2^30) so that the walk-in's lid follows energies above the range.
-__device__ __forceinline__ int energy_bin(const DevState &st, double e) {
-#pragma clang fp contract(off)
-    const double x = (e - st.e_min) / st.bin_w;
-    if (!(x >= -1073741824.0)) return -1073741824;
-    if (x >= 1073741824.0) return 1073741824;
-    return (int)__builtin_floor(x);
-}
+// Bin of a fixed-point energy (also outside [0, B), bounded to +-2^30).
+__device__ __forceinline__ int energy_bin(const DevState &st, int64_t e) { return fx_bin(st.emin_fx, st.binw_fx, e); }
 
 // ---------------------------------------------------------------------------
-// Energy of every walker's starting configuration: pairs i < j in order, one
-// lane (the order fixes the rounding; this runs once per run).
+// Energy of every walker's starting configuration: the exact sum of the
+// pair terms over i < j, rows i dealt to the lanes.  Each term is split into
+// its high and low 32 bits, summed separately (neither sum can overflow), and
+// the total is checked against the energy range; a start with a hard
+// overlap or out of range gets the bin INT32_MIN, which the host refuses.
 __global__ __launch_bounds__(64) void k_trimer_init(DevState st) {
 #pragma clang fp contract(off)
     const int w = blockIdx.x;
-    if (threadIdx.x != 0) return;
+    const int lane = threadIdx.x;
     const float *x = (const float *)(st.spins + (size_t)w * st.Npad);
     const float box = st.box, half = 0.5f * st.box;
-    double e = 0.0;
-    for (int i = 0; i < st.nb; ++i) {
+    int64_t shi = 0, slo = 0;
+    bool bad = false;
+    for (int i = lane; i < st.nb; i += 64) {
         const float p0 = x[3 * i], p1 = x[3 * i + 1], p2 = x[3 * i + 2];
-        for (int j = i + 1; j < st.nb; ++j)
-            e = e + pair_energy(i, j, p0, p1, p2, x[3 * j], x[3 * j + 1], x[3 * j + 2], box, half);
+        for (int j = i + 1; j < st.nb; ++j) {
+            int64_t t = 0;
+            bad |= !fx_term(pair_energy(i, j, p0, p1, p2, x[3 * j], x[3 * j + 1], x[3 * j + 2], box, half), t);
+            shi += t >> 32;
+            slo += t & 0xffffffffll;
+        }
     }
-    st.Ed[w] = e;
-    st.E[w] = energy_bin(st, e);
+    shi = wave_sum64(shi);
+    slo = wave_sum64(slo);
+    bad = __ballot(bad) != 0ull;
+    if (lane == 0) {
+        int64_t e = 0;
+        const bool ok = !bad && shi > -(1ll << 30) && shi < (1ll << 30) && fx_add(shi * 4294967296ll, slo, e);
+        st.Efx[w] = ok ? e : 0;
+        st.E[w] = ok ? energy_bin(st, e) : INT32_MIN;
+    }
 }
 
 // Random words of 64 attempts, one attempt per lane: bead, displacement,
@@ -188,7 +183,7 @@ __global__ __launch_bounds__(64) void k_trimer_walkin(DevState st, int64_t chunk
     const int lo = st.start[k], hi = lo + st.W - 1;
     const int B = st.B;
     int E = st.E[w];
-    double Ed = st.Ed[w];
+    int64_t Ef = st.Efx[w];
     int64_t t = st.walkin_att[w];
     const int slack = st.walkin_slack;
     const bool down = E > hi;
@@ -207,19 +202,20 @@ __global__ __launch_bounds__(64) void k_trimer_walkin(DevState st, int64_t chunk
             const float n0 = wrap(x[3 * b] + d0, st.box);
             const float n1 = wrap(x[3 * b + 1] + d1, st.box);
             const float n2 = wrap(x[3 * b + 2] + d2, st.box);
-            const double e_new = Ed + delta_e(st, x, b, n0, n1, n2, lane);
-            const int bn = energy_bin(st, e_new);
+            int64_t de = 0, e_new = 0;
+            const bool ok = delta_e(st, x, b, n0, n1, n2, lane, de) && fx_add(Ef, de, e_new);
+            const int bn = ok ? energy_bin(st, e_new) : 0;
             const int co = E < 0 ? 0 : (E >= B ? B - 1 : E);
             const int cn = bn < 0 ? 0 : (bn >= B ? B - 1 : bn);
             const double d = (double)((int64_t)cnt[co] - (int64_t)cnt[cn]);
             const bool inside = slack == 0 || (down ? bn <= bound : bn >= bound);
-            if (inside && accept64(d, u)) {
+            if (ok && inside && accept64(d, u)) {
                 if (lane == 0) {
                     x[3 * b] = n0;
                     x[3 * b + 1] = n1;
                     x[3 * b + 2] = n2;
                 }
-                Ed = e_new;
+                Ef = e_new;
                 E = bn;
                 if (slack && down && E + slack < bound) bound = E + slack;
                 if (slack && !down && E - slack > bound) bound = E - slack;
@@ -237,7 +233,7 @@ __global__ __launch_bounds__(64) void k_trimer_walkin(DevState st, int64_t chunk
     for (int b = lane; b < B; b += 64) ocnt[b] = cnt[b];
     if (lane == 0) {
         st.E[w] = E;
-        st.Ed[w] = Ed;
+        st.Efx[w] = Ef;
         st.walkin_att[w] = t;
         st.walkin_done[w] = done ? 1 : 0;
         st.walkin_bound[w] = bound;
@@ -251,40 +247,9 @@ __global__ __launch_bounds__(64) void k_trimer_walkin(DevState st, int64_t chunk
 // the bin after the decision.
 //
 // One workgroup per walker with one wavefront per 64 partner beads: wave c
-// evaluates the partner terms t_j of j = 64c + lane and leaves them in LDS;
-// wave 0 adds them per lane in chunk order, sums the lanes by halving (lane l
-// adds lane l+h: permlane swaps for h = 32, 16, row shifts for h <= 8), and
-// takes the decision.  Every wave draws the same random words.
-
-// Lane l's copy of lane l+STEP (for the lanes that use it): permlane swaps
-// for STEP = 32, 16, a row shift inside rows of 16 lanes for STEP <= 8.
-template <int STEP>
-__device__ __forceinline__ unsigned pull_u32(unsigned v) {
-    if constexpr (STEP == 32) return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
-    else if constexpr (STEP == 16) return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
-    else return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + STEP, 0xf, 0xf, false);
-}
-
-template <int STEP>
-__device__ __forceinline__ double pull(double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = pull_u32<STEP>((unsigned)b);
-    const unsigned hi = pull_u32<STEP>((unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// s_l + s_{l+h} for h = 32, 16, ..., 1 (lanes l < h carry the sum; the
-// others don't matter); returns lane 0's total.
-__device__ __forceinline__ double halving_sum(double s) {
-#pragma clang fp contract(off)
-    s = s + pull<32>(s);
-    s = s + pull<16>(s);
-    s = s + pull<8>(s);
-    s = s + pull<4>(s);
-    s = s + pull<2>(s);
-    s = s + pull<1>(s);
-    return lane0_d(s);
-}
+// evaluates the fixed-point pair terms of partners j = 64c + lane and leaves
+// them in LDS; wave 0 adds them up (exact integers, any order) and takes the
+// decision.  Every wave draws the same random words.
 
 // Layout of a trimer attempt workgroup: partner chunks of 64 beads; with
 // two roles the waves of role 0 evaluate the partners' energies with the bead
@@ -318,7 +283,7 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
     float *gh = (float *)(smem + st.Npad);
     float *gl = gh + Wpad;
     uint32_t *H = (uint32_t *)(smem + st.Npad + (size_t)Wpad * 8);
-    double *tbuf = (double *)(smem + st.Npad + (size_t)Wpad * 12);   // [roles][chunks][64]
+    int64_t *tbuf = (int64_t *)(smem + st.Npad + (size_t)Wpad * 12);   // [roles][chunks][64]
     const uint32_t *gx = (const uint32_t *)(st.spins + (size_t)w * st.Npad);
     for (int i = threadIdx.x; i < st.Npad / 4; i += blockDim.x) ((uint32_t *)x)[i] = gx[i];
     const size_t row = (size_t)w * Wpad;
@@ -334,7 +299,7 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
     __syncthreads();
     const int lo = st.start[k], hi = lo + W - 1;
     int E = st.E[w];
-    double Ed = st.Ed[w];
+    int64_t Ef = st.Efx[w];
     if (E < lo || E > hi) return;   // not walked in: leave the walker untouched
     const double lnf = st.lnf[k];
     const float lnf32 = (float)lnf;
@@ -360,32 +325,41 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
             const float n2 = wrap(o2 + d2, box);
             for (int c = part; c < tw.chunks; c += tw.per_role) {
                 const int j = c * 64 + lane;
-                double v = 0.0;
+                int64_t v = 0;
                 if (j < st.nb && j != b) {
                     const float r0 = x[3 * j], r1 = x[3 * j + 1], r2 = x[3 * j + 2];
+                    int64_t tn = 0, to = 0;
+                    bool ok = true;
                     if (tw.roles == 2) {
-                        v = role == 0 ? pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half)
-                                      : pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half);
+                        ok = role == 0 ? fx_term(pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half), tn)
+                                       : fx_term(pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half), to);
+                        v = role == 0 ? tn : to;
                     } else {
-                        v = pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half) -
-                            pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half);
+                        ok = fx_term(pair_energy(b, j, n0, n1, n2, r0, r1, r2, box, half), tn) &
+                             fx_term(pair_energy(b, j, o0, o1, o2, r0, r1, r2, box, half), to);
+                        v = tn - to;
                     }
+                    if (!ok) v = kFxBad;
                 }
                 tbuf[(role * tw.chunks + c) * 64 + lane] = v;
             }
             __syncthreads();
             if (wave == 0) {
-                // t_j = V(new) - V(old) per partner, summed per lane in chunk order
-                double sl = 0.0;
+                // fx(V(new)) - fx(V(old)) per partner, added up exactly
+                int64_t sl = 0;
+                bool bad = false;
                 for (int c = 0; c < tw.chunks; ++c) {
-                    const double t = tw.roles == 2 ? tbuf[c * 64 + lane] - tbuf[(tw.chunks + c) * 64 + lane]
-                                                   : tbuf[c * 64 + lane];
-                    sl = c == 0 ? t : sl + t;
+                    const int64_t a0 = tbuf[c * 64 + lane];
+                    const int64_t a1 = tw.roles == 2 ? tbuf[(tw.chunks + c) * 64 + lane] : 0;
+                    if (a0 == kFxBad || a1 == kFxBad) bad = true;
+                    else sl += a0 - a1;
                 }
-                const double e_new = Ed + halving_sum(sl);
-                const int bn = energy_bin(st, e_new);
+                const int64_t de = wave_sum64(sl);
+                int64_t e_new = 0;
+                const bool ok = __ballot(bad) == 0ull && fx_add(Ef, de, e_new);
+                const int bn = ok ? energy_bin(st, e_new) : 0;
                 bool acc = false;
-                if (bn >= lo && bn <= hi) {
+                if (ok && bn >= lo && bn <= hi) {
                     const int io = E - lo, in = bn - lo;
                     const double luj = readlane_d_tri(lnu, a);
                     const uint32_t u = __builtin_amdgcn_readlane(dr.u, a);
@@ -408,7 +382,7 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
                         x[3 * b + 1] = n1;
                         x[3 * b + 2] = n2;
                     }
-                    Ed = e_new;
+                    Ef = e_new;
                     E = bn;
                 }
                 if (lane == 0) {
@@ -440,7 +414,7 @@ __global__ __launch_bounds__(1024) void k_trimer_sweep(DevState st, int64_t s0, 
     }
     if (threadIdx.x == 0) {
         st.E[w] = E;
-        st.Ed[w] = Ed;
+        st.Efx[w] = Ef;
     }
 }
 

@@ -29,8 +29,8 @@ def make_pair(nmol, box, e_min, bin_w, bins, h, m, coords_seed=1, threads=8, **o
 
 def assert_same_energies(g, o):
     for w in range(g.nw):
-        a, b = np.float64(g.energy(w)), np.float64(o.energy(w))
-        assert a.view(np.uint64) == b.view(np.uint64), (w, a, b)
+        a, b = g.energy_fx(w), o.energy_fx(w)   # fixed point, units of 2^-32
+        assert a == b, (w, a, b)
 
 
 CASES = [
@@ -66,6 +66,17 @@ def test_trimer_workload_shape_bitexact():
     assert_same_state(g, o)
     assert_same_energies(g, o)
     assert max(g.walker(w)["walkin_attempts"] for w in range(g.nw)) > 0
+
+
+def test_trimer_start_with_hard_overlap_is_refused():
+    # two heads 0.3 apart: a WCA term above 2^18, a hard overlap
+    c = np.array([[1.0, 5.0, 5.0], [2.0, 5.0, 5.0], [3.0, 5.0, 5.0],
+                  [1.0, 5.0, 5.3], [2.0, 5.0, 6.3], [3.0, 5.0, 7.3]], dtype=np.float32)
+    print("[case] trimer start with a hard overlap", flush=True)
+    with pytest.raises(_pk().RewlError):
+        _pk().Rewl.trimer(2, 10.0, -50.0, 0.5, 400, 1, 0.75, 1, c[None])
+    with pytest.raises(ValueError):
+        oracle.Rewl.trimer(2, 10.0, -50.0, 0.5, 400, 1, 0.75, 1, c[None])
 
 
 def test_trimer_full_protocol_bitexact_and_join():

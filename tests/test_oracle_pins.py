@@ -627,24 +627,60 @@ def test_trimer_minimum_image():
     assert abs((e - base) - (1.0 + 2 * lj(np.sqrt(2.0)))) < 1e-5
 
 
+def _np_trimer_energy(x, box):
+    """Plain binary64 sum of the trimer force field over all pairs (numpy)."""
+    n = len(x)
+    e = 0.0
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = (x[j] - x[i]).astype(np.float32)
+            d = np.where(d > box / 2, d - box, np.where(d < -box / 2, d + box, d)).astype(np.float64)
+            r2 = float(np.sum(d * d))
+            if i // 3 == j // 3 and abs(i % 3 - j % 3) == 1:
+                e += 100.0 * (np.sqrt(r2) - 1.0) ** 2
+            elif i % 3 > 0 and j % 3 > 0:
+                e += 4 * (r2 ** -6 - r2 ** -3) if r2 < 6.25 else 0.0
+            elif r2 < 2 ** (1 / 3):
+                e += 4 * (r2 ** -6 - r2 ** -3) + 1.0
+    return e
+
+
 def test_trimer_delta_matches_recomputed_energy_and_drift():
+    # Energies are exact sums of the pair terms rounded once to multiples of
+    # 2^-32: a move's change equals the difference of the two totals exactly,
+    # and the total agrees with the plain binary64 sum within the rounding of
+    # the terms (one half unit of 2^-32 per pair, plus the float sum's own).
     x = workloads.init_trimers(8, 5.0, 1, 3)
     o = _trimer(x, 8, box=5.0, e_min=-200.0, bins=1000)
+    assert abs(o.trimer_energy(0) - _np_trimer_energy(x[0], 5.0)) <= 300 * 2.0**-33 + 1e-12
     rng = np.random.default_rng(1)
     cur = x[0].copy()
     for _ in range(200):
         b = int(rng.integers(24))
         xn = np.mod(cur[b] + rng.uniform(-0.1, 0.1, 3), 5.0).astype(np.float32)
-        d = o.trimer_delta(0, b, xn)
-        e0 = _trimer(cur[None], 8, box=5.0, e_min=-200.0, bins=1000).trimer_energy(0)
+        d = o.trimer_delta_fx(0, b, xn)
+        e0 = _trimer(cur[None], 8, box=5.0, e_min=-200.0, bins=1000).trimer_energy_fx(0)
         cur2 = cur.copy()
         cur2[b] = xn
-        e1 = _trimer(cur2[None], 8, box=5.0, e_min=-200.0, bins=1000).trimer_energy(0)
-        assert abs(d - (e1 - e0)) <= 1e-9 * max(1.0, abs(e0))
-    # incremental energy of a long run against a full recompute
+        e1 = _trimer(cur2[None], 8, box=5.0, e_min=-200.0, bins=1000).trimer_energy_fx(0)
+        assert d == e1 - e0
+    # the incremental energy of a long run equals a full recompute exactly
     o = _trimer(x, 8, box=5.0, e_min=-200.0, bins=1000, lnf_init=0.0, fixed_lnf=1, sync_attempts=10_000)
     o.run(100_000)
-    assert abs(o.energy(0) - o.trimer_energy(0)) < 1e-9
+    assert o.energy_fx(0) == o.trimer_energy_fx(0)
+
+
+def test_trimer_hard_overlap_is_refused_and_rejected():
+    # a pair term of 2^18 or more is a hard overlap: a start holding one is
+    # refused, and a move creating one is no move at all
+    c = np.array([[1.0, 5.0, 5.0], [2.0, 5.0, 5.0], [3.0, 5.0, 5.0],
+                  [1.0, 5.0, 5.3], [2.0, 5.0, 6.3], [3.0, 5.0, 7.3]], dtype=np.float32)   # heads 0.3 apart
+    with pytest.raises(ValueError):
+        _trimer(c[None], 2)
+    c[3, 2] = 6.0
+    o = _trimer(c[None], 2, e_min=-50.0)
+    assert o.trimer_delta_fx(0, 3, np.array([1.0, 5.0, 5.3], dtype=np.float32)) is None
+    assert o.trimer_delta_fx(0, 3, np.array([1.0, 5.0, 5.9], dtype=np.float32)) is not None
 
 
 def test_trimer_fixed_weights_detailed_balance():
@@ -658,8 +694,18 @@ def test_trimer_fixed_weights_detailed_balance():
     for w in range(2):
         d = o.walker(w)
         assert d["H"].sum() == 20_000
-        assert d["E"] == int((o.energy(w) + 60.0) // 0.5)
-        assert abs(o.energy(w) - o.trimer_energy(w)) < 1e-9
+        assert d["E"] == (o.energy_fx(w) + 60 * 2**32) // 2**31
+        assert o.energy_fx(w) == o.trimer_energy_fx(w)
+
+
+def test_trimer_workload_range_covers_the_anneal_and_the_starts():
+    # the trimer workload's bins reach below the lowest energy a seeded
+    # Metropolis anneal (the oracle's walk with weights beta E) finds, and
+    # above every starting energy of its walkers
+    from oracle import trimer_range
+    lowest, starts, ok = trimer_range.check()
+    assert ok, (lowest, starts.min(), starts.max())
+    assert lowest < starts.min() - 300      # the anneal really descends
 
 
 def test_trimer_rewl_walks_in_and_converges():
@@ -977,7 +1023,9 @@ def test_lipid_energy_and_displacement_match_direct_sums():
     x, t, lp = o.lipid_state(0)
     assert list(t[:6]) == [P_, H_, H_, P_, H_, H_] and np.all(t[12:] == W_)
     e = _np_energy(x, t, lp, 4.3, 0.7)
-    assert o.lipid_energy(0) == pytest.approx(e, rel=1e-10) and o.energy(0) == o.lipid_energy(0)
+    npair = len(x) * (len(x) - 1) // 2
+    assert abs(o.lipid_energy(0) - e) <= npair * 2.0**-33 + 1e-10 * abs(e)
+    assert o.energy_fx(0) == o.lipid_energy_fx(0)
     rng = np.random.default_rng(5)
     for b in (0, 1, 2, 7, 13, 23):
         xn = np.mod(x[b] + rng.uniform(-0.1, 0.1, 3), 4.3).astype(np.float32)
@@ -1002,7 +1050,7 @@ def test_lipid_reptation_moves_bonds_types_and_reverses():
     for lipid in range(6):
         for end in (0, 1):
             x, t, lp = o.lipid_state(0)
-            e0 = o.energy(0)
+            e0 = o.energy_fx(0)
             cand = _near_solvent(x, t, lp[lipid][0 if end == 0 else 2], 4.3)
             if not cand:
                 assert o.lipid_reptate(0, lipid, end, 0) is None
@@ -1017,13 +1065,17 @@ def test_lipid_reptation_moves_bonds_types_and_reverses():
             assert list(lp2[lipid]) == new and [t2[i] for i in new] == [P_, H_, H_] and t2[released] == W_
             assert nc == len(cand) and nr == len(_near_solvent(x2, t2, old[1], 4.3))
             assert released in _near_solvent(x2, t2, old[1], 4.3)
-            assert de == pytest.approx(_np_energy(x2, t2, lp2, 4.3) - _np_energy(x, t, lp, 4.3), rel=1e-9, abs=1e-9)
+            # within the rounding of the changed pair terms (4 np of them at most)
+            assert oracle.fx_to_float(de) == pytest.approx(_np_energy(x2, t2, lp2, 4.3) - _np_energy(x, t, lp, 4.3),
+                                                       rel=1e-9, abs=4 * len(x) * 2.0**-33 + 1e-9)
+            # exact: the change is the difference of the recomputed totals
+            assert o.energy_fx(0) == e0 + de == o.lipid_energy_fx(0)
             # the reverse move: capture the released particle at the other end
             back = _near_solvent(x2, t2, old[1], 4.3).index(released)
             nc2, nr2, de2 = o.lipid_reptate(0, lipid, 1 - end, back)
             x3, t3, lp3 = o.lipid_state(0)
             assert np.array_equal(t3, t) and np.array_equal(lp3, lp) and (nc2, nr2) == (nr, nc)
-            assert o.energy(0) == pytest.approx(e0, abs=1e-9)
+            assert o.energy_fx(0) == e0 and de2 == -de
             done += 1
     assert done >= 4
 

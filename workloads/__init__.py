@@ -39,8 +39,9 @@ BATCHED = dict(instances=256, L_choices=(16, 24, 32, 48), q_choices=(2, 4, 8, 10
 # 10, harmonic bonds, tail-tail LJ cut at 2.5, WCA for pairs with a head,
 # +-0.1 bead displacements, energy bins of 0.5 over [e_min, e_min + 0.5 bins),
 # 16 windows at 75% overlap, 4 walkers each, binary64 ln g.  The energy range
-# comes from an annealing pre-run: its lowest energy minus a margin
-# up to above the energies of the starting configurations.
+# lies below the lowest energy a seeded Metropolis anneal of a start reaches
+# (-457.4) and above the energies of all starting configurations (-52.4 ..
+# 30.2); the test suite checks both with the oracle.
 TRIMER = dict(model="trimer", nmol=64, box=10.0, e_min=-460.0, bin_w=0.5, bins=1000, windows=16,
               overlap=0.75, walkers=4, flat=(4, 5), lnf_init=1.0, lnf_final=1e-6, schedule=0,
               sync_attempts=20_000, exchange=1, precision=0, seed=1)
