@@ -866,6 +866,28 @@ def bootstrap_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def lds_peak_measured():
+    """Measured LDS bandwidth of the part (GB/s): ds_read_b128 and ds_write_b64
+    streams over every CU (paper_1312_3004_amd/csrc/lds_peak.hip); None if the
+    library is missing."""
+    import ctypes
+
+    from paper_1312_3004_amd import build as pkbuild
+
+    if not os.path.exists(pkbuild.LDS_PEAK_LIB):
+        return None
+    lib = ctypes.CDLL(pkbuild.LDS_PEAK_LIB)
+    lib.lds_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    for mode, name in ((0, "read_b128"), (1, "write_b64")):
+        bps, ms = ctypes.c_double(0), ctypes.c_double(0)
+        if lib.lds_peak(mode, 2000, ctypes.byref(bps), ctypes.byref(ms)) != 0:
+            return None
+        out[name + "_gb_per_s"] = bps.value / 1e9
+    return out
+
+
 def potts_roofline(attempts_per_launch, avg_ms, launches, traffic):
     """Roofline entry of the Potts attempt kernel: ALU issue slots (the binding
     roof) with the LDS bandwidth roof beside it, per launch of avg_ms."""
@@ -1051,6 +1073,11 @@ def main():
         "early_phase": early,
         "halving_phase": approach,
     }
+    meas = lds_peak_measured()
+    if meas:
+        lds = out["roofline"]["lds"]
+        lds["measured_peak"] = meas
+        lds["frac_of_measured_read_peak"] = lds["achieved_gb_per_s"] / meas["read_b128_gb_per_s"]
     if args.config == "potts_q10_L32" and approach and K_SWEEP_L32_VALU_PER_ATTEMPT:
         v = K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch / (avg_ms * 1e-3)
         out["valu"] = {"instructions_per_attempt": K_SWEEP_L32_VALU_PER_ATTEMPT, "achieved_lane_slots_per_s": v,

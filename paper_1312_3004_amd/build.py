@@ -20,8 +20,25 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-ffp
          "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 
+# The LDS bandwidth microbenchmark the benchmark measures its LDS roofline
+# against (not part of the REWL library).
+LDS_PEAK_SRC = os.path.join(CSRC, "lds_peak.hip")
+LDS_PEAK_LIB = os.path.join(HERE, "liblds_peak.so")
+
+
 def hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+def build_lds_peak(force=True):
+    if not force and os.path.exists(LDS_PEAK_LIB) and os.path.getmtime(LDS_PEAK_LIB) >= os.path.getmtime(LDS_PEAK_SRC):
+        return LDS_PEAK_LIB
+    tmp = LDS_PEAK_LIB + ".tmp"
+    res = subprocess.run([hipcc()] + FLAGS + [LDS_PEAK_SRC, "-o", tmp], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("liblds_peak build failed:\n" + res.stderr[-8000:])
+    os.replace(tmp, LDS_PEAK_LIB)
+    return LDS_PEAK_LIB
 
 
 def build(force=True, verbose=False):
@@ -37,6 +54,7 @@ def build(force=True, verbose=False):
     if verbose and res.stderr:
         print(res.stderr[-4000:])
     os.replace(tmp, LIB)
+    build_lds_peak(force=force)
     return LIB
 
 

@@ -47,6 +47,8 @@ struct DevState {
     double th_e0, th_de;         // energy of bin b for thermodynamics: th_e0 + b th_de
     int Npad, Wpad, Bpad;        // row strides (elements)
     int Ntag;                    // entries of the LDS conflict-tag table (power of two)
+    int rows_glob;               // single runs: 1 if ln g and H rows stay in device memory
+                                 // (lattice plus rows exceed the LDS), 0 if staged in LDS
     uint32_t key0, key1, ctr3;   // Philox key and instance bits of counter word 3
     uint32_t flat_num, flat_den;
     double lnf_final;

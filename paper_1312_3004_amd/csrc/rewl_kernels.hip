@@ -522,13 +522,19 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                         p_nx = propose(st, kDomMove, (uint64_t)(s0 + base + 64 + lane), (uint32_t)w);
                         lnu_nx = lnu_of(p_nx.u);
                     }
+                    constexpr bool kFirst = decltype(first)::value;
                     const unsigned long long Aa = A & act;
                     // energy before the attempt, from the previous round's lanes
-                    const int de4 = dEi + 4;   // in [0, 8]
-                    const unsigned long long B0 = __ballot(de4 & 1), B1 = __ballot(de4 & 2);
-                    const unsigned long long B2 = __ballot(de4 & 4), B3 = __ballot(de4 & 8);
-                    pre = E0 - 4 * mbcnt64(Aa) + mbcnt64(B0 & Aa) + 2 * mbcnt64(B1 & Aa) +
-                          4 * mbcnt64(B2 & Aa) + 8 * mbcnt64(B3 & Aa);
+                    // (the first round guesses every earlier attempt rejected)
+                    if constexpr (kFirst) {
+                        pre = E0;
+                    } else {
+                        const int de4 = dEi + 4;   // in [0, 8]
+                        const unsigned long long B0 = __ballot(de4 & 1), B1 = __ballot(de4 & 2);
+                        const unsigned long long B2 = __ballot(de4 & 4), B3 = __ballot(de4 & 8);
+                        pre = E0 - 4 * mbcnt64(Aa) + mbcnt64(B0 & Aa) + 2 * mbcnt64(B1 & Aa) +
+                              4 * mbcnt64(B2 & Aa) + 8 * mbcnt64(B3 & Aa);
+                    }
                     const int ip = pre - ebase;
                     // ln g before the attempt, and after it for the segment-start dE
                     // (read now; a lane whose dE changed reads again below)
@@ -545,8 +551,8 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                         bL = lane_read_f(cl, ib0 & 63);
                     }
                     // new value and dE from the spins the earlier accepted lanes left
-                    int nvn, dEn;
-                    {
+                    int nvn = nv, dEn = dE;
+                    if constexpr (!kFirst) {
                         int y0 = x0, y1 = x1, y2 = x2, y3 = x3, y4 = x4;
                         const unsigned long long a0 = W0 & Aa, a1 = W1 & Aa, a2 = W2 & Aa, a3 = W3 & Aa,
                                                  a4 = W4 & Aa;
@@ -795,6 +801,14 @@ template <int PREC>
 __global__ __launch_bounds__(64) void k_sweep(DevState st, int64_t s0, int64_t n) {
     extern __shared__ __align__(16) unsigned char smem[];
     sweep_walker<PREC>(st, blockIdx.x, s0, n, smem);
+}
+
+// The same walk for a run whose ln g and H rows do not fit in LDS beside the
+// lattice: the rows stay in device memory (see sweep_walker's GLOB form).
+template <int PREC>
+__global__ __launch_bounds__(64) void k_sweep_glob(DevState st, int64_t s0, int64_t n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_walker<PREC, false, true>(st, blockIdx.x, s0, n, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1864,7 +1878,7 @@ __global__ __launch_bounds__(256) void k_boot_stats(BootView bv, const double *t
 // Launchers.
 
 size_t sweep_lds_bytes(const DevState &st) {
-    return (size_t)st.Npad + (size_t)st.Wpad * 12 + (size_t)st.Ntag * 8;
+    return (size_t)st.Npad + (st.rows_glob ? (size_t)0 : (size_t)st.Wpad * 12) + (size_t)st.Ntag * 8;
 }
 
 size_t walkin_lds_bytes(const DevState &st) { return (size_t)st.Npad + (size_t)st.Bpad * 4; }
@@ -1895,16 +1909,14 @@ hipError_t launch_sweep(const DevState &st, int64_t s0, int64_t n, hipStream_t s
     if (st.model == kModelTrimer3D) return launch_trimer_sweep(st, s0, n, s);
     if (st.model == kModelLipid3D) return launch_lipid_sweep(st, s0, n, s);
     const size_t lds = sweep_lds_bytes(st);
-    if (st.precision == 0) {
-        hipError_t e = allow_lds((const void *)k_sweep<0>, lds);
+    auto go = [&](auto kernel) -> hipError_t {
+        hipError_t e = allow_lds((const void *)kernel, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sweep<0>, dim3(st.nw), dim3(64), lds, s, st, s0, n);
-    } else {
-        hipError_t e = allow_lds((const void *)k_sweep<1>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sweep<1>, dim3(st.nw), dim3(64), lds, s, st, s0, n);
-    }
-    return hipGetLastError();
+        hipLaunchKernelGGL(kernel, dim3(st.nw), dim3(64), lds, s, st, s0, n);
+        return hipGetLastError();
+    };
+    if (st.rows_glob) return st.precision == 0 ? go(k_sweep_glob<0>) : go(k_sweep_glob<1>);
+    return st.precision == 0 ? go(k_sweep<0>) : go(k_sweep<1>);
 }
 
 hipError_t launch_sync(const DevState &st, int64_t attempts, hipStream_t s) {

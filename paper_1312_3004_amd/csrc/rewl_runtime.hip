@@ -50,6 +50,7 @@ constexpr int64_t kWalkinChunk = int64_t(1) << 20;
 
 struct Params {
     int L, q, N, h, m, nw, W, B, e_lo, Npad, Wpad, Bpad, Ntag;
+    bool rows_glob = false;   // ln g and H rows in device memory (too large for LDS)
 };
 
 Layout make_layout(const Params &p, int precision, int shadow, bool trimer, int obs_bins) {
@@ -247,10 +248,14 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     p->Npad = (int)round_up((size_t)p->N, kAlign);
     p->Wpad = (int)round_up((size_t)W, 64);
     p->Bpad = (int)round_up((size_t)p->B, 64);
-    const size_t lds_state = sweep_state_lds(p->Npad, p->Wpad);
+    // the attempt kernel stages the walker's ln g and H rows in LDS when they
+    // fit beside the lattice and a minimal tag table, else reads them from
+    // device memory (the same code, rows touched when the register cache moves)
+    p->rows_glob = sweep_state_lds(p->Npad, p->Wpad) + 64 * 8 > (size_t)kMaxLds;
+    const size_t lds_state = sweep_state_lds(p->Npad, p->Wpad, !p->rows_glob);
     p->Ntag = tag_entries(p->N, lds_state < (size_t)kMaxLds ? (size_t)kMaxLds - lds_state : 0);
     if (lds_state + (size_t)p->Ntag * 8 > (size_t)kMaxLds)
-        return fail(REWL_EINVAL, "lattice plus window state exceed the 160 KiB LDS of a CU");
+        return fail(REWL_EINVAL, "the lattice exceeds the 160 KiB LDS of a CU");
     if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "walk-in ln g over all energies exceeds the 160 KiB LDS (L too large)");
     return REWL_OK;
@@ -399,6 +404,7 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     }
     d.L = p.L; d.q = p.q; d.N = p.N; d.h = p.h; d.m = p.m; d.nw = p.nw; d.W = p.W; d.B = p.B;
     d.e_lo = p.e_lo; d.Npad = p.Npad; d.Wpad = p.Wpad; d.Bpad = p.Bpad; d.Ntag = p.Ntag;
+    d.rows_glob = p.rows_glob ? 1 : 0;
     d.key0 = (uint32_t)op.seed; d.key1 = (uint32_t)(op.seed >> 32);
     d.ctr3 = op.instance & 0xFFFFFFu;
     d.flat_num = op.flat_num; d.flat_den = op.flat_den;
@@ -459,7 +465,7 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
     if (ncu > 0 && !geom) {
         const int per_cu = std::min((p.nw + ncu - 1) / ncu, 16);
         const size_t share = (size_t)kMaxLds / (size_t)per_cu;
-        const size_t state = sweep_state_lds(p.Npad, p.Wpad);
+        const size_t state = sweep_state_lds(p.Npad, p.Wpad, !p.rows_glob);
         if (share > state + 64 * 8) d.Ntag = std::min(d.Ntag, tag_entries(p.N, share - state));
         else d.Ntag = 64;
     }

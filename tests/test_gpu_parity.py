@@ -147,12 +147,26 @@ def test_converged_dos_matches_enumeration_on_gpu():
     assert_same_state(g, o)
 
 
-@pytest.mark.parametrize("L,q,h,m", [(3, 127, 1, 1), (3, 2, 1, 7), (5, 3, 1, 64), (128, 2, 16, 1)])
+# (128, 2, 8, 1): lattice plus ln g and H rows just fit the 160 KiB LDS;
+# (128, 2, 4, 1) and (96, 3, 2, 2): they do not, the rows stay in device memory
+@pytest.mark.parametrize("L,q,h,m", [(3, 127, 1, 1), (3, 2, 1, 7), (5, 3, 1, 64), (128, 2, 16, 1), (128, 2, 8, 1),
+                                     (128, 2, 4, 1), (96, 3, 2, 2)])
 def test_edge_shapes(L, q, h, m):
     g, o = make_pair(L, q, h, m, lnf_init=0.5, lnf_final=1e-2, sync_attempts=300, seed=2)
     n = 3000 if L < 100 else 1000
     g.run(n)
     o.run(n)
+    assert_same_state(g, o)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rows_in_device_memory_small_lnf_bitexact(precision):
+    # a run too large for LDS rows (96 x 96, 2 windows of 14,747 bins) on the
+    # speculative path (small fixed ln f), several sync intervals
+    g, o = make_pair(96, 3, 2, 2, lnf_init=3e-7, fixed_lnf=1, sync_attempts=4001, exchange=1, seed=19,
+                     precision=precision)
+    g.run(12_003)
+    o.run(12_003)
     assert_same_state(g, o)
 
 
