@@ -7,6 +7,10 @@ One step = one sync interval: 10^4 attempts for every walker, then the sync
 point (flatness, averaging, ln f update) and a replica-exchange round.
 Inputs are synthetic (uniform random starting lattices from a seed) and
 resident on the GPU before the timed region; walk-in is timed separately.
+The timed steps run where the workload spends its attempts: once every window
+is in the 1/t regime (98% of the 4.3e10 attempts per walker to ln f < 1e-8);
+the first steps after walk-in (ln f = 1) and the halving phase that leads to
+the timed steps are measured and reported beside them.
 
 Prints one JSON line; the roofline constants below carry their derivations.
 """
@@ -225,9 +229,16 @@ def walkin_with_progress(g, tag, budget=1 << 22):
 
 
 def precision_study(args):
-    """The L=80 workload in binary64 and in the binary32 (hi, lo) form: both
-    start from the same walked-in lattices; throughput of each, and the error
-    of each format's ln g against its exact (double-double) shadow."""
+    """The L=80 workload (64 windows x 16 walkers, ln f halved to 1e-9) to
+    convergence three times: binary64 (seed 1), the binary32 (hi, lo) pair
+    (seed 1, the same trajectory until the formats' roundings part it) and
+    binary64 with seed 2.  Each run keeps the exact double-double shadow of
+    its ln g.  Reports per run the wall time and its own accumulation error
+    max |ln g - shadow|, and for the joined, normalised curves the largest
+    difference between the two formats beside the spread between the two
+    binary64 seeds.  With --checkpoint DIR the three runs can span several
+    processes (each run saved in DIR when this process's --to-convergence
+    budget of seconds is spent, continued on the next call)."""
     import numpy as np
     import torch
 
@@ -239,92 +250,88 @@ def precision_study(args):
     nw, S = h * m, cfg["sync_attempts"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    kw = dict(device=dev, seed=cfg["seed"], flat=cfg["flat"], lnf_init=cfg["lnf_init"],
-              lnf_final=cfg["lnf_final"], schedule=cfg["schedule"], sync_attempts=S,
-              exchange=cfg["exchange"], shadow=1)
     spins = workloads.init_spins(L, q, nw, cfg["seed"])
-    runs, out = {}, {}
-    g0 = pk.Rewl(L, q, h, cfg["overlap"], m, spins, precision=0, **kw)
-    walkin_s = walkin_with_progress(g0, "L=80")
-    log(f"[bench] L=80 walk-in done in {walkin_s:.1f} s")
-    placed = np.stack([g0.walker(w)["spins"] for w in range(nw)])
-    runs[0] = g0
-    runs[1] = pk.Rewl(L, q, h, cfg["overlap"], m, placed, precision=1, **kw)
-    runs[1].walkin()
-    for prec in (0, 1):
-        g = runs[prec]
-        if args.warmup:
-            g.run(args.warmup * S)
+    d = args.checkpoint or ""
+    if d:
+        os.makedirs(d, exist_ok=True)
+    state_path = os.path.join(d, "precision.json") if d else None
+    state = {"runs": {}}
+    if state_path and os.path.exists(state_path):
+        with open(state_path) as f:
+            state = json.load(f)
+    budget = args.to_convergence if args.to_convergence > 0 else 1e30
+    t_start = time.perf_counter()
+    runs = (("f64", 0, cfg["seed"]), ("f32x2", 1, cfg["seed"]), ("f64_seed2", 0, cfg["seed"] + 1))
+    curves = {}
+    for name, prec, seed in runs:
+        rs = state["runs"].setdefault(name, {"seconds": 0.0, "segments": 0})
+        npy = os.path.join(d, name + "_lng.npy") if d else None
+        if rs.get("converged"):
+            curves[name] = np.load(npy)
+            continue
+        if time.perf_counter() - t_start >= budget:
+            break
+        g = pk.Rewl(L, q, h, cfg["overlap"], m, spins, device=dev, seed=seed, flat=cfg["flat"],
+                    lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"], schedule=cfg["schedule"],
+                    sync_attempts=S, exchange=cfg["exchange"], precision=prec, shadow=1)
+        ck = os.path.join(d, name + ".bin") if d else None
+        if ck and os.path.exists(ck):
+            with open(ck, "rb") as f:
+                g.load(f.read())
         torch.cuda.synchronize()
-        g.set_timing(True)
         t0 = time.perf_counter()
-        g.run(args.steps * S)
+        st, last = pk.OK, t0
+        while time.perf_counter() - t_start < budget:
+            st = g.run(200 * S)
+            if st == pk.CONVERGED:
+                break
+            if time.perf_counter() - last > 30:
+                torch.cuda.synchronize()
+                ws = [g.window(k) for k in range(h)]
+                lnf = [w["lnf"] for w in ws if not w["finished"]]
+                log(f"[bench] precision {name}: step {g.step}, {rs['seconds'] + time.perf_counter() - t0:.0f} s, "
+                    f"{h - len(lnf)}/{h} windows finished, ln f max {max(lnf) if lnf else 0.0:.3g}")
+                last = time.perf_counter()
         torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        sweep_ms, launches, sync_ms, syncs = g.timing()
-        g.set_timing(False)
-        err, iters = [], []
-        for k in range(h):
-            iters.append(g.window(k)["iterations"])
-            worst = 0.0
-            for j in range(m):
-                w = k * m + j
+        rs["seconds"] += time.perf_counter() - t0
+        rs["segments"] += 1
+        rs["attempts_per_walker"] = g.step
+        if st == pk.CONVERGED:
+            err = 0.0
+            for w in range(nw):
                 hi, lo = g.shadow(w)
-                lng = g.walker(w)["lng"]
-                worst = max(worst, float(np.max(np.abs((lng - hi) - lo))))
-            err.append(worst)
-        out["f64" if prec == 0 else "f32x2"] = {
-            "attempts_per_s": nw * S * args.steps / el,
-            "k_sweep_avg_ms": sweep_ms / max(launches, 1),
-            "sync_point_avg_ms": sync_ms / max(syncs, 1),
-            "max_abs_lng_minus_exact": max(err),
-            "median_window_max_abs_err": float(np.median(err)),
-            "ln_f_reductions_min_median_max": [int(min(iters)), int(np.median(iters)), int(max(iters))],
-        }
-        log(f"[bench] precision {prec}: {out['f64' if prec == 0 else 'f32x2']}")
-    # Late-phase segment: the halving schedule's increments are powers of two,
-    # which both formats add exactly.  From the binary64 run's ln g (values of
-    # a few thousand), both formats add a fixed ln f that is not a binary
-    # fraction (about the schedule's value after 18 halvings) for the same
-    # number of steps; each is compared with its own exact shadow.
-    lnf_late = 1.0 / (3 * 2**17)
-    src = [runs[0].walker(w)["lng"] for w in range(nw)]
-    late = {}
-    for prec in (0, 1):
-        g = pk.Rewl(L, q, h, cfg["overlap"], m, placed, precision=prec, device=dev, seed=cfg["seed"] + 1,
-                    lnf_init=lnf_late, fixed_lnf=1, sync_attempts=S, exchange=cfg["exchange"], shadow=1)
-        g.walkin()
-        for w in range(nw):
-            g.set_lng(w, src[w])
-        g.run(args.steps * S)
-        torch.cuda.synchronize()
-        worst, vals = 0.0, 0.0
-        for w in range(nw):
-            hi, lo = g.shadow(w)
-            lng = g.walker(w)["lng"]
-            worst = max(worst, float(np.max(np.abs((lng - hi) - lo))))
-            vals = max(vals, float(np.max(np.abs(lng))))
-        late["f64" if prec == 0 else "f32x2"] = {"max_abs_lng_minus_exact": worst, "max_abs_lng": vals}
-        log(f"[bench] late segment precision {prec}: max |ln g - exact| = {worst:.3e} (|ln g| <= {vals:.1f})")
-    out["late_segment"] = {"lnf": lnf_late, "steps": args.steps, **late}
+                err = max(err, float(np.max(np.abs((g.walker(w)["lng"] - hi) - lo))))
+            sj, lng, _ = g.join()
+            rs.update(converged=True, max_abs_lng_minus_shadow=err, join_status=sj,
+                      attempts_per_s=nw * g.step / rs["seconds"])
+            curves[name] = lng
+            if npy:
+                np.save(npy, lng)
+            log(f"[bench] precision {name}: converged after {rs['seconds']:.0f} s, {g.step} attempts per walker, "
+                f"max |ln g - shadow| {err:.3g}")
+        elif ck:
+            with open(ck, "wb") as f:
+                f.write(g.save())
+        if state_path:
+            with open(state_path, "w") as f:
+                json.dump(state, f)
+        del g
+    done = all(state["runs"].get(n, {}).get("converged") for n, _, _ in runs)
     res = {
-        "metric": "spin-flip attempts/s (1 GPU), q=10 Potts L=80 REWL, binary64 vs binary32 (hi, lo) ln g",
-        "value": out["f32x2"]["attempts_per_s"],
-        "unit": "attempts/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32x2",
-        "data": "synthetic",
+        "metric": "max |delta ln g| of converged q=10 Potts L=80 REWL, binary32 (hi, lo) against binary64",
+        "unit": "ln g", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32x2",
         "config": {"workload": "potts_q10_L80: 2D q=10 Potts 80x80 periodic, 64 windows at 75% overlap, "
-                               "16 walkers/window, ln f halving to 1e-9",
-                   "walkers": nw, "attempts_per_step_per_walker": S},
-        "precisions": out,
-        "walkin_s": walkin_s,
+                               "16 walkers/window, ln f halving to 1e-9", "walkers": nw},
+        "runs": state["runs"], "complete": done,
     }
+    if done:
+        def diff(a, b):
+            both = np.isfinite(a) & np.isfinite(b)
+            return float(np.max(np.abs(a[both] - b[both]))), int(both.sum())
+
+        res["f32x2_vs_f64"], res["bins_compared"] = diff(curves["f32x2"], curves["f64"])
+        res["f64_seed_spread"], _ = diff(curves["f64_seed2"], curves["f64"])
+        res["value"] = res["f32x2_vs_f64"]
     print(json.dumps(res), flush=True)
 
 
@@ -568,6 +575,12 @@ def to_convergence(args):
         torch.cuda.synchronize()
         t0 += time.perf_counter() - tl     # loading is not part of the run
         log(f"[bench] resumed at step {g.step} after {side['seconds']:.1f} s in {len(side['segments'])} segments")
+    else:
+        tw = time.perf_counter()
+        g.walkin()
+        torch.cuda.synchronize()
+        side["walkin_s"] = time.perf_counter() - tw
+        log(f"[bench] walk-in {side['walkin_s']:.2f} s")
     st = pk.OK
     last = time.perf_counter()
     while st != pk.CONVERGED and time.perf_counter() - t0 < args.to_convergence:
@@ -593,7 +606,7 @@ def to_convergence(args):
            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
            "config": {"workload": args.config, "L": L, "q": q, "windows": h, "walkers_per_window": m},
            "gpu": {"converged": st == pk.CONVERGED, "seconds": gpu_s, "attempts_per_walker": g.step,
-                   "segments": side["segments"]}}
+                   "segments": side["segments"], "walkin_s": side.get("walkin_s")}}
     if st == pk.CONVERGED:
         # the joined, normalised ln g and its canonical specific heat: the peak
         # lies near the infinite-lattice transition 1/ln(1 + sqrt(q)), shifted
@@ -902,6 +915,68 @@ def potts_roofline(attempts_per_launch, avg_ms, launches, traffic):
                     "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT}}
 
 
+def trace_window(trace_dir, bench_out):
+    """Kernel durations of a `rocprofv3 --kernel-trace --output-format csv`
+    run of this benchmark over its timed window: the k_sweep dispatches whose
+    0-based index lies in the line's `timed_k_sweep_launches` range (the
+    timed sync intervals), their mean, min and max, and the other kernels
+    launched inside the window's time span."""
+    import csv
+    import glob
+
+    line = json.loads([x for x in open(bench_out).read().splitlines() if x.startswith("{")][-1])
+    a, b = line["config"]["timed_k_sweep_launches"]
+    tr = sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True))
+    if not tr:
+        raise SystemExit(f"no *kernel_trace.csv under {trace_dir}")
+    rows = []
+    with open(tr[0]) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    rows.sort()
+    ks = [(t0, t1) for _, name, t0, t1 in rows if "k_sweep<" in name]
+    win = ks[a:b]
+    if not win:
+        raise SystemExit(f"the trace holds {len(ks)} k_sweep dispatches, none in [{a}, {b})")
+    durs = [(t1 - t0) * 1e-6 for t0, t1 in win]
+    span0, span1 = win[0][0], win[-1][1]
+    other = {}
+    for _, name, t0, t1 in rows:
+        if t0 >= span0 and t1 <= span1 and "k_sweep<" not in name:
+            c = other.setdefault(name.replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1], [0, 0.0])
+            c[0] += 1
+            c[1] += (t1 - t0) * 1e-6
+    return {"trace": os.path.basename(tr[0]), "k_sweep_dispatches": len(ks), "window": [a, b], "window_n": len(win),
+            "window_avg_ms": sum(durs) / len(durs), "window_min_ms": min(durs), "window_max_ms": max(durs),
+            "window_span_ms": (span1 - span0) * 1e-6,
+            "bench_kernel_avg_ms": line["roofline"]["kernel_avg_ms"], "bench_value": line["value"],
+            "other_kernels_in_window": {k: {"n": v[0], "avg_ms": v[1] / v[0]} for k, v in other.items()}}
+
+
+def phase_clock_summary(ctr, fields):
+    """Cycle split of the attempt loop from the profiling build's per-walker
+    counters (summed over the timed launches): cycles per attempt of the
+    lane-parallel and decision phases, speculative segments, rounds and
+    exact-path attempts per block, mean and max over the walkers."""
+    import numpy as np
+
+    c = {f: ctr[:, i].astype(np.float64) for i, f in enumerate(fields)}
+    att, blocks = np.maximum(c["attempts"], 1), np.maximum(c["blocks"], 1)
+    per = {
+        "lane_parallel_cycles_per_attempt": c["lane_cycles"] / att,
+        "decision_cycles_per_attempt": c["decide_cycles"] / att,
+        "round_cycles_per_attempt": c["round_cycles"] / att,
+        "segments_per_block": c["segments"] / blocks,
+        "rounds_per_block": c["rounds"] / blocks,
+        "exact_attempts_per_block": c["exact_attempts"] / blocks,
+    }
+    out = {k: {"mean": float(v.mean()), "max": float(v.max())} for k, v in per.items()}
+    out["rounds_per_segment"] = float(c["rounds"].sum() / max(c["segments"].sum(), 1))
+    out["attempts"] = int(c["attempts"].sum())
+    out["library"] = "librewl_clocks.so (profiling build: s_memtime clocks in the attempt loop)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -925,6 +1000,13 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy kernel (torch.neg, fp32) of this many MiB three "
                          "times first: the reference for the HBM byte counters of a profiler run")
+    ap.add_argument("--trace-window", nargs=2, metavar=("TRACE_DIR", "BENCH_OUT"),
+                    help="no GPU work: summarise the k_sweep durations of a rocprofv3 csv kernel trace of "
+                         "this benchmark (TRACE_DIR) over the timed launches named in its output line")
+    ap.add_argument("--phase-clocks", action="store_true",
+                    help="run on the profiling build librewl_clocks.so and report the attempt loop's cycle "
+                         "split (lane-parallel phase, decision phase, speculative rounds) over the timed "
+                         "steps; its rates are those of the profiling build")
     ap.add_argument("--workload", choices=("potts", "batched", "precision", "trimer", "production", "bootstrap",
                                            "lipid", "structure"),
                     default="potts",
@@ -935,10 +1017,17 @@ def main():
                          "independent L=8 runs; lipid: the explicit-solvent lipid system (N = 1000); "
                          "structure: its structural observables over 4,096 configurations")
     args = ap.parse_args()
+    if args.trace_window:
+        print(json.dumps(trace_window(*args.trace_window), indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the REWL hot path runs on a single MI355X "
               "(multi-GPU window sharding is a design note, not implemented).", file=sys.stderr)
         sys.exit(2)
+    if args.phase_clocks:
+        import paper_1312_3004_amd as pk
+
+        pk.use_phase_clocks()
     if args.copy_calibration_mib:
         import torch
 
@@ -1035,6 +1124,8 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} steps done")
     step_timed = g.step
+    if args.phase_clocks:
+        pk.phase_clocks(nw, reset=True)
     elapsed, avg_ms, launches, sync_avg = timed(args.steps)
     attempts = nw * S * args.steps
     value = attempts / elapsed
@@ -1090,6 +1181,8 @@ def main():
             args.warmup * S / per_walker
         out["time_to_lnf_final_s_projected"] = before + (converge_attempts - step_timed) / per_walker
         out["attempts_per_walker_to_lnf_final"] = converge_attempts
+    if args.phase_clocks:
+        out["phase_clocks"] = phase_clock_summary(pk.phase_clocks(nw), pk.PHASE_CLOCK_FIELDS)
     if args.trajectory > 0:
         out["trajectory"] = trajectory(g, S, args.trajectory, converge_attempts, walkin_s, per_walker)
     if not args.no_cpu_baseline:

@@ -19,6 +19,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librewl.so")
+# profiling build: the same library plus per-walker phase clocks of the
+# attempt loop (include/rewl_phase_clocks.h)
+CLOCKS_LIB_PATH = os.path.join(_HERE, "librewl_clocks.so")
 
 OK, CONVERGED, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET = 0, 1, -1, -2, -3, -4, -5
 POTTS2D, TRIMER3D = 0, 1
@@ -143,8 +146,34 @@ def lib():
         L.rewl_batch_bootstrap.argtypes = [P, i32, ctypes.c_uint64, P, i32, P, ctypes.c_size_t, P, P, P, P, P, P]
         L.rewl_batch_set_timing.argtypes = [P, i32]
         L.rewl_batch_get_timing.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+        if hasattr(L, "rewl_phase_clocks"):
+            L.rewl_phase_clocks.argtypes = [P, ctypes.c_size_t, i32]
         _lib = L
     return _lib
+
+
+def use_phase_clocks():
+    """Load the profiling build librewl_clocks.so instead of librewl.so; call
+    before anything else touches the library."""
+    global LIB_PATH
+    if _lib is not None and LIB_PATH != CLOCKS_LIB_PATH:
+        raise RewlError("librewl.so is already loaded; use_phase_clocks() must come first")
+    LIB_PATH = CLOCKS_LIB_PATH
+
+
+PHASE_CLOCK_FIELDS = ("lane_cycles", "decide_cycles", "segments", "rounds", "exact_attempts", "blocks",
+                      "round_cycles", "attempts")
+
+
+def phase_clocks(rows, reset=False):
+    """Per-walker phase counters of the profiling build, uint64 (rows, 8) in
+    the order of PHASE_CLOCK_FIELDS; reset=True zeroes them afterwards."""
+    L = lib()
+    if not hasattr(L, "rewl_phase_clocks"):
+        raise RewlError("phase clocks need the profiling build: call use_phase_clocks() first")
+    out = np.zeros((rows, 8), dtype=np.uint64)
+    _check(L.rewl_phase_clocks(_ptr(out), rows, int(reset)))
+    return out
 
 
 def _ptr(a):

@@ -23,6 +23,40 @@ namespace {
 // v_writelane_b32: lane `lane` of `old` takes the uniform value `v`.
 extern "C" __device__ int writelane_i32(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
+// Phase clocks of the attempt loop.  The profiling build (REWL_PHASE_CLOCKS
+// defined, librewl_clocks.so) adds per-walker cycle and event counts to
+// g_phase_ctr, row w = walker w of a single run, slots kPc*; the product
+// build compiles every call below to nothing.
+enum {
+    kPcLaneCycles = 0,    // lane-parallel phase of a block (proposals, dE, conflicts)
+    kPcDecideCycles = 1,  // decision phase of a block (speculative or serial)
+    kPcSegments = 2,      // speculative segments
+    kPcRounds = 3,        // speculative rounds
+    kPcExact = 4,         // attempts through the exact (settling) path
+    kPcBlocks = 5,        // blocks of up to 64 attempts
+    kPcRoundCycles = 6,   // cycles inside the speculative rounds
+    kPcAttempts = 7,
+};
+#ifdef REWL_PHASE_CLOCKS
+constexpr int kPcRows = 4096;
+__device__ unsigned long long g_phase_ctr[kPcRows * 8];
+struct PhaseClock {
+    unsigned long long v[8] = {};
+    __device__ __forceinline__ long long now() const { return clock64(); }
+    __device__ __forceinline__ void add(int i, long long k) { v[i] += (unsigned long long)k; }
+    __device__ __forceinline__ void flush(int w, int lane) {
+        if (lane == 0 && w < kPcRows)
+            for (int i = 0; i < 8; ++i) atomicAdd(&g_phase_ctr[(size_t)w * 8 + i], v[i]);
+    }
+};
+#else
+struct PhaseClock {
+    __device__ __forceinline__ long long now() const { return 0; }
+    __device__ __forceinline__ void add(int, long long) {}
+    __device__ __forceinline__ void flush(int, int) {}
+};
+#endif
+
 __device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ double rfl(double x) {
     const uint64_t b = (uint64_t)__double_as_longlong(x);
@@ -342,8 +376,10 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     };
     Proposal p_nx = propose(st, kDomMove, (uint64_t)(s0 + lane), (uint32_t)w);
     double lnu_nx = lnu_of(p_nx.u);
+    PhaseClock pc;
 
     for (int64_t base = 0; base < n; base += 64) {
+        const long long pc0 = pc.now();
         const int todo = (int)((n - base) < 64 ? (n - base) : 64);
         const bool live = lane < todo;
         if ((unsigned)(erel - 16) >= 32u) {   // keep the walker near the cache centre
@@ -402,6 +438,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
         // first (recomputing dE from the live lattice), then applies the rule
         // with the carried current ln g and the cached ln g of the new energy.
         auto slow_attempt = [&](int j) -> void {
+            pc.add(kPcExact, 1);
             int dEj = __builtin_amdgcn_readlane(dE, j);
             bool now = false;
             int nvj = 0;
@@ -460,6 +497,8 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             hist = writelane_i32(ebase + erel, j, hist);
         };
 
+        const long long pc1 = pc.now();
+        pc.add(kPcLaneCycles, pc1 - pc0);
         if (spec) {
             // ---- speculative phase (small ln f): every lane evaluates its own
             // attempt from a guess of the earlier attempts of its segment (their
@@ -496,6 +535,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             }
             int start = 0;
             while (start < todo) {
+                pc.add(kPcSegments, 1);
                 if ((unsigned)(erel - 16) >= 32u) {   // keep the walker near the cache centre
                     cache_store();
                     ebase += erel - 32;
@@ -518,6 +558,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 // one round; the first of a segment also draws the next block's
                 // proposals (independent work that fills the round's waits)
                 auto round = [&](auto first) {
+                    pc.add(kPcRounds, 1);
                     if constexpr (decltype(first)::value) {
                         p_nx = propose(st, kDomMove, (uint64_t)(s0 + base + 64 + lane), (uint32_t)w);
                         lnu_nx = lnu_of(p_nx.u);
@@ -615,8 +656,10 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     nvi = nvn;
                     dEi = dEn;
                 };
+                const long long pcr = pc.now();
                 round(std::true_type{});
                 for (int it = 1; it < 66 && !conv; ++it) round(std::false_type{});
+                pc.add(kPcRoundCycles, pc.now() - pcr);
                 if (!conv) c = start;   // not reached (see above); the exact path is always right
                 // commit attempts [start, c): spins, visits, ln g increments per bin
                 const unsigned long long seg = act & (c >= 64 ? ~0ull : ((1ull << c) - 1ull));
@@ -777,7 +820,11 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
         }
         if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
         if (live) atomicAdd(&H[hist - lo], 1u);
+        pc.add(kPcDecideCycles, pc.now() - pc1);
+        pc.add(kPcBlocks, 1);
+        pc.add(kPcAttempts, todo);
     }
+    pc.flush(w, lane);
     cache_store();
     E = ebase + erel;
     walker_sync<WAVE>();
@@ -2125,3 +2172,18 @@ hipError_t sweep_batch_occupancy(int precision, size_t lds_bytes, int *blocks_pe
 }
 
 }  // namespace rewl_gpu
+
+#ifdef REWL_PHASE_CLOCKS
+// Profiling build: copies rows [0, min(rows, 4096)) of the phase counters
+// (8 per walker, in the order of the kPc* slots) to host memory and, if
+// `reset`, zeroes all of them.  Synchronous on the null stream.
+extern "C" int rewl_phase_clocks(unsigned long long *host, size_t rows, int reset) {
+    const size_t n = (rows < (size_t)rewl_gpu::kPcRows ? rows : (size_t)rewl_gpu::kPcRows) * 8;
+    if (host && n && hipMemcpyFromSymbol(host, HIP_SYMBOL(rewl_gpu::g_phase_ctr), n * 8) != hipSuccess) return -1;
+    if (reset) {
+        static unsigned long long zero[rewl_gpu::kPcRows * 8];
+        if (hipMemcpyToSymbol(HIP_SYMBOL(rewl_gpu::g_phase_ctr), zero, sizeof(zero)) != hipSuccess) return -1;
+    }
+    return 0;
+}
+#endif

@@ -42,6 +42,20 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
+def test_profiling_build_exports_the_same_entry_points_and_the_phase_clocks(lib):
+    # librewl_clocks.so: librewl with the attempt loop's phase clocks
+    # (include/rewl_phase_clocks.h); the product library has no clocks
+    if not os.path.exists(pk.CLOCKS_LIB_PATH):
+        pkbuild.build()
+    clocks = ctypes.CDLL(pk.CLOCKS_LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(clocks, name), name
+    text = open(os.path.join(ROOT, "include", "rewl_phase_clocks.h")).read()
+    assert re.findall(r"\b(rewl_[a-z_]+)\s*\(", re.sub(r"/\*.*?\*/", "", text, flags=re.S)) == ["rewl_phase_clocks"]
+    assert hasattr(clocks, "rewl_phase_clocks")
+    assert not hasattr(lib, "rewl_phase_clocks")
+
+
 def test_default_opts(lib):
     o = pk.default_opts()
     assert (o.seed, o.flat_num, o.flat_den, o.lnf_init, o.lnf_final) == (1, 4, 5, 1.0, 1e-6)

@@ -44,3 +44,33 @@ def test_host_cpu_info():
     assert hc["usable"] >= 1 and hc["usable"] <= hc["affinity"] <= (os.cpu_count() or 1)
     threads, _ = bench.oracle_threads(3)
     assert 1 <= threads <= 3
+
+
+def test_trace_window_averages_the_timed_launches(tmp_path):
+    # a synthetic rocprofv3 csv trace: k_sweep dispatch i lasts 1000 + i ns,
+    # a k_sync of 100 ns after each; the timed window is launches [5, 15)
+    import csv
+    import json
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    (tmp_path / "host").mkdir()
+    rows, t = [("Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp")], 0
+    for i in range(20):
+        rows.append((2 * i, "void rewl_gpu::(anonymous namespace)::k_sweep<0>(rewl_gpu::DevState, long, long)",
+                     t, t + 1000 + i))
+        t += 2000
+        rows.append((2 * i + 1, "void rewl_gpu::(anonymous namespace)::k_sync<0>(rewl_gpu::DevState, long)",
+                     t, t + 100))
+        t += 200
+    with open(tmp_path / "host" / "p_kernel_trace.csv", "w", newline="") as f:
+        csv.writer(f).writerows(rows)
+    line = {"config": {"timed_k_sweep_launches": [5, 15]}, "roofline": {"kernel_avg_ms": 1e-3}, "value": 1.0}
+    (tmp_path / "b.json").write_text("[bench] log line\n" + json.dumps(line) + "\n")
+    r = bench.trace_window(str(tmp_path), str(tmp_path / "b.json"))
+    assert r["window_n"] == 10 and r["k_sweep_dispatches"] == 20
+    assert abs(r["window_avg_ms"] - (1000 + 9.5) * 1e-6) < 1e-12
+    assert r["window_min_ms"] == 1005e-6 and r["window_max_ms"] == 1014e-6
+    o = r["other_kernels_in_window"]
+    assert list(o) == ["k_sync<0>"] and o["k_sync<0>"]["n"] == 9 and abs(o["k_sync<0>"]["avg_ms"] - 1e-4) < 1e-15
