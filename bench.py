@@ -236,9 +236,10 @@ def precision_study(args):
     its ln g.  Reports per run the wall time and its own accumulation error
     max |ln g - shadow|, and for the joined, normalised curves the largest
     difference between the two formats beside the spread between the two
-    binary64 seeds.  With --checkpoint DIR the three runs can span several
-    processes (each run saved in DIR when this process's --to-convergence
-    budget of seconds is spent, continued on the next call)."""
+    binary64 seeds.  --to-convergence sets this process's budget of seconds
+    (default 600); with --checkpoint DIR the three runs can span several
+    processes (the run in progress saved in DIR when the budget is spent and
+    continued on the next call)."""
     import numpy as np
     import torch
 
@@ -259,7 +260,7 @@ def precision_study(args):
     if state_path and os.path.exists(state_path):
         with open(state_path) as f:
             state = json.load(f)
-    budget = args.to_convergence if args.to_convergence > 0 else 1e30
+    budget = args.to_convergence if args.to_convergence > 0 else 600.0
     t_start = time.perf_counter()
     runs = (("f64", 0, cfg["seed"]), ("f32x2", 1, cfg["seed"]), ("f64_seed2", 0, cfg["seed"] + 1))
     curves = {}
@@ -966,6 +967,10 @@ def phase_clock_summary(ctr, fields):
         "lane_parallel_cycles_per_attempt": c["lane_cycles"] / att,
         "decision_cycles_per_attempt": c["decide_cycles"] / att,
         "round_cycles_per_attempt": c["round_cycles"] / att,
+        "segment_setup_cycles_per_attempt": c["setup_cycles"] / att,
+        "commit_cycles_per_attempt": c["commit_cycles"] / att,
+        "exact_path_cycles_per_attempt": c["exact_cycles"] / att,
+        "block_tail_cycles_per_attempt": c["tail_cycles"] / att,
         "segments_per_block": c["segments"] / blocks,
         "rounds_per_block": c["rounds"] / blocks,
         "exact_attempts_per_block": c["exact_attempts"] / blocks,
@@ -1040,12 +1045,13 @@ def main():
         log(f"[bench] copy calibration: 3 x torch.neg over {args.copy_calibration_mib} MiB "
             f"(reads and writes {4 * n} bytes per launch)")
         del src, dst
+    if args.workload == "precision":
+        # --to-convergence is this study's time budget
+        return precision_study(args)
     if args.to_convergence > 0:
         return to_convergence(args)
     if args.workload == "batched":
         return batched(args)
-    if args.workload == "precision":
-        return precision_study(args)
     if args.workload == "trimer":
         return trimer(args)
     if args.workload == "production":

@@ -18,7 +18,7 @@ extern "C" {
 #endif
 
 /* Copies the counters of walkers [0, min(rows, 4096)) to `host` (caller
- * owned, 8 unsigned 64-bit words per walker) and, if `reset` is nonzero,
+ * owned, 12 unsigned 64-bit words per walker) and, if `reset` is nonzero,
  * zeroes the counters of every walker; `host` may be NULL to reset only.
  * Per walker, summed over every k_sweep / k_sweep_glob launch since the last
  * reset, in shader clock cycles (s_memtime) or counts:
@@ -26,7 +26,12 @@ extern "C" {
  *   [2] speculative segments                 [3] speculative rounds
  *   [4] attempts taken by the exact path     [5] blocks of up to 64 attempts
  *   [6] cycles inside speculative rounds     [7] attempts
- * The device counters are shared by every run in the process; batched runs
+ *   [8] cycles of segment set-up before the first round
+ *   [9] cycles committing segments (flips, visit counts, ln g increments)
+ *   [10] cycles of the exact path after a speculative stop, with the restart
+ *   [11] cycles at the end of blocks (pending flips, H increments)
+ * [8], [9] and [6] cover the speculative segments: with [10] and [11] they
+ * make up [1] for small ln f. * The device counters are shared by every run in the process; batched runs
  * add to the rows of their walkers' indices within an instance.  Synchronous
  * (null stream).  Returns 0, or -1 on a HIP error. */
 int rewl_phase_clocks(unsigned long long *host, size_t rows, int reset);

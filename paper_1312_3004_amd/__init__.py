@@ -162,16 +162,16 @@ def use_phase_clocks():
 
 
 PHASE_CLOCK_FIELDS = ("lane_cycles", "decide_cycles", "segments", "rounds", "exact_attempts", "blocks",
-                      "round_cycles", "attempts")
+                      "round_cycles", "attempts", "setup_cycles", "commit_cycles", "exact_cycles", "tail_cycles")
 
 
 def phase_clocks(rows, reset=False):
-    """Per-walker phase counters of the profiling build, uint64 (rows, 8) in
+    """Per-walker phase counters of the profiling build, uint64 (rows, 12) in
     the order of PHASE_CLOCK_FIELDS; reset=True zeroes them afterwards."""
     L = lib()
     if not hasattr(L, "rewl_phase_clocks"):
         raise RewlError("phase clocks need the profiling build: call use_phase_clocks() first")
-    out = np.zeros((rows, 8), dtype=np.uint64)
+    out = np.zeros((rows, len(PHASE_CLOCK_FIELDS)), dtype=np.uint64)
     _check(L.rewl_phase_clocks(_ptr(out), rows, int(reset)))
     return out
 

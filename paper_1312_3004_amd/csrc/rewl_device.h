@@ -166,7 +166,12 @@ constexpr int64_t kFxELimit = (int64_t)1 << 61;
 __device__ __forceinline__ bool fx_term(double v, int64_t &out) {
 #pragma clang fp contract(off)
     if (!(__builtin_fabs(v) < 0x1p18)) return false;
-    out = (int64_t)__builtin_rint(v * 0x1p32);
+    // rint(v 2^32) without a binary64 -> int64 conversion: |v 2^32| < 2^50
+    // (the scaling is exact), so adding 1.5 2^52 rounds it to the nearest
+    // integer, ties to even, which then sits in the low bits of the sum's
+    // significand (the sum lies in [2^52, 2^53), where the spacing is 1)
+    const double y = v * 0x1p32 + 0x1.8p52;
+    out = (int64_t)__double_as_longlong(y) - (int64_t)0x4338000000000000ll;
     return true;
 }
 
@@ -180,20 +185,49 @@ __device__ __forceinline__ bool fx_add(int64_t e, int64_t de, int64_t &out) {
 
 // Bin of a fixed-point energy: floor((E - e_min) / bin_w) on the 2^-32 grid,
 // also outside [0, B) (bounded to +-2^30) so the walk-in's lid can follow it.
+// The quotient comes from binary64 (relative error below 2^-51, so the
+// estimate's floor is within one of the exact one for quotients up to 2^31)
+// and is then corrected with exact integer products, which stay below 2^63
+// because |E - e_min| < 2^62 and bin_w < 2^61 units.
 __device__ __forceinline__ int fx_bin(int64_t emin_fx, int64_t binw_fx, int64_t e) {
+#pragma clang fp contract(off)
     const int64_t diff = e - emin_fx;
-    int64_t q = diff / binw_fx;
-    if (q * binw_fx != diff && diff < 0) q -= 1;
+    const double qd = __builtin_floor((double)diff / (double)binw_fx);
+    if (qd <= -1073741825.0) return -1073741824;   // the exact quotient is <= -2^30
+    if (qd >= 1073741825.0) return 1073741824;     // ... >= 2^30
+    int64_t q = (int64_t)qd;
+    if (q * binw_fx > diff) q -= 1;
+    else if ((q + 1) * binw_fx <= diff) q += 1;
     if (q < -1073741824) return -1073741824;
     if (q > 1073741824) return 1073741824;
     return (int)q;
 }
 
-// Sum of an int64 over the 64 lanes (any order: integer addition is exact);
-// every lane returns the total.
+// Lane-to-lane move of an int64 by a DPP row pattern (the two 32-bit halves
+// separately); lanes of rows outside ROWS read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)v >> 32), CTRL, ROWS,
+                                                              0xF, false);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Sum of an int64 over the 64 lanes of a wavefront (all lanes active; any
+// order gives the same value, integer addition being exact); every lane
+// returns the total.  DPP steps: pairs and quads (quad_perm), half rows and
+// rows (mirrors), then row 0 into 1 and row 2 into 3 (row_bcast:15) and the
+// first half into row 3 (row_bcast:31); lane 63 holds the total.
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp64<0xB1, 0xF>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp64<0x4E, 0xF>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp64<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp64<0x140, 0xF>(v);   // row_mirror
+    v += dpp64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), 63);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // ---------------------------------------------------------------------------

@@ -13,6 +13,7 @@ namespace rewl_host {
 
 constexpr size_t kAlign = 256;          // every workspace array starts on 256 bytes
 constexpr int kMaxLds = 160 * 1024;     // LDS of one gfx950 compute unit
+constexpr int kCUs = 256;               // compute units of an MI355X
 
 // Record `msg` as the calling thread's last error and return `code`.
 int fail(int code, const std::string &msg);

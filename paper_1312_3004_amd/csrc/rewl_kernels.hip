@@ -36,17 +36,22 @@ enum {
     kPcBlocks = 5,        // blocks of up to 64 attempts
     kPcRoundCycles = 6,   // cycles inside the speculative rounds
     kPcAttempts = 7,
+    kPcSetupCycles = 8,   // segment set-up before the first round (margins, cache)
+    kPcCommitCycles = 9,  // committing a segment (flips, visit counts, ln g replay)
+    kPcExactCycles = 10,  // the exact path after a speculative stop, with the restart
+    kPcTailCycles = 11,   // end of a block (pending flips, H increments)
+    kPcSlots = 12,
 };
 #ifdef REWL_PHASE_CLOCKS
 constexpr int kPcRows = 4096;
-__device__ unsigned long long g_phase_ctr[kPcRows * 8];
+__device__ unsigned long long g_phase_ctr[kPcRows * kPcSlots];
 struct PhaseClock {
-    unsigned long long v[8] = {};
+    unsigned long long v[kPcSlots] = {};
     __device__ __forceinline__ long long now() const { return clock64(); }
     __device__ __forceinline__ void add(int i, long long k) { v[i] += (unsigned long long)k; }
     __device__ __forceinline__ void flush(int w, int lane) {
         if (lane == 0 && w < kPcRows)
-            for (int i = 0; i < 8; ++i) atomicAdd(&g_phase_ctr[(size_t)w * 8 + i], v[i]);
+            for (int i = 0; i < kPcSlots; ++i) atomicAdd(&g_phase_ctr[(size_t)w * kPcSlots + i], v[i]);
     }
 };
 #else
@@ -536,6 +541,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             int start = 0;
             while (start < todo) {
                 pc.add(kPcSegments, 1);
+                const long long pcs = pc.now();
                 if ((unsigned)(erel - 16) >= 32u) {   // keep the walker near the cache centre
                     cache_store();
                     ebase += erel - 32;
@@ -657,9 +663,11 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     dEi = dEn;
                 };
                 const long long pcr = pc.now();
+                pc.add(kPcSetupCycles, pcr - pcs);
                 round(std::true_type{});
                 for (int it = 1; it < 66 && !conv; ++it) round(std::false_type{});
-                pc.add(kPcRoundCycles, pc.now() - pcr);
+                const long long pcc = pc.now();
+                pc.add(kPcRoundCycles, pcc - pcr);
                 if (!conv) c = start;   // not reached (see above); the exact path is always right
                 // commit attempts [start, c): spins, visits, ln g increments per bin
                 const unsigned long long seg = act & (c >= 64 ? ~0ull : ((1ull << c) - 1ull));
@@ -719,6 +727,8 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 }
                 accepted |= aseg;
                 flushed |= aseg;
+                const long long pce = pc.now();
+                pc.add(kPcCommitCycles, pce - pcc);
                 if (c >= todo) break;
                 // attempt c on the exact path, with the walker's current ln g
                 // (its own new value and dE are settled there from the lattice)
@@ -751,6 +761,7 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 W3 &= keep;
                 W4 &= keep;
                 anyconf = __ballot(conf != 0ull);
+                pc.add(kPcExactCycles, pc.now() - pce);
             }
         } else {
             // ---- serial phase: runs of attempts with no possible conflict take the
@@ -814,13 +825,16 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             }
         }
 
+        const long long pct = pc.now();
         if (!spec) {
             p_nx = propose(st, kDomMove, (uint64_t)(s0 + base + 64 + lane), (uint32_t)w);
             lnu_nx = lnu_of(p_nx.u);
         }
         if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
         if (live) atomicAdd(&H[hist - lo], 1u);
-        pc.add(kPcDecideCycles, pc.now() - pc1);
+        const long long pcd = pc.now();
+        pc.add(kPcTailCycles, pcd - pct);
+        pc.add(kPcDecideCycles, pcd - pc1);
         pc.add(kPcBlocks, 1);
         pc.add(kPcAttempts, todo);
     }
@@ -2175,13 +2189,13 @@ hipError_t sweep_batch_occupancy(int precision, size_t lds_bytes, int *blocks_pe
 
 #ifdef REWL_PHASE_CLOCKS
 // Profiling build: copies rows [0, min(rows, 4096)) of the phase counters
-// (8 per walker, in the order of the kPc* slots) to host memory and, if
+// (12 per walker, in the order of the kPc* slots) to host memory and, if
 // `reset`, zeroes all of them.  Synchronous on the null stream.
 extern "C" int rewl_phase_clocks(unsigned long long *host, size_t rows, int reset) {
-    const size_t n = (rows < (size_t)rewl_gpu::kPcRows ? rows : (size_t)rewl_gpu::kPcRows) * 8;
+    const size_t n = (rows < (size_t)rewl_gpu::kPcRows ? rows : (size_t)rewl_gpu::kPcRows) * rewl_gpu::kPcSlots;
     if (host && n && hipMemcpyFromSymbol(host, HIP_SYMBOL(rewl_gpu::g_phase_ctr), n * 8) != hipSuccess) return -1;
     if (reset) {
-        static unsigned long long zero[rewl_gpu::kPcRows * 8];
+        static unsigned long long zero[rewl_gpu::kPcRows * rewl_gpu::kPcSlots];
         if (hipMemcpyToSymbol(HIP_SYMBOL(rewl_gpu::g_phase_ctr), zero, sizeof(zero)) != hipSuccess) return -1;
     }
     return 0;

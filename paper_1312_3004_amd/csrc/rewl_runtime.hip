@@ -256,6 +256,13 @@ int check_params(int model, int L, int q, int h, double o, int m, const rewl_opt
     p->Ntag = tag_entries(p->N, lds_state < (size_t)kMaxLds ? (size_t)kMaxLds - lds_state : 0);
     if (lds_state + (size_t)p->Ntag * 8 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "the lattice exceeds the 160 KiB LDS of a CU");
+    // one workgroup per walker: halve the tag table (down to 256 entries) while
+    // that lets more of the walkers a CU must hold share its LDS, so that a
+    // launch runs in one pass over the CUs where it can (a smaller table only
+    // adds hashed candidates, which the kernel checks site by site)
+    const int per_cu = (p->nw + kCUs - 1) / kCUs;
+    auto fits = [&](int t) { return (int)((size_t)kMaxLds / (lds_state + (size_t)t * 8)); };
+    while (p->Ntag > 256 && fits(p->Ntag) < per_cu && fits(p->Ntag / 2) > fits(p->Ntag)) p->Ntag /= 2;
     if ((size_t)p->Npad + (size_t)p->Bpad * 4 > (size_t)kMaxLds)
         return fail(REWL_EINVAL, "walk-in ln g over all energies exceeds the 160 KiB LDS (L too large)");
     return REWL_OK;
