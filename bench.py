@@ -256,29 +256,37 @@ def precision_study(args):
     if d:
         os.makedirs(d, exist_ok=True)
     state_path = os.path.join(d, "precision.json") if d else None
-    state = {"runs": {}}
+    lnf_final = args.lnf_final if args.lnf_final > 0 else cfg["lnf_final"]
+    state = {"runs": {}, "lnf_final": lnf_final}
     if state_path and os.path.exists(state_path):
         with open(state_path) as f:
             state = json.load(f)
+        if state.get("lnf_final") != lnf_final:
+            raise SystemExit(f"{state_path} holds runs to ln f < {state.get('lnf_final')}, not {lnf_final}")
     budget = args.to_convergence if args.to_convergence > 0 else 600.0
     t_start = time.perf_counter()
     runs = (("f64", 0, cfg["seed"]), ("f32x2", 1, cfg["seed"]), ("f64_seed2", 0, cfg["seed"] + 1))
     curves = {}
+    started = 0
     for name, prec, seed in runs:
         rs = state["runs"].setdefault(name, {"seconds": 0.0, "segments": 0})
         npy = os.path.join(d, name + "_lng.npy") if d else None
         if rs.get("converged"):
             curves[name] = np.load(npy)
             continue
-        if time.perf_counter() - t_start >= budget:
+        if time.perf_counter() - t_start >= budget or (args.max_runs and started >= args.max_runs):
             break
+        started += 1
         g = pk.Rewl(L, q, h, cfg["overlap"], m, spins, device=dev, seed=seed, flat=cfg["flat"],
-                    lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"], schedule=cfg["schedule"],
+                    lnf_init=cfg["lnf_init"], lnf_final=lnf_final, schedule=cfg["schedule"],
                     sync_attempts=S, exchange=cfg["exchange"], precision=prec, shadow=1)
         ck = os.path.join(d, name + ".bin") if d else None
         if ck and os.path.exists(ck):
             with open(ck, "rb") as f:
                 g.load(f.read())
+        elif rs["segments"]:
+            # its saved state is gone: the run starts again
+            rs.update(seconds=0.0, segments=0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st, last = pk.OK, t0
@@ -322,7 +330,8 @@ def precision_study(args):
         "metric": "max |delta ln g| of converged q=10 Potts L=80 REWL, binary32 (hi, lo) against binary64",
         "unit": "ln g", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32x2",
         "config": {"workload": "potts_q10_L80: 2D q=10 Potts 80x80 periodic, 64 windows at 75% overlap, "
-                               "16 walkers/window, ln f halving to 1e-9", "walkers": nw},
+                               f"16 walkers/window, ln f halving to {lnf_final:g}", "walkers": nw,
+                   "lnf_final": lnf_final},
         "runs": state["runs"], "complete": done,
     }
     if done:
@@ -998,6 +1007,11 @@ def main():
     ap.add_argument("--checkpoint", default="",
                     help="with --to-convergence: continue the run saved at this path (if present) and save it "
                          "back there when this process's budget is spent or the run converged")
+    ap.add_argument("--lnf-final", type=float, default=0.0,
+                    help="precision study: stop each run when every window's ln f is below this instead of "
+                         "the workload's own ln f_final")
+    ap.add_argument("--max-runs", type=int, default=0,
+                    help="precision study: start at most this many of its runs in this process")
     ap.add_argument("--save-lng", default="", help="with --to-convergence: write the joined ln g (.npy) here")
     ap.add_argument("--trajectory", type=float, default=0.0,
                     help="after the measurement, continue the run for this many seconds and report "

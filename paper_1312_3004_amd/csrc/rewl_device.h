@@ -44,6 +44,7 @@ struct DevState {
     float box;                   // trimer: side of the periodic cube
     double e_min, bin_w;         // trimer: energy of bin 0's lower edge, bin width
     int64_t emin_fx, binw_fx;    // the same in units of 2^-32 (rint(x 2^32))
+    double binw_inv;             // 1 / binw_fx (binary64), for the bin estimate
     double th_e0, th_de;         // energy of bin b for thermodynamics: th_e0 + b th_de
     int Npad, Wpad, Bpad;        // row strides (elements)
     int Ntag;                    // entries of the LDS conflict-tag table (power of two)
@@ -185,17 +186,18 @@ __device__ __forceinline__ bool fx_add(int64_t e, int64_t de, int64_t &out) {
 
 // Bin of a fixed-point energy: floor((E - e_min) / bin_w) on the 2^-32 grid,
 // also outside [0, B) (bounded to +-2^30) so the walk-in's lid can follow it.
-// The quotient comes from binary64 (relative error below 2^-51, so the
-// estimate's floor is within one of the exact one for quotients up to 2^31)
-// and is then corrected with exact integer products, which stay below 2^63
-// because |E - e_min| < 2^62 and bin_w < 2^61 units.
-__device__ __forceinline__ int fx_bin(int64_t emin_fx, int64_t binw_fx, int64_t e) {
+// The quotient comes from binary64, E - e_min times binw_inv = 1 / bin_w
+// (three roundings, relative error below 2^-50, so the estimate's floor is
+// within one of the exact one for quotients up to 2^31), and is then
+// corrected with exact integer products, which stay below 2^63 because
+// |E - e_min| < 2^62 and bin_w < 2^61 units.
+__device__ __forceinline__ int fx_bin(int64_t emin_fx, int64_t binw_fx, double binw_inv, int64_t e) {
 #pragma clang fp contract(off)
     const int64_t diff = e - emin_fx;
-    const double qd = __builtin_floor((double)diff / (double)binw_fx);
+    const double qd = __builtin_floor((double)diff * binw_inv);
     if (qd <= -1073741825.0) return -1073741824;   // the exact quotient is <= -2^30
     if (qd >= 1073741825.0) return 1073741824;     // ... >= 2^30
-    int64_t q = (int64_t)qd;
+    int64_t q = (int64_t)(int)qd;
     if (q * binw_fx > diff) q -= 1;
     else if ((q + 1) * binw_fx <= diff) q += 1;
     if (q < -1073741824) return -1073741824;

@@ -381,6 +381,19 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
     };
     Proposal p_nx = propose(st, kDomMove, (uint64_t)(s0 + lane), (uint32_t)w);
     double lnu_nx = lnu_of(p_nx.u);
+    // decision margin of lane j in a speculative segment from `start`: the
+    // exact-mode slack plus, for each of the segment's earlier visits and the
+    // two subtractions, ln f and the rounding of values up to |a| + |b| (the
+    // two ln g read); M = M0 + (|a| + |b| + 1) Mr.  Almost every segment
+    // starts its block, so those margins are computed once.
+    auto margins = [&](int start, double &M0, double &Mr) {
+        const double slack = (double)(lane - start + 2);
+        M0 = PREC == 0 ? kMargin64 + slack * lnf * (1.0 + 0x1p-50)
+                       : kMargin32 + slack * ((double)lnf32 * (1.0 + 0x1p-20) + 64.0 * lnf * 0x1p-46);
+        Mr = slack * (PREC == 0 ? 0x1p-50 : 0x1p-46);
+    };
+    double M0b = 0.0, Mrb = 0.0;
+    if (spec) margins(0, M0b, Mrb);
     PhaseClock pc;
 
     for (int64_t base = 0; base < n; base += 64) {
@@ -551,13 +564,8 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 const int E0 = ebase + erel;
                 const unsigned long long act = livem & (~0ull << start);
                 const bool mine = (act >> lane) & 1ull;
-                // decision margin of lane j: the exact-mode slack plus, for each of
-                // the segment's earlier visits and the two subtractions, ln f and
-                // the rounding of values up to |a| + |b| (the two ln g read)
-                const double slack = (double)(lane - start + 2);
-                const double M0 = PREC == 0 ? kMargin64 + slack * lnf * (1.0 + 0x1p-50)
-                                            : kMargin32 + slack * ((double)lnf32 * (1.0 + 0x1p-20) + 64.0 * lnf * 0x1p-46);
-                const double Mr = slack * (PREC == 0 ? 0x1p-50 : 0x1p-46);
+                double M0 = M0b, Mr = Mrb;
+                if (start != 0) margins(start, M0, Mr);
                 unsigned long long A = 0ull, Sg = 0ull;
                 int c = todo, pre = E0, nvi = nv, dEi = dE;
                 bool conv = false;
@@ -694,6 +702,13 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                     wave_lds_sync();
                     uint32_t nb = cnt[lane];
                     cnt[lane] = 0u;
+                    // the segment's visits go to H here, one add per energy (device-
+                    // memory rows: atomic, since a later block may read the bin from
+                    // another lane)
+                    if (nb != 0u) {
+                        if (GLOB) atomicAdd(&H[ebase + lane - lo], nb);
+                        else H[ebase + lane - lo] += nb;
+                    }
                     if (PREC == 0 && nb != 0u) {
                         // n sequential adds of ln f in closed form: after the first
                         // add, every add moves x by the same exact step d2 while x
@@ -736,6 +751,10 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                 if (PREC == 0) { gEs = readlane_d(c64, erel); gEv = gEs; }
                 else { gEh = readlane_f(ch, erel); gEl = readlane_f(cl, erel); }
                 slow_attempt(c);
+                if (lane == 0) {
+                    if (GLOB) atomicAdd(&H[ebase + erel - lo], 1u);
+                    else H[ebase + erel - lo] += 1u;
+                }
                 start = c + 1;
                 // every accepted flip so far goes to the lattice; proposals after
                 // c that one of them touched read their spins from it again
@@ -831,7 +850,8 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
             lnu_nx = lnu_of(p_nx.u);
         }
         if (((accepted & ~flushed) >> lane) & 1ull) sp[p.site] = (int8_t)nv;
-        if (live) atomicAdd(&H[hist - lo], 1u);
+        // (the speculative phase counted its visits per segment)
+        if (!spec && live) atomicAdd(&H[hist - lo], 1u);
         const long long pcd = pc.now();
         pc.add(kPcTailCycles, pcd - pct);
         pc.add(kPcDecideCycles, pcd - pc1);

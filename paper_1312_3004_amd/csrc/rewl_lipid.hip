@@ -119,7 +119,7 @@ __device__ __forceinline__ bool lip_bonded(int a, int b) {
     return a - b == 1 || b - a == 1;
 }
 
-__device__ __forceinline__ int lip_bin(const DevState &st, int64_t e) { return fx_bin(st.emin_fx, st.binw_fx, e); }
+__device__ __forceinline__ int lip_bin(const DevState &st, int64_t e) { return fx_bin(st.emin_fx, st.binw_fx, st.binw_inv, e); }
 
 // fx(V_new) - fx(V_old) of one pair; false for a hard overlap.
 __device__ __forceinline__ bool lip_term(double vn, double vo, int64_t &t) {

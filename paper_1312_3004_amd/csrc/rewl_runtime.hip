@@ -402,6 +402,7 @@ int create_run(rewl_t **out, const Params &p, const std::vector<int32_t> &starts
         d.e_min = geom->e_min; d.bin_w = geom->bin_w;
         d.emin_fx = (int64_t)std::rint(geom->e_min * 0x1p32);
         d.binw_fx = (int64_t)std::rint(geom->bin_w * 0x1p32);
+        d.binw_inv = 1.0 / (double)d.binw_fx;
         d.th_e0 = geom->e_min + 0.5 * geom->bin_w;   // bin centres
         d.th_de = geom->bin_w;
         d.Efx = (int64_t *)(b + lay.Ed);

@@ -105,7 +105,7 @@ __device__ __forceinline__ bool delta_e(const DevState &st, const float *x, int 
 }
 
 // Bin of a fixed-point energy (also outside [0, B), bounded to +-2^30).
-__device__ __forceinline__ int energy_bin(const DevState &st, int64_t e) { return fx_bin(st.emin_fx, st.binw_fx, e); }
+__device__ __forceinline__ int energy_bin(const DevState &st, int64_t e) { return fx_bin(st.emin_fx, st.binw_fx, st.binw_inv, e); }
 
 // ---------------------------------------------------------------------------
 // Energy of every walker's starting configuration: the exact sum of the
