@@ -240,6 +240,8 @@ def precision_study(args):
     (default 600); with --checkpoint DIR the three runs can span several
     processes (the run in progress saved in DIR when the budget is spent and
     continued on the next call)."""
+    import zlib
+
     import numpy as np
     import torch
 
@@ -280,10 +282,11 @@ def precision_study(args):
         g = pk.Rewl(L, q, h, cfg["overlap"], m, spins, device=dev, seed=seed, flat=cfg["flat"],
                     lnf_init=cfg["lnf_init"], lnf_final=lnf_final, schedule=cfg["schedule"],
                     sync_attempts=S, exchange=cfg["exchange"], precision=prec, shadow=1)
-        ck = os.path.join(d, name + ".bin") if d else None
+        # saved states are zlib-compressed (the walk-in counts are mostly zeros)
+        ck = os.path.join(d, name + ".bin.z") if d else None
         if ck and os.path.exists(ck):
             with open(ck, "rb") as f:
-                g.load(f.read())
+                g.load(zlib.decompress(f.read()))
         elif rs["segments"]:
             # its saved state is gone: the run starts again
             rs.update(seconds=0.0, segments=0)
@@ -320,7 +323,7 @@ def precision_study(args):
                 f"max |ln g - shadow| {err:.3g}")
         elif ck:
             with open(ck, "wb") as f:
-                f.write(g.save())
+                f.write(zlib.compress(g.save(), 1))
         if state_path:
             with open(state_path, "w") as f:
                 json.dump(state, f)
@@ -356,13 +359,13 @@ TRIMER_FLOPS_PER_ATTEMPT = 2 * 191 * 5
 # mul/add) of the ~52 partners inside the 2.5 cut-off at density 0.8, twice.
 # HBM bytes of one k_trimer_sweep launch of the trimer workload (64 walkers x
 # 20,000 attempts): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a
-# 256 MiB torch.neg copy in the same program), 242.5 KiB and 308.0 KiB.
-TRIMER_SWEEP_HBM_BYTES = 812_000
+# 256 MiB torch.neg copy in the same program), 227.75 KiB and 308.0 KiB.
+TRIMER_SWEEP_HBM_BYTES = 781_800
 LIPID_FLOPS_PER_ATTEMPT = 2 * 999 * 5 + 2 * 52 * 6
 # HBM bytes of one k_lipid_sweep launch of the lipid workload (64 walkers x 2,000
 # attempts): FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB
-# torch.neg copy in the same program), 907.1 KiB and 1,302.0 KiB per launch.
-LIPID_SWEEP_HBM_BYTES = 3_191_000
+# torch.neg copy in the same program), 792.7 KiB and 1,302.0 KiB per launch.
+LIPID_SWEEP_HBM_BYTES = 2_956_600
 
 
 def trimer(args):
@@ -433,7 +436,10 @@ def lipid(args):
     import paper_1312_3004_amd as pk
     import workloads
 
-    cfg = workloads.LIPID
+    cfg = dict(workloads.LIPID)
+    if args.lipid_emin is not None:
+        # the same 800 bins placed lower: the walkers walk in from the lattice start
+        cfg["e_min"] = args.lipid_emin
     h, m = cfg["windows"], cfg["walkers"]
     nw, S = h * m, cfg["sync_attempts"]
     np_ = 3 * cfg["nlip"] + cfg["nsol"]
@@ -472,10 +478,14 @@ def lipid(args):
         "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "lipid: 125 P-H-H lipids + 625 solvent particles, density 0.8, reptation "
-                               "probability 0.0375, bins of 1 over [7000, 7800), 16 windows at 75% overlap, "
-                               "4 walkers each", "walkers": nw, "attempts_per_step_per_walker": S},
+                               f"probability 0.0375, bins of 1 over [{cfg['e_min']:g}, "
+                               f"{cfg['e_min'] + cfg['bins'] * cfg['bin_w']:g}), 16 windows at 75% overlap, "
+                               "4 walkers each", "walkers": nw, "attempts_per_step_per_walker": S,
+                   "e_min": cfg["e_min"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_UNFUSED_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_UNFUSED_PEAK_TFLOPS, "traffic": LIPID_SWEEP_HBM_BYTES, "kernel": "k_lipid_sweep",
+                     "frac": achieved / FP64_UNFUSED_PEAK_TFLOPS,
+                     "traffic": LIPID_SWEEP_HBM_BYTES if cfg["e_min"] == workloads.LIPID["e_min"] else None,
+                     "kernel": "k_lipid_sweep",
                      "kernel_avg_ms": avg_ms, "kernel_launches": launches, "flops_per_attempt": flops},
         "per_walker_attempts_per_s": S * args.steps / el,
         "walkin_s": walkin_s,
@@ -1010,6 +1020,9 @@ def main():
     ap.add_argument("--lnf-final", type=float, default=0.0,
                     help="precision study: stop each run when every window's ln f is below this instead of "
                          "the workload's own ln f_final")
+    ap.add_argument("--lipid-emin", type=float, default=None,
+                    help="lipid workload: lower end of its 800 unit-wide energy bins (default 7000, the band "
+                         "just below the lattice starts)")
     ap.add_argument("--max-runs", type=int, default=0,
                     help="precision study: start at most this many of its runs in this process")
     ap.add_argument("--save-lng", default="", help="with --to-convergence: write the joined ln g (.npy) here")
