@@ -129,6 +129,17 @@ def cpu_baseline(cfg, spins, attempts_per_walker):
                         f"{threads} OpenMP threads on {hc['model']}"))
 
 
+def batched_roofline(attempts_per_step, step_s):
+    """ALU and LDS roofline of the batched persistent step (k_sweep_batch*),
+    priced per attempt like the single-run kernel, over the step wall time."""
+    achieved = ALU_SLOTS_PER_ATTEMPT * attempts_per_step / step_s / 1e12
+    lds = LDS_BYTES_PER_ATTEMPT * attempts_per_step / step_s / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "kernel": "k_sweep_batch_slots",
+            "time_basis": "wall time of one batched step (graph replay)",
+            "lds": {"achieved_gb_per_s": lds, "peak_gb_per_s": LDS_PEAK_GBS, "frac": lds / LDS_PEAK_GBS}}
+
+
 def batched(args):
     """The 256-instance batched workload: autotuned persistent launch (graph
     replay) against one launch per instance, alternating step by step."""
@@ -203,6 +214,10 @@ def batched(args):
         "per_instance_launches": {"value": attempts_per_step / t_single, "ms_per_step": 1e3 * t_single,
                                   "steps": 1},
         "speedup_vs_per_instance": t_single / (t_batch / args.steps),
+        # the same per-attempt work as the single-run kernel (205 VALU issue
+        # slots, 38 LDS bytes) against the step's wall time: one graph replay
+        # is the attempt launch plus the small sync-point kernels
+        "roofline": batched_roofline(attempts_per_step, t_batch / args.steps),
         "walkin_s": walkin_s,
         "tune_s": tune_s,
         "converged_instances": conv,

@@ -29,6 +29,9 @@ def test_roofline_constants():
     r = bench.potts_roofline(640_000, 1.812, 20, None)
     assert abs(r["frac"] - 205 * 640_000 / 1.812e-3 / 3.93216e13) < 1e-12
     assert abs(r["lds"]["frac"] - 38 * 640_000 / 1.812e-3 / 78.6432e12) < 1e-12
+    rb = bench.batched_roofline(8.96e9, 0.6735)
+    assert abs(rb["frac"] - 205 * 8.96e9 / 0.6735 / 3.93216e13) < 1e-12
+    assert abs(rb["lds"]["frac"] - 38 * 8.96e9 / 0.6735 / 78.6432e12) < 1e-12
     # HBM bytes: FETCH_SIZE x 2 + WRITE_SIZE x 1, in KiB, as recorded with the profiles
     assert abs(bench.STRUCT_4096_HBM_BYTES - (12588.7 * 2 + 256.0) * 1024) < 1000
     assert abs(bench.LIPID_SWEEP_HBM_BYTES - (792.67 * 2 + 1302.0) * 1024) < 1000
