@@ -54,12 +54,12 @@ LDS_BYTES_PER_ATTEMPT = 38
 LDS_PEAK_GBS = CU * 128 * CLOCK_HZ / 1e9
 # HBM bytes per k_sweep launch of the potts_q10_L32 workload in its timed (1/t)
 # phase, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a torch.neg
-# copy of known size (profiles/k_sweep_potts_q10_L32_pmc.md): 282.10 KiB x 2.000
+# copy of known size (profiles/k_sweep_potts_q10_L32_pmc.md): 268.18 KiB x 2.000
 # + 390.0 KiB x 1.000.  Valid for the kernel as profiled.
-K_SWEEP_L32_HBM_BYTES = 977_100
+K_SWEEP_L32_HBM_BYTES = 948_600
 # VALU instructions (wave64) per attempt of the same kernel, rocprofv3 SQ_INSTS_VALU
 # over the same workload (same profile).
-K_SWEEP_L32_VALU_PER_ATTEMPT = 9.92
+K_SWEEP_L32_VALU_PER_ATTEMPT = 9.76
 # 1/t phase ends once W/t < 1e-8, i.e. after W/1e-8 attempts per walker.
 
 

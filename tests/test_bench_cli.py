@@ -36,7 +36,7 @@ def test_roofline_constants():
     assert abs(bench.STRUCT_4096_HBM_BYTES - (12588.7 * 2 + 256.0) * 1024) < 1000
     assert abs(bench.LIPID_SWEEP_HBM_BYTES - (792.67 * 2 + 1302.0) * 1024) < 1000
     assert abs(bench.TRIMER_SWEEP_HBM_BYTES - (227.75 * 2 + 308.0) * 1024) < 1000
-    assert abs(bench.K_SWEEP_L32_HBM_BYTES - (282.10 * 2 + 390.0) * 1024) < 1000
+    assert abs(bench.K_SWEEP_L32_HBM_BYTES - (268.18 * 2 + 390.0) * 1024) < 1000
 
 
 def test_host_cpu_info():
@@ -77,3 +77,28 @@ def test_trace_window_averages_the_timed_launches(tmp_path):
     assert r["window_min_ms"] == 1005e-6 and r["window_max_ms"] == 1014e-6
     o = r["other_kernels_in_window"]
     assert list(o) == ["k_sync<0>"] and o["k_sync<0>"]["n"] == 9 and abs(o["k_sync<0>"]["avg_ms"] - 1e-4) < 1e-15
+
+
+def test_phase_clock_summary_per_attempt_and_per_block():
+    # two walkers' counters in the order of the binding's PHASE_CLOCK_FIELDS
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import paper_1312_3004_amd as pk
+
+    f = pk.PHASE_CLOCK_FIELDS
+    assert len(f) == 12 and f[:8] == ("lane_cycles", "decide_cycles", "segments", "rounds", "exact_attempts",
+                                      "blocks", "round_cycles", "attempts")
+    row = dict(lane_cycles=700, decide_cycles=8000, segments=11, rounds=30, exact_attempts=1, blocks=10,
+               round_cycles=3600, attempts=640, setup_cycles=640, commit_cycles=1280, exact_cycles=64,
+               tail_cycles=320)
+    ctr = np.array([[row[k] for k in f], [2 * row[k] for k in f]], dtype=np.uint64)
+    s = bench.phase_clock_summary(ctr, f)
+    assert s["attempts"] == 3 * 640
+    assert abs(s["lane_parallel_cycles_per_attempt"]["mean"] - 700 / 640) < 1e-12
+    assert abs(s["decision_cycles_per_attempt"]["max"] - 8000 / 640) < 1e-12
+    assert abs(s["segments_per_block"]["mean"] - 1.1) < 1e-12
+    assert abs(s["rounds_per_segment"] - 90 / 33) < 1e-12
+    assert abs(s["commit_cycles_per_attempt"]["mean"] - 2.0) < 1e-12
+    assert abs(s["exact_attempts_per_block"]["mean"] - 0.1) < 1e-12
