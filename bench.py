@@ -178,7 +178,7 @@ def batched(args):
     # persistent steps, with one step of one-launch-per-instance in the middle
     t_batch = t_single = 0.0
     for i in range(args.steps):
-        if i == args.steps // 2:
+        if i == args.steps // 2 and not args.no_per_instance:
             t0 = time.perf_counter()
             b.run_per_instance(1)
             torch.cuda.synchronize()
@@ -211,9 +211,9 @@ def batched(args):
                    "attempts_per_step": attempts_per_step},
         "plan": plan,
         "tuner_trials": trials,
-        "per_instance_launches": {"value": attempts_per_step / t_single, "ms_per_step": 1e3 * t_single,
-                                  "steps": 1},
-        "speedup_vs_per_instance": t_single / (t_batch / args.steps),
+        "per_instance_launches": ({"value": attempts_per_step / t_single, "ms_per_step": 1e3 * t_single,
+                                   "steps": 1} if t_single else None),
+        "speedup_vs_per_instance": t_single / (t_batch / args.steps) if t_single else None,
         # the same per-attempt work as the single-run kernel (205 VALU issue
         # slots, 38 LDS bytes) against the step's wall time: one graph replay
         # is the attempt launch plus the small sync-point kernels
@@ -1035,6 +1035,8 @@ def main():
     ap.add_argument("--lnf-final", type=float, default=0.0,
                     help="precision study: stop each run when every window's ln f is below this instead of "
                          "the workload's own ln f_final")
+    ap.add_argument("--no-per-instance", action="store_true",
+                    help="batched workload: skip the step with one launch per instance (for profiler runs)")
     ap.add_argument("--lipid-emin", type=float, default=None,
                     help="lipid workload: lower end of its 800 unit-wide energy bins (default 7000, the band "
                          "just below the lattice starts)")
