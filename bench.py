@@ -1035,6 +1035,9 @@ def main():
     ap.add_argument("--lnf-final", type=float, default=0.0,
                     help="precision study: stop each run when every window's ln f is below this instead of "
                          "the workload's own ln f_final")
+    ap.add_argument("--precision", type=int, choices=(0, 1), default=None,
+                    help="Potts workload: ln g in binary64 (0, the workload's own) or as the binary32 "
+                         "(hi, lo) pair (1)")
     ap.add_argument("--no-per-instance", action="store_true",
                     help="batched workload: skip the step with one launch per instance (for profiler runs)")
     ap.add_argument("--lipid-emin", type=float, default=None,
@@ -1113,6 +1116,8 @@ def main():
     import workloads
 
     cfg = dict(workloads.CONFIGS[args.config])
+    if args.precision is not None:
+        cfg["precision"] = args.precision
     L, q, h, m = cfg["L"], cfg["q"], cfg["windows"], cfg["walkers"]
     nw = h * m
     S = cfg["sync_attempts"]
@@ -1207,7 +1212,8 @@ def main():
                    # launches of the run (0-based, for matching a profiler's trace)
                    "timed_k_sweep_launches": [step_timed // S, step_timed // S + args.steps]},
         "roofline": potts_roofline(attempts_per_launch, avg_ms, launches,
-                                   K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" and approach else None),
+                                   K_SWEEP_L32_HBM_BYTES if args.config == "potts_q10_L32" and approach
+                                   and cfg["precision"] == 0 else None),
         "per_walker_attempts_per_s": per_walker,
         "sync_point_avg_ms": sync_avg,
         "walkin_s": walkin_s,
@@ -1219,7 +1225,7 @@ def main():
         lds = out["roofline"]["lds"]
         lds["measured_peak"] = meas
         lds["frac_of_measured_read_peak"] = lds["achieved_gb_per_s"] / meas["read_b128_gb_per_s"]
-    if args.config == "potts_q10_L32" and approach and K_SWEEP_L32_VALU_PER_ATTEMPT:
+    if args.config == "potts_q10_L32" and approach and cfg["precision"] == 0 and K_SWEEP_L32_VALU_PER_ATTEMPT:
         v = K_SWEEP_L32_VALU_PER_ATTEMPT * 64 * attempts_per_launch / (avg_ms * 1e-3)
         out["valu"] = {"instructions_per_attempt": K_SWEEP_L32_VALU_PER_ATTEMPT, "achieved_lane_slots_per_s": v,
                        "peak_lane_slots_per_s": VALU_LANE_SLOTS_PEAK, "frac": v / VALU_LANE_SLOTS_PEAK}
