@@ -726,6 +726,22 @@ __device__ __forceinline__ void sweep_walker(const DevState &st, int w, int64_t 
                             nb = 0u;
                         }
                     }
+                    if (PREC == 1 && nb != 0u && ch + lnf32 == ch) {
+                        // (hi, lo) pair whose high word ln f leaves unchanged: TwoSum
+                        // then hands the whole ln f to the low word at every add, and
+                        // the low word's n adds follow the closed form above in binary32
+                        const float x1 = cl + lnf32;
+                        const float d2 = (x1 + lnf32) - x1;
+                        int ex;
+                        (void)__builtin_frexpf(x1, &ex);
+                        const float top = __builtin_ldexpf(1.0f, ex);
+                        const float nm1 = (float)(nb - 1u);
+                        if (d2 * 64.0f <= x1 &&
+                            (double)x1 + (double)nm1 * (double)d2 + 4.0 * (double)lnf32 < (double)top * (1.0 - 0x1p-20)) {
+                            cl = x1 + nm1 * d2;
+                            nb = 0u;
+                        }
+                    }
                     while (__ballot(nb != 0u)) {
                         if (PREC == 0) {
                             const double x = c64 + lnf_v;

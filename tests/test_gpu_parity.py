@@ -253,6 +253,24 @@ def test_small_lnf_trajectories_bitexact(L, q, h, m, attempts, precision, lnf):
     assert_same_state(g, o)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_lng_small_lnf_replay_bitexact(precision):
+    # ln g values in the thousands with ln f = 3.6e-7 (the 1/t phase of the L=32
+    # workload): the speculative commit replays a bin's n visits in closed form,
+    # in binary64, and for the (hi, lo) pair whose high word ln f leaves unchanged,
+    # in the low word
+    L, q, h, m = 32, 10, 4, 2
+    g, o = make_pair(L, q, h, m, lnf_init=3.6e-7, fixed_lnf=1, sync_attempts=4001, exchange=1,
+                     precision=precision, seed=17)
+    for w in range(h * m):
+        lng = 1500.0 + 1.4 * np.arange(g.W, dtype=np.float64) + 0.37 * np.sin(0.01 * w * np.arange(g.W))
+        g.set_lng(w, lng)
+        o.set_lng(w, lng)
+    g.run(40_003)
+    o.run(40_003)
+    assert_same_state(g, o)
+
+
 @pytest.mark.parametrize("tilt,precision", [(0.7, 0), (-0.7, 0), (0.7, 1), (0.05, 0), (17.0, 0), (-17.0, 1)])
 def test_tilted_weights_drive_walker_across_cache(tilt, precision):
     # A steep fixed ln g makes the walker drift through a wide window, so it
